@@ -1,0 +1,162 @@
+"""FP64 CPU oracle for the SPIIR filter bank: TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package. It shares no code with the HIP library (the C source is
+``spiir_oracle.c``, built with gcc into ``liboracle.so`` next to it).
+
+Functions (all double precision; see the C source for the definitions):
+  z(bank, x, templates)          complex128 [len(templates), n]
+  snr(bank, x, templates)        float64    [len(templates), n]
+  trigger(bank, x)               (float64 max [n], int32 argmax [n])
+  backward(bank, x, G)           (grad_a, grad_b) complex128 [F]
+  overlap_loss(z, g)             per-template loss and its gradient G
+
+Parity status: every function here is pinned by tests in
+``tests/test_oracle_pins.py`` against closed forms, a library IIR routine,
+brute-force convolution, superposition, finite differences and an
+independent autograd implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spiir_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.oracle_z.argtypes = [P, P, P, P, P, i32, P, i64, P, i32]
+        lib.oracle_snr.argtypes = [P, P, P, P, P, i32, P, i64, P, i32]
+        lib.oracle_trigger.argtypes = [P, P, P, P, i32, P, i64, P, P, i32]
+        lib.oracle_backward.argtypes = [P, P, P, P, i32, P, i64, P, P, P, i32]
+        for f in (lib.oracle_z, lib.oracle_snr, lib.oracle_trigger, lib.oracle_backward):
+            f.restype = ctypes.c_int
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _p(arr):
+    return arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _bank_arrays(bank):
+    off = np.ascontiguousarray(bank.offsets, dtype=np.int64)
+    a = np.ascontiguousarray(np.asarray(bank.a, dtype=np.complex128))
+    b = np.ascontiguousarray(np.asarray(bank.b, dtype=np.complex128))
+    d = np.ascontiguousarray(bank.d, dtype=np.int32)
+    return off, a, b, d
+
+
+def _threads(nthreads):
+    return max_threads() if nthreads is None else int(nthreads)
+
+
+def z(bank, x, templates=None, nthreads=None) -> np.ndarray:
+    """Summed filter output z_j[m] (complex128 [len(templates), n]) from a cold start."""
+    lib = _load()
+    off, a, b, d = _bank_arrays(bank)
+    T = len(off) - 1
+    tpl = np.arange(T, dtype=np.int32) if templates is None else np.asarray(templates, np.int32)
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros((len(tpl), len(xd)), np.complex128)
+    rc = lib.oracle_z(_p(off), _p(a), _p(b), _p(d), _p(tpl), len(tpl), _p(xd), len(xd),
+                      _p(out), _threads(nthreads))
+    if rc:
+        raise RuntimeError("oracle_z failed (%d)" % rc)
+    return out
+
+
+def snr(bank, x, templates=None, nthreads=None) -> np.ndarray:
+    """SNR_j[m] = |z_j[m]|^2 (float64 [len(templates), n])."""
+    lib = _load()
+    off, a, b, d = _bank_arrays(bank)
+    T = len(off) - 1
+    tpl = np.arange(T, dtype=np.int32) if templates is None else np.asarray(templates, np.int32)
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros((len(tpl), len(xd)), np.float64)
+    rc = lib.oracle_snr(_p(off), _p(a), _p(b), _p(d), _p(tpl), len(tpl), _p(xd), len(xd),
+                        _p(out), _threads(nthreads))
+    if rc:
+        raise RuntimeError("oracle_snr failed (%d)" % rc)
+    return out
+
+
+def trigger(bank, x, nthreads=None):
+    """Per-sample max over templates of SNR and the smallest index attaining it."""
+    lib = _load()
+    off, a, b, d = _bank_arrays(bank)
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    mx = np.zeros(len(xd), np.float64)
+    am = np.zeros(len(xd), np.int32)
+    rc = lib.oracle_trigger(_p(off), _p(a), _p(b), _p(d), len(off) - 1, _p(xd), len(xd),
+                            _p(mx), _p(am), _threads(nthreads))
+    if rc:
+        raise RuntimeError("oracle_trigger failed (%d)" % rc)
+    return mx, am
+
+
+def backward(bank, x, G, nthreads=None):
+    """Gradients (grad_a, grad_b), complex128 [F], of a real loss whose gradient
+    with respect to z is G (complex128 [T, n], convention dL/dRe + i dL/dIm)."""
+    lib = _load()
+    off, a, b, d = _bank_arrays(bank)
+    T = len(off) - 1
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    Gc = np.ascontiguousarray(G, dtype=np.complex128)
+    if Gc.shape != (T, len(xd)):
+        raise ValueError("G must be [T, n]")
+    ga = np.zeros(len(a), np.complex128)
+    gb = np.zeros(len(a), np.complex128)
+    rc = lib.oracle_backward(_p(off), _p(a), _p(b), _p(d), T, _p(xd), len(xd), _p(Gc),
+                             _p(ga), _p(gb), _threads(nthreads))
+    if rc:
+        raise RuntimeError("oracle_backward failed (%d)" % rc)
+    return ga, gb
+
+
+def overlap_loss(zs: np.ndarray, gs: np.ndarray):
+    """Template-overlap loss L_j = 1 - |<z_j, g_j>| / (|z_j| |g_j|), with
+    <u, v> = sum_m u[m] conj(v[m]), and G_j = dL_j/dRe(z_j) + i dL_j/dIm(z_j):
+
+      G = -(1/(Z Gn)) [ (c/|c|) g - (|c|/Z^2) z ],  c = <z, g>, Z = |z|, Gn = |g|.
+
+    Inputs complex128 [T, n]; returns (loss [T] float64, G [T, n] complex128).
+    """
+    zs = np.asarray(zs, np.complex128)
+    gs = np.asarray(gs, np.complex128)
+    c = np.sum(zs * np.conj(gs), axis=1)
+    Z = np.sqrt(np.sum(np.abs(zs) ** 2, axis=1))
+    Gn = np.sqrt(np.sum(np.abs(gs) ** 2, axis=1))
+    ac = np.abs(c)
+    loss = 1.0 - ac / (Z * Gn)
+    phase = np.where(ac > 0, c / np.where(ac > 0, ac, 1.0), 0.0)
+    G = -(1.0 / (Z * Gn))[:, None] * (phase[:, None] * gs - (ac / Z ** 2)[:, None] * zs)
+    return loss, G

@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle against results fixed by mathematics, not by itself.
+
+Each test targets a plausible mistake in the oracle (a dropped term, a wrong
+sign, an off-by-one delay, a transposed conjugate, a wrong tie rule):
+  * closed-form impulse response b a^(m-d) of a delayed single-pole filter
+  * scipy.signal.lfilter with complex coefficients (a library IIR routine)
+  * exact finite convolution written out by brute force on tiny inputs
+  * FFT convolution with the full (untruncated) kernel on longer inputs
+  * superposition / linearity / time shift / permutation of filters
+  * closed-form energy of the impulse response of a whole template
+  * the tie rule of the per-sample argmax (duplicated template)
+  * adjoint: closed-form derivatives at an impulse, central finite
+    differences in FP64, and an independent torch autograd implementation
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.signal
+
+import oracle
+from workloads import Bank, random_bank, strain
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def one_filter_bank(a, b, d, dmax=None):
+    return Bank(np.array([0, 1], np.int64), np.array([a], np.complex128),
+                np.array([b], np.complex128), np.array([d], np.int32),
+                int(d if dmax is None else dmax))
+
+
+def small_bank(seed=0, T=3, klo=2, khi=6, dmax=9, rlo=0.5, rhi=0.97):
+    return random_bank(90 + seed, 0, T, klo, khi, rlo, rhi, dmax)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# --------------------------------------------------------------------------
+# single filter
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [0, 1, 17])
+def test_impulse_response_closed_form(d):
+    a = 0.995 * np.exp(1j * 0.3)
+    b = 0.7 - 0.4j
+    n = 400
+    x = np.zeros(n)
+    x[0] = 1.0
+    z = oracle.z(one_filter_bank(a, b, d), x)[0]
+    m = np.arange(n)
+    expect = np.where(m >= d, b * a ** np.maximum(m - d, 0), 0.0)
+    assert np.all(z[:d] == 0)
+    assert rel(z, expect) < 1e-13
+
+
+def test_matches_lfilter_complex():
+    rng = np.random.default_rng(5)
+    n = 3000
+    x = rng.standard_normal(n)
+    for a, b, d in [(0.99 * np.exp(0.1j), 1 + 2j, 0),
+                    (0.9999 * np.exp(-1.2j), -0.3 + 0.05j, 5),
+                    (0.5 * np.exp(2.9j), 0.2j, 123)]:
+        z = oracle.z(one_filter_bank(a, b, d), x)[0]
+        xs = np.concatenate([np.zeros(d), x])[:n]
+        ref = scipy.signal.lfilter([b], [1.0, -a], xs)
+        assert rel(z, ref) < 1e-11, (a, b, d)
+
+
+def test_bruteforce_finite_convolution():
+    # y[m] = b * sum_{i=0}^{m-d} a^i x[m-d-i]: exact for a finite input
+    rng = np.random.default_rng(11)
+    bank = small_bank(1, T=2, klo=3, khi=4, dmax=7)
+    n = 37
+    x = rng.standard_normal(n)
+    got = oracle.z(bank, x)
+    for j in range(bank.n_templates):
+        for m in range(n):
+            acc = 0j
+            for k in range(int(bank.offsets[j]), int(bank.offsets[j + 1])):
+                a, b, d = complex(bank.a[k]), complex(bank.b[k]), int(bank.d[k])
+                for i in range(0, m - d + 1):
+                    acc += b * a ** i * x[m - d - i]
+            assert abs(got[j, m] - acc) <= 1e-12 * (1 + abs(acc))
+
+
+def test_fft_convolution_long():
+    rng = np.random.default_rng(12)
+    bank = small_bank(2, T=2, klo=5, khi=8, dmax=300, rlo=0.99, rhi=0.9999)
+    n = 6000
+    x = rng.standard_normal(n)
+    got = oracle.z(bank, x)
+    i = np.arange(n)
+    for j in range(bank.n_templates):
+        h = np.zeros(n, np.complex128)
+        for k in range(int(bank.offsets[j]), int(bank.offsets[j + 1])):
+            d = int(bank.d[k])
+            h[d:] += bank.b[k] * bank.a[k] ** i[: n - d]
+        ref = scipy.signal.fftconvolve(x, h)[:n]
+        assert rel(got[j], ref) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# template sum: superposition, linearity, shift, permutation, energy
+# --------------------------------------------------------------------------
+
+def test_linearity_in_x():
+    rng = np.random.default_rng(3)
+    bank = small_bank(3, T=3)
+    n = 500
+    x1, x2 = rng.standard_normal(n), rng.standard_normal(n)
+    al, be = 1.7, -0.45
+    lhs = oracle.z(bank, al * x1 + be * x2)
+    rhs = al * oracle.z(bank, x1) + be * oracle.z(bank, x2)
+    assert rel(lhs, rhs) < 1e-12
+
+
+def test_bank_is_sum_of_single_filters():
+    rng = np.random.default_rng(4)
+    bank = small_bank(4, T=2, klo=4, khi=7)
+    n = 700
+    x = rng.standard_normal(n)
+    z = oracle.z(bank, x)
+    for j in range(bank.n_templates):
+        acc = np.zeros(n, np.complex128)
+        for k in range(int(bank.offsets[j]), int(bank.offsets[j + 1])):
+            acc += oracle.z(one_filter_bank(bank.a[k], bank.b[k], bank.d[k]), x)[0]
+        assert rel(z[j], acc) < 1e-13
+
+
+def test_filter_permutation_and_threads():
+    rng = np.random.default_rng(6)
+    bank = small_bank(5, T=1, klo=40, khi=40, dmax=50)
+    x = rng.standard_normal(1000)
+    perm = rng.permutation(bank.n_filters)
+    pb = Bank(bank.offsets, bank.a[perm], bank.b[perm], bank.d[perm], bank.dmax)
+    z1 = oracle.z(bank, x, nthreads=1)
+    z2 = oracle.z(pb, x, nthreads=1)
+    z3 = oracle.z(bank, x, nthreads=4)
+    assert rel(z1, z2) < 1e-13
+    assert rel(z1, z3) < 1e-13
+
+
+def test_time_shift():
+    rng = np.random.default_rng(7)
+    bank = small_bank(6, T=2)
+    n, s = 400, 23
+    x = rng.standard_normal(n)
+    xs = np.concatenate([np.zeros(s), x[: n - s]])
+    z = oracle.z(bank, x)
+    zs = oracle.z(bank, xs)
+    assert np.all(zs[:, :s] == 0)
+    assert rel(zs[:, s:], z[:, : n - s]) < 1e-13
+
+
+def test_impulse_energy_closed_form():
+    # |z|^2 summed over m < N for x = delta:
+    #   sum_{k,l} b_k conj(b_l) a_k^(M-d_k) conj(a_l)^(M-d_l) (1 - (a_k conj a_l)^(N-M)) / (1 - a_k conj a_l)
+    # with M = max(d_k, d_l)
+    bank = small_bank(7, T=2, klo=5, khi=9, dmax=40, rlo=0.9, rhi=0.99)
+    N = 900
+    x = np.zeros(N)
+    x[0] = 1.0
+    z = oracle.z(bank, x)
+    for j in range(bank.n_templates):
+        ks = range(int(bank.offsets[j]), int(bank.offsets[j + 1]))
+        e = 0j
+        for k in ks:
+            for l in ks:
+                ak, al = bank.a[k], bank.a[l]
+                M = max(int(bank.d[k]), int(bank.d[l]))
+                q = ak * np.conj(al)
+                e += (bank.b[k] * np.conj(bank.b[l]) * ak ** (M - bank.d[k])
+                      * np.conj(al) ** (M - bank.d[l]) * (1 - q ** (N - M)) / (1 - q))
+        direct = np.sum(np.abs(z[j]) ** 2)
+        assert abs(e.imag) < 1e-10 * abs(e.real)
+        assert abs(direct - e.real) < 1e-11 * e.real
+
+
+def test_snr_is_abs_squared():
+    rng = np.random.default_rng(8)
+    bank = small_bank(8, T=3)
+    x = rng.standard_normal(300)
+    z = oracle.z(bank, x)
+    s = oracle.snr(bank, x)
+    assert np.array_equal(s, z.real ** 2 + z.imag ** 2)
+
+
+# --------------------------------------------------------------------------
+# max / argmax over templates
+# --------------------------------------------------------------------------
+
+def test_trigger_tie_rule_lowest_index():
+    rng = np.random.default_rng(9)
+    base = small_bank(9, T=3, klo=3, khi=5)
+    # template order: 0, 1, 2, then duplicates of 1 and 0 at indices 3, 4
+    bank = base.subset([0, 1, 2, 1, 0])
+    x = rng.standard_normal(400)
+    s = oracle.snr(bank, x)
+    first = np.argmax(s == s.max(axis=0)[None, :], axis=0)
+    for nt in (1, 2, 3, 5):
+        mx, am = oracle.trigger(bank, x, nthreads=nt)
+        assert np.array_equal(mx, s.max(axis=0))
+        assert np.all(am <= 2)          # duplicates never win
+        assert np.array_equal(am, first)
+
+
+def test_trigger_threads_agree():
+    rng = np.random.default_rng(10)
+    bank = small_bank(10, T=7, klo=2, khi=5)
+    x = rng.standard_normal(333)
+    m1, j1 = oracle.trigger(bank, x, nthreads=1)
+    m4, j4 = oracle.trigger(bank, x, nthreads=4)
+    assert np.array_equal(m1, m4) and np.array_equal(j1, j4)
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+
+def test_backward_impulse_closed_form():
+    # x = delta: dz[m]/db_k = a_k^(m-d_k), dz[m]/da_k = b_k (m-d_k) a_k^(m-d_k-1);
+    # grad = sum_m G[m] conj(dz[m]/dp) in the dL/dRe + i dL/dIm convention.
+    rng = np.random.default_rng(13)
+    bank = small_bank(11, T=2, klo=3, khi=5, dmax=20, rlo=0.9, rhi=0.99)
+    n = 300
+    x = np.zeros(n)
+    x[0] = 1.0
+    G = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    ga, gb = oracle.backward(bank, x, G)
+    m = np.arange(n)
+    for j in range(2):
+        for k in range(int(bank.offsets[j]), int(bank.offsets[j + 1])):
+            a, b, d = bank.a[k], bank.b[k], int(bank.d[k])
+            on = m >= d
+            e = np.maximum(m - d, 0)
+            dzb = np.where(on, a ** e, 0)
+            dza = np.where(m >= d + 1, b * e * a ** np.maximum(e - 1, 0), 0)
+            assert abs(gb[k] - np.sum(G[j] * np.conj(dzb))) < 1e-10 * np.sum(np.abs(G[j]))
+            assert abs(ga[k] - np.sum(G[j] * np.conj(dza))) < 1e-9 * np.sum(np.abs(G[j] * dza))
+
+
+def _loss_of(bank, x, g):
+    z = oracle.z(bank, x)
+    loss, G = oracle.overlap_loss(z, g)
+    return float(np.sum(loss)), G
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(14)
+    bank = small_bank(12, T=2, klo=3, khi=4, dmax=15, rlo=0.9, rhi=0.99)
+    n = 200
+    x = rng.standard_normal(n)
+    g = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    L0, G = _loss_of(bank, x, g)
+    ga, gb = oracle.backward(bank, x, G)
+    h = 1e-6
+    for k in range(bank.n_filters):
+        for which, grad in (("a", ga), ("b", gb)):
+            fd = 0j
+            for unit, part in ((1.0, 1.0), (1j, 1j)):
+                vals = []
+                for s in (+1, -1):
+                    a2, b2 = bank.a.copy(), bank.b.copy()
+                    (a2 if which == "a" else b2)[k] += s * h * unit
+                    vals.append(_loss_of(Bank(bank.offsets, a2, b2, bank.d, bank.dmax), x, g)[0])
+                fd += part * (vals[0] - vals[1]) / (2 * h)
+            assert abs(grad[k] - fd) <= 1e-6 * max(1e-3, abs(fd)), (which, k, grad[k], fd)
+
+
+def test_backward_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(15)
+    bank = small_bank(13, T=2, klo=2, khi=3, dmax=6, rlo=0.8, rhi=0.98)
+    n = 60
+    x = rng.standard_normal(n)
+    g = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    a = torch.tensor(bank.a, dtype=torch.complex128, requires_grad=True)
+    b = torch.tensor(bank.b, dtype=torch.complex128, requires_grad=True)
+    xt = torch.tensor(x, dtype=torch.float64)
+    gt = torch.tensor(g)
+    total = 0
+    for j in range(2):
+        zj = [torch.zeros((), dtype=torch.complex128) for _ in range(n)]
+        for k in range(int(bank.offsets[j]), int(bank.offsets[j + 1])):
+            y = torch.zeros((), dtype=torch.complex128)
+            d = int(bank.d[k])
+            for m in range(n):
+                xin = xt[m - d] if m >= d else torch.zeros((), dtype=torch.float64)
+                y = a[k] * y + b[k] * xin
+                zj[m] = zj[m] + y
+        zv = torch.stack(zj)
+        c = torch.sum(zv * torch.conj(gt[j]))
+        total = total + 1 - torch.abs(c) / (torch.linalg.norm(zv) * torch.linalg.norm(gt[j]))
+    total.backward()
+    L0, G = _loss_of(bank, x, g)
+    assert abs(float(total) - L0) < 1e-12
+    ga, gb = oracle.backward(bank, x, G)
+    assert rel(ga, a.grad.numpy()) < 1e-10
+    assert rel(gb, b.grad.numpy()) < 1e-10
+
+
+def test_overlap_loss_gradient_fd():
+    rng = np.random.default_rng(16)
+    z = rng.standard_normal((2, 50)) + 1j * rng.standard_normal((2, 50))
+    g = rng.standard_normal((2, 50)) + 1j * rng.standard_normal((2, 50))
+    loss, G = oracle.overlap_loss(z, g)
+    # scale invariance of the overlap
+    l2, _ = oracle.overlap_loss(3.7 * np.exp(0.4j) * z, g)
+    assert np.allclose(loss, l2, atol=1e-14)
+    assert np.all((loss >= -1e-15) & (loss <= 1 + 1e-15))
+    h = 1e-6
+    for j in range(2):
+        for m in (0, 7, 49):
+            fd = 0j
+            for unit in (1.0, 1j):
+                zp, zm = z.copy(), z.copy()
+                zp[j, m] += h * unit
+                zm[j, m] -= h * unit
+                fd += unit * (oracle.overlap_loss(zp, g)[0][j] - oracle.overlap_loss(zm, g)[0][j]) / (2 * h)
+            assert abs(G[j, m] - fd) < 1e-7
+
+
+def test_identical_target_has_zero_loss():
+    rng = np.random.default_rng(17)
+    z = rng.standard_normal((1, 64)) + 1j * rng.standard_normal((1, 64))
+    loss, G = oracle.overlap_loss(z, 2.5j * z)
+    assert abs(loss[0]) < 1e-14
+    assert np.max(np.abs(G)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# generators
+# --------------------------------------------------------------------------
+
+def test_generators_are_deterministic_and_in_range():
+    b1 = random_bank(1, 0, 20, 100, 800, 0.99, 1 - 1e-5, 16384)
+    b2 = random_bank(1, 0, 20, 100, 800, 0.99, 1 - 1e-5, 16384)
+    assert np.array_equal(b1.a, b2.a) and np.array_equal(b1.d, b2.d)
+    r = np.abs(b1.a)
+    w = np.angle(b1.a)
+    assert r.min() >= 0.99 and r.max() <= 1 - 1e-5 + 1e-15
+    assert w.min() >= 0.001 * math.pi - 1e-12 and w.max() <= 0.5 * math.pi + 1e-12
+    assert b1.d.min() >= 0 and b1.d.max() <= 16384
+    k = b1.counts()
+    assert k.min() >= 100 and k.max() <= 800
+    x1, x2 = strain(1000, 1), strain(1000, 1)
+    assert x1.dtype == np.float32 and np.array_equal(x1, x2)
+    assert not np.array_equal(strain(1000, 1), strain(1000, 0))

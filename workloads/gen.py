@@ -1,0 +1,224 @@
+"""Seeded generators for the five synthetic SPIIR workloads.
+
+The paper's SPIIR experiment (Sect. "GPU accelerated SPIIR method",
+subsection "Experimental results") ran on real pipeline data and real
+template banks that are not public. These generators stand in for them with
+banks of first-order complex IIR filters of the shapes the workloads name.
+
+Seeds: ``numpy.random.default_rng([1602, cfg, role, idx])`` with role 0 =
+strain, 1 = bank, 2 = chirp parameters, and idx = stream / template index.
+The float32 strain array is canonical; bank coefficients are canonical in
+complex128 (the library rounds them itself).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_ROOT = 1602
+ROLE_STRAIN, ROLE_BANK, ROLE_CHIRP = 0, 1, 2
+
+FS = 4096.0                 # sample rate of the chirp workloads (Hz)
+T_SUN = 4.925491025543576e-06  # G * M_sun / c^3 in seconds
+
+
+def _rng(cfg: int, role: int, idx: int = 0) -> np.random.Generator:
+    return np.random.default_rng([SEED_ROOT, cfg, role, idx])
+
+
+@dataclass
+class Bank:
+    """A bank of templates, each a list of first-order complex IIR filters.
+
+    offsets: int64 [T+1], filters of template j are offsets[j]:offsets[j+1]
+    a, b:    complex128 [F] pole and gain of every filter
+    d:       int32 [F] input delay in samples
+    dmax:    int, the delay bound the bank is built for (>= max d)
+    """
+
+    offsets: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    d: np.ndarray
+    dmax: int
+
+    @property
+    def n_templates(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_filters(self) -> int:
+        return int(self.offsets[-1])
+
+    def counts(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def subset(self, templates) -> "Bank":
+        """A bank made of the listed templates, in the given order."""
+        templates = [int(j) for j in templates]
+        parts = [slice(int(self.offsets[j]), int(self.offsets[j + 1])) for j in templates]
+        cnt = np.array([s.stop - s.start for s in parts], dtype=np.int64)
+        off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+        cat = lambda v: np.concatenate([v[s] for s in parts])  # noqa: E731
+        return Bank(off, cat(self.a), cat(self.b), cat(self.d).astype(np.int32), self.dmax)
+
+
+def strain(n: int, cfg: int, idx: int = 0) -> np.ndarray:
+    """Whitened strain stand-in: seeded white Gaussian noise, sigma = 1, float32."""
+    return _rng(cfg, ROLE_STRAIN, idx).standard_normal(int(n)).astype(np.float32)
+
+
+def random_bank(cfg: int, idx: int, n_templates: int, k_lo: int, k_hi: int,
+                r_lo: float, r_hi: float, dmax: int,
+                w_lo: float = 0.001 * math.pi, w_hi: float = 0.5 * math.pi) -> Bank:
+    """Random bank: K_j ~ U{k_lo..k_hi}; per filter r ~ U[r_lo, r_hi],
+    omega ~ U[w_lo, w_hi], a = r e^{i omega}; b circular complex normal
+    (Re, Im iid N(0, 1/2)) scaled by 1/sqrt(K_j); d ~ U{0..dmax}.
+
+    Draw order: all K_j first, then per template r, omega, Re b, Im b, d.
+    """
+    rng = _rng(cfg, ROLE_BANK, idx)
+    k = rng.integers(k_lo, k_hi + 1, size=n_templates).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    nf = int(off[-1])
+    a = np.empty(nf, np.complex128)
+    b = np.empty(nf, np.complex128)
+    d = np.empty(nf, np.int32)
+    s = math.sqrt(0.5)
+    for j in range(n_templates):
+        kj = int(k[j])
+        sl = slice(int(off[j]), int(off[j + 1]))
+        r = rng.uniform(r_lo, r_hi, kj)
+        w = rng.uniform(w_lo, w_hi, kj)
+        br = rng.standard_normal(kj) * s
+        bi = rng.standard_normal(kj) * s
+        dd = rng.integers(0, dmax + 1, size=kj)
+        a[sl] = r * np.exp(1j * w)
+        b[sl] = (br + 1j * bi) / math.sqrt(kj)
+        d[sl] = dd
+    return Bank(off, a, b, d, int(dmax))
+
+
+# ---------------------------------------------------------------------------
+# The five workloads. Each returns (bank(s), strain(s)) at full size unless a
+# smaller n is asked for (tests use prefixes or reduced template counts).
+# ---------------------------------------------------------------------------
+
+def config0(n: int = 16384):
+    """4 templates x 128 filters, r ~ U[0.99, 0.9999], d ~ U{0..2047}, 16,384 samples."""
+    bank = random_bank(0, 0, 4, 128, 128, 0.99, 0.9999, 2047)
+    return bank, strain(n, 0)
+
+
+def config1(n: int = 4194304, n_templates: int = 1024):
+    """1,024 templates, K_j ~ U{100..800}, r ~ U[0.99, 1-1e-5], d ~ U{0..16384},
+    4,194,304 samples at 4,096 Hz, processed in 4,096-sample blocks."""
+    bank = random_bank(1, 0, n_templates, 100, 800, 0.99, 1.0 - 1e-5, 16384)
+    return bank, strain(n, 1)
+
+
+def config2_lengths(n_streams: int = 8) -> np.ndarray:
+    """Stream lengths round(2^u), u ~ U[18, 22]."""
+    u = _rng(2, ROLE_STRAIN, 1000).uniform(18.0, 22.0, n_streams)
+    return np.round(2.0 ** u).astype(np.int64)
+
+
+def config2(n_streams: int = 8, n_templates: int = 256, length_scale: float = 1.0):
+    """8 streams of uneven length, each with its own 256-template bank of
+    U{200..600} filters (coefficients as config 1, d <= 16,384)."""
+    lengths = config2_lengths(n_streams)
+    if length_scale != 1.0:
+        lengths = np.maximum(1, np.round(lengths * length_scale)).astype(np.int64)
+    banks = [random_bank(2, s, n_templates, 200, 600, 0.99, 1.0 - 1e-5, 16384)
+             for s in range(n_streams)]
+    xs = [strain(int(lengths[s]), 2, s) for s in range(n_streams)]
+    return banks, xs
+
+
+def config4(n: int = 16777216, n_templates: int = 64):
+    """64 templates x 1,000 filters, r ~ U[1-1e-6, 1-1e-4], d ~ U{0..2047},
+    16,777,216 samples."""
+    bank = random_bank(4, 0, n_templates, 1000, 1000, 1.0 - 1e-6, 1.0 - 1e-4, 2047)
+    return bank, strain(n, 4)
+
+
+# ---------------------------------------------------------------------------
+# Chirp targets for the adjoint fit (config 3).
+# ---------------------------------------------------------------------------
+
+def _chirp_tau_of_f(f, mc):
+    """Time to coalescence at GW frequency f (leading-order quadrupole)."""
+    return (5.0 / 256.0) * (math.pi * f) ** (-8.0 / 3.0) * (mc * T_SUN) ** (-5.0 / 3.0)
+
+
+def chirp_target(mc: float, n: int = 65536, fs: float = FS,
+                 f_lo: float = 30.0, f_hi: float = 1000.0) -> np.ndarray:
+    """Time-reversed analytic Newtonian chirp g[n] = conj(h_c[N-1-n]).
+
+    h_c(t) = f(t)^{2/3} exp(i phi(t)), tau = t_c - t,
+    f(tau) = (1/pi) (5/(256 tau))^{3/8} (Mc T_sun)^{-5/8},
+    phi(tau) = -2 (tau / (5 Mc T_sun))^{5/8}; zero outside [f_lo, f_hi].
+    t_c is placed so that f = f_hi at the last sample. Real part of h_c is the
+    A f^{2/3} cos(phi) waveform with A = 1 (the overlap loss is scale free).
+    """
+    tau_last = _chirp_tau_of_f(f_hi, mc)
+    # g[m] corresponds to original index N-1-m, i.e. tau = tau_last + m/fs
+    tau = tau_last + np.arange(n, dtype=np.float64) / fs
+    f = (1.0 / math.pi) * (5.0 / (256.0 * tau)) ** (3.0 / 8.0) * (mc * T_SUN) ** (-5.0 / 8.0)
+    phi = -2.0 * (tau / (5.0 * mc * T_SUN)) ** (5.0 / 8.0)
+    h = f ** (2.0 / 3.0) * np.exp(1j * phi)
+    h[(f < f_lo) | (f > f_hi * (1 + 1e-12))] = 0.0
+    return np.conj(h)
+
+
+def config3_masses(n_templates: int = 256) -> np.ndarray:
+    return _rng(3, ROLE_CHIRP, 0).uniform(1.0, 30.0, n_templates)
+
+
+def chirp_init_bank(g: np.ndarray, k: int, fs: float = FS):
+    """Heuristic starting bank for fitting one target g with k filters.
+
+    The support of g is cut into k equal segments; filter i starts at its
+    segment (d = segment start), rotates at the local phase increment of g,
+    decays over about one segment and takes the target sample as its gain.
+    Returns (a, b, d) as complex128, complex128, int32.
+    """
+    nz = np.nonzero(np.abs(g) > 0)[0]
+    n0, n1 = (int(nz[0]), int(nz[-1]) + 1) if nz.size else (0, len(g))
+    edges = np.linspace(n0, n1, k + 1)
+    starts = np.floor(edges[:-1]).astype(np.int64)
+    seg = np.maximum(1.0, np.diff(edges))
+    ph = np.unwrap(np.angle(g))
+    nxt = np.minimum(starts + 1, len(g) - 1)
+    w = ph[nxt] - ph[starts]
+    w = np.where(np.abs(g[nxt]) > 0, w, 2 * math.pi * 30.0 / fs)
+    r = np.minimum(np.exp(-1.0 / seg), 1.0 - 1e-6)
+    a = r * np.exp(1j * w)
+    b = np.where(np.abs(g[starts]) > 0, g[starts], 1e-6)
+    return a.astype(np.complex128), b.astype(np.complex128), starts.astype(np.int32)
+
+
+def config3(n: int = 65536, n_templates: int = 256, k: int = 400):
+    """256 templates x 400 filters fitted to time-reversed Newtonian chirps with
+    chirp masses ~ U[1, 30] M_sun, 30-1,000 Hz, 65,536 samples at 4,096 Hz.
+    Input x is a unit impulse, so the bank output is its impulse response.
+
+    Returns (initial bank, x, targets g [T, n] complex128, chirp masses)."""
+    mcs = config3_masses(n_templates)
+    gs = np.empty((n_templates, n), np.complex128)
+    a = np.empty(n_templates * k, np.complex128)
+    b = np.empty_like(a)
+    d = np.empty(n_templates * k, np.int32)
+    for j, mc in enumerate(mcs):
+        g = chirp_target(float(mc), n)
+        gs[j] = g
+        aj, bj, dj = chirp_init_bank(g, k)
+        a[j * k:(j + 1) * k] = aj
+        b[j * k:(j + 1) * k] = bj
+        d[j * k:(j + 1) * k] = dj
+    off = np.arange(n_templates + 1, dtype=np.int64) * k
+    x = np.zeros(n, np.float32)
+    x[0] = 1.0
+    return Bank(off, a, b, d, int(n - 1)), x, gs, mcs
