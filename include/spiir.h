@@ -1,0 +1,272 @@
+/*
+ * spiir.h - C ABI of the MI355X (gfx950) summed parallel IIR (SPIIR) library.
+ *
+ * The operation (Sect. "GPU accelerated SPIIR method", subsections "SPIIR
+ * method" and "Optimized GPU implementation of SPIIR"): a template's SNR is
+ * approximated by the summed output of a parallel bank of single-pole IIR
+ * filters run over the (whitened) detector stream; each filter's output is
+ * fed back as its next input, and the template's SNR needs the outputs of all
+ * its filters. In this library, for template j with filters k and samples m:
+ *
+ *   y_k[m]   = a_k * y_k[m-1] + b_k * x[m - d_k]          (complex a_k, b_k; real x)
+ *   z_j[m]   = sum_k y_k[m]
+ *   snr_j[m] = Re(z_j[m])^2 + Im(z_j[m])^2
+ *   max[m]   = max_j snr_j[m],  argmax[m] = smallest j attaining it
+ *
+ * The recursion runs in FP32 complex arithmetic; every chunk_len samples each
+ * filter's carried state is corrected in FP64 (see spiir_precision).
+ *
+ * Conventions for every function below:
+ *  - Return value: SPIIR_OK (0) or a negative spiir_status. The message of the
+ *    last failure on the calling thread is returned by spiir_last_error().
+ *  - Pointers named *_dev are device pointers (hipMalloc / torch CUDA tensors)
+ *    owned by the caller; the library never frees them. Pointers without the
+ *    suffix are host pointers, read during the call only.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream). Device
+ *    work is enqueued asynchronously on it; argument errors are reported
+ *    before anything is enqueued; device faults surface at the caller's next
+ *    synchronisation.
+ *  - A bank is not thread safe: use it from one host thread and one stream at
+ *    a time. Banks keep streaming state (filter states and the last max_delay
+ *    samples), so consecutive calls continue one stream.
+ *  - Complex arrays are interleaved (re, im): complex128 on the host, complex64
+ *    on the device.
+ */
+#ifndef SPIIR_H
+#define SPIIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spiir_bank spiir_bank;
+typedef struct spiir_tape spiir_tape;
+typedef struct spiir_batch spiir_batch;
+
+typedef enum {
+    SPIIR_OK = 0,
+    SPIIR_EINVAL = -1,  /* bad argument: null pointer, size, |a| >= 1, d out of range, ... */
+    SPIIR_ENOMEM = -2,  /* host or device allocation failed */
+    SPIIR_EHIP = -3,    /* a HIP runtime call failed; spiir_last_error() has its message */
+    SPIIR_ESTATE = -4,  /* object used in the wrong state (stale tape, foreign bank, ...) */
+    SPIIR_ENODEV = -5   /* no usable gfx950 device */
+} spiir_status;
+
+/* Precision plan of the recursion (the bulk loop is FP32 in every mode). */
+typedef enum {
+    /* FP64 chunk-carry powers a^L, and FP64 cross-chunk carry propagation for
+     * filters with |a| > 1 - 1e-5; other filters get an FP32 correction by
+     * (a^L - fl32(a)^L) times the chunk's starting state. Default. */
+    SPIIR_PREC_HYBRID = 0,
+    /* plain FP32 recursion with fl32(a), fl32(b); no correction */
+    SPIIR_PREC_FP32 = 1,
+    /* FP64 carry propagation for every filter */
+    SPIIR_PREC_FP64_CARRY = 2
+} spiir_precision;
+
+typedef struct {
+    int32_t chunk_len;        /* L: samples between carry corrections; multiple of 8 in
+                                 [8, 4096]; 0 = 256 */
+    int32_t filters_per_lane; /* filters held in registers by each lane: 1..4;
+                                 0 = chosen from the bank size */
+    int32_t max_delay;        /* upper bound on every d_k (size of the kept history);
+                                 0 = max_k d_k */
+    int32_t precision;        /* spiir_precision */
+    int32_t device;           /* HIP device ordinal; -1 = the current device */
+    int32_t max_block;        /* most samples handled by one kernel launch (longer calls
+                                 are split); 0 = 16384 */
+    int32_t waves_per_group;  /* 64-lane waves per workgroup, 1..16; 0 = automatic */
+    int32_t autotune;         /* 1: time the candidate (chunk_len, filters_per_lane)
+                                 pairs on this bank and keep the fastest */
+} spiir_bank_opts;
+
+/* Layout facts of a created bank (for tests, tuning reports and benchmarks). */
+typedef struct {
+    int32_t n_templates;
+    int64_t n_filters;
+    int32_t max_delay;
+    int32_t chunk_len;
+    int32_t filters_per_lane;
+    int32_t waves_per_group;
+    int32_t n_groups;         /* workgroups per forward launch */
+    int64_t n_slots;          /* filter slots incl. padding (n_groups * waves * 64 * F) */
+    int32_t lds_bytes;        /* LDS per workgroup of the forward kernel */
+    int32_t x_in_lds;         /* 1: the delayed strain window is staged in LDS */
+    int32_t sub_block;        /* samples per LDS window fill */
+    int32_t precision;
+    int32_t device;
+    int32_t n_cu;             /* compute units of the device */
+} spiir_bank_info;
+
+/* Fills *opts with the defaults listed above. */
+void spiir_bank_opts_default(spiir_bank_opts *opts);
+
+/*
+ * Builds a bank on the device (the per-template parameter arrays of subsection
+ * "Optimized GPU implementation of SPIIR": aligned, contiguous, loaded with
+ * coalesced accesses).
+ *   n_templates     T >= 1
+ *   filter_offsets  int64 [T+1]: filters of template j are offsets[j] .. offsets[j+1]-1;
+ *                   offsets[0] = 0, strictly increasing (every template has >= 1 filter)
+ *   a, b            complex128 [F] (interleaved), F = offsets[T]; |a_k| < 1 required
+ *   d               int32 [F], 0 <= d_k <= max_delay
+ *   opts            NULL = defaults
+ * Filters are reordered into device slots internally; every per-filter output
+ * (gradients, state) is reported in the caller's order. The bank starts cold
+ * (zero states, zero history). *out receives the bank, or NULL on failure.
+ */
+int spiir_bank_create(spiir_bank **out, int32_t n_templates, const int64_t *filter_offsets,
+                      const double *a, const double *b, const int32_t *d,
+                      const spiir_bank_opts *opts);
+
+/* Frees the bank and its device buffers (synchronises its device). NULL is ignored. */
+int spiir_bank_destroy(spiir_bank *bank);
+
+/* Returns the layout facts of the bank. */
+int spiir_bank_get_info(const spiir_bank *bank, spiir_bank_info *info);
+
+/* Cold start: zero filter states and history, enqueued on stream. */
+int spiir_bank_reset(spiir_bank *bank, void *stream);
+
+/*
+ * Replaces every a_k and b_k (same F, same d, same layout); the streaming
+ * state is kept. Host arrays complex128 [F] in the caller's filter order,
+ * |a_k| < 1. Synchronous with respect to the device (copies complete on
+ * return).
+ */
+int spiir_bank_set_coeffs(spiir_bank *bank, const double *a, const double *b);
+
+/* Size in bytes of a state checkpoint of this bank. */
+int spiir_bank_state_size(const spiir_bank *bank, size_t *nbytes);
+
+/*
+ * Checkpoint / resume of the streaming state (filter states and history).
+ * host_buf must hold spiir_bank_state_size() bytes. Both calls synchronise the
+ * device. Resuming from a checkpoint continues the stream bit for bit.
+ */
+int spiir_bank_get_state(const spiir_bank *bank, void *host_buf, size_t nbytes);
+int spiir_bank_set_state(spiir_bank *bank, const void *host_buf, size_t nbytes);
+
+/*
+ * Filters the next n samples of the stream and writes every template's SNR.
+ *   x_dev    float32 [n], the next n samples
+ *   snr_dev  float32, row-major [T][ld_snr], ld_snr >= n; row j receives snr_j
+ * n = 0 is a no-op. One launch covers all templates.
+ */
+int spiir_filter_block(spiir_bank *bank, const float *x_dev, int64_t n,
+                       float *snr_dev, int64_t ld_snr, void *stream);
+
+/*
+ * Filters the next n samples and writes only the per-sample maximum of the
+ * SNR over templates and its smallest attaining template index; the [T][n]
+ * SNR is never stored (fused epilogue).
+ *   x_dev       float32 [n]
+ *   max_dev     float32 [n]
+ *   argmax_dev  int32 [n]
+ */
+int spiir_trigger_max(spiir_bank *bank, const float *x_dev, int64_t n,
+                      float *max_dev, int32_t *argmax_dev, void *stream);
+
+/*
+ * Reference design for comparison: the same outputs as spiir_trigger_max, but
+ * computed with one kernel launch per template (as in the paper's
+ * template-to-block mapping), each writing that template's SNR row to
+ * snr_scratch_dev (float32 [T][n], caller-owned), followed by a separate
+ * max/argmax pass over the stored rows.
+ */
+int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t n,
+                                   float *max_dev, int32_t *argmax_dev,
+                                   float *snr_scratch_dev, void *stream);
+
+/*
+ * One-shot forward from a cold start over x[0..n), independent of the
+ * bank's streaming state (which is left untouched). Writes z_j[m] as complex64
+ * into z_dev [T][n] (interleaved). If tape_out is not NULL, *tape_out receives
+ * a tape holding the FP32 pair (hi, lo) carried at every chunk start of every
+ * filter (n / chunk_len rounded up per filter), which spiir_backward uses to
+ * recompute y chunk by chunk instead of storing every y_k. The tape keeps a
+ * reference to x_dev: keep x_dev alive and unchanged until spiir_backward.
+ */
+int spiir_forward_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_dev,
+                    spiir_tape **tape_out, void *stream);
+
+/*
+ * Reverse-time adjoint of spiir_forward_z for a real loss L of z.
+ *   grad_z_dev  complex64 [T][n]: dL/dRe(z) + i dL/dIm(z)
+ *   grad_a_dev, grad_b_dev  complex64 [F], caller's filter order, same convention
+ * lambda_k[m] = G_j[m] + conj(a_k) lambda_k[m+1] runs backwards chunk by
+ * chunk; y is recomputed from the tape; grad_b_k = sum_m lambda_k[m] x[m-d_k],
+ * grad_a_k = sum_m lambda_k[m] conj(y_k[m-1]). Per-chunk sums are FP32 and
+ * are accumulated across chunks in FP64. Returns SPIIR_ESTATE if the tape
+ * belongs to another bank or the coefficients changed since it was made.
+ */
+int spiir_backward(spiir_bank *bank, const spiir_tape *tape, const float *grad_z_dev,
+                   float *grad_a_dev, float *grad_b_dev, void *stream);
+
+/* Frees a tape (after the work that uses it has completed). NULL is ignored. */
+int spiir_tape_destroy(spiir_tape *tape);
+
+/*
+ * Batched streams: n_streams banks, each filtering its own stream, advanced
+ * together one block per step by one persistent kernel launch recorded in a
+ * HIP graph (created on stream). All banks must share filters_per_lane.
+ *   banks       [n_streams] banks (not used elsewhere while the batch lives)
+ *   x_dev       [n_streams] float32 streams, whole, resident on the device
+ *   lengths     [n_streams] samples of each stream (>= 1)
+ *   max_dev     [n_streams] float32 [length] per-sample maxima (outputs)
+ *   argmax_dev  [n_streams] int32 [length] argmax template indices (outputs)
+ *   block_len   samples per step and stream, multiple of 8 (e.g. 4096)
+ * The stream positions live on the device, so each replay of the same graph
+ * advances every live stream by one block; ended streams are skipped and the
+ * last block of a stream may be partial. Banks start cold.
+ */
+int spiir_batch_create(spiir_batch **out, int32_t n_streams, spiir_bank *const *banks,
+                       const float *const *x_dev, const int64_t *lengths,
+                       float *const *max_dev, int32_t *const *argmax_dev,
+                       int32_t block_len, void *stream);
+
+/* One graph replay on stream: one block of every live stream. */
+int spiir_batch_step(spiir_batch *batch, void *stream);
+
+/* Number of steps until every stream has ended (host-side count). */
+int spiir_batch_steps_total(const spiir_batch *batch, int64_t *steps);
+
+/* Rewinds every stream to its start and resets the banks (cold start). */
+int spiir_batch_reset(spiir_batch *batch, void *stream);
+
+int spiir_batch_destroy(spiir_batch *batch);
+
+/*
+ * Autotuner: times the candidate chunk lengths {64, 128, 256, 512} and filters
+ * per lane {1, 2, 3, 4} on the given bank definitions (the same arguments as
+ * spiir_bank_create, for n_banks banks at once, run as a batch over
+ * block_len-sample blocks of synthetic input) and writes the fastest pair.
+ * Results are cached per device and bank signature for the process.
+ *   n_banks           >= 1
+ *   n_templates       [n_banks]
+ *   filter_offsets    [n_banks] pointers to int64 [T+1]
+ *   a, b, d           [n_banks] pointers, as in spiir_bank_create
+ *   max_delay         as spiir_bank_opts.max_delay (0 = max d)
+ *   table             optional float [16] receiving ns per block-step for
+ *                     (L index * 4 + F-1), L index over {64,128,256,512}; NULL allowed
+ */
+int spiir_autotune(int32_t n_banks, const int32_t *n_templates,
+                   const int64_t *const *filter_offsets, const double *const *a,
+                   const double *const *b, const int32_t *const *d, int32_t max_delay,
+                   int32_t block_len, int32_t device, int32_t *chunk_len_out,
+                   int32_t *filters_per_lane_out, float *table);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *spiir_last_error(void);
+
+/* Library version string. */
+const char *spiir_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIIR_H */

@@ -1,0 +1,304 @@
+"""Python surface of libspiir: banks, tapes, batches and an autograd Function.
+
+PyTorch provides device memory and the current HIP stream; every computation
+is a call into the library (see include/spiir.h for the operations).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BankInfo, call, default_opts, load
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t: torch.Tensor, dtype, name: str):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dtype))
+
+
+def _c128(v) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(v, dtype=np.complex128))
+    return arr
+
+
+class SpiirBank:
+    """A device-resident SPIIR template bank with streaming state.
+
+    offsets: int64 [T+1]; a, b: complex [F]; d: int [F]. Options as in
+    spiir_bank_opts (chunk_len, filters_per_lane, max_delay, precision,
+    device, max_block, waves_per_group, autotune).
+    """
+
+    def __init__(self, offsets, a, b, d, **opts):
+        lib = load()
+        self._off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self._a = _c128(a)
+        self._b = _c128(b)
+        self._d = np.ascontiguousarray(d, dtype=np.int32)
+        o = default_opts()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError("unknown bank option %r" % k)
+            setattr(o, k, int(v))
+        h = ctypes.c_void_p()
+        call("spiir_bank_create", ctypes.byref(h), len(self._off) - 1,
+             self._off.ctypes.data_as(ctypes.c_void_p), self._a.ctypes.data_as(ctypes.c_void_p),
+             self._b.ctypes.data_as(ctypes.c_void_p), self._d.ctypes.data_as(ctypes.c_void_p),
+             ctypes.byref(o))
+        self._h = h
+        self._lib = lib
+        self.info = self.get_info()
+
+    @classmethod
+    def from_bank(cls, bank, **opts):
+        """From a workloads.Bank (offsets, a, b, d, dmax)."""
+        opts.setdefault("max_delay", int(bank.dmax))
+        return cls(bank.offsets, bank.a, bank.b, bank.d, **opts)
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            call("spiir_bank_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- facts --------------------------------------------------------------
+    def get_info(self) -> dict:
+        info = BankInfo()
+        call("spiir_bank_get_info", self._h, ctypes.byref(info))
+        return info.as_dict()
+
+    @property
+    def n_templates(self) -> int:
+        return self.info["n_templates"]
+
+    @property
+    def n_filters(self) -> int:
+        return self.info["n_filters"]
+
+    # -- state --------------------------------------------------------------
+    def reset(self, stream=None):
+        call("spiir_bank_reset", self._h, _stream_ptr(stream))
+
+    def set_coeffs(self, a, b):
+        self._a = _c128(a)
+        self._b = _c128(b)
+        call("spiir_bank_set_coeffs", self._h, self._a.ctypes.data_as(ctypes.c_void_p),
+             self._b.ctypes.data_as(ctypes.c_void_p))
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        call("spiir_bank_state_size", self._h, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        call("spiir_bank_get_state", self._h, buf, n.value)
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        call("spiir_bank_set_state", self._h, buf, len(blob))
+
+    # -- forward ------------------------------------------------------------
+    def filter_block(self, x: torch.Tensor, snr: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Next len(x) samples -> SNR of every template, float32 [T, n]."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if snr is None:
+            snr = torch.empty((self.n_templates, n), dtype=torch.float32, device=x.device)
+        _require_cuda(snr, torch.float32, "snr")
+        call("spiir_filter_block", self._h, _ptr(x), n, _ptr(snr), snr.shape[-1], _stream_ptr(stream))
+        return snr
+
+    def trigger_max(self, x: torch.Tensor, out=None, stream=None):
+        """Next len(x) samples -> (max SNR over templates float32 [n], argmax int32 [n])."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float32, device=x.device),
+                   torch.empty(n, dtype=torch.int32, device=x.device))
+        mx, am = out
+        call("spiir_trigger_max", self._h, _ptr(x), n, _ptr(mx), _ptr(am), _stream_ptr(stream))
+        return mx, am
+
+    def trigger_max_per_template(self, x: torch.Tensor, out=None, snr_scratch=None, stream=None):
+        """Same outputs as trigger_max via one launch per template plus a max pass."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float32, device=x.device),
+                   torch.empty(n, dtype=torch.int32, device=x.device))
+        if snr_scratch is None:
+            snr_scratch = torch.empty((self.n_templates, n), dtype=torch.float32, device=x.device)
+        mx, am = out
+        call("spiir_trigger_max_per_template", self._h, _ptr(x), n, _ptr(mx), _ptr(am),
+             _ptr(snr_scratch), _stream_ptr(stream))
+        return mx, am
+
+    def forward_z(self, x: torch.Tensor, want_tape: bool = False, stream=None):
+        """One-shot forward from a cold start: z complex64 [T, n] (and a Tape)."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        z = torch.empty((self.n_templates, n), dtype=torch.complex64, device=x.device)
+        tp = ctypes.c_void_p()
+        call("spiir_forward_z", self._h, _ptr(x), n, _ptr(z),
+             ctypes.byref(tp) if want_tape else None, _stream_ptr(stream))
+        return (z, Tape(tp, self)) if want_tape else z
+
+    def backward(self, tape: "Tape", grad_z: torch.Tensor, stream=None):
+        """Adjoint: grad_z complex64 [T, n] -> (grad_a, grad_b) complex64 [F]."""
+        _require_cuda(grad_z, torch.complex64, "grad_z")
+        F = self.n_filters
+        ga = torch.empty(F, dtype=torch.complex64, device=grad_z.device)
+        gb = torch.empty(F, dtype=torch.complex64, device=grad_z.device)
+        call("spiir_backward", self._h, tape.handle, _ptr(grad_z), _ptr(ga), _ptr(gb), _stream_ptr(stream))
+        return ga, gb
+
+
+class Tape:
+    """Chunk-start carries kept by forward_z for the adjoint."""
+
+    def __init__(self, h, bank):
+        self._h = h
+        self._bank = bank
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            call("spiir_tape_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SpiirBatch:
+    """Several banks advanced one block per step by one graph replay."""
+
+    def __init__(self, banks, xs, block_len: int = 4096, stream=None):
+        self.banks = list(banks)
+        self.xs = list(xs)
+        for x in self.xs:
+            _require_cuda(x, torch.float32, "x")
+        dev = self.xs[0].device
+        self.max = [torch.empty(x.numel(), dtype=torch.float32, device=dev) for x in self.xs]
+        self.argmax = [torch.empty(x.numel(), dtype=torch.int32, device=dev) for x in self.xs]
+        ns = len(self.banks)
+        VP = ctypes.c_void_p * ns
+        self._bh = VP(*[b.handle.value for b in self.banks])
+        self._xh = VP(*[x.data_ptr() for x in self.xs])
+        self._mh = VP(*[m.data_ptr() for m in self.max])
+        self._ah = VP(*[a.data_ptr() for a in self.argmax])
+        self._len = (ctypes.c_int64 * ns)(*[x.numel() for x in self.xs])
+        h = ctypes.c_void_p()
+        call("spiir_batch_create", ctypes.byref(h), ns, self._bh, self._xh, self._len, self._mh,
+             self._ah, int(block_len), _stream_ptr(stream))
+        self._h = h
+        self.block_len = int(block_len)
+
+    def step(self, stream=None):
+        call("spiir_batch_step", self._h, _stream_ptr(stream))
+
+    def steps_total(self) -> int:
+        v = ctypes.c_int64()
+        call("spiir_batch_steps_total", self._h, ctypes.byref(v))
+        return int(v.value)
+
+    def reset(self, stream=None):
+        call("spiir_batch_reset", self._h, _stream_ptr(stream))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            call("spiir_batch_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(banks, block_len: int = 4096, max_delay: int = 0, device: int = -1):
+    """Times (chunk_len, filters_per_lane) candidates on workloads.Bank-like
+    objects run as one batch; returns (chunk_len, filters_per_lane, table[4][4] ns)."""
+    n = len(banks)
+    offs = [np.ascontiguousarray(b.offsets, dtype=np.int64) for b in banks]
+    aas = [_c128(b.a) for b in banks]
+    bbs = [_c128(b.b) for b in banks]
+    dds = [np.ascontiguousarray(b.d, dtype=np.int32) for b in banks]
+    VP = ctypes.c_void_p * n
+    T = (ctypes.c_int32 * n)(*[len(o) - 1 for o in offs])
+    L = ctypes.c_int32()
+    F = ctypes.c_int32()
+    table = (ctypes.c_float * 16)()
+    call("spiir_autotune", n, T, VP(*[o.ctypes.data for o in offs]), VP(*[a.ctypes.data for a in aas]),
+         VP(*[b.ctypes.data for b in bbs]), VP(*[d.ctypes.data for d in dds]), int(max_delay),
+         int(block_len), int(device), ctypes.byref(L), ctypes.byref(F), table)
+    return int(L.value), int(F.value), np.array(list(table), dtype=np.float64).reshape(4, 4)
+
+
+class SpiirFn(torch.autograd.Function):
+    """z = bank(x) from a cold start, differentiable in the coefficients.
+
+    forward(ctx, a, b, bank, x): a, b complex128 CPU tensors [F] (set into the
+    bank), x float32 CUDA [n]; returns z complex64 CUDA [T, n]. backward runs
+    the library's reverse-time adjoint and returns complex128 CPU gradients in
+    PyTorch's convention (dL/dRe + i dL/dIm).
+    """
+
+    @staticmethod
+    def forward(ctx, a, b, bank: SpiirBank, x: torch.Tensor):
+        bank.set_coeffs(a.detach().cpu().numpy(), b.detach().cpu().numpy())
+        z, tape = bank.forward_z(x, want_tape=True)
+        ctx.bank = bank
+        ctx.tape = tape
+        ctx.a_dev = a.device
+        return z
+
+    @staticmethod
+    def backward(ctx, grad_z):
+        gz = grad_z.to(torch.complex64).contiguous()
+        ga, gb = ctx.bank.backward(ctx.tape, gz)
+        ctx.tape.close()
+        return (ga.to(torch.complex128).to(ctx.a_dev), gb.to(torch.complex128).to(ctx.a_dev),
+                None, None)
+
+
+def version() -> str:
+    return load().spiir_version().decode()
+
+
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "autotune", "version", "_lib"]

@@ -1,0 +1,1114 @@
+// Host side of libspiir: argument checking, bank layout, FP64 precomputation,
+// launches, streaming state, the adjoint tape, batches in a HIP graph and the
+// autotuner. Declared in include/spiir.h.
+#include "spiir.h"
+#include "spiir_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace spiir;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(SPIIR_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+std::pair<double, double> cpow(double re, double im, long e) {
+    double rr = 1.0, ri = 0.0;
+    while (e > 0) {
+        if (e & 1) {
+            const double t = rr * re - ri * im;
+            ri = rr * im + ri * re;
+            rr = t;
+        }
+        const double t = re * re - im * im;
+        im = 2.0 * re * im;
+        re = t;
+        e >>= 1;
+    }
+    return {rr, ri};
+}
+
+// Filter-to-slot layout of one bank.
+struct Layout {
+    int fl = 1, wpg = 1, groups = 0;
+    int64_t nslots = 0;
+    std::vector<WaveInfo> waves;          // [groups * wpg]
+    std::vector<int32_t> slot_filter;     // [nslots], -1 = padding
+    std::vector<int32_t> tpl_group;       // [T]
+};
+
+struct Plan {
+    int64_t total_waves = 0;
+    int max_nw = 0;
+};
+
+Plan plan_waves(int T, const int64_t *off, int fl) {
+    Plan p;
+    for (int j = 0; j < T; ++j) {
+        const int64_t k = off[j + 1] - off[j];
+        const int nw = (int)((k + 64 * fl - 1) / (64 * fl));
+        p.total_waves += nw;
+        p.max_nw = std::max(p.max_nw, nw);
+    }
+    return p;
+}
+
+int auto_wpg(int64_t total_waves, int max_nw, int n_cu) {
+    int w = (int)((total_waves + n_cu - 1) / n_cu);
+    return std::min(kMaxWaves, std::max(w, max_nw));
+}
+
+// First-fit decreasing packing of whole templates into workgroups of wpg waves,
+// then the filter-to-slot assignment inside every template: filters sorted by
+// d mod 64 are dealt round-robin over the template's (wave, slot) columns, so
+// the 64 lanes of a column read x[m - d] from (mostly) distinct LDS banks.
+int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
+    std::vector<int> nw(T);
+    int max_nw = 0;
+    for (int j = 0; j < T; ++j) {
+        const int64_t k = off[j + 1] - off[j];
+        nw[j] = (int)((k + 64 * fl - 1) / (64 * fl));
+        max_nw = std::max(max_nw, nw[j]);
+    }
+    if (max_nw > wpg)
+        return fail(SPIIR_EINVAL, "a template needs %d waves of %d filters but a workgroup has %d",
+                    max_nw, 64 * fl, wpg);
+    std::vector<int> order(T);
+    for (int j = 0; j < T; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nw[x] > nw[y]; });
+    std::vector<int> room;                  // free waves per group
+    std::vector<std::vector<int>> members;  // templates per group
+    for (int j : order) {
+        size_t g = 0;
+        for (; g < room.size(); ++g)
+            if (room[g] >= nw[j]) break;
+        if (g == room.size()) {
+            room.push_back(wpg);
+            members.emplace_back();
+        }
+        room[g] -= nw[j];
+        members[g].push_back(j);
+    }
+    lay.fl = fl;
+    lay.wpg = wpg;
+    lay.groups = (int)members.size();
+    lay.nslots = (int64_t)lay.groups * wpg * fl * 64;
+    lay.waves.assign((size_t)lay.groups * wpg, WaveInfo{-1, 0, 0, 0});
+    lay.slot_filter.assign((size_t)lay.nslots, -1);
+    lay.tpl_group.assign(T, -1);
+    std::vector<int32_t> ks;
+    for (int g = 0; g < lay.groups; ++g) {
+        std::vector<int> &mem = members[g];
+        std::sort(mem.begin(), mem.end());
+        int w0 = 0;
+        for (int j : mem) {
+            lay.tpl_group[j] = g;
+            for (int w = 0; w < nw[j]; ++w) lay.waves[(size_t)g * wpg + w0 + w] = WaveInfo{j, w0, nw[j], 0};
+            ks.clear();
+            for (int64_t k = off[j]; k < off[j + 1]; ++k) ks.push_back((int32_t)k);
+            std::stable_sort(ks.begin(), ks.end(), [&](int32_t x, int32_t y) { return (d[x] & 63) < (d[y] & 63); });
+            const int cols = nw[j] * fl;
+            for (size_t i = 0; i < ks.size(); ++i) {
+                const int c = (int)(i % cols), lane = (int)(i / cols);
+                const int wave = w0 + c % nw[j], f = c / nw[j];
+                const int64_t slot = ((int64_t)(g * wpg + wave) * fl + f) * 64 + lane;
+                lay.slot_filter[(size_t)slot] = ks[i];
+            }
+            w0 += nw[j];
+        }
+    }
+    return SPIIR_OK;
+}
+
+struct DeviceFacts {
+    int n_cu = 0;
+    size_t lds_cap = 0;
+};
+
+int device_facts(int dev, DeviceFacts &f) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(SPIIR_ENODEV, "no HIP device available");
+    if (dev < 0 || dev >= count) return fail(SPIIR_ENODEV, "device %d out of range (%d devices)", dev, count);
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SPIIR_ENODEV, "device %d is %s; this library is built for gfx950 only", dev,
+                    prop.gcnArchName);
+    f.n_cu = prop.multiProcessorCount;
+    f.lds_cap = prop.sharedMemPerBlock;
+    return SPIIR_OK;
+}
+
+}  // namespace
+
+struct spiir_bank {
+    int device = 0;
+    int T = 0;
+    int64_t F = 0;
+    int dmax = 0, L = 256, prec = 0, max_block = 16384;
+    DeviceFacts dev;
+    std::vector<int64_t> off;
+    std::vector<double> a, b;
+    std::vector<int32_t> d;
+    Layout lay;
+    int nb = 0;
+    bool xlds = true;
+    size_t lds = 0;
+    uint64_t coeff_version = 1;
+    // device buffers
+    float2 *a32 = nullptr, *b32 = nullptr;
+    int32_t *xoff = nullptr, *flags = nullptr, *slot_filter = nullptr;
+    double2 *aL = nullptr, *dL = nullptr, *a64 = nullptr;
+    float4 *state = nullptr, *zstate = nullptr;
+    WaveInfo *waves = nullptr;
+    float *hist[2] = {nullptr, nullptr};
+    int hist_cur = 0;
+    uint64_t *keys = nullptr;
+    float *xwin = nullptr;
+    int64_t xwin_cap = 0;
+    float2 *ysub = nullptr;
+
+    SlotArrays slots() const { return SlotArrays{a32, b32, xoff, aL, dL, a64, flags}; }
+
+    FwdArgs base_args() const {
+        FwdArgs p;
+        std::memset(&p, 0, sizeof p);
+        p.s = slots();
+        p.dmax = dmax;
+        p.L = L;
+        p.nb = nb;
+        p.prec = prec;
+        p.wpg = lay.wpg;
+        p.only_tpl = -1;
+        p.gbase = 0;
+        p.waves = waves;
+        p.nslots = lay.nslots;
+        return p;
+    }
+};
+
+struct spiir_tape {
+    spiir_bank *bank = nullptr;
+    uint64_t coeff_version = 0;
+    int64_t n = 0, nchunks = 0;
+    float4 *tape = nullptr;
+    float *xwin = nullptr;
+};
+
+struct spiir_batch {
+    int device = 0;
+    int ns = 0, B = 0, fl = 1, wpg = 1, grid = 0, nitems = 0;
+    size_t lds = 0;
+    std::vector<spiir_bank *> banks;
+    std::vector<int64_t> len;
+    BatchStream *streams = nullptr;
+    int2 *items = nullptr;
+    int *counter = nullptr;
+    int64_t *pos = nullptr;
+    uint64_t *keys = nullptr;
+    int64_t key_stride = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Host-side checks of create arguments; no HIP call is made here.
+int check_bank_args(int32_t T, const int64_t *off, const double *a, const double *b, const int32_t *d,
+                    const spiir_bank_opts &o, int &dmax_out) {
+    if (T < 1) return fail(SPIIR_EINVAL, "n_templates must be >= 1 (got %d)", T);
+    if (!off || !a || !b || !d) return fail(SPIIR_EINVAL, "null coefficient / offset / delay array");
+    if (off[0] != 0) return fail(SPIIR_EINVAL, "filter_offsets[0] must be 0");
+    for (int j = 0; j < T; ++j)
+        if (off[j + 1] <= off[j])
+            return fail(SPIIR_EINVAL, "template %d has no filters (offsets must strictly increase)", j);
+    const int64_t F = off[T];
+    if (F > (int64_t)INT32_MAX) return fail(SPIIR_EINVAL, "too many filters (%lld)", (long long)F);
+    int dm = 0;
+    for (int64_t k = 0; k < F; ++k) {
+        const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+        if (!std::isfinite(ar) || !std::isfinite(ai) || !std::isfinite(br) || !std::isfinite(bi))
+            return fail(SPIIR_EINVAL, "filter %lld has a non-finite coefficient", (long long)k);
+        if (std::hypot(ar, ai) >= 1.0)
+            return fail(SPIIR_EINVAL, "filter %lld is not stable: |a| = %.17g >= 1", (long long)k, std::hypot(ar, ai));
+        if (d[k] < 0) return fail(SPIIR_EINVAL, "filter %lld has a negative delay", (long long)k);
+        dm = std::max(dm, d[k]);
+    }
+    if (o.max_delay < 0) return fail(SPIIR_EINVAL, "max_delay must be >= 0");
+    if (o.max_delay > 0 && dm > o.max_delay)
+        return fail(SPIIR_EINVAL, "a delay (%d) exceeds max_delay (%d)", dm, o.max_delay);
+    const int dmax = o.max_delay > 0 ? o.max_delay : dm;
+    if (dmax > (1 << 26)) return fail(SPIIR_EINVAL, "max_delay %d too large", dmax);
+    if (o.chunk_len != 0 && (o.chunk_len < 8 || o.chunk_len > 4096 || o.chunk_len % 8))
+        return fail(SPIIR_EINVAL, "chunk_len must be a multiple of 8 in [8, 4096] (got %d)", o.chunk_len);
+    if (o.filters_per_lane < 0 || o.filters_per_lane > 4)
+        return fail(SPIIR_EINVAL, "filters_per_lane must be 0..4 (got %d)", o.filters_per_lane);
+    if (o.precision < 0 || o.precision > 2) return fail(SPIIR_EINVAL, "precision must be 0, 1 or 2");
+    if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
+    if (o.waves_per_group < 0 || o.waves_per_group > kMaxWaves)
+        return fail(SPIIR_EINVAL, "waves_per_group must be 0..%d", kMaxWaves);
+    dmax_out = dmax;
+    return SPIIR_OK;
+}
+
+// Slot arrays on the host, then uploaded.
+int upload_coeffs(spiir_bank *bk) {
+    const int64_t S = bk->lay.nslots;
+    std::vector<float2> a32((size_t)S, make_float2(0.f, 0.f)), b32((size_t)S, make_float2(0.f, 0.f));
+    std::vector<int32_t> xo((size_t)S, 0), fl((size_t)S, 0);
+    std::vector<double2> aL((size_t)S, make_double2(0, 0)), dL((size_t)S, make_double2(0, 0)),
+        a64((size_t)S, make_double2(0, 0));
+    for (int64_t s = 0; s < S; ++s) {
+        const int32_t k = bk->lay.slot_filter[(size_t)s];
+        if (k < 0) continue;
+        const double ar = bk->a[2 * (size_t)k], ai = bk->a[2 * (size_t)k + 1];
+        const float far = (float)ar, fai = (float)ai;
+        a32[(size_t)s] = make_float2(far, fai);
+        b32[(size_t)s] = make_float2((float)bk->b[2 * (size_t)k], (float)bk->b[2 * (size_t)k + 1]);
+        xo[(size_t)s] = bk->dmax - bk->d[(size_t)k];
+        const auto p = cpow(ar, ai, bk->L);
+        const auto q = cpow((double)far, (double)fai, bk->L);
+        aL[(size_t)s] = make_double2(p.first, p.second);
+        dL[(size_t)s] = make_double2(p.first - q.first, p.second - q.second);
+        a64[(size_t)s] = make_double2(ar, ai);
+        fl[(size_t)s] = std::hypot(ar, ai) > 1.0 - 1e-5 ? 1 : 0;
+    }
+    HIPCHK(hipMemcpy(bk->a32, a32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->b32, b32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->xoff, xo.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->flags, fl.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->aL, aL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->dL, dL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->a64, a64.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    return SPIIR_OK;
+}
+
+void free_bank_buffers(spiir_bank *bk) {
+    dfree(bk->a32); dfree(bk->b32); dfree(bk->xoff); dfree(bk->flags); dfree(bk->slot_filter);
+    dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
+    dfree(bk->waves); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
+    dfree(bk->ysub);
+}
+
+// Picks filters per lane from a simple cost model: time ~ rounds of
+// workgroups x per-CU resident lane-work (waves x filters per lane).
+int choose_fl(int T, const int64_t *off, int n_cu, size_t lds_cap, int dmax, int L, int max_block) {
+    double best = 1e300;
+    int best_fl = 1;
+    for (int fl = 1; fl <= 4; ++fl) {
+        const Plan p = plan_waves(T, off, fl);
+        if (p.max_nw > kMaxWaves) continue;
+        const int wpg = auto_wpg(p.total_waves, p.max_nw, n_cu);
+        const int64_t groups_est = (p.total_waves + wpg - 1) / wpg;
+        int nb = (int)(((int64_t)lds_cap - (int64_t)fwd_lds_bytes(wpg, 0, 0, false) - 4 * (int64_t)dmax - 64) / (4 * L)) * L;
+        nb = std::min(nb, max_block);
+        const size_t lds = fwd_lds_bytes(wpg, dmax, std::max(nb, L), nb >= L);
+        int occ = (int)std::max<size_t>(1, lds_cap / std::max<size_t>(lds, 1));
+        occ = std::max(1, std::min(occ, kMaxWaves / wpg));
+        const int64_t per_round = (int64_t)n_cu * occ;
+        const int64_t rounds = (groups_est + per_round - 1) / per_round;
+        const int64_t resident = std::min<int64_t>(occ, (groups_est + n_cu - 1) / n_cu);
+        double cost = (double)rounds * resident * wpg * fl;
+        const double waves_per_simd = resident * wpg / 4.0;
+        if (waves_per_simd < 2.0) cost *= 2.0 / std::max(waves_per_simd, 0.25);
+        if (nb < L) cost *= 4.0;  // strain window not in LDS
+        if (cost < best * 0.999) {
+            best = cost;
+            best_fl = fl;
+        }
+    }
+    return best_fl;
+}
+
+int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a, const double *b,
+                const int32_t *d, const spiir_bank_opts &o) {
+    int dmax = 0;
+    int rc = check_bank_args(T, off, a, b, d, o, dmax);
+    if (rc) return rc;
+    int dev = o.device;
+    if (dev < 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+            return fail(SPIIR_ENODEV, "no HIP device available");
+        HIPCHK(hipGetDevice(&dev));
+    }
+    DeviceFacts df;
+    rc = device_facts(dev, df);
+    if (rc) return rc;
+    DeviceGuard guard(dev);
+
+    const int L = o.chunk_len ? o.chunk_len : 256;
+    int max_block = o.max_block ? o.max_block : 16384;
+    max_block = std::max(L, (max_block / L) * L);
+    int fl = o.filters_per_lane ? o.filters_per_lane : choose_fl(T, off, df.n_cu, df.lds_cap, dmax, L, max_block);
+    const Plan plan = plan_waves(T, off, fl);
+    if (plan.max_nw > kMaxWaves)
+        return fail(SPIIR_EINVAL, "a template has more than %d filters; use more filters per lane",
+                    kMaxWaves * 64 * fl);
+    const int wpg = o.waves_per_group ? o.waves_per_group : auto_wpg(plan.total_waves, plan.max_nw, df.n_cu);
+
+    spiir_bank *bk = new (std::nothrow) spiir_bank();
+    if (!bk) return fail(SPIIR_ENOMEM, "out of host memory");
+    bk->device = dev;
+    bk->T = T;
+    bk->F = off[T];
+    bk->dmax = dmax;
+    bk->L = L;
+    bk->prec = o.precision;
+    bk->max_block = max_block;
+    bk->dev = df;
+    bk->off.assign(off, off + T + 1);
+    bk->a.assign(a, a + 2 * bk->F);
+    bk->b.assign(b, b + 2 * bk->F);
+    bk->d.assign(d, d + bk->F);
+    rc = build_layout(T, off, d, fl, wpg, bk->lay);
+    if (rc) {
+        delete bk;
+        return rc;
+    }
+    // LDS: the strain window of nb samples plus max_delay history, if it fits
+    const int64_t fixed = (int64_t)fwd_lds_bytes(wpg, 0, 0, false);
+    int64_t nb = ((int64_t)df.lds_cap - fixed - 4 * (int64_t)dmax - 64) / (4 * L) * L;
+    nb = std::min<int64_t>(nb, max_block);
+    if (nb >= L) {
+        bk->xlds = true;
+        bk->nb = (int)nb;
+    } else {
+        bk->xlds = false;
+        bk->nb = max_block;
+    }
+    bk->lds = fwd_lds_bytes(wpg, dmax, bk->nb, bk->xlds);
+
+    const int64_t S = bk->lay.nslots;
+    const int G = bk->lay.groups;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    A(dalloc(&bk->a32, S)); A(dalloc(&bk->b32, S)); A(dalloc(&bk->xoff, S)); A(dalloc(&bk->flags, S));
+    A(dalloc(&bk->slot_filter, S)); A(dalloc(&bk->aL, S)); A(dalloc(&bk->dL, S)); A(dalloc(&bk->a64, S));
+    A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->waves, (size_t)G * wpg));
+    A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
+    A(dalloc(&bk->keys, (size_t)G * max_block));
+    A(dalloc(&bk->ysub, (size_t)((L + kSub - 1) / kSub) * S));
+    if (e != hipSuccess) {
+        free_bank_buffers(bk);
+        delete bk;
+        return fail(SPIIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    rc = upload_coeffs(bk);
+    if (!rc) {
+        e = hipMemcpy(bk->slot_filter, bk->lay.slot_filter.data(), S * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(bk->waves, bk->lay.waves.data(), bk->lay.waves.size() * sizeof(WaveInfo),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(bk->state, 0, S * sizeof(float4));
+        if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[0], 0, (size_t)dmax * sizeof(float));
+        if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[1], 0, (size_t)dmax * sizeof(float));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = fail(SPIIR_EHIP, "bank upload: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        free_bank_buffers(bk);
+        delete bk;
+        return rc;
+    }
+    *out = bk;
+    return SPIIR_OK;
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int ensure_xwin(spiir_bank *bk, int64_t need) {
+    if (need <= bk->xwin_cap) return SPIIR_OK;
+    HIPCHK(hipDeviceSynchronize());
+    dfree(bk->xwin);
+    bk->xwin_cap = 0;
+    HIPCHK(dalloc(&bk->xwin, (size_t)need));
+    bk->xwin_cap = need;
+    return SPIIR_OK;
+}
+
+// Shared driver of the streaming calls (snr rows or fused keys).
+int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr, int64_t ld,
+                float *mx, int32_t *am, hipStream_t st) {
+    DeviceGuard guard(bk->device);
+    const float *hist = bk->hist[bk->hist_cur];
+    if (!bk->xlds) {
+        int rc = ensure_xwin(bk, n + bk->dmax);
+        if (rc) return rc;
+        HIPCHK(launch_window_fill(bk->xwin, hist, x, n, bk->dmax, st));
+    }
+    for (int64_t P = 0; P < n; P += bk->max_block) {
+        const int64_t np = std::min<int64_t>(bk->max_block, n - P);
+        FwdArgs a = bk->base_args();
+        a.state = bk->state;
+        a.x = x;
+        a.hist = hist;
+        a.xwin = bk->xwin;
+        a.xbase = P;
+        a.n = np;
+        a.obase = P;
+        if (mode == kModeSnr) {
+            a.snr = snr;
+            a.ld = ld;
+        } else {
+            a.keys = bk->keys;
+            a.ld = bk->max_block;
+        }
+        HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->xlds, bk->lay.groups, bk->lds, st));
+        if (mode == kModeKeys)
+            HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st));
+    }
+    HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
+    bk->hist_cur ^= 1;
+    return SPIIR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spiir_bank_opts_default(spiir_bank_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->chunk_len = 256;
+    o->filters_per_lane = 0;
+    o->max_delay = 0;
+    o->precision = SPIIR_PREC_HYBRID;
+    o->device = -1;
+    o->max_block = 16384;
+    o->waves_per_group = 0;
+    o->autotune = 0;
+}
+
+int spiir_bank_create(spiir_bank **out, int32_t n_templates, const int64_t *filter_offsets,
+                      const double *a, const double *b, const int32_t *d, const spiir_bank_opts *opts) {
+    if (!out) return fail(SPIIR_EINVAL, "out is null");
+    *out = nullptr;
+    spiir_bank_opts o;
+    spiir_bank_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.autotune) {
+        int dmax = 0;
+        int rc = check_bank_args(n_templates, filter_offsets, a, b, d, o, dmax);
+        if (rc) return rc;
+        int32_t L = 0, F = 0;
+        const int32_t block = o.max_block ? std::min(o.max_block, 4096) : 4096;
+        rc = spiir_autotune(1, &n_templates, &filter_offsets, &a, &b, &d, o.max_delay, block, o.device,
+                            &L, &F, nullptr);
+        if (rc) return rc;
+        o.chunk_len = L;
+        o.filters_per_lane = F;
+        o.autotune = 0;
+    }
+    return create_bank(out, n_templates, filter_offsets, a, b, d, o);
+}
+
+int spiir_bank_destroy(spiir_bank *bk) {
+    if (!bk) return SPIIR_OK;
+    {
+        DeviceGuard guard(bk->device);
+        (void)hipDeviceSynchronize();
+        free_bank_buffers(bk);
+    }
+    delete bk;
+    return SPIIR_OK;
+}
+
+int spiir_bank_get_info(const spiir_bank *bk, spiir_bank_info *info) {
+    if (!bk || !info) return fail(SPIIR_EINVAL, "null argument");
+    info->n_templates = bk->T;
+    info->n_filters = bk->F;
+    info->max_delay = bk->dmax;
+    info->chunk_len = bk->L;
+    info->filters_per_lane = bk->lay.fl;
+    info->waves_per_group = bk->lay.wpg;
+    info->n_groups = bk->lay.groups;
+    info->n_slots = bk->lay.nslots;
+    info->lds_bytes = (int32_t)bk->lds;
+    info->x_in_lds = bk->xlds ? 1 : 0;
+    info->sub_block = bk->nb;
+    info->precision = bk->prec;
+    info->device = bk->device;
+    info->n_cu = bk->dev.n_cu;
+    return SPIIR_OK;
+}
+
+int spiir_bank_reset(spiir_bank *bk, void *stream) {
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    DeviceGuard guard(bk->device);
+    hipStream_t st = as_stream(stream);
+    HIPCHK(launch_fill_zero(bk->state, bk->lay.nslots * sizeof(float4), st));
+    HIPCHK(launch_fill_zero(bk->hist[0], (size_t)bk->dmax * sizeof(float), st));
+    HIPCHK(launch_fill_zero(bk->hist[1], (size_t)bk->dmax * sizeof(float), st));
+    return SPIIR_OK;
+}
+
+int spiir_bank_set_coeffs(spiir_bank *bk, const double *a, const double *b) {
+    if (!bk || !a || !b) return fail(SPIIR_EINVAL, "null argument");
+    for (int64_t k = 0; k < bk->F; ++k) {
+        const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+        if (!std::isfinite(ar) || !std::isfinite(ai) || !std::isfinite(br) || !std::isfinite(bi))
+            return fail(SPIIR_EINVAL, "filter %lld has a non-finite coefficient", (long long)k);
+        if (std::hypot(ar, ai) >= 1.0)
+            return fail(SPIIR_EINVAL, "filter %lld is not stable: |a| >= 1", (long long)k);
+    }
+    DeviceGuard guard(bk->device);
+    HIPCHK(hipDeviceSynchronize());
+    std::copy(a, a + 2 * bk->F, bk->a.begin());
+    std::copy(b, b + 2 * bk->F, bk->b.begin());
+    int rc = upload_coeffs(bk);
+    if (rc) return rc;
+    ++bk->coeff_version;
+    return SPIIR_OK;
+}
+
+int spiir_bank_state_size(const spiir_bank *bk, size_t *nbytes) {
+    if (!bk || !nbytes) return fail(SPIIR_EINVAL, "null argument");
+    *nbytes = 32 + (size_t)bk->F * sizeof(float4) + (size_t)bk->dmax * sizeof(float);
+    return SPIIR_OK;
+}
+
+// Checkpoint format: magic, version, F, dmax (4 x int64), then per filter in the
+// caller's order (hi.re, hi.im, lo.re, lo.im) float32, then the history.
+int spiir_bank_get_state(const spiir_bank *bk, void *buf, size_t nbytes) {
+    if (!bk || !buf) return fail(SPIIR_EINVAL, "null argument");
+    size_t need = 0;
+    spiir_bank_state_size(bk, &need);
+    if (nbytes < need) return fail(SPIIR_EINVAL, "buffer too small (%zu < %zu)", nbytes, need);
+    DeviceGuard guard(bk->device);
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<float4> st((size_t)bk->lay.nslots);
+    HIPCHK(hipMemcpy(st.data(), bk->state, st.size() * sizeof(float4), hipMemcpyDeviceToHost));
+    int64_t *h = static_cast<int64_t *>(buf);
+    h[0] = 0x52494950535ll;  // "SPIIR"
+    h[1] = 1;
+    h[2] = bk->F;
+    h[3] = bk->dmax;
+    float4 *fs = reinterpret_cast<float4 *>(static_cast<char *>(buf) + 32);
+    for (int64_t s = 0; s < bk->lay.nslots; ++s) {
+        const int32_t k = bk->lay.slot_filter[(size_t)s];
+        if (k >= 0) std::memcpy(&fs[k], &st[(size_t)s], sizeof(float4));
+    }
+    if (bk->dmax > 0)
+        HIPCHK(hipMemcpy(static_cast<char *>(buf) + 32 + bk->F * sizeof(float4), bk->hist[bk->hist_cur],
+                         (size_t)bk->dmax * sizeof(float), hipMemcpyDeviceToHost));
+    return SPIIR_OK;
+}
+
+int spiir_bank_set_state(spiir_bank *bk, const void *buf, size_t nbytes) {
+    if (!bk || !buf) return fail(SPIIR_EINVAL, "null argument");
+    size_t need = 0;
+    spiir_bank_state_size(bk, &need);
+    if (nbytes < need) return fail(SPIIR_EINVAL, "buffer too small (%zu < %zu)", nbytes, need);
+    const int64_t *h = static_cast<const int64_t *>(buf);
+    if (h[0] != 0x52494950535ll || h[1] != 1 || h[2] != bk->F || h[3] != bk->dmax)
+        return fail(SPIIR_ESTATE, "checkpoint does not belong to a bank of this shape");
+    std::vector<float4> st((size_t)bk->lay.nslots, make_float4(0.f, 0.f, 0.f, 0.f));
+    const float4 *fs = reinterpret_cast<const float4 *>(static_cast<const char *>(buf) + 32);
+    for (int64_t s = 0; s < bk->lay.nslots; ++s) {
+        const int32_t k = bk->lay.slot_filter[(size_t)s];
+        if (k >= 0) std::memcpy(&st[(size_t)s], &fs[k], sizeof(float4));
+    }
+    DeviceGuard guard(bk->device);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(bk->state, st.data(), st.size() * sizeof(float4), hipMemcpyHostToDevice));
+    if (bk->dmax > 0)
+        HIPCHK(hipMemcpy(bk->hist[bk->hist_cur], static_cast<const char *>(buf) + 32 + bk->F * sizeof(float4),
+                         (size_t)bk->dmax * sizeof(float), hipMemcpyHostToDevice));
+    return SPIIR_OK;
+}
+
+int spiir_filter_block(spiir_bank *bk, const float *x, int64_t n, float *snr, int64_t ld, void *stream) {
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
+    if (n == 0) return SPIIR_OK;
+    if (!x || !snr) return fail(SPIIR_EINVAL, "null device pointer");
+    if (ld < n) return fail(SPIIR_EINVAL, "ld_snr (%lld) < n (%lld)", (long long)ld, (long long)n);
+    return stream_call(bk, x, n, kModeSnr, snr, ld, nullptr, nullptr, as_stream(stream));
+}
+
+int spiir_trigger_max(spiir_bank *bk, const float *x, int64_t n, float *mx, int32_t *am, void *stream) {
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
+    if (n == 0) return SPIIR_OK;
+    if (!x || !mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
+    return stream_call(bk, x, n, kModeKeys, nullptr, 0, mx, am, as_stream(stream));
+}
+
+int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, float *mx, int32_t *am,
+                                   float *snr, void *stream) {
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
+    if (n == 0) return SPIIR_OK;
+    if (!x || !mx || !am || !snr) return fail(SPIIR_EINVAL, "null device pointer");
+    DeviceGuard guard(bk->device);
+    hipStream_t st = as_stream(stream);
+    const float *hist = bk->hist[bk->hist_cur];
+    if (!bk->xlds) {
+        int rc = ensure_xwin(bk, n + bk->dmax);
+        if (rc) return rc;
+        HIPCHK(launch_window_fill(bk->xwin, hist, x, n, bk->dmax, st));
+    }
+    for (int64_t P = 0; P < n; P += bk->max_block) {
+        const int64_t np = std::min<int64_t>(bk->max_block, n - P);
+        for (int j = 0; j < bk->T; ++j) {
+            FwdArgs a = bk->base_args();
+            a.state = bk->state;
+            a.x = x;
+            a.hist = hist;
+            a.xwin = bk->xwin;
+            a.xbase = P;
+            a.n = np;
+            a.obase = P;
+            a.snr = snr;
+            a.ld = n;
+            a.only_tpl = j;
+            a.gbase = bk->lay.tpl_group[j];
+            HIPCHK(launch_forward(a, kModeSnr, bk->lay.fl, bk->xlds, 1, bk->lds, st));
+        }
+    }
+    HIPCHK(launch_rows_argmax(snr, bk->T, n, n, mx, am, st));
+    HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
+    bk->hist_cur ^= 1;
+    return SPIIR_OK;
+}
+
+int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_tape **tape_out, void *stream) {
+    if (tape_out) *tape_out = nullptr;
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    if (n < 1) return fail(SPIIR_EINVAL, "n must be >= 1");
+    if (!x || !z) return fail(SPIIR_EINVAL, "null device pointer");
+    DeviceGuard guard(bk->device);
+    hipStream_t st = as_stream(stream);
+    spiir_tape *tp = nullptr;
+    float *xwin = nullptr;
+    if (tape_out || !bk->xlds) {
+        tp = new (std::nothrow) spiir_tape();
+        if (!tp) return fail(SPIIR_ENOMEM, "out of host memory");
+        tp->bank = bk;
+        tp->coeff_version = bk->coeff_version;
+        tp->n = n;
+        tp->nchunks = (n + bk->L - 1) / bk->L;
+        hipError_t e = dalloc(&tp->xwin, (size_t)(n + bk->dmax));
+        if (e == hipSuccess && tape_out) e = dalloc(&tp->tape, (size_t)(tp->nchunks * bk->lay.nslots));
+        if (e != hipSuccess) {
+            dfree(tp->xwin);
+            dfree(tp->tape);
+            delete tp;
+            return fail(SPIIR_ENOMEM, "tape allocation failed: %s", hipGetErrorString(e));
+        }
+        xwin = tp->xwin;
+        hipError_t le = launch_window_fill(xwin, nullptr, x, n, bk->dmax, st);
+        if (le != hipSuccess) {
+            spiir_tape_destroy(tp);
+            return fail(SPIIR_EHIP, "window fill: %s", hipGetErrorString(le));
+        }
+    }
+    hipError_t e = launch_fill_zero(bk->zstate, bk->lay.nslots * sizeof(float4), st);
+    for (int64_t P = 0; P < n && e == hipSuccess; P += bk->max_block) {
+        const int64_t np = std::min<int64_t>(bk->max_block, n - P);
+        FwdArgs a = bk->base_args();
+        a.state = bk->zstate;
+        a.x = x;
+        a.hist = nullptr;
+        a.xwin = xwin;
+        a.xbase = P;
+        a.n = np;
+        a.obase = P;
+        a.z = reinterpret_cast<float2 *>(z);
+        a.ld = n;
+        a.tape = tp ? tp->tape : nullptr;
+        a.chunk0 = P / bk->L;
+        e = launch_forward(a, kModeZ, bk->lay.fl, bk->xlds, bk->lay.groups, bk->lds, st);
+    }
+    if (e != hipSuccess) {
+        if (tp) {
+            (void)hipDeviceSynchronize();
+            spiir_tape_destroy(tp);
+        }
+        return fail(SPIIR_EHIP, "forward_z launch: %s", hipGetErrorString(e));
+    }
+    if (tape_out) {
+        *tape_out = tp;
+    } else if (tp) {
+        (void)hipStreamSynchronize(st);
+        spiir_tape_destroy(tp);
+    }
+    return SPIIR_OK;
+}
+
+int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float *ga, float *gb, void *stream) {
+    if (!bk || !tp) return fail(SPIIR_EINVAL, "null bank or tape");
+    if (!gz || !ga || !gb) return fail(SPIIR_EINVAL, "null device pointer");
+    if (tp->bank != bk) return fail(SPIIR_ESTATE, "tape was made by another bank");
+    if (tp->coeff_version != bk->coeff_version)
+        return fail(SPIIR_ESTATE, "bank coefficients changed since the tape was made");
+    if (!tp->tape) return fail(SPIIR_ESTATE, "tape holds no carries");
+    DeviceGuard guard(bk->device);
+    BwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.s = bk->slots();
+    a.waves = bk->waves;
+    a.slot_filter = bk->slot_filter;
+    a.tape = tp->tape;
+    a.xwin = tp->xwin;
+    a.gz = reinterpret_cast<const float2 *>(gz);
+    a.ysub = bk->ysub;
+    a.grad_a = reinterpret_cast<float2 *>(ga);
+    a.grad_b = reinterpret_cast<float2 *>(gb);
+    a.n = tp->n;
+    a.nslots = bk->lay.nslots;
+    a.dmax = bk->dmax;
+    a.L = bk->L;
+    a.prec = bk->prec;
+    a.wpg = bk->lay.wpg;
+    HIPCHK(launch_backward(a, bk->lay.fl, bk->lay.groups, as_stream(stream)));
+    return SPIIR_OK;
+}
+
+int spiir_tape_destroy(spiir_tape *tp) {
+    if (!tp) return SPIIR_OK;
+    dfree(tp->tape);
+    dfree(tp->xwin);
+    delete tp;
+    return SPIIR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, const float *const *x,
+                       const int64_t *lengths, float *const *mx, int32_t *const *am, int32_t B, void *stream) {
+    if (!out) return fail(SPIIR_EINVAL, "out is null");
+    *out = nullptr;
+    if (ns < 1) return fail(SPIIR_EINVAL, "n_streams must be >= 1");
+    if (!banks || !x || !lengths || !mx || !am) return fail(SPIIR_EINVAL, "null array argument");
+    if (B < 8 || B % 8) return fail(SPIIR_EINVAL, "block_len must be a positive multiple of 8");
+    for (int s = 0; s < ns; ++s) {
+        if (!banks[s] || !x[s] || !mx[s] || !am[s]) return fail(SPIIR_EINVAL, "null entry for stream %d", s);
+        if (lengths[s] < 1) return fail(SPIIR_EINVAL, "stream %d has length < 1", s);
+        if (banks[s]->device != banks[0]->device) return fail(SPIIR_EINVAL, "banks on different devices");
+        if (banks[s]->lay.fl != banks[0]->lay.fl || banks[s]->lay.wpg != banks[0]->lay.wpg)
+            return fail(SPIIR_EINVAL, "banks must share filters_per_lane and waves_per_group");
+        if (!banks[s]->xlds) return fail(SPIIR_EINVAL, "bank %d keeps its strain window outside LDS", s);
+        for (int t = 0; t < s; ++t)
+            if (banks[t] == banks[s]) return fail(SPIIR_EINVAL, "a bank appears twice in the batch");
+    }
+    spiir_batch *bt = new (std::nothrow) spiir_batch();
+    if (!bt) return fail(SPIIR_ENOMEM, "out of host memory");
+    bt->device = banks[0]->device;
+    DeviceGuard guard(bt->device);
+    bt->ns = ns;
+    bt->B = B;
+    bt->fl = banks[0]->lay.fl;
+    bt->wpg = banks[0]->lay.wpg;
+    bt->banks.assign(banks, banks + ns);
+    bt->len.assign(lengths, lengths + ns);
+    int max_groups = 0;
+    for (int s = 0; s < ns; ++s) {
+        bt->lds = std::max(bt->lds, banks[s]->lds);
+        max_groups = std::max(max_groups, banks[s]->lay.groups);
+    }
+    bt->key_stride = (int64_t)max_groups * B;
+    // work items, largest first: (stream length) x (filters in the group)
+    std::vector<std::tuple<double, int, int>> it;
+    for (int s = 0; s < ns; ++s) {
+        const spiir_bank *bk = banks[s];
+        std::vector<int64_t> gf(bk->lay.groups, 0);
+        for (int j = 0; j < bk->T; ++j) gf[bk->lay.tpl_group[j]] += bk->off[j + 1] - bk->off[j];
+        for (int g = 0; g < bk->lay.groups; ++g) it.emplace_back(-(double)lengths[s] * gf[g], s, g);
+    }
+    std::sort(it.begin(), it.end());
+    std::vector<int2> items;
+    for (auto &t : it) items.push_back(make_int2(std::get<1>(t), std::get<2>(t)));
+    bt->nitems = (int)items.size();
+    std::vector<BatchStream> hs(ns);
+    for (int s = 0; s < ns; ++s) {
+        std::memset(&hs[s], 0, sizeof(BatchStream));
+        FwdArgs a = banks[s]->base_args();
+        a.state = banks[s]->state;
+        a.x = x[s];
+        a.hist = nullptr;
+        a.ld = B;
+        hs[s].args = a;
+        hs[s].len = lengths[s];
+        hs[s].groups = banks[s]->lay.groups;
+        hs[s].max_out = mx[s];
+        hs[s].arg_out = am[s];
+    }
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    A(dalloc(&bt->streams, (size_t)ns));
+    A(dalloc(&bt->items, items.size()));
+    A(dalloc(&bt->counter, 1));
+    A(dalloc(&bt->pos, (size_t)ns));
+    A(dalloc(&bt->keys, (size_t)(bt->key_stride * ns)));
+    if (e == hipSuccess) {
+        for (int s = 0; s < ns; ++s) hs[s].args.keys = bt->keys + s * bt->key_stride;
+        A(hipMemcpy(bt->streams, hs.data(), ns * sizeof(BatchStream), hipMemcpyHostToDevice));
+        A(hipMemcpy(bt->items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+        A(hipMemset(bt->counter, 0, sizeof(int)));
+        A(hipMemset(bt->pos, 0, ns * sizeof(int64_t)));
+    }
+    const int occ = std::max(1, batch_occupancy(bt->fl, bt->wpg, bt->lds));
+    bt->grid = std::min(bt->nitems, banks[0]->dev.n_cu * occ);
+    hipStream_t cap = nullptr;
+    if (e == hipSuccess) A(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (e == hipSuccess) {
+        A(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        if (e == hipSuccess) {
+            A(launch_batch(bt->streams, bt->items, bt->nitems, bt->counter, bt->pos, B, bt->fl, bt->grid,
+                           bt->wpg, bt->lds, cap));
+            A(launch_batch_finalize(bt->streams, ns, bt->keys, bt->key_stride, bt->pos, B, max_groups, cap));
+            A(launch_batch_advance(bt->pos, bt->streams, ns, bt->counter, B, cap));
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(cap, &g);
+            A(ee);
+            bt->graph = g;
+        }
+        if (e == hipSuccess) A(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+    }
+    if (cap) (void)hipStreamDestroy(cap);
+    for (int s = 0; s < ns && e == hipSuccess; ++s) {
+        A(launch_fill_zero(banks[s]->state, banks[s]->lay.nslots * sizeof(float4), as_stream(stream)));
+    }
+    if (e == hipSuccess) A(hipStreamSynchronize(as_stream(stream)));
+    if (e != hipSuccess) {
+        spiir_batch_destroy(bt);
+        return fail(SPIIR_EHIP, "batch creation: %s", hipGetErrorString(e));
+    }
+    *out = bt;
+    return SPIIR_OK;
+}
+
+int spiir_batch_step(spiir_batch *bt, void *stream) {
+    if (!bt) return fail(SPIIR_EINVAL, "batch is null");
+    DeviceGuard guard(bt->device);
+    HIPCHK(hipGraphLaunch(bt->exec, as_stream(stream)));
+    return SPIIR_OK;
+}
+
+int spiir_batch_steps_total(const spiir_batch *bt, int64_t *steps) {
+    if (!bt || !steps) return fail(SPIIR_EINVAL, "null argument");
+    int64_t m = 0;
+    for (int64_t l : bt->len) m = std::max(m, (l + bt->B - 1) / bt->B);
+    *steps = m;
+    return SPIIR_OK;
+}
+
+int spiir_batch_reset(spiir_batch *bt, void *stream) {
+    if (!bt) return fail(SPIIR_EINVAL, "batch is null");
+    DeviceGuard guard(bt->device);
+    hipStream_t st = as_stream(stream);
+    HIPCHK(launch_fill_zero(bt->pos, bt->ns * sizeof(int64_t), st));
+    HIPCHK(launch_fill_zero(bt->counter, sizeof(int), st));
+    for (spiir_bank *bk : bt->banks) HIPCHK(launch_fill_zero(bk->state, bk->lay.nslots * sizeof(float4), st));
+    return SPIIR_OK;
+}
+
+int spiir_batch_destroy(spiir_batch *bt) {
+    if (!bt) return SPIIR_OK;
+    {
+        DeviceGuard guard(bt->device);
+        (void)hipDeviceSynchronize();
+        if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+        if (bt->graph) (void)hipGraphDestroy(bt->graph);
+        dfree(bt->streams);
+        dfree(bt->items);
+        dfree(bt->counter);
+        dfree(bt->pos);
+        dfree(bt->keys);
+    }
+    delete bt;
+    return SPIIR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+int spiir_autotune(int32_t nbk, const int32_t *T, const int64_t *const *off, const double *const *a,
+                   const double *const *b, const int32_t *const *d, int32_t max_delay, int32_t B,
+                   int32_t device, int32_t *L_out, int32_t *F_out, float *table) {
+    static std::mutex mu;
+    static std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> cache;
+    if (nbk < 1 || !T || !off || !a || !b || !d || !L_out || !F_out)
+        return fail(SPIIR_EINVAL, "null or empty autotune argument");
+    if (B < 8 || B % 8) return fail(SPIIR_EINVAL, "block_len must be a positive multiple of 8");
+    spiir_bank_opts probe;
+    spiir_bank_opts_default(&probe);
+    probe.max_delay = max_delay;
+    for (int i = 0; i < nbk; ++i) {
+        int dm = 0;
+        int rc = check_bank_args(T[i], off[i], a[i], b[i], d[i], probe, dm);
+        if (rc) return rc;
+    }
+    int dev = device;
+    if (dev < 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SPIIR_ENODEV, "no HIP device available");
+        HIPCHK(hipGetDevice(&dev));
+    }
+    DeviceFacts df;
+    int rc = device_facts(dev, df);
+    if (rc) return rc;
+    std::vector<int64_t> key = {dev, nbk, max_delay, B};
+    for (int i = 0; i < nbk; ++i) {
+        key.push_back(T[i]);
+        int64_t h = 0;
+        for (int j = 0; j <= T[i]; ++j) h = h * 1000003 + off[i][j];
+        key.push_back(h);
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto itc = cache.find(key);
+        if (itc != cache.end() && !table) {
+            *L_out = itc->second.first;
+            *F_out = itc->second.second;
+            return SPIIR_OK;
+        }
+    }
+    DeviceGuard guard(dev);
+    const int Ls[4] = {64, 128, 256, 512};
+    float best = 1e30f;
+    int bestL = 256, bestF = 1;
+    hipStream_t st = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int warm = 2, iters = 6;
+    const int64_t len = (int64_t)B * (warm + iters);
+    std::vector<float *> xs(nbk, nullptr), ms(nbk, nullptr);
+    std::vector<int32_t *> as(nbk, nullptr);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nbk && e == hipSuccess; ++i) {
+        e = dalloc(&xs[i], (size_t)len);
+        if (e == hipSuccess) e = dalloc(&ms[i], (size_t)len);
+        if (e == hipSuccess) e = dalloc(&as[i], (size_t)len);
+        if (e == hipSuccess) e = launch_noise_fill(xs[i], len, 1602u + (uint32_t)i, st);
+    }
+    for (int li = 0; li < 4 && e == hipSuccess; ++li) {
+        for (int fl = 1; fl <= 4; ++fl) {
+            if (table) table[li * 4 + fl - 1] = -1.f;
+            int64_t total = 0;
+            int maxnw = 0;
+            for (int i = 0; i < nbk; ++i) {
+                const Plan p = plan_waves(T[i], off[i], fl);
+                total += p.total_waves;
+                maxnw = std::max(maxnw, p.max_nw);
+            }
+            if (maxnw > kMaxWaves) continue;
+            spiir_bank_opts o;
+            spiir_bank_opts_default(&o);
+            o.chunk_len = Ls[li];
+            o.filters_per_lane = fl;
+            o.max_delay = max_delay;
+            o.device = dev;
+            o.waves_per_group = auto_wpg(total, maxnw, df.n_cu);
+            std::vector<spiir_bank *> bks(nbk, nullptr);
+            bool ok = true;
+            for (int i = 0; i < nbk && ok; ++i)
+                ok = create_bank(&bks[i], T[i], off[i], a[i], b[i], d[i], o) == SPIIR_OK && bks[i]->xlds;
+            spiir_batch *bt = nullptr;
+            std::vector<int64_t> lens(nbk, len);
+            if (ok)
+                ok = spiir_batch_create(&bt, nbk, bks.data(), xs.data(), lens.data(), ms.data(), as.data(), B, st) ==
+                     SPIIR_OK;
+            float ms_per = -1.f;
+            if (ok) {
+                for (int w = 0; w < warm && ok; ++w) ok = spiir_batch_step(bt, st) == SPIIR_OK;
+                if (ok) ok = hipEventRecord(e0, st) == hipSuccess;
+                for (int w = 0; w < iters && ok; ++w) ok = spiir_batch_step(bt, st) == SPIIR_OK;
+                if (ok) ok = hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                if (ok) ok = hipEventElapsedTime(&ms_per, e0, e1) == hipSuccess;
+                if (ok) ms_per /= iters;
+            }
+            if (bt) spiir_batch_destroy(bt);
+            for (spiir_bank *bk : bks) spiir_bank_destroy(bk);
+            if (ok && ms_per > 0.f) {
+                if (table) table[li * 4 + fl - 1] = ms_per * 1e6f;
+                if (ms_per < best) {
+                    best = ms_per;
+                    bestL = Ls[li];
+                    bestF = fl;
+                }
+            }
+        }
+    }
+    for (int i = 0; i < nbk; ++i) {
+        dfree(xs[i]);
+        dfree(ms[i]);
+        dfree(as[i]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (e != hipSuccess) return fail(SPIIR_EHIP, "autotune setup: %s", hipGetErrorString(e));
+    if (best >= 1e30f) return fail(SPIIR_EINVAL, "no autotune candidate could run on this bank");
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = {bestL, bestF};
+    }
+    *L_out = bestL;
+    *F_out = bestF;
+    g_err.clear();
+    return SPIIR_OK;
+}
+
+const char *spiir_last_error(void) { return g_err.c_str(); }
+
+const char *spiir_version(void) { return "spiir-mi355x 0.1.0 (gfx950)"; }
+
+}  // extern "C"

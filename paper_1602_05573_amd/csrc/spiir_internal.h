@@ -1,0 +1,105 @@
+// Internal declarations shared by the kernels and the host side of libspiir.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spiir {
+
+constexpr int kTile = 8;        // time steps per template-sum tile
+constexpr int kMaxWaves = 16;   // 64-lane waves per workgroup (1024 threads)
+constexpr int kSub = 16;        // adjoint: steps kept in registers per recompute
+constexpr float kFlagRadius = 1.0f - 1e-5f;
+
+enum Mode { kModeSnr = 0, kModeKeys = 1, kModeZ = 2 };
+enum Prec { kPrecHybrid = 0, kPrecFp32 = 1, kPrecFp64 = 2 };
+
+// Per wave of a workgroup: the template it serves (-1: none), the first wave
+// of that template inside the workgroup and the number of its waves.
+struct WaveInfo {
+    int32_t tpl, w0, nw, pad;
+};
+
+// Per filter slot (lane-major inside each wave and slot column).
+struct SlotArrays {
+    const float2 *a32;    // fl32(a)
+    const float2 *b32;    // fl32(b)
+    const int32_t *xoff;  // max_delay - d: offset of x[m - d] inside the window
+    const double2 *aL;    // a^L in FP64
+    const double2 *dL;    // a^L - fl32(a)^L in FP64
+    const double2 *a64;   // a in FP64 (powers for ragged chunks)
+    const int32_t *flags; // bit 0: |a| > 1 - 1e-5 (FP64 carry in hybrid mode)
+};
+
+struct FwdArgs {
+    SlotArrays s;
+    float4 *state;        // (hi.re, hi.im, lo.re, lo.im) per slot; null: cold start, not stored
+    const float *x;       // samples; launch sample t is x[xbase + t]
+    const float *hist;    // max_delay samples before x[0] (null: zeros); hist[dmax + m], m < 0
+    const float *xwin;    // global-window mode: xwin[dmax + m] = sample m (m >= -dmax)
+    int64_t xbase;
+    int64_t n;            // samples in this launch
+    int32_t dmax, L, nb, prec, wpg, only_tpl;
+    int32_t gbase;        // group of blockIdx.x == 0
+    int32_t pad0;
+    const WaveInfo *waves;  // [groups * wpg]
+    int64_t obase;        // output column of launch sample 0
+    int64_t ld;           // row length of snr / z / keys
+    float *snr;           // kModeSnr: snr[tpl * ld + obase + t]
+    uint64_t *keys;       // kModeKeys: keys[group * ld + t]
+    float2 *z;            // kModeZ: z[tpl * ld + obase + t]
+    float4 *tape;         // kModeZ: tape[(chunk0 + c) * nslots + slot] = state at chunk start
+    int64_t chunk0;
+    int64_t nslots;
+};
+
+struct BwdArgs {
+    SlotArrays s;
+    const WaveInfo *waves;
+    const int32_t *slot_filter;  // slot -> caller filter index (-1 padding)
+    const float4 *tape;          // [nchunks][nslots]
+    const float *xwin;           // xwin[dmax + m] = x[m] for m in [-dmax, n)
+    const float2 *gz;            // [T][n]
+    float2 *ysub;                // scratch [ceil(L / kSub)][nslots]
+    float2 *grad_a, *grad_b;     // [F] caller order
+    int64_t n, nslots;
+    int32_t dmax, L, prec, wpg;
+};
+
+// One stream of a batch, as the persistent kernel sees it.
+struct BatchStream {
+    FwdArgs args;       // bank part filled at creation; x = whole stream, xbase/n per step
+    int64_t len;
+    int32_t groups;
+    int32_t pad;
+    float *max_out;
+    int32_t *arg_out;
+};
+
+// Launch helpers (kernels.hip). All enqueue on `stream` and return the launch error.
+size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds);
+hipError_t launch_forward(const FwdArgs &a, int mode, int fl, bool x_in_lds, int groups,
+                          size_t lds, hipStream_t stream);
+hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
+                                float *mx, int32_t *am, hipStream_t stream);
+hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, float *mx,
+                              int32_t *am, hipStream_t stream);
+hipError_t launch_hist_update(const float *old_h, float *new_h, const float *x, int64_t n,
+                              int dmax, hipStream_t stream);
+hipError_t launch_window_fill(float *xwin, const float *hist, const float *x, int64_t n,
+                              int dmax, hipStream_t stream);
+int batch_occupancy(int fl, int wpg, size_t lds);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
+hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
+hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitems,
+                        int *counter, const int64_t *pos, int block_len, int fl, int grid,
+                        int wpg, size_t lds, hipStream_t stream);
+hipError_t launch_batch_finalize(const BatchStream *streams, int nstreams, const uint64_t *keys,
+                                 int64_t key_stride, const int64_t *pos, int block_len,
+                                 int max_groups, hipStream_t stream);
+hipError_t launch_batch_advance(int64_t *pos, const BatchStream *streams, int nstreams,
+                                int *counter, int block_len, hipStream_t stream);
+hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t stream);
+int forward_max_threads();
+
+}  // namespace spiir

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/spiir.h declares, and rejects bad arguments on the host before
+anything reaches a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1602_05573_amd as pkg
+from paper_1602_05573_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "spiir.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spiir_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libspiir.so missing: run __graft_entry__.build() first")
+    return _lib.load()
+
+
+def test_exports_match_header(lib):
+    declared = header_functions()
+    assert len(declared) >= 20
+    assert sorted(_lib.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.spiir_version()
+    assert isinstance(lib.spiir_last_error(), bytes)
+
+
+def test_opts_default(lib):
+    o = _lib.default_opts()
+    assert o.chunk_len == 256 and o.precision == 0 and o.device == -1 and o.max_block == 16384
+
+
+def _create(lib, T, off, a, b, d, **kw):
+    o = _lib.default_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    off = np.ascontiguousarray(off, np.int64)
+    a = np.ascontiguousarray(a, np.complex128)
+    b = np.ascontiguousarray(b, np.complex128)
+    d = np.ascontiguousarray(d, np.int32)
+    rc = lib.spiir_bank_create(ctypes.byref(h), T, off.ctypes.data_as(ctypes.c_void_p),
+                               a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                               d.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o))
+    return rc, h
+
+
+GOOD = dict(T=2, off=[0, 2, 3], a=[0.5, 0.9j, -0.3 + 0.1j], b=[1, 1j, 0.5], d=[0, 3, 7])
+
+
+@pytest.mark.parametrize("change,needle", [
+    (dict(T=0), "n_templates"),
+    (dict(off=[1, 2, 3]), "offsets[0]"),
+    (dict(off=[0, 2, 2]), "no filters"),
+    (dict(a=[0.5, 1.0, 0.1]), "not stable"),
+    (dict(a=[0.5, 0.6 + 0.8j, 0.1]), "not stable"),
+    (dict(a=[0.5, np.nan, 0.1]), "non-finite"),
+    (dict(b=[1, np.inf, 0.5]), "non-finite"),
+    (dict(d=[0, -1, 7]), "negative delay"),
+    (dict(max_delay=5), "exceeds max_delay"),
+    (dict(chunk_len=12), "chunk_len"),
+    (dict(chunk_len=8192), "chunk_len"),
+    (dict(filters_per_lane=5), "filters_per_lane"),
+    (dict(precision=3), "precision"),
+    (dict(waves_per_group=17), "waves_per_group"),
+])
+def test_create_rejects_bad_arguments(lib, change, needle):
+    args = dict(GOOD)
+    opts = {}
+    for k, v in change.items():
+        if k in args:
+            args[k] = v
+        else:
+            opts[k] = v
+    rc, h = _create(lib, args["T"], args["off"], args["a"], args["b"], args["d"], **opts)
+    assert rc == _lib.SPIIR_EINVAL
+    assert not h.value
+    assert needle in lib.spiir_last_error().decode()
+
+
+def test_null_arguments(lib):
+    assert lib.spiir_bank_create(None, 1, None, None, None, None, None) == _lib.SPIIR_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.spiir_bank_create(ctypes.byref(h), 1, None, None, None, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_bank_destroy(None) == 0
+    assert lib.spiir_tape_destroy(None) == 0
+    assert lib.spiir_batch_destroy(None) == 0
+    assert lib.spiir_filter_block(None, None, 0, None, 0, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_trigger_max(None, None, 0, None, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_backward(None, None, None, None, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_bank_get_info(None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_batch_create(None, 1, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
+    bh = ctypes.c_void_p()
+    assert lib.spiir_batch_create(ctypes.byref(bh), 0, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
+    L, F = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.spiir_autotune(0, None, None, None, None, None, 0, 4096, -1, ctypes.byref(L),
+                              ctypes.byref(F), None) == _lib.SPIIR_EINVAL
+
+
+def test_no_device_reported_cleanly(lib):
+    """With valid arguments and no GPU, creation fails with ENODEV (never a fallback)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    rc, h = _create(lib, GOOD["T"], GOOD["off"], GOOD["a"], GOOD["b"], GOOD["d"])
+    assert rc == _lib.SPIIR_ENODEV
+    assert not h.value
+
+
+def test_package_has_no_cpu_fallback():
+    # the binding holds only marshalling code: no oracle import, no numpy recursion
+    pkgdir = os.path.dirname(pkg.__file__)
+    for fn in os.listdir(pkgdir):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkgdir, fn)).read()
+            assert "import oracle" not in src and "from oracle" not in src, fn

@@ -1,0 +1,258 @@
+"""GPU parity of the forward path (filter recursion, template sum, SNR, fused
+max/argmax, streaming state) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import SNR_TOL, check_argmax, snr_err
+from workloads import Bank, config0, random_bank, strain
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1602_05573_amd import load
+    load()
+
+
+def mk(bank, **kw):
+    from paper_1602_05573_amd import SpiirBank
+    return SpiirBank.from_bank(bank, **kw)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def banner(msg):
+    print("[case] " + msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# config 0: 4 templates x 128 filters, 16,384 samples
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c0():
+    bank, x = config0()
+    ref = oracle.snr(bank, x)
+    return bank, x, ref
+
+
+@pytest.mark.parametrize("fl", [0, 1, 2, 4])
+def test_config0_snr_parity(c0, fl):
+    bank, x, ref = c0
+    banner("config0 snr fl=%d" % fl)
+    with mk(bank, filters_per_lane=fl) as bk:
+        snr = bk.filter_block(dev(x)).cpu().numpy()
+    err, _ = snr_err(snr, ref)
+    print("config0 fl=%d err=%.3g" % (fl, err))
+    assert err <= SNR_TOL
+
+
+def test_config0_trigger_parity(c0):
+    bank, x, ref = c0
+    banner("config0 trigger")
+    with mk(bank) as bk:
+        mx, am = bk.trigger_max(dev(x))
+        mx, am = mx.cpu().numpy(), am.cpu().numpy()
+    ties = check_argmax(mx, am, ref)
+    print("config0 documented ties: %d of %d" % (ties, len(x)))
+
+
+def test_fused_equals_max_of_plain_rows(c0):
+    bank, x, _ = c0
+    banner("fused vs plain rows")
+    xd = dev(x)
+    with mk(bank) as b1, mk(bank) as b2:
+        snr = b1.filter_block(xd)
+        mx, am = b2.trigger_max(xd)
+        torch.cuda.synchronize()
+    s = snr.cpu().numpy()
+    m = s.max(axis=0)
+    first = np.argmax(s == m[None, :], axis=0)
+    assert np.array_equal(mx.cpu().numpy(), m)
+    assert np.array_equal(am.cpu().numpy(), first)
+
+
+def test_per_template_launches_match_fused(c0):
+    bank, x, _ = c0
+    banner("per-template vs fused")
+    xd = dev(x)
+    with mk(bank) as b1, mk(bank) as b2:
+        m1, a1 = b1.trigger_max(xd)
+        m2, a2 = b2.trigger_max_per_template(xd)
+        torch.cuda.synchronize()
+    assert torch.equal(m1, m2) and torch.equal(a1, a2)
+
+
+def test_determinism(c0):
+    bank, x, _ = c0
+    banner("determinism")
+    xd = dev(x)
+    with mk(bank) as bk:
+        s1 = bk.filter_block(xd).clone()
+        bk.reset()
+        s2 = bk.filter_block(xd).clone()
+        bk.reset()
+        m1, a1 = bk.trigger_max(xd)
+        m1, a1 = m1.clone(), a1.clone()
+        bk.reset()
+        m2, a2 = bk.trigger_max(xd)
+    assert torch.equal(s1, s2)
+    assert torch.equal(m1, m2) and torch.equal(a1, a2)
+
+
+def test_block_split_invariance(c0):
+    bank, x, ref = c0
+    banner("block split")
+    xd = dev(x)
+    with mk(bank, chunk_len=256) as bk:
+        whole = bk.filter_block(xd).clone()
+        bk.reset()
+        parts = []
+        for a, b in [(0, 4096), (4096, 4608), (4608, 8192), (8192, 16384)]:   # multiples of L
+            parts.append(bk.filter_block(xd[a:b].contiguous()).clone())
+        split = torch.cat(parts, dim=1)
+        bk.reset()
+        rag = []
+        for a, b in [(0, 1000), (1000, 1003), (1003, 9000), (9000, 16384)]:    # arbitrary cuts
+            rag.append(bk.filter_block(xd[a:b].contiguous()).clone())
+        ragged = torch.cat(rag, dim=1)
+    assert torch.equal(whole, split)
+    err, _ = snr_err(ragged.cpu().numpy(), ref)
+    assert err <= SNR_TOL
+
+
+def test_state_checkpoint_resume(c0):
+    bank, x, _ = c0
+    banner("checkpoint")
+    xd = dev(x)
+    with mk(bank) as b1, mk(bank) as b2:
+        b1.filter_block(xd[:6000].contiguous())
+        blob = b1.get_state()
+        rest1 = b1.filter_block(xd[6000:].contiguous()).clone()
+        b2.set_state(blob)
+        rest2 = b2.filter_block(xd[6000:].contiguous()).clone()
+    assert torch.equal(rest1, rest2)
+
+
+def test_exact_ties_resolve_to_lowest_index():
+    banner("ties")
+    base = random_bank(50, 0, 3, 40, 90, 0.99, 0.9999, 300)
+    bank = base.subset([0, 1, 2, 1, 0, 2])       # 3..5 duplicate 1, 0, 2
+    x = strain(3000, 50)
+    with mk(bank) as bk:
+        mx, am = bk.trigger_max(dev(x))
+        am = am.cpu().numpy()
+    assert am.max() <= 2
+    ref = oracle.snr(bank, x)
+    check_argmax(mx.cpu().numpy(), am, ref)
+
+
+# ---------------------------------------------------------------------------
+# layouts, precisions, ragged sizes, edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def mid():
+    # 12 templates, 1..700 filters, several waves per template, ragged length
+    bank = random_bank(51, 0, 12, 1, 700, 0.99, 1 - 1e-5, 1500)
+    x = strain(5003, 51)
+    return bank, x, oracle.snr(bank, x)
+
+
+@pytest.mark.parametrize("fl,L,wpg,prec", [
+    (1, 64, 0, 0), (2, 256, 0, 0), (3, 128, 16, 0), (4, 512, 0, 0),
+    (2, 8, 0, 0), (1, 256, 16, 2), (3, 256, 12, 2)])
+def test_layouts_and_precisions(mid, fl, L, wpg, prec):
+    bank, x, ref = mid
+    banner("layout fl=%d L=%d wpg=%d prec=%d" % (fl, L, wpg, prec))
+    with mk(bank, filters_per_lane=fl, chunk_len=L, waves_per_group=wpg, precision=prec) as bk:
+        snr = bk.filter_block(dev(x)).cpu().numpy()
+        info = bk.info
+    err, _ = snr_err(snr, ref)
+    print("layout", info, "err=%.3g" % err)
+    assert err <= SNR_TOL
+
+
+def test_all_fp32_mode_runs(mid):
+    bank, x, ref = mid
+    banner("all fp32")
+    with mk(bank, precision=1) as bk:
+        snr = bk.filter_block(dev(x)).cpu().numpy()
+    err, _ = snr_err(snr, ref)
+    print("all-fp32 err=%.3g" % err)
+    assert np.isfinite(snr).all() and err < 0.05
+
+
+def test_multi_piece_calls(mid):
+    bank, x, ref = mid
+    banner("pieces")
+    with mk(bank, max_block=1024, chunk_len=128) as bk:       # one call, five launches
+        snr = bk.filter_block(dev(x)).cpu().numpy()
+    err, _ = snr_err(snr, ref)
+    assert err <= SNR_TOL
+
+
+def test_small_lds_sub_blocks(mid):
+    bank, x, ref = mid
+    banner("sub-blocks")
+    # a long stream with windows refilled several times per launch
+    with mk(bank, chunk_len=64, max_block=16384) as bk:
+        assert bk.info["x_in_lds"] == 1
+        mx, am = bk.trigger_max(dev(x))
+        mx, am = mx.cpu().numpy(), am.cpu().numpy()
+    check_argmax(mx, am, ref)
+
+
+def test_strain_window_in_global_memory():
+    banner("global window")
+    bank = random_bank(52, 0, 5, 20, 200, 0.99, 0.9999, 60000)   # 240 KB of history: not in LDS
+    x = strain(7000, 52)
+    ref = oracle.snr(bank, x)
+    with mk(bank) as bk:
+        assert bk.info["x_in_lds"] == 0
+        snr = bk.filter_block(dev(x[:3000])).clone()
+        snr2 = bk.filter_block(dev(x[3000:]))
+        s = torch.cat([snr, snr2], dim=1).cpu().numpy()
+    err, _ = snr_err(s, ref)
+    assert err <= SNR_TOL
+
+
+def test_single_filter_templates_and_zero_delay():
+    banner("tiny templates")
+    off = np.array([0, 1, 2, 66, 67], np.int64)
+    rng = np.random.default_rng(3)
+    F = 67
+    a = 0.995 * np.exp(1j * rng.uniform(0.01, 1.5, F))
+    b = (rng.standard_normal(F) + 1j * rng.standard_normal(F)) / 8
+    d = rng.integers(0, 40, F).astype(np.int32)
+    d[0] = 0
+    bank = Bank(off, a, b, d, 40)
+    x = strain(777, 53)
+    ref = oracle.snr(bank, x)
+    with mk(bank) as bk:
+        s = bk.filter_block(dev(x)).cpu().numpy()
+        mx, am = bk.trigger_max(dev(np.zeros(0, np.float32)))
+    assert mx.numel() == 0
+    err, _ = snr_err(s, ref)
+    assert err <= SNR_TOL
+
+
+def test_impulse_response_on_gpu():
+    banner("impulse")
+    bank = random_bank(54, 0, 3, 100, 300, 0.99, 0.9999, 200)
+    n = 4000
+    x = np.zeros(n, np.float32)
+    x[0] = 1.0
+    ref = oracle.snr(bank, x)
+    with mk(bank) as bk:
+        s = bk.filter_block(dev(x)).cpu().numpy()
+    err, _ = snr_err(s, ref)
+    assert err <= SNR_TOL
