@@ -85,9 +85,16 @@ int oracle_z(const int64_t *off, const double *a, const double *b, const int32_t
 {
     if (!off || !a || !b || !d || !tpl || !x || !z_out || n < 0 || ntpl < 0) return -1;
     if (nthreads < 1) nthreads = 1;
-    if (ntpl == 1)
-        return template_z(a, b, d, off[tpl[0]], off[tpl[0] + 1], x, n, z_out, nthreads);
     int rc = 0;
+    if (ntpl * 2 <= nthreads) {
+        /* few templates: one at a time, each split over its filters */
+        for (int32_t i = 0; i < ntpl; ++i) {
+            int r = template_z(a, b, d, off[tpl[i]], off[tpl[i] + 1], x, n,
+                               z_out + (size_t)i * 2 * (size_t)n, nthreads);
+            if (r) rc = r;
+        }
+        return rc;
+    }
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int32_t i = 0; i < ntpl; ++i) {
         int r = template_z(a, b, d, off[tpl[i]], off[tpl[i] + 1], x, n,
@@ -105,8 +112,9 @@ int oracle_snr(const int64_t *off, const double *a, const double *b, const int32
     if (!snr_out || n < 0) return -1;
     if (nthreads < 1) nthreads = 1;
     int rc = 0;
-    int outer = (ntpl == 1) ? 1 : nthreads;
-    int inner = (ntpl == 1) ? nthreads : 1;
+    /* few templates: one at a time, each split over its filters */
+    int outer = (ntpl * 2 <= nthreads) ? 1 : nthreads;
+    int inner = (outer == 1) ? nthreads : 1;
 #pragma omp parallel for num_threads(outer) schedule(dynamic, 1)
     for (int32_t i = 0; i < ntpl; ++i) {
         double *z = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));

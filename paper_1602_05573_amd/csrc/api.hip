@@ -81,89 +81,117 @@ std::pair<double, double> cpow(double re, double im, long e) {
 struct Layout {
     int fl = 1, wpg = 1, groups = 0;
     int64_t nslots = 0;
-    std::vector<WaveInfo> waves;          // [groups * wpg]
+    std::vector<RowInfo> rows;            // [groups * wpg * 4]
     std::vector<int32_t> slot_filter;     // [nslots], -1 = padding
     std::vector<int32_t> tpl_group;       // [T]
 };
 
 struct Plan {
-    int64_t total_waves = 0;
-    int max_nw = 0;
+    int64_t total_rows = 0;
+    int max_nr = 0;
 };
 
-Plan plan_waves(int T, const int64_t *off, int fl) {
+inline int rows_of(int64_t k, int fl) { return (int)((k + kRowLanes * fl - 1) / (kRowLanes * fl)); }
+
+Plan plan_rows(int T, const int64_t *off, int fl) {
     Plan p;
     for (int j = 0; j < T; ++j) {
-        const int64_t k = off[j + 1] - off[j];
-        const int nw = (int)((k + 64 * fl - 1) / (64 * fl));
-        p.total_waves += nw;
-        p.max_nw = std::max(p.max_nw, nw);
+        const int nr = rows_of(off[j + 1] - off[j], fl);
+        p.total_rows += nr;
+        p.max_nr = std::max(p.max_nr, nr);
     }
     return p;
 }
 
-int auto_wpg(int64_t total_waves, int max_nw, int n_cu) {
-    int w = (int)((total_waves + n_cu - 1) / n_cu);
-    return std::min(kMaxWaves, std::max(w, max_nw));
+int auto_wpg(int64_t total_rows, int max_nr, int n_cu) {
+    const int64_t waves = (total_rows + 3) / 4;
+    int w = (int)((waves + n_cu - 1) / n_cu);
+    return std::min(kMaxWaves, std::max(w, (max_nr + 3) / 4));
 }
 
-// First-fit decreasing packing of whole templates into workgroups of wpg waves,
-// then the filter-to-slot assignment inside every template: filters sorted by
-// d mod 64 are dealt round-robin over the template's (wave, slot) columns, so
-// the 64 lanes of a column read x[m - d] from (mostly) distinct LDS banks.
+// First-fit decreasing packing of whole templates, in 16-lane rows, into
+// workgroups of 4 * wpg rows; then the filter-to-slot assignment inside every
+// template: a slot in lane L of its wave preferably gets a filter with
+// d = L (mod 64), else the nearest residue still available, so that the 64
+// lanes of one x[m - d] read hit (nearly) distinct LDS banks for every m.
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
-    std::vector<int> nw(T);
-    int max_nw = 0;
+    const int R = 4 * wpg;
+    std::vector<int> nr(T);
+    int max_nr = 0;
     for (int j = 0; j < T; ++j) {
-        const int64_t k = off[j + 1] - off[j];
-        nw[j] = (int)((k + 64 * fl - 1) / (64 * fl));
-        max_nw = std::max(max_nw, nw[j]);
+        nr[j] = rows_of(off[j + 1] - off[j], fl);
+        max_nr = std::max(max_nr, nr[j]);
     }
-    if (max_nw > wpg)
-        return fail(SPIIR_EINVAL, "a template needs %d waves of %d filters but a workgroup has %d",
-                    max_nw, 64 * fl, wpg);
+    if (max_nr > R)
+        return fail(SPIIR_EINVAL, "a template needs %d rows of %d filters but a workgroup has %d",
+                    max_nr, kRowLanes * fl, R);
     std::vector<int> order(T);
     for (int j = 0; j < T; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nw[x] > nw[y]; });
-    std::vector<int> room;                  // free waves per group
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nr[x] > nr[y]; });
+    std::vector<int> room;                  // free rows per group
     std::vector<std::vector<int>> members;  // templates per group
     for (int j : order) {
         size_t g = 0;
         for (; g < room.size(); ++g)
-            if (room[g] >= nw[j]) break;
+            if (room[g] >= nr[j]) break;
         if (g == room.size()) {
-            room.push_back(wpg);
+            room.push_back(R);
             members.emplace_back();
         }
-        room[g] -= nw[j];
+        room[g] -= nr[j];
         members[g].push_back(j);
     }
     lay.fl = fl;
     lay.wpg = wpg;
     lay.groups = (int)members.size();
     lay.nslots = (int64_t)lay.groups * wpg * fl * 64;
-    lay.waves.assign((size_t)lay.groups * wpg, WaveInfo{-1, 0, 0, 0});
+    lay.rows.assign((size_t)lay.groups * R, RowInfo{-1, 0, 0, 0});
     lay.slot_filter.assign((size_t)lay.nslots, -1);
     lay.tpl_group.assign(T, -1);
-    std::vector<int32_t> ks;
+    std::vector<std::vector<int32_t>> bucket(64);
+    std::vector<std::pair<int64_t, int>> slots;  // (slot, lane in wave)
+    std::vector<char> taken;
     for (int g = 0; g < lay.groups; ++g) {
         std::vector<int> &mem = members[g];
         std::sort(mem.begin(), mem.end());
-        int w0 = 0;
+        int r0 = 0;
         for (int j : mem) {
             lay.tpl_group[j] = g;
-            for (int w = 0; w < nw[j]; ++w) lay.waves[(size_t)g * wpg + w0 + w] = WaveInfo{j, w0, nw[j], 0};
-            ks.clear();
-            for (int64_t k = off[j]; k < off[j + 1]; ++k) ks.push_back((int32_t)k);
-            std::stable_sort(ks.begin(), ks.end(), [&](int32_t x, int32_t y) { return (d[x] & 63) < (d[y] & 63); });
-            const int cols = nw[j] * fl;
-            for (size_t i = 0; i < ks.size(); ++i) {
-                const int c = (int)(i % cols), lane = (int)(i / cols);
-                const int wave = w0 + c % nw[j], f = c / nw[j];
-                const int64_t slot = ((int64_t)(g * wpg + wave) * fl + f) * 64 + lane;
-                lay.slot_filter[(size_t)slot] = ks[i];
+            for (int r = 0; r < nr[j]; ++r) lay.rows[(size_t)g * R + r0 + r] = RowInfo{j, r0, nr[j], 0};
+            for (auto &bk : bucket) bk.clear();
+            for (int64_t k = off[j + 1] - 1; k >= off[j]; --k) bucket[d[k] & 63].push_back((int32_t)k);
+            slots.clear();
+            for (int f = 0; f < fl; ++f)
+                for (int r = r0; r < r0 + nr[j]; ++r)
+                    for (int l = 0; l < kRowLanes; ++l) {
+                        const int lane = (r % 4) * kRowLanes + l;
+                        slots.emplace_back(((int64_t)(g * wpg + r / 4) * fl + f) * 64 + lane, lane);
+                    }
+            taken.assign(slots.size(), 0);
+            int64_t left = off[j + 1] - off[j];
+            for (size_t i = 0; i < slots.size() && left > 0; ++i) {  // exact residue
+                auto &bk = bucket[slots[i].second];
+                if (bk.empty()) continue;
+                lay.slot_filter[(size_t)slots[i].first] = bk.back();
+                bk.pop_back();
+                taken[i] = 1;
+                --left;
             }
-            w0 += nw[j];
+            for (size_t i = 0; i < slots.size() && left > 0; ++i) {  // nearest residue left
+                if (taken[i]) continue;
+                for (int dr = 1; dr <= 32; ++dr) {
+                    int pick = -1;
+                    if (!bucket[(slots[i].second + dr) & 63].empty()) pick = (slots[i].second + dr) & 63;
+                    else if (!bucket[(slots[i].second - dr) & 63].empty()) pick = (slots[i].second - dr) & 63;
+                    if (pick < 0) continue;
+                    lay.slot_filter[(size_t)slots[i].first] = bucket[pick].back();
+                    bucket[pick].pop_back();
+                    taken[i] = 1;
+                    --left;
+                    break;
+                }
+            }
+            r0 += nr[j];
         }
     }
     return SPIIR_OK;
@@ -210,7 +238,8 @@ struct spiir_bank {
     int32_t *xoff = nullptr, *flags = nullptr, *slot_filter = nullptr;
     double2 *aL = nullptr, *dL = nullptr, *a64 = nullptr;
     float4 *state = nullptr, *zstate = nullptr;
-    WaveInfo *waves = nullptr;
+    RowInfo *rows = nullptr;
+    int tt = 16;
     float *hist[2] = {nullptr, nullptr};
     int hist_cur = 0;
     uint64_t *keys = nullptr;
@@ -231,7 +260,7 @@ struct spiir_bank {
         p.wpg = lay.wpg;
         p.only_tpl = -1;
         p.gbase = 0;
-        p.waves = waves;
+        p.rows = rows;
         p.nslots = lay.nslots;
         return p;
     }
@@ -247,7 +276,7 @@ struct spiir_tape {
 
 struct spiir_batch {
     int device = 0;
-    int ns = 0, B = 0, fl = 1, wpg = 1, grid = 0, nitems = 0;
+    int ns = 0, B = 0, fl = 1, tt = 16, wpg = 1, grid = 0, nitems = 0;
     size_t lds = 0;
     std::vector<spiir_bank *> banks;
     std::vector<int64_t> len;
@@ -336,38 +365,49 @@ int upload_coeffs(spiir_bank *bk) {
 void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->a32); dfree(bk->b32); dfree(bk->xoff); dfree(bk->flags); dfree(bk->slot_filter);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
-    dfree(bk->waves); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
+    dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
     dfree(bk->ysub);
 }
 
-// Picks filters per lane from a simple cost model: time ~ rounds of
-// workgroups x per-CU resident lane-work (waves x filters per lane).
-int choose_fl(int T, const int64_t *off, int n_cu, size_t lds_cap, int dmax, int L, int max_block) {
-    double best = 1e300;
-    int best_fl = 1;
-    for (int fl = 1; fl <= 4; ++fl) {
-        const Plan p = plan_waves(T, off, fl);
-        if (p.max_nw > kMaxWaves) continue;
-        const int wpg = auto_wpg(p.total_waves, p.max_nw, n_cu);
-        const int64_t groups_est = (p.total_waves + wpg - 1) / wpg;
-        int nb = (int)(((int64_t)lds_cap - (int64_t)fwd_lds_bytes(wpg, 0, 0, false) - 4 * (int64_t)dmax - 64) / (4 * L)) * L;
-        nb = std::min(nb, max_block);
-        const size_t lds = fwd_lds_bytes(wpg, dmax, std::max(nb, L), nb >= L);
-        int occ = (int)std::max<size_t>(1, lds_cap / std::max<size_t>(lds, 1));
-        occ = std::max(1, std::min(occ, kMaxWaves / wpg));
-        const int64_t per_round = (int64_t)n_cu * occ;
-        const int64_t rounds = (groups_est + per_round - 1) / per_round;
-        const int64_t resident = std::min<int64_t>(occ, (groups_est + n_cu - 1) / n_cu);
-        double cost = (double)rounds * resident * wpg * fl;
-        const double waves_per_simd = resident * wpg / 4.0;
-        if (waves_per_simd < 2.0) cost *= 2.0 / std::max(waves_per_simd, 0.25);
-        if (nb < L) cost *= 4.0;  // strain window not in LDS
-        if (cost < best * 0.999) {
-            best = cost;
-            best_fl = fl;
+// Filters per lane: the largest count that still gives every SIMD about two
+// waves (more filters per lane amortise the template sums over more updates);
+// banks too small for that get one filter per lane.
+int choose_fl(int T, const int64_t *off, int n_cu) {
+    for (int fl = 4; fl >= 1; --fl) {
+        const Plan p = plan_rows(T, off, fl);
+        if (p.max_nr > 4 * kMaxWaves) return std::min(4, fl + 1);
+        if ((p.total_rows + 3) / 4 >= (int64_t)7 * n_cu) return fl;
+    }
+    return 1;
+}
+
+struct Geometry {
+    int tt = 16, nb = 0;
+    bool xlds = true;
+    size_t lds = 0;
+};
+
+// LDS plan for a workgroup of wpg waves: the strain window (max_delay + nb
+// samples) when it fits, and 16-step tiles when they fit beside it.
+Geometry plan_geometry(int wpg, int dmax, int L, int max_block, size_t lds_cap) {
+    Geometry best;
+    for (int tt : {16, 8}) {
+        Geometry g;
+        g.tt = tt;
+        const int64_t fixed = (int64_t)fwd_lds_bytes(wpg, 0, 0, false, tt);
+        int64_t nb = ((int64_t)lds_cap - fixed - 4 * (int64_t)(dmax + tt) - 64) / (4 * L) * L;
+        nb = std::min<int64_t>(nb, max_block);
+        g.xlds = nb >= L;
+        g.nb = g.xlds ? (int)nb : max_block;
+        g.lds = fwd_lds_bytes(wpg, dmax, g.nb, g.xlds, tt);
+        if (tt == 16) {
+            best = g;
+            if (!g.xlds || g.nb >= std::min(max_block, 2048)) return g;
+        } else if (g.xlds && (!best.xlds || g.nb > best.nb)) {
+            return g;
         }
     }
-    return best_fl;
+    return best;
 }
 
 int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a, const double *b,
@@ -390,12 +430,25 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     const int L = o.chunk_len ? o.chunk_len : 256;
     int max_block = o.max_block ? o.max_block : 16384;
     max_block = std::max(L, (max_block / L) * L);
-    int fl = o.filters_per_lane ? o.filters_per_lane : choose_fl(T, off, df.n_cu, df.lds_cap, dmax, L, max_block);
-    const Plan plan = plan_waves(T, off, fl);
-    if (plan.max_nw > kMaxWaves)
+    int fl = o.filters_per_lane ? o.filters_per_lane : choose_fl(T, off, df.n_cu);
+    const Plan plan = plan_rows(T, off, fl);
+    if (plan.max_nr > 4 * kMaxWaves)
         return fail(SPIIR_EINVAL, "a template has more than %d filters; use more filters per lane",
-                    kMaxWaves * 64 * fl);
-    const int wpg = o.waves_per_group ? o.waves_per_group : auto_wpg(plan.total_waves, plan.max_nw, df.n_cu);
+                    4 * kMaxWaves * kRowLanes * fl);
+    int wpg = o.waves_per_group;
+    if (wpg == 0) {
+        // smallest workgroup that packs the bank into one round of resident workgroups
+        const int w0 = auto_wpg(plan.total_rows, plan.max_nr, df.n_cu);
+        wpg = w0;
+        for (int w = w0; w <= kMaxWaves; ++w) {
+            const Geometry gm = plan_geometry(w, dmax, L, max_block, df.lds_cap);
+            const int occ = std::max(1, forward_occupancy(fl, gm.tt, w, gm.lds));
+            Layout trial;
+            if (build_layout(T, off, d, fl, w, trial)) continue;
+            wpg = w;
+            if (trial.groups <= (int64_t)df.n_cu * occ) break;
+        }
+    }
 
     spiir_bank *bk = new (std::nothrow) spiir_bank();
     if (!bk) return fail(SPIIR_ENOMEM, "out of host memory");
@@ -416,18 +469,11 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
         delete bk;
         return rc;
     }
-    // LDS: the strain window of nb samples plus max_delay history, if it fits
-    const int64_t fixed = (int64_t)fwd_lds_bytes(wpg, 0, 0, false);
-    int64_t nb = ((int64_t)df.lds_cap - fixed - 4 * (int64_t)dmax - 64) / (4 * L) * L;
-    nb = std::min<int64_t>(nb, max_block);
-    if (nb >= L) {
-        bk->xlds = true;
-        bk->nb = (int)nb;
-    } else {
-        bk->xlds = false;
-        bk->nb = max_block;
-    }
-    bk->lds = fwd_lds_bytes(wpg, dmax, bk->nb, bk->xlds);
+    const Geometry gm = plan_geometry(wpg, dmax, L, max_block, df.lds_cap);
+    bk->tt = gm.tt;
+    bk->xlds = gm.xlds;
+    bk->nb = gm.nb;
+    bk->lds = gm.lds;
 
     const int64_t S = bk->lay.nslots;
     const int G = bk->lay.groups;
@@ -435,7 +481,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     A(dalloc(&bk->a32, S)); A(dalloc(&bk->b32, S)); A(dalloc(&bk->xoff, S)); A(dalloc(&bk->flags, S));
     A(dalloc(&bk->slot_filter, S)); A(dalloc(&bk->aL, S)); A(dalloc(&bk->dL, S)); A(dalloc(&bk->a64, S));
-    A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->waves, (size_t)G * wpg));
+    A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->rows, (size_t)G * wpg * 4));
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
     A(dalloc(&bk->keys, (size_t)G * max_block));
     A(dalloc(&bk->ysub, (size_t)((L + kSub - 1) / kSub) * S));
@@ -448,7 +494,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     if (!rc) {
         e = hipMemcpy(bk->slot_filter, bk->lay.slot_filter.data(), S * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(bk->waves, bk->lay.waves.data(), bk->lay.waves.size() * sizeof(WaveInfo),
+            e = hipMemcpy(bk->rows, bk->lay.rows.data(), bk->lay.rows.size() * sizeof(RowInfo),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(bk->state, 0, S * sizeof(float4));
         if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[0], 0, (size_t)dmax * sizeof(float));
@@ -472,7 +518,7 @@ int ensure_xwin(spiir_bank *bk, int64_t need) {
     HIPCHK(hipDeviceSynchronize());
     dfree(bk->xwin);
     bk->xwin_cap = 0;
-    HIPCHK(dalloc(&bk->xwin, (size_t)need));
+    HIPCHK(dalloc(&bk->xwin, (size_t)need + 16));  // one tile of read-ahead padding
     bk->xwin_cap = need;
     return SPIIR_OK;
 }
@@ -504,7 +550,7 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.keys = bk->keys;
             a.ld = bk->max_block;
         }
-        HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->xlds, bk->lay.groups, bk->lds, st));
+        HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st));
         if (mode == kModeKeys)
             HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st));
     }
@@ -714,7 +760,7 @@ int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, fl
             a.ld = n;
             a.only_tpl = j;
             a.gbase = bk->lay.tpl_group[j];
-            HIPCHK(launch_forward(a, kModeSnr, bk->lay.fl, bk->xlds, 1, bk->lds, st));
+            HIPCHK(launch_forward(a, kModeSnr, bk->lay.fl, bk->tt, bk->xlds, 1, bk->lds, st));
         }
     }
     HIPCHK(launch_rows_argmax(snr, bk->T, n, n, mx, am, st));
@@ -739,7 +785,7 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
         tp->coeff_version = bk->coeff_version;
         tp->n = n;
         tp->nchunks = (n + bk->L - 1) / bk->L;
-        hipError_t e = dalloc(&tp->xwin, (size_t)(n + bk->dmax));
+        hipError_t e = dalloc(&tp->xwin, (size_t)(n + bk->dmax) + 16);  // read-ahead padding
         if (e == hipSuccess && tape_out) e = dalloc(&tp->tape, (size_t)(tp->nchunks * bk->lay.nslots));
         if (e != hipSuccess) {
             dfree(tp->xwin);
@@ -769,7 +815,7 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
         a.ld = n;
         a.tape = tp ? tp->tape : nullptr;
         a.chunk0 = P / bk->L;
-        e = launch_forward(a, kModeZ, bk->lay.fl, bk->xlds, bk->lay.groups, bk->lds, st);
+        e = launch_forward(a, kModeZ, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st);
     }
     if (e != hipSuccess) {
         if (tp) {
@@ -798,7 +844,7 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     BwdArgs a;
     std::memset(&a, 0, sizeof a);
     a.s = bk->slots();
-    a.waves = bk->waves;
+    a.rows = bk->rows;
     a.slot_filter = bk->slot_filter;
     a.tape = tp->tape;
     a.xwin = tp->xwin;
@@ -839,8 +885,9 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
         if (!banks[s] || !x[s] || !mx[s] || !am[s]) return fail(SPIIR_EINVAL, "null entry for stream %d", s);
         if (lengths[s] < 1) return fail(SPIIR_EINVAL, "stream %d has length < 1", s);
         if (banks[s]->device != banks[0]->device) return fail(SPIIR_EINVAL, "banks on different devices");
-        if (banks[s]->lay.fl != banks[0]->lay.fl || banks[s]->lay.wpg != banks[0]->lay.wpg)
-            return fail(SPIIR_EINVAL, "banks must share filters_per_lane and waves_per_group");
+        if (banks[s]->lay.fl != banks[0]->lay.fl || banks[s]->lay.wpg != banks[0]->lay.wpg ||
+            banks[s]->tt != banks[0]->tt)
+            return fail(SPIIR_EINVAL, "banks must share filters_per_lane, waves_per_group and tile length");
         if (!banks[s]->xlds) return fail(SPIIR_EINVAL, "bank %d keeps its strain window outside LDS", s);
         for (int t = 0; t < s; ++t)
             if (banks[t] == banks[s]) return fail(SPIIR_EINVAL, "a bank appears twice in the batch");
@@ -853,6 +900,7 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
     bt->B = B;
     bt->fl = banks[0]->lay.fl;
     bt->wpg = banks[0]->lay.wpg;
+    bt->tt = banks[0]->tt;
     bt->banks.assign(banks, banks + ns);
     bt->len.assign(lengths, lengths + ns);
     int max_groups = 0;
@@ -901,15 +949,15 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
         A(hipMemset(bt->counter, 0, sizeof(int)));
         A(hipMemset(bt->pos, 0, ns * sizeof(int64_t)));
     }
-    const int occ = std::max(1, batch_occupancy(bt->fl, bt->wpg, bt->lds));
+    const int occ = std::max(1, batch_occupancy(bt->fl, bt->tt, bt->wpg, bt->lds));
     bt->grid = std::min(bt->nitems, banks[0]->dev.n_cu * occ);
     hipStream_t cap = nullptr;
     if (e == hipSuccess) A(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     if (e == hipSuccess) {
         A(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         if (e == hipSuccess) {
-            A(launch_batch(bt->streams, bt->items, bt->nitems, bt->counter, bt->pos, B, bt->fl, bt->grid,
-                           bt->wpg, bt->lds, cap));
+            A(launch_batch(bt->streams, bt->items, bt->nitems, bt->counter, bt->pos, B, bt->fl, bt->tt,
+                           bt->grid, bt->wpg, bt->lds, cap));
             A(launch_batch_finalize(bt->streams, ns, bt->keys, bt->key_stride, bt->pos, B, max_groups, cap));
             A(launch_batch_advance(bt->pos, bt->streams, ns, bt->counter, B, cap));
             hipGraph_t g = nullptr;
@@ -1043,20 +1091,20 @@ int spiir_autotune(int32_t nbk, const int32_t *T, const int64_t *const *off, con
         for (int fl = 1; fl <= 4; ++fl) {
             if (table) table[li * 4 + fl - 1] = -1.f;
             int64_t total = 0;
-            int maxnw = 0;
+            int maxnr = 0;
             for (int i = 0; i < nbk; ++i) {
-                const Plan p = plan_waves(T[i], off[i], fl);
-                total += p.total_waves;
-                maxnw = std::max(maxnw, p.max_nw);
+                const Plan p = plan_rows(T[i], off[i], fl);
+                total += p.total_rows;
+                maxnr = std::max(maxnr, p.max_nr);
             }
-            if (maxnw > kMaxWaves) continue;
+            if (maxnr > 4 * kMaxWaves) continue;
             spiir_bank_opts o;
             spiir_bank_opts_default(&o);
             o.chunk_len = Ls[li];
             o.filters_per_lane = fl;
             o.max_delay = max_delay;
             o.device = dev;
-            o.waves_per_group = auto_wpg(total, maxnw, df.n_cu);
+            o.waves_per_group = auto_wpg(total, maxnr, df.n_cu);
             std::vector<spiir_bank *> bks(nbk, nullptr);
             bool ok = true;
             for (int i = 0; i < nbk && ok; ++i)

@@ -44,6 +44,11 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ float dpp_swap_pairs(float v) {
+    // quad_perm [1,0,3,2]: the value of lane ^ 1
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ int64_t slot_index(int g, int wpg, int wave, int f, int fl, int lane) {
     return ((int64_t)(g * wpg + wave) * fl + f) * 64 + lane;
 }
@@ -52,30 +57,49 @@ __device__ __forceinline__ int64_t slot_index(int g, int wpg, int wave, int f, i
 template <int FL>
 struct Lane {
     float ar[FL], ai[FL], br[FL], bi[FL];
-    int xo[FL], fl[FL];
+    int xo[FL];
     float yr[FL], yi[FL];     // running state (FP32)
     float y0r[FL], y0i[FL];   // state at the chunk start (hi part)
     float l0r[FL], l0i[FL];   // low part of the chunk-start carry
-    int64_t slot[FL];
+    unsigned flags;           // bit f: slot f carries in FP64 (hybrid mode)
+    int64_t slot0;            // slot of filter f is slot0 + 64 f
+    __device__ __forceinline__ int64_t slot(int f) const { return slot0 + 64 * f; }
 };
 
-// One tile of time steps: FL filter updates per step and per lane, the lane's
-// partial template sum written to the wave's LDS tile.
-template <int FL, bool FULL, typename XP>
-__device__ __forceinline__ void compute_tile(Lane<FL> &s, XP xw, int t0, int steps,
-                                             float2 *wt, int lane) {
-    XP xp[FL];
+constexpr int kAhead = 2;  // steps of x[m - d] read ahead of their use
+
+// x[m - d] of every filter for steps t0 .. t0 + kAhead - 1 of a tile. The
+// window is padded by one tile, so reads past the sub-block end stay inside it
+// (their values are never used).
+template <int FL, int TT>
+__device__ __forceinline__ void load_ahead(float (&xv)[TT][FL], const float *xw, const Lane<FL> &s, int t0) {
 #pragma unroll
-    for (int f = 0; f < FL; ++f) xp[f] = xw + (s.xo[f] + t0);
+    for (int f = 0; f < FL; ++f) {
+        const float *xp = xw + (s.xo[f] + t0);
 #pragma unroll
-    for (int t = 0; t < kTile; ++t) {
-        if (!FULL && t >= steps) break;
+        for (int t = 0; t < kAhead; ++t) xv[t][f] = xp[t];
+    }
+}
+
+// One tile: FL filter updates per step and per lane, the lane's partial
+// template sum of every step written to the wave's LDS tile [TT][64]. x for
+// step t + kAhead is read while step t computes (xv[0..kAhead) arrive loaded).
+template <int FL, int TT, bool FULL>
+__device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], const float *xw, int t0,
+                                             int steps, float2 *wt, int lane) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+        if (t + kAhead < TT) {
+#pragma unroll
+            for (int f = 0; f < FL; ++f) xv[t + kAhead][f] = xw[s.xo[f] + t0 + t + kAhead];
+        }
+        if (!FULL && t >= steps) continue;  // uniform; keeps every index static
         float pr = 0.f, pi = 0.f;
 #pragma unroll
         for (int f = 0; f < FL; ++f) {
-            const float xv = xp[f][t];
-            const float nr = fmaf(-s.ai[f], s.yi[f], fmaf(s.ar[f], s.yr[f], s.br[f] * xv));
-            const float ni = fmaf(s.ai[f], s.yr[f], fmaf(s.ar[f], s.yi[f], s.bi[f] * xv));
+            const float xv_ = xv[t][f];
+            const float nr = fmaf(-s.ai[f], s.yi[f], fmaf(s.ar[f], s.yr[f], s.br[f] * xv_));
+            const float ni = fmaf(s.ai[f], s.yr[f], fmaf(s.ar[f], s.yi[f], s.bi[f] * xv_));
             s.yr[f] = nr;
             s.yi[f] = ni;
             if (f == 0) {
@@ -90,6 +114,62 @@ __device__ __forceinline__ void compute_tile(Lane<FL> &s, XP xw, int t0, int ste
     }
 }
 
+// Row sums of a wave tile: wsum[t][4 * wave + r] = sum of the 16 lanes of row r
+// at step t. Lane L reads its row's 16-byte chunks in a lane-rotated order
+// (offsets precomputed by row_sum_offsets) so that the 8 / 16 lanes served by
+// the LDS in one cycle touch distinct banks.
+template <int TT>
+struct RowSumPlan {
+    static constexpr int kChunks = TT == 16 ? 8 : 4;
+    int off[kChunks];   // byte offsets of the chunks inside the wave tile, in read order
+    int t, r;           // step and row this lane sums
+};
+
+template <int TT>
+__device__ __forceinline__ RowSumPlan<TT> row_sum_plan(int lane) {
+    RowSumPlan<TT> pl;
+    if (TT == 16) {
+        pl.t = lane >> 2;
+        pl.r = lane & 3;
+        const int rot = (lane + (lane >> 3)) & 7;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pl.off[i] = (pl.t * 64 + pl.r * 16) * 8 + ((i + rot) & 7) * 16;
+    } else {
+        pl.t = lane >> 3;
+        const int part = lane & 7;
+        pl.r = part >> 1;
+        const int rot = ((part >> 1) + pl.t) & 3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pl.off[i] = (pl.t * 64 + part * 8) * 8 + ((i + rot) & 3) * 16;
+    }
+    return pl;
+}
+
+template <int TT>
+__device__ __forceinline__ void row_sums(const float2 *wt, const RowSumPlan<TT> &pl, float2 *wsum_buf,
+                                         int Rp, int wave, int lane) {
+    const char *base = reinterpret_cast<const char *>(wt);
+    if (TT == 16) {
+        float4 v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
+        float sr = (((v[0].x + v[0].z) + (v[1].x + v[1].z)) + ((v[2].x + v[2].z) + (v[3].x + v[3].z))) +
+                   (((v[4].x + v[4].z) + (v[5].x + v[5].z)) + ((v[6].x + v[6].z) + (v[7].x + v[7].z)));
+        float si = (((v[0].y + v[0].w) + (v[1].y + v[1].w)) + ((v[2].y + v[2].w) + (v[3].y + v[3].w))) +
+                   (((v[4].y + v[4].w) + (v[5].y + v[5].w)) + ((v[6].y + v[6].w) + (v[7].y + v[7].w)));
+        wsum_buf[pl.t * Rp + wave * 4 + pl.r] = make_float2(sr, si);
+    } else {
+        float4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
+        const float sr = ((v[0].x + v[0].z) + (v[1].x + v[1].z)) + ((v[2].x + v[2].z) + (v[3].x + v[3].z));
+        const float si = ((v[0].y + v[0].w) + (v[1].y + v[1].w)) + ((v[2].y + v[2].w) + (v[3].y + v[3].w));
+        // the two halves of a row sit in lanes 2k and 2k+1
+        const float or_ = dpp_swap_pairs(sr), oi = dpp_swap_pairs(si);
+        if ((lane & 1) == 0) wsum_buf[pl.t * Rp + wave * 4 + pl.r] = make_float2(sr + or_, si + oi);
+    }
+}
+
 // Chunk-end correction of the carried state (len = samples in the chunk).
 template <int FL>
 __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa, int prec,
@@ -100,15 +180,15 @@ __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa,
         if (prec != kPrecFp32) {
             double2 al, dl;
             if (len == L) {
-                al = sa.aL[s.slot[f]];
-                dl = sa.dL[s.slot[f]];
+                al = sa.aL[s.slot(f)];
+                dl = sa.dL[s.slot(f)];
             } else {
-                const double2 a = sa.a64[s.slot[f]];
+                const double2 a = sa.a64[s.slot(f)];
                 al = cpow64(a, len);
                 const double2 ah = cpow64(make_double2((double)s.ar[f], (double)s.ai[f]), len);
                 dl = make_double2(al.x - ah.x, al.y - ah.y);
             }
-            if (prec == kPrecFp64 || (s.fl[f] & 1)) {
+            if (prec == kPrecFp64 || ((s.flags >> f) & 1u)) {
                 // c_end = y_end + (a^l - fl(a)^l) * hi_start + a^l * lo_start, in FP64
                 const double y0r = s.y0r[f], y0i = s.y0i[f], l0r = s.l0r[f], l0i = s.l0i[f];
                 const double cr = (double)hr + (dl.x * y0r - dl.y * y0i) + (al.x * l0r - al.y * l0i);
@@ -133,45 +213,50 @@ __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa,
 }
 
 // The whole forward pass of workgroup g over p.n samples.
-template <int FL, int MODE, bool XLDS>
+template <int FL, int TT, int MODE, bool XLDS>
 __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int W = p.wpg;
-    const size_t win_bytes = XLDS ? (size_t)((p.dmax + p.nb + 3) & ~3) * 4 : 0;
+    const int W = p.wpg, R = 4 * W, Rp = R + 1;  // odd row stride of wsum: no bank aliasing over t
+    const size_t win_bytes = XLDS ? (size_t)((p.dmax + p.nb + TT + 3) & ~3) * 4 : 0;
     float *xs = reinterpret_cast<float *>(smem);
-    float2 *wt = reinterpret_cast<float2 *>(smem + win_bytes) + wave * kTile * 64;
-    float2 *wsum = reinterpret_cast<float2 *>(smem + win_bytes) + W * kTile * 64;  // [2][kTile][W]
-    unsigned long long *kmax = reinterpret_cast<unsigned long long *>(wsum + 2 * kTile * W);
+    float2 *wt = reinterpret_cast<float2 *>(smem + win_bytes) + wave * TT * 64;
+    float2 *wsum = reinterpret_cast<float2 *>(smem + win_bytes) + W * TT * 64;  // [2][TT][Rp]
+    unsigned long long *kmax = reinterpret_cast<unsigned long long *>(wsum + 2 * TT * Rp);  // [2][TT]
+    const RowSumPlan<TT> rsp = row_sum_plan<TT>(lane);
 
-    const WaveInfo wi = p.waves[g * W + wave];
-    const bool active = wi.tpl >= 0 && (p.only_tpl < 0 || wi.tpl == p.only_tpl);
-    const bool leader = active && wi.w0 == wave;
+    const int row = wave * 4 + (lane >> 4);
+    const RowInfo ri = p.rows[(int64_t)g * R + row];
+    const bool ract = ri.tpl >= 0 && (p.only_tpl < 0 || ri.tpl == p.only_tpl);
+    const bool wact = __ballot(ract) != 0;
+    const int tl16 = lane & 15;
+    const bool leader = ract && ri.r0 == row && tl16 < TT;
 
     Lane<FL> s;
+    s.slot0 = slot_index(g, W, wave, 0, FL, lane);
+    s.flags = 0u;
 #pragma unroll
     for (int f = 0; f < FL; ++f) {
-        s.slot[f] = slot_index(g, W, wave, f, FL, lane);
-        if (active) {
-            const float2 a = p.s.a32[s.slot[f]], b = p.s.b32[s.slot[f]];
+        if (ract) {
+            const float2 a = p.s.a32[s.slot(f)], b = p.s.b32[s.slot(f)];
             s.ar[f] = a.x; s.ai[f] = a.y; s.br[f] = b.x; s.bi[f] = b.y;
-            s.xo[f] = p.s.xoff[s.slot[f]];
-            s.fl[f] = p.s.flags[s.slot[f]];
+            s.xo[f] = p.s.xoff[s.slot(f)];
+            s.flags |= (unsigned)(p.s.flags[s.slot(f)] & 1) << f;
             float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (p.state) st = p.state[s.slot[f]];
+            if (p.state) st = p.state[s.slot(f)];
             s.yr[f] = st.x; s.yi[f] = st.y; s.l0r[f] = st.z; s.l0i[f] = st.w;
         } else {
             s.ar[f] = s.ai[f] = s.br[f] = s.bi[f] = 0.f;
-            s.xo[f] = 0; s.fl[f] = 0;
+            s.xo[f] = 0;
             s.yr[f] = s.yi[f] = s.l0r[f] = s.l0i[f] = 0.f;
         }
         s.y0r[f] = s.yr[f];
         s.y0i[f] = s.yi[f];
     }
-    if (MODE == kModeKeys && tid < 2 * kTile) kmax[tid] = 0ull;
-    if (MODE == kModeZ && active && p.tape) {
+    if (MODE == kModeKeys && tid < 2 * TT) kmax[tid] = 0ull;
+    if (MODE == kModeZ && ract && p.tape) {
 #pragma unroll
         for (int f = 0; f < FL; ++f)
-            p.tape[(int64_t)p.chunk0 * p.nslots + s.slot[f]] =
+            p.tape[(int64_t)p.chunk0 * p.nslots + s.slot(f)] =
                 make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
     }
 
@@ -181,6 +266,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
     bool pending = false;
     int64_t pend_t = 0;
     int pend_steps = 0;
+    float xv[TT][FL];
 
     for (int64_t s0 = 0; s0 < p.n; s0 += p.nb) {
         const int nbs = (int)min((int64_t)p.nb, p.n - s0);
@@ -198,53 +284,49 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
         } else {
             xw = p.xwin + (p.xbase + s0);
         }
+        if (wact) load_ahead<FL, TT>(xv, xw, s, 0);
 
-        for (int t0 = 0; t0 < nbs; t0 += kTile) {
-            const int steps = min(kTile, nbs - t0);
-            if (active) {
-                if (steps == kTile)
-                    compute_tile<FL, true>(s, xw, t0, steps, wt, lane);
+        for (int t0 = 0; t0 < nbs; t0 += TT) {
+            const int steps = min(TT, nbs - t0);
+            if (wact) {
+                if (steps == TT)
+                    compute_tile<FL, TT, true>(s, xv, xw, t0, steps, wt, lane);
                 else
-                    compute_tile<FL, false>(s, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, false>(s, xv, xw, t0, steps, wt, lane);
                 wave_lds_sync();
-                // wave-local transpose-reduce: lane (t, part) sums 8 lanes of step t
-                const int t = lane >> 3, part = lane & 7;
-                const float4 *src = reinterpret_cast<const float4 *>(wt + t * 64 + part * 8);
-                const float4 v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
-                float sr = ((v0.x + v0.z) + (v1.x + v1.z)) + ((v2.x + v2.z) + (v3.x + v3.z));
-                float si = ((v0.y + v0.w) + (v1.y + v1.w)) + ((v2.y + v2.w) + (v3.y + v3.w));
-                sr += __shfl_xor(sr, 1, 8);
-                si += __shfl_xor(si, 1, 8);
-                sr += __shfl_xor(sr, 2, 8);
-                si += __shfl_xor(si, 2, 8);
-                sr += __shfl_xor(sr, 4, 8);
-                si += __shfl_xor(si, 4, 8);
-                if (part == 0) wsum[(buf * kTile + t) * W + wave] = make_float2(sr, si);
+                row_sums<TT>(wt, rsp, wsum + buf * TT * Rp, Rp, wave, lane);
+                if (t0 + TT < nbs) load_ahead<FL, TT>(xv, xw, s, t0 + TT);
             }
             __syncthreads();
             if (MODE == kModeKeys && pending && wave == 0 && lane < pend_steps) {
                 const int pb = buf ^ 1;
-                p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * kTile + lane];
-                kmax[pb * kTile + lane] = 0ull;
+                p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * TT + lane];
+                kmax[pb * TT + lane] = 0ull;
             }
-            if (leader && lane < steps) {
-                const float2 *ws = wsum + (buf * kTile + lane) * W;
-                float zr = ws[wi.w0].x, zi = ws[wi.w0].y;
-                for (int w = 1; w < wi.nw; ++w) {
-                    zr += ws[wi.w0 + w].x;
-                    zi += ws[wi.w0 + w].y;
+            if (leader && tl16 < steps) {
+                const float2 *ws = wsum + (buf * TT + tl16) * Rp + ri.r0;
+                float zr = 0.f, zi = 0.f;
+                int r = 0;
+                for (; r + 4 <= ri.nr; r += 4) {
+                    const float2 v0 = ws[r], v1 = ws[r + 1], v2 = ws[r + 2], v3 = ws[r + 3];
+                    zr += (v0.x + v1.x) + (v2.x + v3.x);
+                    zi += (v0.y + v1.y) + (v2.y + v3.y);
                 }
-                const int64_t tl = s0 + t0 + lane;
+                for (; r < ri.nr; ++r) {
+                    zr += ws[r].x;
+                    zi += ws[r].y;
+                }
+                const int64_t tl = s0 + t0 + tl16;
                 if (MODE == kModeSnr) {
-                    p.snr[(int64_t)wi.tpl * p.ld + p.obase + tl] = zr * zr + zi * zi;
+                    p.snr[(int64_t)ri.tpl * p.ld + p.obase + tl] = zr * zr + zi * zi;
                 } else if (MODE == kModeZ) {
-                    p.z[(int64_t)wi.tpl * p.ld + p.obase + tl] = make_float2(zr, zi);
+                    p.z[(int64_t)ri.tpl * p.ld + p.obase + tl] = make_float2(zr, zi);
                 } else {
                     const float sn = zr * zr + zi * zi;
                     const unsigned long long key =
                         ((unsigned long long)__float_as_uint(sn) << 32) |
-                        (unsigned long long)(0xFFFFFFFFu - (uint32_t)wi.tpl);
-                    atomicMax(&kmax[buf * kTile + lane], key);
+                        (unsigned long long)(0xFFFFFFFFu - (uint32_t)ri.tpl);
+                    atomicMax(&kmax[buf * TT + tl16], key);
                 }
             }
             if (MODE == kModeKeys) {
@@ -254,12 +336,12 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
             }
             const int64_t tend = s0 + t0 + steps;
             if (tend - chunk_start == p.L || tend == p.n) {
-                if (active) {
+                if (wact) {
                     carry_correct<FL>(s, p.s, p.prec, (int)(tend - chunk_start), p.L);
-                    if (MODE == kModeZ && p.tape && tend < p.n) {
+                    if (MODE == kModeZ && ract && p.tape && tend < p.n) {
 #pragma unroll
                         for (int f = 0; f < FL; ++f)
-                            p.tape[(p.chunk0 + chunk_idx + 1) * p.nslots + s.slot[f]] =
+                            p.tape[(p.chunk0 + chunk_idx + 1) * p.nslots + s.slot(f)] =
                                 make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
                     }
                 }
@@ -273,29 +355,29 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
         __syncthreads();
         if (pending && wave == 0 && lane < pend_steps) {
             const int pb = buf ^ 1;
-            p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * kTile + lane];
-            kmax[pb * kTile + lane] = 0ull;
+            p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * TT + lane];
+            kmax[pb * TT + lane] = 0ull;
         }
     }
-    if (active && p.state) {
+    if (ract && p.state) {
 #pragma unroll
         for (int f = 0; f < FL; ++f)
-            p.state[s.slot[f]] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+            p.state[s.slot(f)] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
     }
 }
 
-template <int FL, int MODE, bool XLDS>
-__global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs p) {
+template <int FL, int TT, int MODE, bool XLDS>
+__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_group<FL, MODE, XLDS>(p, p.gbase + blockIdx.x, smem);
+    fwd_group<FL, TT, MODE, XLDS>(p, p.gbase + blockIdx.x, smem);
 }
 
 // Persistent batch kernel: workgroups pop (stream, group) items until the list
 // is exhausted; every item is one block of one stream for one group.
-template <int FL>
-__global__ void __launch_bounds__(1024) batch_kernel(const BatchStream *streams, const int2 *items,
-                                                     int nitems, int *counter, const int64_t *pos,
-                                                     int block_len) {
+template <int FL, int TT>
+__global__ void __launch_bounds__(512) batch_kernel(const BatchStream *streams, const int2 *items,
+                                                    int nitems, int *counter, const int64_t *pos,
+                                                    int block_len) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int item_s;
     for (;;) {
@@ -314,21 +396,29 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchStream *streams,
         a.xbase = p0;
         a.n = min((int64_t)block_len, len - p0);
         a.ld = block_len;
-        fwd_group<FL, kModeKeys, true>(a, g, smem);
+        fwd_group<FL, TT, kModeKeys, true>(a, g, smem);
     }
 }
 
-__global__ void finalize_keys_kernel(const uint64_t *keys, int groups, int64_t ld, int64_t n,
-                                     float *mx, int32_t *am) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Max over workgroup partial keys: 16 samples x 16 group slices per block.
+__global__ void __launch_bounds__(256) finalize_keys_kernel(const uint64_t *keys, int groups, int64_t ld,
+                                                            int64_t n, float *mx, int32_t *am) {
+    __shared__ uint64_t red[16][17];
+    const int si = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int64_t i = (int64_t)blockIdx.x * 16 + si;
     uint64_t k = 0;
-    for (int g = 0; g < groups; ++g) {
-        const uint64_t v = keys[(int64_t)g * ld + i];
-        k = v > k ? v : k;
+    if (i < n)
+        for (int g = q; g < groups; g += 16) {
+            const uint64_t v = keys[(int64_t)g * ld + i];
+            k = v > k ? v : k;
+        }
+    red[q][si] = k;
+    __syncthreads();
+    if (q == 0 && i < n) {
+        for (int r = 1; r < 16; ++r) k = red[r][si] > k ? red[r][si] : k;
+        mx[i] = __uint_as_float((uint32_t)(k >> 32));
+        am[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
     }
-    mx[i] = __uint_as_float((uint32_t)(k >> 32));
-    am[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
 }
 
 __global__ void rows_argmax_kernel(const float *snr, int T, int64_t ld, int64_t n, float *mx,
@@ -391,11 +481,11 @@ __global__ void __launch_bounds__(256) bwd_kernel(BwdArgs p) {
     const int waves_per_block = blockDim.x >> 6;
     const int gw = blockIdx.x * waves_per_block + wave_in_block;  // global wave
     const int g = gw / p.wpg, wave = gw % p.wpg;
-    const WaveInfo wi = p.waves[gw];
-    if (wi.tpl < 0) return;
+    const RowInfo ri = p.rows[(int64_t)g * 4 * p.wpg + wave * 4 + (lane >> 4)];
+    if (ri.tpl < 0) return;
     const int64_t n = p.n;
     const int64_t nch = (n + p.L - 1) / p.L;
-    const float2 *gz = p.gz + (int64_t)wi.tpl * n;
+    const float2 *gz = p.gz + (int64_t)ri.tpl * n;
     for (int f = 0; f < FL; ++f) {
         const int64_t slot = slot_index(g, p.wpg, wave, f, FL, lane);
         const int k = p.slot_filter[slot];
@@ -487,22 +577,31 @@ __global__ void __launch_bounds__(256) bwd_kernel(BwdArgs p) {
 }
 
 // Batch bookkeeping.
-__global__ void batch_finalize_kernel(const BatchStream *streams, const uint64_t *keys,
-                                      int64_t key_stride, const int64_t *pos, int block_len) {
+__global__ void __launch_bounds__(256) batch_finalize_kernel(const BatchStream *streams, const uint64_t *keys,
+                                                             int64_t key_stride, const int64_t *pos,
+                                                             int block_len) {
+    __shared__ uint64_t red[16][17];
     const int sidx = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int si = threadIdx.x & 15, q = threadIdx.x >> 4;
+    const int64_t i = (int64_t)blockIdx.x * 16 + si;
     const int64_t p0 = pos[sidx];
     const int64_t len = streams[sidx].len;
-    if (p0 >= len || i >= min((int64_t)block_len, len - p0)) return;
+    const bool live = p0 < len && i < min((int64_t)block_len, len - p0);
     const uint64_t *kk = keys + sidx * key_stride;
     const int groups = streams[sidx].groups;
     uint64_t k = 0;
-    for (int g = 0; g < groups; ++g) {
-        const uint64_t v = kk[(int64_t)g * block_len + i];
-        k = v > k ? v : k;
+    if (live)
+        for (int g = q; g < groups; g += 16) {
+            const uint64_t v = kk[(int64_t)g * block_len + i];
+            k = v > k ? v : k;
+        }
+    red[q][si] = k;
+    __syncthreads();
+    if (q == 0 && live) {
+        for (int r = 1; r < 16; ++r) k = red[r][si] > k ? red[r][si] : k;
+        streams[sidx].max_out[p0 + i] = __uint_as_float((uint32_t)(k >> 32));
+        streams[sidx].arg_out[p0 + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
     }
-    streams[sidx].max_out[p0 + i] = __uint_as_float((uint32_t)(k >> 32));
-    streams[sidx].arg_out[p0 + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
 }
 
 __global__ void batch_advance_kernel(int64_t *pos, const BatchStream *streams, int nstreams,
@@ -515,55 +614,86 @@ __global__ void batch_advance_kernel(int64_t *pos, const BatchStream *streams, i
     }
 }
 
-template <int FL, int MODE, bool XLDS>
+template <int FL, int TT, int MODE, bool XLDS>
 hipError_t launch_fwd_t(const FwdArgs &a, int groups, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((fwd_kernel<FL, MODE, XLDS>), dim3(groups), dim3(a.wpg * 64), lds, st, a);
+    hipLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS>), dim3(groups), dim3(a.wpg * 64), lds, st, a);
     return hipGetLastError();
 }
 
-template <int MODE, bool XLDS>
+template <int TT, int MODE, bool XLDS>
 hipError_t launch_fwd_m(const FwdArgs &a, int fl, int groups, size_t lds, hipStream_t st) {
     switch (fl) {
-        case 1: return launch_fwd_t<1, MODE, XLDS>(a, groups, lds, st);
-        case 2: return launch_fwd_t<2, MODE, XLDS>(a, groups, lds, st);
-        case 3: return launch_fwd_t<3, MODE, XLDS>(a, groups, lds, st);
-        case 4: return launch_fwd_t<4, MODE, XLDS>(a, groups, lds, st);
+        case 1: return launch_fwd_t<1, TT, MODE, XLDS>(a, groups, lds, st);
+        case 2: return launch_fwd_t<2, TT, MODE, XLDS>(a, groups, lds, st);
+        case 3: return launch_fwd_t<3, TT, MODE, XLDS>(a, groups, lds, st);
+        case 4: return launch_fwd_t<4, TT, MODE, XLDS>(a, groups, lds, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int TT, bool XLDS>
+hipError_t launch_fwd_x(const FwdArgs &a, int mode, int fl, int groups, size_t lds, hipStream_t st) {
+    switch (mode) {
+        case kModeSnr: return launch_fwd_m<TT, kModeSnr, XLDS>(a, fl, groups, lds, st);
+        case kModeKeys: return launch_fwd_m<TT, kModeKeys, XLDS>(a, fl, groups, lds, st);
+        case kModeZ: return launch_fwd_m<TT, kModeZ, XLDS>(a, fl, groups, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int FL, int TT>
+int occ_t(int wpg, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<FL, TT, kModeKeys, true>, wpg * 64, lds) !=
+        hipSuccess)
+        return 0;
+    return nb;
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
 
-size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds) {
-    size_t win = x_in_lds ? (size_t)((dmax + nb + 3) & ~3) * 4 : 0;
-    return win + (size_t)wpg * kTile * 64 * 8 + (size_t)2 * kTile * wpg * 8 + (size_t)2 * kTile * 8;
+size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt) {
+    const size_t win = x_in_lds ? (size_t)((dmax + nb + tt + 3) & ~3) * 4 : 0;
+    return win + (size_t)wpg * tt * 64 * 8 + (size_t)2 * tt * (4 * wpg + 1) * 8 + (size_t)2 * tt * 8;
 }
 
-hipError_t launch_forward(const FwdArgs &a, int mode, int fl, bool x_in_lds, int groups,
+hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
                           size_t lds, hipStream_t st) {
     if (groups <= 0) return hipSuccess;
-    if (x_in_lds) {
-        switch (mode) {
-            case kModeSnr: return launch_fwd_m<kModeSnr, true>(a, fl, groups, lds, st);
-            case kModeKeys: return launch_fwd_m<kModeKeys, true>(a, fl, groups, lds, st);
-            case kModeZ: return launch_fwd_m<kModeZ, true>(a, fl, groups, lds, st);
+    if (tt == 16)
+        return x_in_lds ? launch_fwd_x<16, true>(a, mode, fl, groups, lds, st)
+                        : launch_fwd_x<16, false>(a, mode, fl, groups, lds, st);
+    if (tt == 8)
+        return x_in_lds ? launch_fwd_x<8, true>(a, mode, fl, groups, lds, st)
+                        : launch_fwd_x<8, false>(a, mode, fl, groups, lds, st);
+    return hipErrorInvalidValue;
+}
+
+int forward_occupancy(int fl, int tt, int wpg, size_t lds) {
+    if (tt == 16) {
+        switch (fl) {
+            case 1: return occ_t<1, 16>(wpg, lds);
+            case 2: return occ_t<2, 16>(wpg, lds);
+            case 3: return occ_t<3, 16>(wpg, lds);
+            case 4: return occ_t<4, 16>(wpg, lds);
         }
     } else {
-        switch (mode) {
-            case kModeSnr: return launch_fwd_m<kModeSnr, false>(a, fl, groups, lds, st);
-            case kModeKeys: return launch_fwd_m<kModeKeys, false>(a, fl, groups, lds, st);
-            case kModeZ: return launch_fwd_m<kModeZ, false>(a, fl, groups, lds, st);
+        switch (fl) {
+            case 1: return occ_t<1, 8>(wpg, lds);
+            case 2: return occ_t<2, 8>(wpg, lds);
+            case 3: return occ_t<3, 8>(wpg, lds);
+            case 4: return occ_t<4, 8>(wpg, lds);
         }
     }
-    return hipErrorInvalidValue;
+    return 0;
 }
 
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_keys_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, keys, groups,
+    hipLaunchKernelGGL(finalize_keys_kernel, dim3(nblocks(n, 16)), dim3(256), 0, st, keys, groups,
                        ld, n, mx, am);
     return hipGetLastError();
 }
@@ -592,17 +722,26 @@ hipError_t launch_window_fill(float *xwin, const float *hist, const float *x, in
     return hipGetLastError();
 }
 
-int batch_occupancy(int fl, int wpg, size_t lds) {
+template <int FL, int TT>
+int bocc_t(int wpg, size_t lds) {
     int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (fl) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<1>, wpg * 64, lds); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<2>, wpg * 64, lds); break;
-        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<3>, wpg * 64, lds); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<4>, wpg * 64, lds); break;
-        default: break;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<FL, TT>, wpg * 64, lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+int batch_occupancy(int fl, int tt, int wpg, size_t lds) {
+    switch (fl * 100 + tt) {
+        case 108: return bocc_t<1, 8>(wpg, lds);
+        case 208: return bocc_t<2, 8>(wpg, lds);
+        case 308: return bocc_t<3, 8>(wpg, lds);
+        case 408: return bocc_t<4, 8>(wpg, lds);
+        case 116: return bocc_t<1, 16>(wpg, lds);
+        case 216: return bocc_t<2, 16>(wpg, lds);
+        case 316: return bocc_t<3, 16>(wpg, lds);
+        case 416: return bocc_t<4, 16>(wpg, lds);
+        default: return 0;
     }
-    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
@@ -635,25 +774,35 @@ hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int FL, int TT>
+hipError_t launch_batch_t(const BatchStream *streams, const int2 *items, int nitems, int *counter,
+                          const int64_t *pos, int block_len, int grid, int wpg, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((batch_kernel<FL, TT>), dim3(grid), dim3(wpg * 64), lds, st, streams, items, nitems,
+                       counter, pos, block_len);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitems, int *counter,
-                        const int64_t *pos, int block_len, int fl, int grid, int wpg, size_t lds,
+                        const int64_t *pos, int block_len, int fl, int tt, int grid, int wpg, size_t lds,
                         hipStream_t st) {
-    const dim3 g(grid), b(wpg * 64);
-    switch (fl) {
-        case 1: hipLaunchKernelGGL(batch_kernel<1>, g, b, lds, st, streams, items, nitems, counter, pos, block_len); break;
-        case 2: hipLaunchKernelGGL(batch_kernel<2>, g, b, lds, st, streams, items, nitems, counter, pos, block_len); break;
-        case 3: hipLaunchKernelGGL(batch_kernel<3>, g, b, lds, st, streams, items, nitems, counter, pos, block_len); break;
-        case 4: hipLaunchKernelGGL(batch_kernel<4>, g, b, lds, st, streams, items, nitems, counter, pos, block_len); break;
+    switch (fl * 100 + tt) {
+        case 108: return launch_batch_t<1, 8>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 208: return launch_batch_t<2, 8>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 308: return launch_batch_t<3, 8>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 408: return launch_batch_t<4, 8>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 116: return launch_batch_t<1, 16>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 216: return launch_batch_t<2, 16>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 316: return launch_batch_t<3, 16>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
+        case 416: return launch_batch_t<4, 16>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_batch_finalize(const BatchStream *streams, int nstreams, const uint64_t *keys,
                                  int64_t key_stride, const int64_t *pos, int block_len,
                                  int max_groups, hipStream_t st) {
     (void)max_groups;
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3(nblocks(block_len, 256), nstreams), dim3(256), 0,
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(nblocks(block_len, 16), nstreams), dim3(256), 0,
                        st, streams, keys, key_stride, pos, block_len);
     return hipGetLastError();
 }

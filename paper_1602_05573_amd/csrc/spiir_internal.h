@@ -6,18 +6,18 @@
 
 namespace spiir {
 
-constexpr int kTile = 8;        // time steps per template-sum tile
-constexpr int kMaxWaves = 16;   // 64-lane waves per workgroup (1024 threads)
+constexpr int kMaxWaves = 8;    // 64-lane waves per workgroup (512 threads)
+constexpr int kRowLanes = 16;   // lanes per row; a row serves exactly one template
 constexpr int kSub = 16;        // adjoint: steps kept in registers per recompute
 constexpr float kFlagRadius = 1.0f - 1e-5f;
 
 enum Mode { kModeSnr = 0, kModeKeys = 1, kModeZ = 2 };
 enum Prec { kPrecHybrid = 0, kPrecFp32 = 1, kPrecFp64 = 2 };
 
-// Per wave of a workgroup: the template it serves (-1: none), the first wave
-// of that template inside the workgroup and the number of its waves.
-struct WaveInfo {
-    int32_t tpl, w0, nw, pad;
+// Per 16-lane row of a workgroup: the template it serves (-1: none), the
+// first row of that template inside the workgroup and its number of rows.
+struct RowInfo {
+    int32_t tpl, r0, nr, pad;
 };
 
 // Per filter slot (lane-major inside each wave and slot column).
@@ -42,7 +42,7 @@ struct FwdArgs {
     int32_t dmax, L, nb, prec, wpg, only_tpl;
     int32_t gbase;        // group of blockIdx.x == 0
     int32_t pad0;
-    const WaveInfo *waves;  // [groups * wpg]
+    const RowInfo *rows;  // [groups * wpg * 4]
     int64_t obase;        // output column of launch sample 0
     int64_t ld;           // row length of snr / z / keys
     float *snr;           // kModeSnr: snr[tpl * ld + obase + t]
@@ -55,7 +55,7 @@ struct FwdArgs {
 
 struct BwdArgs {
     SlotArrays s;
-    const WaveInfo *waves;
+    const RowInfo *rows;
     const int32_t *slot_filter;  // slot -> caller filter index (-1 padding)
     const float4 *tape;          // [nchunks][nslots]
     const float *xwin;           // xwin[dmax + m] = x[m] for m in [-dmax, n)
@@ -77,9 +77,10 @@ struct BatchStream {
 };
 
 // Launch helpers (kernels.hip). All enqueue on `stream` and return the launch error.
-size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds);
-hipError_t launch_forward(const FwdArgs &a, int mode, int fl, bool x_in_lds, int groups,
+size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt);
+hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
                           size_t lds, hipStream_t stream);
+int forward_occupancy(int fl, int tt, int wpg, size_t lds);
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t stream);
 hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, float *mx,
@@ -88,11 +89,11 @@ hipError_t launch_hist_update(const float *old_h, float *new_h, const float *x, 
                               int dmax, hipStream_t stream);
 hipError_t launch_window_fill(float *xwin, const float *hist, const float *x, int64_t n,
                               int dmax, hipStream_t stream);
-int batch_occupancy(int fl, int wpg, size_t lds);
+int batch_occupancy(int fl, int tt, int wpg, size_t lds);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
 hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitems,
-                        int *counter, const int64_t *pos, int block_len, int fl, int grid,
+                        int *counter, const int64_t *pos, int block_len, int fl, int tt, int grid,
                         int wpg, size_t lds, hipStream_t stream);
 hipError_t launch_batch_finalize(const BatchStream *streams, int nstreams, const uint64_t *keys,
                                  int64_t key_stride, const int64_t *pos, int block_len,
