@@ -270,6 +270,20 @@ def autotune(banks, block_len: int = 4096, max_delay: int = 0, device: int = -1)
     return int(L.value), int(F.value), np.array(list(table), dtype=np.float64).reshape(4, 4)
 
 
+def batch_banks(banks, chunk_len: int, filters_per_lane: int, device: int = 0, **opts):
+    """SpiirBanks for several workloads.Bank objects with one common layout
+    (filters per lane, chunk length and workgroup size), as a batch needs.
+    The workgroup size spreads all banks' rows over the device's CUs."""
+    rows = lambda k: -(-int(k) // (16 * filters_per_lane))  # noqa: E731
+    total = sum(rows(k) for b in banks for k in np.diff(b.offsets))
+    max_nr = max(rows(k) for b in banks for k in np.diff(b.offsets))
+    n_cu = torch.cuda.get_device_properties(device).multi_processor_count
+    waves = -(-total // 4)
+    wpg = min(8, max(-(-waves // n_cu), -(-max_nr // 4)))
+    return [SpiirBank.from_bank(b, chunk_len=chunk_len, filters_per_lane=filters_per_lane,
+                                waves_per_group=wpg, device=device, **opts) for b in banks]
+
+
 class SpiirFn(torch.autograd.Function):
     """z = bank(x) from a cold start, differentiable in the coefficients.
 
@@ -301,4 +315,4 @@ def version() -> str:
     return load().spiir_version().decode()
 
 
-__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "autotune", "version", "_lib"]
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "autotune", "batch_banks", "version", "_lib"]

@@ -138,9 +138,10 @@ def config2(n_streams: int = 8, n_templates: int = 256, length_scale: float = 1.
 
 
 def config4(n: int = 16777216, n_templates: int = 64):
-    """64 templates x 1,000 filters, r ~ U[1-1e-6, 1-1e-4], d ~ U{0..2047},
-    16,777,216 samples."""
-    bank = random_bank(4, 0, n_templates, 1000, 1000, 1.0 - 1e-6, 1.0 - 1e-4, 2047)
+    """64 templates x 1,000 filters with poles between 1-1e-4 and 1-1e-6 in
+    radius (the interval is stated as [1-1e-6, 1-1e-4]; read as its sorted
+    form), d ~ U{0..2047}, 16,777,216 samples."""
+    bank = random_bank(4, 0, n_templates, 1000, 1000, 1.0 - 1e-4, 1.0 - 1e-6, 2047)
     return bank, strain(n, 4)
 
 
