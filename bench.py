@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("bank", "batch"), default="bank",
+    ap.add_argument("--workload", choices=("bank", "batch", "adjoint"), default="bank",
                     help="bank: the 1,024-template bank (default, the headline); "
                          "batch: 8 uneven streams with their own banks in one graph replay per block")
     ap.add_argument("--length-scale", type=float, default=1.0, help="batch: scale of the stream lengths")
@@ -91,6 +91,8 @@ def main():
         del src, dst
     if args.workload == "batch":
         return run_batch(args, torch)
+    if args.workload == "adjoint":
+        return run_adjoint(args, torch)
     return run_bank(args, torch)
 
 
@@ -297,6 +299,70 @@ def run_batch(args, torch):
     bt.close()
     for b in bks:
         b.close()
+    print(json.dumps(res), flush=True)
+
+
+def run_adjoint(args, torch):
+    """256 templates x 400 filters fitted to time-reversed chirps over 65,536
+    samples: forward_z with its carry tape, the overlap loss and its gradient
+    (torch, on the device), and the reverse-time adjoint (spiir_backward)."""
+    from paper_1602_05573_amd import SpiirBank
+    from workloads import config3
+
+    bank, x, gs, _ = config3()
+    F, T, N = bank.n_filters, bank.n_templates, len(x)
+    bk = SpiirBank.from_bank(bank)
+    xd = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(gs.astype(np.complex64)).cuda()
+    stream = torch.cuda.current_stream()
+
+    def upstream(z):
+        c = torch.sum(z * torch.conj(gt), dim=1)
+        Z = torch.linalg.norm(z, dim=1)
+        Gn = torch.linalg.norm(gt, dim=1)
+        ac = torch.abs(c)
+        return (-(1 / (Z * Gn))[:, None] * ((c / ac)[:, None] * gt - (ac / Z ** 2)[:, None] * z)).contiguous()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        z, tape = bk.forward_z(xd, want_tape=True)
+        if ev is not None:
+            ev[1].record(stream)
+        G = upstream(z)
+        if ev is not None:
+            ev[2].record(stream)
+        ga, gb = bk.backward(tape, G)
+        if ev is not None:
+            ev[3].record(stream)
+        torch.cuda.synchronize()
+        tape.close()
+        return ga
+
+    for _ in range(args.warmup):
+        step()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ts = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    t_total = time.perf_counter() - ts
+    fwd = np.mean([e[0].elapsed_time(e[1]) for e in evs])
+    loss = np.mean([e[1].elapsed_time(e[2]) for e in evs])
+    bwd = np.mean([e[2].elapsed_time(e[3]) for e in evs])
+    updates = float(F) * N
+    res = {
+        "metric": METRIC, "value": updates / ((fwd + bwd) * 1e-3), "unit": "filter-updates/s (forward + adjoint)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (leading-order chirps, chirp masses U[1,30])",
+        "config": {"workload": "adjoint fit: %d templates x 400 filters, %d samples, unit impulse input" % (T, N),
+                   "chunk_len": bk.info["chunk_len"], "filters_per_lane": bk.info["filters_per_lane"]},
+        "forward_ms": fwd, "loss_ms": loss, "backward_ms": bwd,
+        "forward_updates_per_s": updates / (fwd * 1e-3), "backward_updates_per_s": updates / (bwd * 1e-3),
+        "backward_tflops": 30.0 * updates / (bwd * 1e-3) / 1e12,
+    }
+    log("adjoint: forward %.2f ms, loss %.2f ms, backward %.2f ms" % (fwd, loss, bwd))
+    bk.close()
     print(json.dumps(res), flush=True)
 
 

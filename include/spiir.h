@@ -78,9 +78,15 @@ typedef struct {
     int32_t device;           /* HIP device ordinal; -1 = the current device */
     int32_t max_block;        /* most samples handled by one kernel launch (longer calls
                                  are split); 0 = 16384 */
-    int32_t waves_per_group;  /* 64-lane waves per workgroup, 1..16; 0 = automatic */
+    int32_t waves_per_group;  /* 64-lane waves per workgroup, 1..8; 0 = automatic */
     int32_t autotune;         /* 1: time the candidate (chunk_len, filters_per_lane)
                                  pairs on this bank and keep the fastest */
+    int32_t time_split;       /* segments each streaming launch is cut into when the bank
+                                 alone cannot fill the device: every segment is filtered
+                                 from rest in parallel, then the true segment-start states
+                                 follow from an FP64 carry chain and their free response is
+                                 added. 0 = automatic, 1 = off, 2..8 = forced. Not used in
+                                 SPIIR_PREC_FP32 mode nor by the per-template comparator. */
 } spiir_bank_opts;
 
 /* Layout facts of a created bank (for tests, tuning reports and benchmarks). */
@@ -99,6 +105,7 @@ typedef struct {
     int32_t precision;
     int32_t device;
     int32_t n_cu;             /* compute units of the device */
+    int32_t time_split;       /* segments per streaming launch (1 = no split) */
 } spiir_bank_info;
 
 /* Fills *opts with the defaults listed above. */

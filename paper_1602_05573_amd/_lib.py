@@ -36,7 +36,8 @@ class BankOpts(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_int32), ("filters_per_lane", ctypes.c_int32),
                 ("max_delay", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("max_block", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("waves_per_group", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("time_split", ctypes.c_int32)]
 
 
 class BankInfo(ctypes.Structure):
@@ -46,7 +47,7 @@ class BankInfo(ctypes.Structure):
                 ("n_groups", ctypes.c_int32), ("n_slots", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int32), ("x_in_lds", ctypes.c_int32),
                 ("sub_block", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("n_cu", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("n_cu", ctypes.c_int32), ("time_split", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

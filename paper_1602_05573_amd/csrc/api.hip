@@ -83,6 +83,7 @@ struct Layout {
     int64_t nslots = 0;
     std::vector<RowInfo> rows;            // [groups * wpg * 4]
     std::vector<int32_t> slot_filter;     // [nslots], -1 = padding
+    std::vector<int64_t> pad_src;         // [nslots], padding: slot whose window offset it reuses
     std::vector<int32_t> tpl_group;       // [T]
 };
 
@@ -111,9 +112,12 @@ int auto_wpg(int64_t total_rows, int max_nr, int n_cu) {
 
 // First-fit decreasing packing of whole templates, in 16-lane rows, into
 // workgroups of 4 * wpg rows; then the filter-to-slot assignment inside every
-// template: a slot in lane L of its wave preferably gets a filter with
-// d = L (mod 64), else the nearest residue still available, so that the 64
-// lanes of one x[m - d] read hit (nearly) distinct LDS banks for every m.
+// template. A template has nr rows x fl slots = C columns of 16 lanes, and one
+// ds_read_b32 of x[m - d] serves a column's 16 lanes in one LDS pass: filters
+// sorted by d mod 32 are dealt round-robin over the C columns, so the lanes
+// of a column have distinct d mod 32 (a residue class holds about K/32 < C
+// filters) and read from distinct banks. Padding lanes take the window offset
+// of a real lane of their column (same address: a broadcast, not a conflict).
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
     const int R = 4 * wpg;
     std::vector<int> nr(T);
@@ -147,10 +151,9 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
     lay.nslots = (int64_t)lay.groups * wpg * fl * 64;
     lay.rows.assign((size_t)lay.groups * R, RowInfo{-1, 0, 0, 0});
     lay.slot_filter.assign((size_t)lay.nslots, -1);
+    lay.pad_src.assign((size_t)lay.nslots, -1);
     lay.tpl_group.assign(T, -1);
-    std::vector<std::vector<int32_t>> bucket(64);
-    std::vector<std::pair<int64_t, int>> slots;  // (slot, lane in wave)
-    std::vector<char> taken;
+    std::vector<int32_t> ks;
     for (int g = 0; g < lay.groups; ++g) {
         std::vector<int> &mem = members[g];
         std::sort(mem.begin(), mem.end());
@@ -158,38 +161,21 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
         for (int j : mem) {
             lay.tpl_group[j] = g;
             for (int r = 0; r < nr[j]; ++r) lay.rows[(size_t)g * R + r0 + r] = RowInfo{j, r0, nr[j], 0};
-            for (auto &bk : bucket) bk.clear();
-            for (int64_t k = off[j + 1] - 1; k >= off[j]; --k) bucket[d[k] & 63].push_back((int32_t)k);
-            slots.clear();
-            for (int f = 0; f < fl; ++f)
-                for (int r = r0; r < r0 + nr[j]; ++r)
-                    for (int l = 0; l < kRowLanes; ++l) {
-                        const int lane = (r % 4) * kRowLanes + l;
-                        slots.emplace_back(((int64_t)(g * wpg + r / 4) * fl + f) * 64 + lane, lane);
-                    }
-            taken.assign(slots.size(), 0);
-            int64_t left = off[j + 1] - off[j];
-            for (size_t i = 0; i < slots.size() && left > 0; ++i) {  // exact residue
-                auto &bk = bucket[slots[i].second];
-                if (bk.empty()) continue;
-                lay.slot_filter[(size_t)slots[i].first] = bk.back();
-                bk.pop_back();
-                taken[i] = 1;
-                --left;
-            }
-            for (size_t i = 0; i < slots.size() && left > 0; ++i) {  // nearest residue left
-                if (taken[i]) continue;
-                for (int dr = 1; dr <= 32; ++dr) {
-                    int pick = -1;
-                    if (!bucket[(slots[i].second + dr) & 63].empty()) pick = (slots[i].second + dr) & 63;
-                    else if (!bucket[(slots[i].second - dr) & 63].empty()) pick = (slots[i].second - dr) & 63;
-                    if (pick < 0) continue;
-                    lay.slot_filter[(size_t)slots[i].first] = bucket[pick].back();
-                    bucket[pick].pop_back();
-                    taken[i] = 1;
-                    --left;
-                    break;
-                }
+            ks.clear();
+            for (int64_t k = off[j]; k < off[j + 1]; ++k) ks.push_back((int32_t)k);
+            std::stable_sort(ks.begin(), ks.end(), [&](int32_t x, int32_t y) { return (d[x] & 31) < (d[y] & 31); });
+            const int cols = nr[j] * fl;
+            auto slot_of = [&](int c, int lane16) {
+                const int row = r0 + c % nr[j], f = c / nr[j];
+                return ((int64_t)(g * wpg + row / 4) * fl + f) * 64 + (row % 4) * kRowLanes + lane16;
+            };
+            for (size_t i = 0; i < ks.size(); ++i)
+                lay.slot_filter[(size_t)slot_of((int)(i % cols), (int)(i / cols))] = ks[i];
+            for (int c = 0; c < cols; ++c) {
+                const int64_t first = slot_of(c, 0);   // filled whenever the column holds any filter
+                if (lay.slot_filter[(size_t)first] < 0) continue;
+                for (int l = 1; l < kRowLanes; ++l)
+                    if (lay.slot_filter[(size_t)slot_of(c, l)] < 0) lay.pad_src[(size_t)slot_of(c, l)] = first;
             }
             r0 += nr[j];
         }
@@ -246,6 +232,11 @@ struct spiir_bank {
     float *xwin = nullptr;
     int64_t xwin_cap = 0;
     float2 *ysub = nullptr;
+    int nseg = 1;                 // time segments per streaming launch
+    int64_t seg_len_max = 0;
+    size_t lds_carry = 0;
+    float4 *seg_end = nullptr, *seg_start = nullptr;
+    float2 *zl = nullptr;
 
     SlotArrays slots() const { return SlotArrays{a32, b32, xoff, aL, dL, a64, flags}; }
 
@@ -262,6 +253,11 @@ struct spiir_bank {
         p.gbase = 0;
         p.rows = rows;
         p.nslots = lay.nslots;
+        p.groups = lay.groups;
+        p.n_templates = T;
+        p.seg_end = seg_end;
+        p.seg_start = seg_start;
+        p.zl = zl;
         return p;
     }
 };
@@ -326,6 +322,7 @@ int check_bank_args(int32_t T, const int64_t *off, const double *a, const double
     if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
     if (o.waves_per_group < 0 || o.waves_per_group > kMaxWaves)
         return fail(SPIIR_EINVAL, "waves_per_group must be 0..%d", kMaxWaves);
+    if (o.time_split < 0 || o.time_split > 8) return fail(SPIIR_EINVAL, "time_split must be 0..8");
     dmax_out = dmax;
     return SPIIR_OK;
 }
@@ -339,7 +336,11 @@ int upload_coeffs(spiir_bank *bk) {
         a64((size_t)S, make_double2(0, 0));
     for (int64_t s = 0; s < S; ++s) {
         const int32_t k = bk->lay.slot_filter[(size_t)s];
-        if (k < 0) continue;
+        if (k < 0) {
+            const int64_t src = bk->lay.pad_src[(size_t)s];
+            if (src >= 0) xo[(size_t)s] = bk->dmax - bk->d[(size_t)bk->lay.slot_filter[(size_t)src]];
+            continue;
+        }
         const double ar = bk->a[2 * (size_t)k], ai = bk->a[2 * (size_t)k + 1];
         const float far = (float)ar, fai = (float)ai;
         a32[(size_t)s] = make_float2(far, fai);
@@ -366,7 +367,7 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->a32); dfree(bk->b32); dfree(bk->xoff); dfree(bk->flags); dfree(bk->slot_filter);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
-    dfree(bk->ysub);
+    dfree(bk->ysub); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
 }
 
 // Filters per lane: the largest count that still gives every SIMD about two
@@ -474,6 +475,20 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     bk->xlds = gm.xlds;
     bk->nb = gm.nb;
     bk->lds = gm.lds;
+    bk->lds_carry = fwd_lds_bytes(wpg, 0, 0, false, gm.tt);
+    // time split: only when the bank's workgroups fill at most half the device
+    if (o.precision != SPIIR_PREC_FP32 && o.time_split != 1) {
+        if (o.time_split >= 2) {
+            bk->nseg = o.time_split;
+        } else {
+            const int occ = std::max(1, forward_occupancy(fl, gm.tt, wpg, gm.lds));
+            const int64_t slots_dev = (int64_t)df.n_cu * occ;
+            if (2 * (int64_t)bk->lay.groups <= slots_dev)
+                bk->nseg = (int)std::min<int64_t>(8, slots_dev / std::max(1, bk->lay.groups));
+        }
+        bk->nseg = std::min(bk->nseg, std::max(1, max_block / L));
+    }
+    if (bk->nseg > 1) bk->seg_len_max = ((max_block + bk->nseg - 1) / bk->nseg + L - 1) / L * L;
 
     const int64_t S = bk->lay.nslots;
     const int G = bk->lay.groups;
@@ -485,6 +500,11 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
     A(dalloc(&bk->keys, (size_t)G * max_block));
     A(dalloc(&bk->ysub, (size_t)((L + kSub - 1) / kSub) * S));
+    if (bk->nseg > 1) {
+        A(dalloc(&bk->seg_end, (size_t)bk->nseg * S));
+        A(dalloc(&bk->seg_start, (size_t)bk->nseg * S));
+        A(dalloc(&bk->zl, (size_t)(bk->nseg - 1) * T * bk->seg_len_max));
+    }
     if (e != hipSuccess) {
         free_bank_buffers(bk);
         delete bk;
@@ -497,6 +517,8 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
             e = hipMemcpy(bk->rows, bk->lay.rows.data(), bk->lay.rows.size() * sizeof(RowInfo),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(bk->state, 0, S * sizeof(float4));
+        if (e == hipSuccess && bk->nseg > 1) e = hipMemset(bk->seg_end, 0, (size_t)bk->nseg * S * sizeof(float4));
+        if (e == hipSuccess && bk->nseg > 1) e = hipMemset(bk->seg_start, 0, (size_t)bk->nseg * S * sizeof(float4));
         if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[0], 0, (size_t)dmax * sizeof(float));
         if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[1], 0, (size_t)dmax * sizeof(float));
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -550,7 +572,16 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.keys = bk->keys;
             a.ld = bk->max_block;
         }
-        HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st));
+        int nseg = 1;
+        if (bk->nseg > 1) {
+            a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
+            nseg = (int)((np + a.seg_len - 1) / a.seg_len);
+        }
+        if (nseg >= 2)
+            HIPCHK(launch_forward_split(a, mode, bk->lay.fl, bk->tt, bk->xlds, nseg, bk->lds, bk->lds_carry,
+                                        bk->slot_filter, st));
+        else
+            HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st));
         if (mode == kModeKeys)
             HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st));
     }
@@ -574,6 +605,7 @@ void spiir_bank_opts_default(spiir_bank_opts *o) {
     o->max_block = 16384;
     o->waves_per_group = 0;
     o->autotune = 0;
+    o->time_split = 0;
 }
 
 int spiir_bank_create(spiir_bank **out, int32_t n_templates, const int64_t *filter_offsets,
@@ -626,6 +658,7 @@ int spiir_bank_get_info(const spiir_bank *bk, spiir_bank_info *info) {
     info->precision = bk->prec;
     info->device = bk->device;
     info->n_cu = bk->dev.n_cu;
+    info->time_split = bk->nseg;
     return SPIIR_OK;
 }
 

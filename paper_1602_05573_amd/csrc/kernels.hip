@@ -84,12 +84,12 @@ __device__ __forceinline__ void load_ahead(float (&xv)[TT][FL], const float *xw,
 // One tile: FL filter updates per step and per lane, the lane's partial
 // template sum of every step written to the wave's LDS tile [TT][64]. x for
 // step t + kAhead is read while step t computes (xv[0..kAhead) arrive loaded).
-template <int FL, int TT, bool FULL>
+template <int FL, int TT, bool FULL, bool CARRY>
 __device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], const float *xw, int t0,
                                              int steps, float2 *wt, int lane) {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-        if (t + kAhead < TT) {
+        if (!CARRY && t + kAhead < TT) {
 #pragma unroll
             for (int f = 0; f < FL; ++f) xv[t + kAhead][f] = xw[s.xo[f] + t0 + t + kAhead];
         }
@@ -97,9 +97,15 @@ __device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], c
         float pr = 0.f, pi = 0.f;
 #pragma unroll
         for (int f = 0; f < FL; ++f) {
-            const float xv_ = xv[t][f];
-            const float nr = fmaf(-s.ai[f], s.yi[f], fmaf(s.ar[f], s.yr[f], s.br[f] * xv_));
-            const float ni = fmaf(s.ai[f], s.yr[f], fmaf(s.ar[f], s.yi[f], s.bi[f] * xv_));
+            float nr, ni;
+            if (CARRY) {  // free response of the carried state: y <- a y
+                nr = fmaf(-s.ai[f], s.yi[f], s.ar[f] * s.yr[f]);
+                ni = fmaf(s.ai[f], s.yr[f], s.ar[f] * s.yi[f]);
+            } else {
+                const float xv_ = xv[t][f];
+                nr = fmaf(-s.ai[f], s.yi[f], fmaf(s.ar[f], s.yr[f], s.br[f] * xv_));
+                ni = fmaf(s.ai[f], s.yr[f], fmaf(s.ar[f], s.yi[f], s.bi[f] * xv_));
+            }
             s.yr[f] = nr;
             s.yi[f] = ni;
             if (f == 0) {
@@ -114,59 +120,58 @@ __device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], c
     }
 }
 
-// Row sums of a wave tile: wsum[t][4 * wave + r] = sum of the 16 lanes of row r
-// at step t. Lane L reads its row's 16-byte chunks in a lane-rotated order
-// (offsets precomputed by row_sum_offsets) so that the 8 / 16 lanes served by
-// the LDS in one cycle touch distinct banks.
+// Row sums of a wave tile: wsum[t][4 * wave + r] = sum of the 16 lanes of row
+// r at step t. Tile row k = 4 t + r is 128 bytes = four 32-byte units. Lanes
+// 2p and 2p+1 read the two halves of one unit together (the LDS serves a
+// ds_read_b128 per lane pair), and pair p walks its row's units in an order
+// rotated by p / 2, so the 8 pairs served in one cycle hit distinct banks.
+// Each lane sums its halves; one DPP swap adds the partner's half.
 template <int TT>
 struct RowSumPlan {
-    static constexpr int kChunks = TT == 16 ? 8 : 4;
-    int off[kChunks];   // byte offsets of the chunks inside the wave tile, in read order
-    int t, r;           // step and row this lane sums
+    static constexpr int kReads = TT == 16 ? 8 : 4;
+    int off[kReads];   // byte offsets inside the wave tile, in read order
+    int k0, k1;        // tile rows this pair sums (TT = 16: two rows; TT = 8: one)
 };
 
 template <int TT>
 __device__ __forceinline__ RowSumPlan<TT> row_sum_plan(int lane) {
     RowSumPlan<TT> pl;
-    if (TT == 16) {
-        pl.t = lane >> 2;
-        pl.r = lane & 3;
-        const int rot = (lane + (lane >> 3)) & 7;
+    const int p = lane >> 1, h = lane & 1;
+    pl.k0 = p;
+    pl.k1 = p + 32;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) pl.off[i] = (pl.t * 64 + pl.r * 16) * 8 + ((i + rot) & 7) * 16;
-    } else {
-        pl.t = lane >> 3;
-        const int part = lane & 7;
-        pl.r = part >> 1;
-        const int rot = ((part >> 1) + pl.t) & 3;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) pl.off[i] = (pl.t * 64 + part * 8) * 8 + ((i + rot) & 3) * 16;
+    for (int i = 0; i < pl.kReads; ++i) {
+        const int k = (i < 4) ? pl.k0 : pl.k1;
+        const int q = ((i & 3) + (p >> 1)) & 3;
+        pl.off[i] = k * 128 + (2 * q + h) * 16;
     }
     return pl;
+}
+
+__device__ __forceinline__ float2 sum_chunks4(const float4 &a, const float4 &b, const float4 &c, const float4 &d) {
+    return make_float2(((a.x + a.z) + (b.x + b.z)) + ((c.x + c.z) + (d.x + d.z)),
+                       ((a.y + a.w) + (b.y + b.w)) + ((c.y + c.w) + (d.y + d.w)));
 }
 
 template <int TT>
 __device__ __forceinline__ void row_sums(const float2 *wt, const RowSumPlan<TT> &pl, float2 *wsum_buf,
                                          int Rp, int wave, int lane) {
     const char *base = reinterpret_cast<const char *>(wt);
+    const bool lo = (lane & 1) == 0;
+    float4 v[pl.kReads];
+#pragma unroll
+    for (int i = 0; i < pl.kReads; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
+    const float2 s0 = sum_chunks4(v[0], v[1], v[2], v[3]);
+    const float o0r = dpp_swap_pairs(s0.x), o0i = dpp_swap_pairs(s0.y);
     if (TT == 16) {
-        float4 v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
-        float sr = (((v[0].x + v[0].z) + (v[1].x + v[1].z)) + ((v[2].x + v[2].z) + (v[3].x + v[3].z))) +
-                   (((v[4].x + v[4].z) + (v[5].x + v[5].z)) + ((v[6].x + v[6].z) + (v[7].x + v[7].z)));
-        float si = (((v[0].y + v[0].w) + (v[1].y + v[1].w)) + ((v[2].y + v[2].w) + (v[3].y + v[3].w))) +
-                   (((v[4].y + v[4].w) + (v[5].y + v[5].w)) + ((v[6].y + v[6].w) + (v[7].y + v[7].w)));
-        wsum_buf[pl.t * Rp + wave * 4 + pl.r] = make_float2(sr, si);
+        const float2 s1 = sum_chunks4(v[4], v[5], v[6], v[7]);
+        const float o1r = dpp_swap_pairs(s1.x), o1i = dpp_swap_pairs(s1.y);
+        // the even lane writes row k0, the odd lane row k1; both as (even half) + (odd half)
+        const int k = lo ? pl.k0 : pl.k1;
+        const float2 tot = lo ? make_float2(s0.x + o0r, s0.y + o0i) : make_float2(o1r + s1.x, o1i + s1.y);
+        wsum_buf[(k >> 2) * Rp + wave * 4 + (k & 3)] = tot;
     } else {
-        float4 v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
-        const float sr = ((v[0].x + v[0].z) + (v[1].x + v[1].z)) + ((v[2].x + v[2].z) + (v[3].x + v[3].z));
-        const float si = ((v[0].y + v[0].w) + (v[1].y + v[1].w)) + ((v[2].y + v[2].w) + (v[3].y + v[3].w));
-        // the two halves of a row sit in lanes 2k and 2k+1
-        const float or_ = dpp_swap_pairs(sr), oi = dpp_swap_pairs(si);
-        if ((lane & 1) == 0) wsum_buf[pl.t * Rp + wave * 4 + pl.r] = make_float2(sr + or_, si + oi);
+        if (lo) wsum_buf[(pl.k0 >> 2) * Rp + wave * 4 + (pl.k0 & 3)] = make_float2(s0.x + o0r, s0.y + o0i);
     }
 }
 
@@ -212,9 +217,20 @@ __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa,
     }
 }
 
-// The whole forward pass of workgroup g over p.n samples.
-template <int FL, int TT, int MODE, bool XLDS>
-__device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
+// Time range and data routing of one workgroup item.
+struct SegCtx {
+    int64_t tb, tn;          // launch samples [tb, tb + tn)
+    const float4 *st_in;     // initial state per slot (null: cold start)
+    float4 *st_out;          // final state per slot (null: not stored)
+    float2 *zl_out;          // local z goes here ([T][ld_zl]) instead of the mode's output
+    const float2 *zl_in;     // added to z before the mode's output (carry pass)
+    int64_t ld_zl;
+};
+
+// The whole forward pass of workgroup g over launch samples [sc.tb, sc.tb + sc.tn).
+// CARRY: free response of the given state only (no input), z_local added.
+template <int FL, int TT, int MODE, bool XLDS, bool CARRY>
+__device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const SegCtx &sc) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = p.wpg, R = 4 * W, Rp = R + 1;  // odd row stride of wsum: no bank aliasing over t
     const size_t win_bytes = XLDS ? (size_t)((p.dmax + p.nb + TT + 3) & ~3) * 4 : 0;
@@ -242,7 +258,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
             s.xo[f] = p.s.xoff[s.slot(f)];
             s.flags |= (unsigned)(p.s.flags[s.slot(f)] & 1) << f;
             float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (p.state) st = p.state[s.slot(f)];
+            if (sc.st_in) st = sc.st_in[s.slot(f)];
             s.yr[f] = st.x; s.yi[f] = st.y; s.l0r[f] = st.z; s.l0i[f] = st.w;
         } else {
             s.ar[f] = s.ai[f] = s.br[f] = s.bi[f] = 0.f;
@@ -252,7 +268,10 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
         s.y0r[f] = s.yr[f];
         s.y0i[f] = s.yi[f];
     }
-    if (MODE == kModeKeys && tid < 2 * TT) kmax[tid] = 0ull;
+    const bool keys_out = MODE == kModeKeys && sc.zl_out == nullptr;
+    const int64_t n = sc.tn;
+    const int64_t xbase = p.xbase + sc.tb;
+    if (keys_out && tid < 2 * TT) kmax[tid] = 0ull;
     if (MODE == kModeZ && ract && p.tape) {
 #pragma unroll
         for (int f = 0; f < FL; ++f)
@@ -268,13 +287,15 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
     int pend_steps = 0;
     float xv[TT][FL];
 
-    for (int64_t s0 = 0; s0 < p.n; s0 += p.nb) {
-        const int nbs = (int)min((int64_t)p.nb, p.n - s0);
-        const float *xw;
-        if (XLDS) {
+    for (int64_t s0 = 0; s0 < n; s0 += p.nb) {
+        const int nbs = (int)min((int64_t)p.nb, n - s0);
+        const float *xw = nullptr;
+        if (CARRY) {
+            xw = nullptr;
+        } else if (XLDS) {
             __syncthreads();
             const int cnt = p.dmax + nbs;
-            const int64_t m0 = p.xbase + s0 - p.dmax;
+            const int64_t m0 = xbase + s0 - p.dmax;
             for (int i = tid; i < cnt; i += blockDim.x) {
                 const int64_t m = m0 + i;
                 xs[i] = m >= 0 ? p.x[m] : (p.hist ? p.hist[p.dmax + m] : 0.f);
@@ -282,25 +303,25 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
             __syncthreads();
             xw = xs;
         } else {
-            xw = p.xwin + (p.xbase + s0);
+            xw = p.xwin + (xbase + s0);
         }
-        if (wact) load_ahead<FL, TT>(xv, xw, s, 0);
+        if (!CARRY && wact) load_ahead<FL, TT>(xv, xw, s, 0);
 
         for (int t0 = 0; t0 < nbs; t0 += TT) {
             const int steps = min(TT, nbs - t0);
             if (wact) {
                 if (steps == TT)
-                    compute_tile<FL, TT, true>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, true, CARRY>(s, xv, xw, t0, steps, wt, lane);
                 else
-                    compute_tile<FL, TT, false>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, false, CARRY>(s, xv, xw, t0, steps, wt, lane);
                 wave_lds_sync();
                 row_sums<TT>(wt, rsp, wsum + buf * TT * Rp, Rp, wave, lane);
-                if (t0 + TT < nbs) load_ahead<FL, TT>(xv, xw, s, t0 + TT);
+                if (!CARRY && t0 + TT < nbs) load_ahead<FL, TT>(xv, xw, s, t0 + TT);
             }
             __syncthreads();
-            if (MODE == kModeKeys && pending && wave == 0 && lane < pend_steps) {
+            if (keys_out && pending && wave == 0 && lane < pend_steps) {
                 const int pb = buf ^ 1;
-                p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * TT + lane];
+                p.keys[(int64_t)g * p.ld + sc.tb + pend_t + lane] = kmax[pb * TT + lane];
                 kmax[pb * TT + lane] = 0ull;
             }
             if (leader && tl16 < steps) {
@@ -317,10 +338,17 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
                     zi += ws[r].y;
                 }
                 const int64_t tl = s0 + t0 + tl16;
-                if (MODE == kModeSnr) {
-                    p.snr[(int64_t)ri.tpl * p.ld + p.obase + tl] = zr * zr + zi * zi;
+                if (sc.zl_in) {
+                    const float2 zl = sc.zl_in[(int64_t)ri.tpl * sc.ld_zl + tl];
+                    zr += zl.x;
+                    zi += zl.y;
+                }
+                if (sc.zl_out) {
+                    sc.zl_out[(int64_t)ri.tpl * sc.ld_zl + tl] = make_float2(zr, zi);
+                } else if (MODE == kModeSnr) {
+                    p.snr[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = zr * zr + zi * zi;
                 } else if (MODE == kModeZ) {
-                    p.z[(int64_t)ri.tpl * p.ld + p.obase + tl] = make_float2(zr, zi);
+                    p.z[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = make_float2(zr, zi);
                 } else {
                     const float sn = zr * zr + zi * zi;
                     const unsigned long long key =
@@ -329,16 +357,16 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
                     atomicMax(&kmax[buf * TT + tl16], key);
                 }
             }
-            if (MODE == kModeKeys) {
+            if (keys_out) {
                 pending = true;
                 pend_t = s0 + t0;
                 pend_steps = steps;
             }
             const int64_t tend = s0 + t0 + steps;
-            if (tend - chunk_start == p.L || tend == p.n) {
+            if (tend - chunk_start == p.L || tend == n) {
                 if (wact) {
                     carry_correct<FL>(s, p.s, p.prec, (int)(tend - chunk_start), p.L);
-                    if (MODE == kModeZ && ract && p.tape && tend < p.n) {
+                    if (MODE == kModeZ && ract && p.tape && tend < n) {
 #pragma unroll
                         for (int f = 0; f < FL; ++f)
                             p.tape[(p.chunk0 + chunk_idx + 1) * p.nslots + s.slot(f)] =
@@ -351,25 +379,101 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem) {
             buf ^= 1;
         }
     }
-    if (MODE == kModeKeys) {
+    if (keys_out) {
         __syncthreads();
         if (pending && wave == 0 && lane < pend_steps) {
             const int pb = buf ^ 1;
-            p.keys[(int64_t)g * p.ld + pend_t + lane] = kmax[pb * TT + lane];
+            p.keys[(int64_t)g * p.ld + sc.tb + pend_t + lane] = kmax[pb * TT + lane];
             kmax[pb * TT + lane] = 0ull;
         }
     }
-    if (ract && p.state) {
+    if (ract && sc.st_out) {
 #pragma unroll
         for (int f = 0; f < FL; ++f)
-            p.state[s.slot(f)] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+            sc.st_out[s.slot(f)] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
     }
+}
+
+__device__ __forceinline__ SegCtx whole_launch(const FwdArgs &p) {
+    SegCtx sc;
+    sc.tb = 0;
+    sc.tn = p.n;
+    sc.st_in = p.state;
+    sc.st_out = p.state;
+    sc.zl_out = nullptr;
+    sc.zl_in = nullptr;
+    sc.ld_zl = 0;
+    return sc;
 }
 
 template <int FL, int TT, int MODE, bool XLDS>
 __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_group<FL, TT, MODE, XLDS>(p, p.gbase + blockIdx.x, smem);
+    const SegCtx sc = whole_launch(p);
+    fwd_group<FL, TT, MODE, XLDS, false>(p, p.gbase + blockIdx.x, smem, sc);
+}
+
+// Time split, local pass: item (segment, group). Segment 0 starts from the
+// carried state and writes the mode's output; later segments start cold and
+// keep their local z. Every item stores its end state.
+template <int FL, int TT, int MODE, bool XLDS>
+__global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = blockIdx.x % p.groups, seg = blockIdx.x / p.groups;
+    SegCtx sc;
+    sc.tb = (int64_t)seg * p.seg_len;
+    sc.tn = min(p.seg_len, p.n - sc.tb);
+    sc.st_in = seg == 0 ? p.state : nullptr;
+    sc.st_out = p.seg_end + (int64_t)seg * p.nslots;
+    sc.zl_out = seg == 0 ? nullptr : p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
+    sc.zl_in = nullptr;
+    sc.ld_zl = p.seg_len;
+    fwd_group<FL, TT, MODE, XLDS, false>(p, g, smem, sc);
+}
+
+// Time split, carry pass over segments 1..: free response of the true
+// segment-start state plus the local z, then the mode's output.
+template <int FL, int TT, int MODE>
+__global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = blockIdx.x % p.groups, seg = 1 + blockIdx.x / p.groups;
+    SegCtx sc;
+    sc.tb = (int64_t)seg * p.seg_len;
+    sc.tn = min(p.seg_len, p.n - sc.tb);
+    sc.st_in = p.seg_start + (int64_t)seg * p.nslots;
+    sc.st_out = nullptr;
+    sc.zl_out = nullptr;
+    sc.zl_in = p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
+    sc.ld_zl = p.seg_len;
+    fwd_group<FL, TT, MODE, false, true>(p, g, smem, sc);
+}
+
+// Time split, carry chain: c_{s+1} = a^len_s c_s + e_s in FP64 per slot, from
+// the true end of segment 0; writes every segment's true start state and the
+// launch's final state.
+__global__ void seg_chain_kernel(const float4 *seg_end, float4 *seg_start, float4 *state, const double2 *a64,
+                                 const int32_t *slot_filter, int64_t nslots, int nseg, int64_t seg_len,
+                                 int64_t n) {
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    (void)slot_filter;
+    if (sl >= nslots) return;  // every slot, padding included (its states stay zero)
+    const float4 e0 = seg_end[sl];
+    double cr = (double)e0.x + (double)e0.z, ci = (double)e0.y + (double)e0.w;
+    const double2 a = a64[sl];
+    for (int k = 1; k < nseg; ++k) {
+        const float hr = (float)cr, hi = (float)ci;
+        seg_start[(int64_t)k * nslots + sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+        const int len = (int)min(seg_len, n - (int64_t)k * seg_len);
+        const double2 al = cpow64(a, len);
+        const float4 e = seg_end[(int64_t)k * nslots + sl];
+        const double er = (double)e.x + (double)e.z, ei = (double)e.y + (double)e.w;
+        const double nr = al.x * cr - al.y * ci + er;
+        const double ni = al.x * ci + al.y * cr + ei;
+        cr = nr;
+        ci = ni;
+    }
+    const float hr = (float)cr, hi = (float)ci;
+    state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
 }
 
 // Persistent batch kernel: workgroups pop (stream, group) items until the list
@@ -396,7 +500,8 @@ __global__ void __launch_bounds__(512) batch_kernel(const BatchStream *streams, 
         a.xbase = p0;
         a.n = min((int64_t)block_len, len - p0);
         a.ld = block_len;
-        fwd_group<FL, TT, kModeKeys, true>(a, g, smem);
+        const SegCtx sc = whole_launch(a);
+        fwd_group<FL, TT, kModeKeys, true, false>(a, g, smem, sc);
     }
 }
 
@@ -641,6 +746,42 @@ hipError_t launch_fwd_x(const FwdArgs &a, int mode, int fl, int groups, size_t l
     }
 }
 
+template <int FL, int TT, int MODE, bool XLDS>
+hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_carry, const int32_t *slot_filter,
+                          hipStream_t st) {
+    hipLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS>), dim3(a.groups * nseg), dim3(a.wpg * 64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((a.nslots + 255) / 256);
+    hipLaunchKernelGGL(seg_chain_kernel, dim3(nb), dim3(256), 0, st, a.seg_end, a.seg_start, a.state, a.s.a64,
+                       slot_filter, a.nslots, nseg, a.seg_len, a.n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64), lds_carry, st,
+                       a);
+    return hipGetLastError();
+}
+
+template <int TT, int MODE, bool XLDS>
+hipError_t launch_split_m(const FwdArgs &a, int fl, int nseg, size_t lds, size_t ldc, const int32_t *sf,
+                          hipStream_t st) {
+    switch (fl) {
+        case 1: return launch_split_t<1, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
+        case 2: return launch_split_t<2, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
+        case 3: return launch_split_t<3, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
+        case 4: return launch_split_t<4, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TT, bool XLDS>
+hipError_t launch_split_x(const FwdArgs &a, int mode, int fl, int nseg, size_t lds, size_t ldc, const int32_t *sf,
+                          hipStream_t st) {
+    if (mode == kModeSnr) return launch_split_m<TT, kModeSnr, XLDS>(a, fl, nseg, lds, ldc, sf, st);
+    if (mode == kModeKeys) return launch_split_m<TT, kModeKeys, XLDS>(a, fl, nseg, lds, ldc, sf, st);
+    return hipErrorInvalidValue;
+}
+
 template <int FL, int TT>
 int occ_t(int wpg, size_t lds) {
     int nb = 0;
@@ -668,6 +809,18 @@ hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_
     if (tt == 8)
         return x_in_lds ? launch_fwd_x<8, true>(a, mode, fl, groups, lds, st)
                         : launch_fwd_x<8, false>(a, mode, fl, groups, lds, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int nseg, size_t lds,
+                                size_t lds_carry, const int32_t *slot_filter, hipStream_t st) {
+    if (a.groups <= 0 || nseg < 2) return hipErrorInvalidValue;
+    if (tt == 16)
+        return x_in_lds ? launch_split_x<16, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st)
+                        : launch_split_x<16, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st);
+    if (tt == 8)
+        return x_in_lds ? launch_split_x<8, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st)
+                        : launch_split_x<8, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st);
     return hipErrorInvalidValue;
 }
 

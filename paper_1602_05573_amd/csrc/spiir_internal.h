@@ -51,6 +51,13 @@ struct FwdArgs {
     float4 *tape;         // kModeZ: tape[(chunk0 + c) * nslots + slot] = state at chunk start
     int64_t chunk0;
     int64_t nslots;
+    // time split of one launch into nseg segments of seg_len samples
+    int32_t groups;       // workgroups of the bank (item = segment * groups + group)
+    int32_t n_templates;
+    int64_t seg_len;
+    float4 *seg_end;      // [nseg][nslots] state at each segment end (local from zero for segments > 0)
+    float4 *seg_start;    // [nseg][nslots] true state at each segment start (segments > 0)
+    float2 *zl;           // [nseg - 1][T][seg_len] local z of segments > 0
 };
 
 struct BwdArgs {
@@ -80,6 +87,11 @@ struct BatchStream {
 size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt);
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
                           size_t lds, hipStream_t stream);
+// Time-split launch (modes kModeSnr / kModeKeys): local pass over every
+// segment, FP64 carry chain, carry-only pass with the local z added.
+hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int nseg,
+                                size_t lds, size_t lds_carry, const int32_t *slot_filter,
+                                hipStream_t stream);
 int forward_occupancy(int fl, int tt, int wpg, size_t lds);
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t stream);

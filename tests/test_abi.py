@@ -43,6 +43,7 @@ def test_version_and_empty_error(lib):
 def test_opts_default(lib):
     o = _lib.default_opts()
     assert o.chunk_len == 256 and o.precision == 0 and o.device == -1 and o.max_block == 16384
+    assert o.time_split == 0 and o.autotune == 0 and o.waves_per_group == 0
 
 
 def _create(lib, T, off, a, b, d, **kw):
@@ -78,6 +79,7 @@ GOOD = dict(T=2, off=[0, 2, 3], a=[0.5, 0.9j, -0.3 + 0.1j], b=[1, 1j, 0.5], d=[0
     (dict(filters_per_lane=5), "filters_per_lane"),
     (dict(precision=3), "precision"),
     (dict(waves_per_group=17), "waves_per_group"),
+    (dict(time_split=9), "time_split"),
 ])
 def test_create_rejects_bad_arguments(lib, change, needle):
     args = dict(GOOD)
