@@ -266,6 +266,26 @@ int spiir_autotune(int32_t n_banks, const int32_t *n_templates,
                    int32_t block_len, int32_t device, int32_t *chunk_len_out,
                    int32_t *filters_per_lane_out, float *table);
 
+/* Kernel timing of a bank's forward launches (measurement aid; results do not
+ * depend on it).
+ *
+ * spiir_bank_time_kernels(bank, 1) makes every later forward launch of the bank
+ * (spiir_filter_block, spiir_trigger_max, spiir_forward_z; one launch per piece
+ * of at most max_block samples) record the start time of its first forward
+ * kernel and the end time of its last forward kernel with HIP events attached
+ * to the kernel dispatches themselves; the max/argmax finalisation and history
+ * copy are not included. 0 switches it off and frees the events. Enabling
+ * clears the running totals.
+ *
+ * spiir_bank_kernel_time waits for the recorded launches to finish, returns the
+ * summed kernel time in milliseconds and the number of launches since the last
+ * read, and clears both. The events live in a ring of 256 pairs: a launch that
+ * would reuse a pair first waits on the host for the launch 256 calls earlier.
+ * Returns SPIIR_ESTATE if timing is off.
+ */
+int spiir_bank_time_kernels(spiir_bank *bank, int32_t enable);
+int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *spiir_last_error(void);
 

@@ -22,7 +22,8 @@ EXPORTS = (
     "spiir_bank_set_state", "spiir_filter_block", "spiir_trigger_max",
     "spiir_trigger_max_per_template", "spiir_forward_z", "spiir_backward", "spiir_tape_destroy",
     "spiir_batch_create", "spiir_batch_step", "spiir_batch_steps_total", "spiir_batch_reset",
-    "spiir_batch_destroy", "spiir_autotune", "spiir_last_error", "spiir_version",
+    "spiir_batch_destroy", "spiir_autotune", "spiir_bank_time_kernels", "spiir_bank_kernel_time",
+    "spiir_last_error", "spiir_version",
 )
 
 
@@ -90,6 +91,8 @@ def load():
         "spiir_batch_destroy": (ctypes.c_int, [P]),
         "spiir_autotune": (ctypes.c_int, [I32, P, P, P, P, P, I32, I32, I32,
                                           ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
+        "spiir_bank_time_kernels": (ctypes.c_int, [P, I32]),
+        "spiir_bank_kernel_time": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
         "spiir_last_error": (ctypes.c_char_p, []),
         "spiir_version": (ctypes.c_char_p, []),
     }

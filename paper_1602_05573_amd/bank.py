@@ -124,6 +124,16 @@ class SpiirBank:
         buf = ctypes.create_string_buffer(blob, len(blob))
         call("spiir_bank_set_state", self._h, buf, len(blob))
 
+    # -- kernel timing ------------------------------------------------------
+    def time_kernels(self, enable: bool = True):
+        call("spiir_bank_time_kernels", self._h, 1 if enable else 0)
+
+    def kernel_time(self):
+        """(total ms, launches) of the forward kernels since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        call("spiir_bank_kernel_time", self._h, ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
     # -- forward ------------------------------------------------------------
     def filter_block(self, x: torch.Tensor, snr: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """Next len(x) samples -> SNR of every template, float32 [T, n]."""

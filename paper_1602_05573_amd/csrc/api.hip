@@ -237,6 +237,17 @@ struct spiir_bank {
     size_t lds_carry = 0;
     float4 *seg_end = nullptr, *seg_start = nullptr;
     float2 *zl = nullptr;
+    int tsplit_opt = 0;           // opts.time_split as given (the adjoint honours it too)
+    // adjoint scratch, grown on demand: ysub [cap][ceil(L/kSub)][S], lam [2][cap][S], gpart [cap][2][S]
+    int bwd_cap = 0;
+    float2 *blam = nullptr;
+    double2 *bgpart = nullptr;
+    // optional kernel timing ring (spiir_bank_time_kernels)
+    std::vector<hipEvent_t> tev0, tev1;
+    std::vector<char> tpend;
+    int tidx = 0;
+    double tms = 0.0;
+    int64_t tn = 0;
 
     SlotArrays slots() const { return SlotArrays{a32, b32, xoff, aL, dL, a64, flags}; }
 
@@ -363,11 +374,49 @@ int upload_coeffs(spiir_bank *bk) {
     return SPIIR_OK;
 }
 
+constexpr int kTimerRing = 256;
+
+hipError_t timer_collect(spiir_bank *bk, int i) {
+    if (!bk->tpend[i]) return hipSuccess;
+    hipError_t e = hipEventSynchronize(bk->tev1[i]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, bk->tev0[i], bk->tev1[i]);
+    if (e != hipSuccess) return e;
+    bk->tpend[i] = 0;
+    bk->tms += ms;
+    bk->tn += 1;
+    return hipSuccess;
+}
+
+// Events for the next forward launch (none while timing is off).
+hipError_t timer_next(spiir_bank *bk, KernelEvents *ev) {
+    *ev = KernelEvents();
+    if (bk->tev0.empty()) return hipSuccess;
+    const int i = bk->tidx;
+    hipError_t e = timer_collect(bk, i);
+    if (e != hipSuccess) return e;
+    ev->start = bk->tev0[i];
+    ev->stop = bk->tev1[i];
+    bk->tpend[i] = 1;
+    bk->tidx = (i + 1) % kTimerRing;
+    return hipSuccess;
+}
+
+void timer_free(spiir_bank *bk) {
+    for (auto e : bk->tev0) (void)hipEventDestroy(e);
+    for (auto e : bk->tev1) (void)hipEventDestroy(e);
+    bk->tev0.clear();
+    bk->tev1.clear();
+    bk->tpend.clear();
+    bk->tidx = 0;
+}
+
 void free_bank_buffers(spiir_bank *bk) {
+    timer_free(bk);
     dfree(bk->a32); dfree(bk->b32); dfree(bk->xoff); dfree(bk->flags); dfree(bk->slot_filter);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
-    dfree(bk->ysub); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
+    dfree(bk->ysub); dfree(bk->blam); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
 }
 
 // Filters per lane: the largest count that still gives every SIMD about two
@@ -476,6 +525,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     bk->nb = gm.nb;
     bk->lds = gm.lds;
     bk->lds_carry = fwd_lds_bytes(wpg, 0, 0, false, gm.tt);
+    bk->tsplit_opt = o.time_split;
     // time split: only when the bank's workgroups fill at most half the device
     if (o.precision != SPIIR_PREC_FP32 && o.time_split != 1) {
         if (o.time_split >= 2) {
@@ -499,7 +549,6 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->rows, (size_t)G * wpg * 4));
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
     A(dalloc(&bk->keys, (size_t)G * max_block));
-    A(dalloc(&bk->ysub, (size_t)((L + kSub - 1) / kSub) * S));
     if (bk->nseg > 1) {
         A(dalloc(&bk->seg_end, (size_t)bk->nseg * S));
         A(dalloc(&bk->seg_start, (size_t)bk->nseg * S));
@@ -577,11 +626,13 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
             nseg = (int)((np + a.seg_len - 1) / a.seg_len);
         }
+        KernelEvents ev;
+        HIPCHK(timer_next(bk, &ev));
         if (nseg >= 2)
             HIPCHK(launch_forward_split(a, mode, bk->lay.fl, bk->tt, bk->xlds, nseg, bk->lds, bk->lds_carry,
-                                        bk->slot_filter, st));
+                                        bk->slot_filter, st, ev));
         else
-            HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st));
+            HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev));
         if (mode == kModeKeys)
             HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st));
     }
@@ -639,6 +690,47 @@ int spiir_bank_destroy(spiir_bank *bk) {
         free_bank_buffers(bk);
     }
     delete bk;
+    return SPIIR_OK;
+}
+
+int spiir_bank_time_kernels(spiir_bank *bk, int32_t enable) {
+    if (!bk) return fail(SPIIR_EINVAL, "null bank");
+    DeviceGuard guard(bk->device);
+    if (!bk->tev0.empty()) {
+        for (int i = 0; i < kTimerRing; ++i)
+            if (bk->tpend[i]) (void)hipEventSynchronize(bk->tev1[i]);
+        timer_free(bk);
+    }
+    bk->tms = 0.0;
+    bk->tn = 0;
+    if (!enable) return SPIIR_OK;
+    bk->tev0.assign(kTimerRing, nullptr);
+    bk->tev1.assign(kTimerRing, nullptr);
+    bk->tpend.assign(kTimerRing, 0);
+    for (int i = 0; i < kTimerRing; ++i) {
+        hipError_t e = hipEventCreate(&bk->tev0[i]);
+        if (e == hipSuccess) e = hipEventCreate(&bk->tev1[i]);
+        if (e != hipSuccess) {
+            timer_free(bk);
+            return fail(SPIIR_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+        }
+    }
+    return SPIIR_OK;
+}
+
+int spiir_bank_kernel_time(spiir_bank *bk, double *total_ms, int64_t *launches) {
+    if (!bk || !total_ms || !launches) return fail(SPIIR_EINVAL, "null argument");
+    if (bk->tev0.empty()) return fail(SPIIR_ESTATE, "kernel timing is off (spiir_bank_time_kernels)");
+    DeviceGuard guard(bk->device);
+    for (int k = 0; k < kTimerRing; ++k) {
+        const int i = (bk->tidx + k) % kTimerRing;  // oldest first
+        hipError_t e = timer_collect(bk, i);
+        if (e != hipSuccess) return fail(SPIIR_EHIP, "kernel timing: %s", hipGetErrorString(e));
+    }
+    *total_ms = bk->tms;
+    *launches = bk->tn;
+    bk->tms = 0.0;
+    bk->tn = 0;
     return SPIIR_OK;
 }
 
@@ -848,7 +940,19 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
         a.ld = n;
         a.tape = tp ? tp->tape : nullptr;
         a.chunk0 = P / bk->L;
-        e = launch_forward(a, kModeZ, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st);
+        int nseg = 1;
+        if (bk->nseg > 1) {
+            a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
+            nseg = (int)((np + a.seg_len - 1) / a.seg_len);
+        }
+        KernelEvents ev;
+        e = timer_next(bk, &ev);
+        if (e != hipSuccess) break;
+        if (nseg >= 2)
+            e = launch_forward_split(a, kModeZ, bk->lay.fl, bk->tt, bk->xlds, nseg, bk->lds, bk->lds_carry,
+                                     bk->slot_filter, st, ev);
+        else
+            e = launch_forward(a, kModeZ, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev);
     }
     if (e != hipSuccess) {
         if (tp) {
@@ -882,7 +986,42 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     a.tape = tp->tape;
     a.xwin = tp->xwin;
     a.gz = reinterpret_cast<const float2 *>(gz);
+    // time segments: enough waves for about 8 per SIMD, at most 16 segments
+    const int64_t nch = (tp->n + bk->L - 1) / bk->L;
+    int want = 1;
+    if (bk->tsplit_opt >= 2) {
+        want = bk->tsplit_opt;
+    } else if (bk->tsplit_opt == 0) {
+        const int64_t waves = std::max<int64_t>(1, (int64_t)bk->lay.groups * bk->lay.wpg);
+        const int64_t target = (int64_t)32 * bk->dev.n_cu;
+        want = (int)std::min<int64_t>(16, (target + waves - 1) / waves);
+    }
+    want = (int)std::max<int64_t>(1, std::min<int64_t>(want, nch));
+    const int64_t seg_chunks = (nch + want - 1) / want;
+    const int nseg = (int)((nch + seg_chunks - 1) / seg_chunks);
+    const int64_t S = bk->lay.nslots;
+    if (bk->bwd_cap < nseg) {
+        dfree(bk->ysub);
+        dfree(bk->blam);
+        dfree(bk->bgpart);
+        bk->bwd_cap = 0;
+        hipError_t e = dalloc(&bk->ysub, (size_t)nseg * ((bk->L + kSub - 1) / kSub) * S);
+        if (e == hipSuccess) e = dalloc(&bk->blam, (size_t)2 * nseg * S);
+        if (e == hipSuccess) e = dalloc(&bk->bgpart, (size_t)2 * nseg * S);
+        if (e != hipSuccess) {
+            dfree(bk->ysub);
+            dfree(bk->blam);
+            dfree(bk->bgpart);
+            return fail(SPIIR_ENOMEM, "adjoint scratch allocation failed: %s", hipGetErrorString(e));
+        }
+        bk->bwd_cap = nseg;
+    }
     a.ysub = bk->ysub;
+    a.lam_loc = bk->blam;
+    a.lam_in = bk->blam + (size_t)nseg * S;
+    a.gpart = bk->bgpart;
+    a.nseg = nseg;
+    a.seg_chunks = (int32_t)seg_chunks;
     a.grad_a = reinterpret_cast<float2 *>(ga);
     a.grad_b = reinterpret_cast<float2 *>(gb);
     a.n = tp->n;

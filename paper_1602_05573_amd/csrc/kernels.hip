@@ -18,6 +18,8 @@
 //     state plus the in-chunk response);
 //   * epilogues: per-template SNR rows, z rows, or a fused per-sample
 //     max/argmax encoded as a 64-bit key (SNR bits << 32 | ~template).
+#include <hip/hip_ext.h>
+
 #include "spiir_internal.h"
 
 namespace spiir {
@@ -66,32 +68,38 @@ struct Lane {
     __device__ __forceinline__ int64_t slot(int f) const { return slot0 + 64 * f; }
 };
 
-constexpr int kAhead = 2;  // steps of x[m - d] read ahead of their use
+// Steps of x[m - d] read ahead of their use: short for the LDS window, longer
+// when the window stays in global memory (so more of the load latency is
+// covered by the recursion itself).
+template <bool XLDS, int TT>
+struct Ahead {
+    static constexpr int value = XLDS ? 2 : (TT >= 16 ? 8 : 4);
+};
 
-// x[m - d] of every filter for steps t0 .. t0 + kAhead - 1 of a tile. The
-// window is padded by one tile, so reads past the sub-block end stay inside it
-// (their values are never used).
-template <int FL, int TT>
+// x[m - d] of every filter for steps t0 .. t0 + AH - 1 of a tile. The window
+// is padded by one tile, so reads past the sub-block end stay inside it (their
+// values are never used).
+template <int FL, int TT, int AH>
 __device__ __forceinline__ void load_ahead(float (&xv)[TT][FL], const float *xw, const Lane<FL> &s, int t0) {
 #pragma unroll
     for (int f = 0; f < FL; ++f) {
         const float *xp = xw + (s.xo[f] + t0);
 #pragma unroll
-        for (int t = 0; t < kAhead; ++t) xv[t][f] = xp[t];
+        for (int t = 0; t < AH; ++t) xv[t][f] = xp[t];
     }
 }
 
 // One tile: FL filter updates per step and per lane, the lane's partial
 // template sum of every step written to the wave's LDS tile [TT][64]. x for
-// step t + kAhead is read while step t computes (xv[0..kAhead) arrive loaded).
-template <int FL, int TT, bool FULL, bool CARRY>
+// step t + AH is read while step t computes (xv[0..AH) arrive loaded).
+template <int FL, int TT, bool FULL, bool CARRY, int AH>
 __device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], const float *xw, int t0,
                                              int steps, float2 *wt, int lane) {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-        if (!CARRY && t + kAhead < TT) {
+        if (!CARRY && t + AH < TT) {
 #pragma unroll
-            for (int f = 0; f < FL; ++f) xv[t + kAhead][f] = xw[s.xo[f] + t0 + t + kAhead];
+            for (int f = 0; f < FL; ++f) xv[t + AH][f] = xw[s.xo[f] + t0 + t + AH];
         }
         if (!FULL && t >= steps) continue;  // uniform; keeps every index static
         float pr = 0.f, pi = 0.f;
@@ -227,6 +235,21 @@ struct SegCtx {
     int64_t ld_zl;
 };
 
+// Tape entry (chunk-start state as float-float hi/lo) of filter f. The carry
+// pass adds its state to the local entry already there, in FP64.
+template <int FL, bool ADD>
+__device__ __forceinline__ void tape_put(float4 *tp, const Lane<FL> &s, int f) {
+    if (ADD) {
+        const float4 o = *tp;
+        const double cr = ((double)o.x + (double)o.z) + ((double)s.yr[f] + (double)s.l0r[f]);
+        const double ci = ((double)o.y + (double)o.w) + ((double)s.yi[f] + (double)s.l0i[f]);
+        const float hr = (float)cr, hi = (float)ci;
+        *tp = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+    } else {
+        *tp = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+    }
+}
+
 // The whole forward pass of workgroup g over launch samples [sc.tb, sc.tb + sc.tn).
 // CARRY: free response of the given state only (no input), z_local added.
 template <int FL, int TT, int MODE, bool XLDS, bool CARRY>
@@ -239,6 +262,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
     float2 *wsum = reinterpret_cast<float2 *>(smem + win_bytes) + W * TT * 64;  // [2][TT][Rp]
     unsigned long long *kmax = reinterpret_cast<unsigned long long *>(wsum + 2 * TT * Rp);  // [2][TT]
     const RowSumPlan<TT> rsp = row_sum_plan<TT>(lane);
+    constexpr int AH = Ahead<XLDS, TT>::value;
 
     const int row = wave * 4 + (lane >> 4);
     const RowInfo ri = p.rows[(int64_t)g * R + row];
@@ -272,11 +296,11 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
     const int64_t n = sc.tn;
     const int64_t xbase = p.xbase + sc.tb;
     if (keys_out && tid < 2 * TT) kmax[tid] = 0ull;
+    // tape chunk index of the item's first sample (items start on chunk bounds)
+    const int64_t tchunk0 = p.chunk0 + sc.tb / p.L;
     if (MODE == kModeZ && ract && p.tape) {
 #pragma unroll
-        for (int f = 0; f < FL; ++f)
-            p.tape[(int64_t)p.chunk0 * p.nslots + s.slot(f)] =
-                make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+        for (int f = 0; f < FL; ++f) tape_put<FL, CARRY>(p.tape + tchunk0 * p.nslots + s.slot(f), s, f);
     }
 
     int64_t chunk_start = 0;
@@ -305,18 +329,18 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
         } else {
             xw = p.xwin + (xbase + s0);
         }
-        if (!CARRY && wact) load_ahead<FL, TT>(xv, xw, s, 0);
+        if (!CARRY && wact) load_ahead<FL, TT, AH>(xv, xw, s, 0);
 
         for (int t0 = 0; t0 < nbs; t0 += TT) {
             const int steps = min(TT, nbs - t0);
             if (wact) {
                 if (steps == TT)
-                    compute_tile<FL, TT, true, CARRY>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, true, CARRY, AH>(s, xv, xw, t0, steps, wt, lane);
                 else
-                    compute_tile<FL, TT, false, CARRY>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, false, CARRY, AH>(s, xv, xw, t0, steps, wt, lane);
                 wave_lds_sync();
                 row_sums<TT>(wt, rsp, wsum + buf * TT * Rp, Rp, wave, lane);
-                if (!CARRY && t0 + TT < nbs) load_ahead<FL, TT>(xv, xw, s, t0 + TT);
+                if (!CARRY && t0 + TT < nbs) load_ahead<FL, TT, AH>(xv, xw, s, t0 + TT);
             }
             __syncthreads();
             if (keys_out && pending && wave == 0 && lane < pend_steps) {
@@ -369,8 +393,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
                     if (MODE == kModeZ && ract && p.tape && tend < n) {
 #pragma unroll
                         for (int f = 0; f < FL; ++f)
-                            p.tape[(p.chunk0 + chunk_idx + 1) * p.nslots + s.slot(f)] =
-                                make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+                            tape_put<FL, CARRY>(p.tape + (tchunk0 + chunk_idx + 1) * p.nslots + s.slot(f), s, f);
                     }
                 }
                 chunk_start = tend;
@@ -425,9 +448,14 @@ __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
     sc.tn = min(p.seg_len, p.n - sc.tb);
     sc.st_in = seg == 0 ? p.state : nullptr;
     sc.st_out = p.seg_end + (int64_t)seg * p.nslots;
-    sc.zl_out = seg == 0 ? nullptr : p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
+    if (MODE == kModeZ) {  // the local z goes straight to the output rows; the carry pass adds to it
+        sc.zl_out = seg == 0 ? nullptr : p.z + p.obase + sc.tb;
+        sc.ld_zl = p.ld;
+    } else {
+        sc.zl_out = seg == 0 ? nullptr : p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
+        sc.ld_zl = p.seg_len;
+    }
     sc.zl_in = nullptr;
-    sc.ld_zl = p.seg_len;
     fwd_group<FL, TT, MODE, XLDS, false>(p, g, smem, sc);
 }
 
@@ -443,8 +471,13 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     sc.st_in = p.seg_start + (int64_t)seg * p.nslots;
     sc.st_out = nullptr;
     sc.zl_out = nullptr;
-    sc.zl_in = p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
-    sc.ld_zl = p.seg_len;
+    if (MODE == kModeZ) {
+        sc.zl_in = p.z + p.obase + sc.tb;
+        sc.ld_zl = p.ld;
+    } else {
+        sc.zl_in = p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
+        sc.ld_zl = p.seg_len;
+    }
     fwd_group<FL, TT, MODE, false, true>(p, g, smem, sc);
 }
 
@@ -575,32 +608,248 @@ __global__ void noise_fill_kernel(float *x, int64_t n, uint32_t seed) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint. Each lane owns FL filter slots and handles them one after another:
-// chunks in reverse order; y is recomputed from the tape (chunk-start state),
-// first over the whole chunk keeping every kSub-th state in scratch memory,
-// then per sub-chunk into registers; lambda runs backwards with conj(a).
+// Adjoint. The reverse recursion lambda[m] = G[m] + conj(a) lambda[m+1] is
+// linear, so the stream is cut into nseg segments of whole chunks and, inside
+// a segment [s0, e),
+//     lambda[m] = lambda_loc[m] + conj(a)^(e - m) lambda[e],
+// with lambda_loc started from zero at e. bwd_scan_kernel runs lambda_loc over
+// every segment but the first (reading only G), bwd_chain_kernel composes the
+// segments from the end in FP64, which gives the true lambda entering each
+// segment, and bwd_seg_kernel runs the full backward of every segment from
+// that value: chunks in reverse order, y recomputed from the tape (chunk-start
+// state), first over the whole chunk keeping every kSub-th state in scratch
+// memory, then per sub-chunk in registers. bwd_reduce_kernel adds the
+// per-segment gradients in FP64 in segment order.
 // ---------------------------------------------------------------------------
+
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// v[t] = p[t] for t < ql, else 0; full runs use 16-byte loads (p is only
+// 4-byte aligned, which global loads accept).
+__device__ __forceinline__ void fetch_x(const float *p, int ql, float (&v)[kSub]) {
+    if (ql == kSub) {
+#pragma unroll
+        for (int i = 0; i < kSub / 4; ++i) {
+            const f4u q = *reinterpret_cast<const f4u *>(p + 4 * i);
+            v[4 * i] = q.x;
+            v[4 * i + 1] = q.y;
+            v[4 * i + 2] = q.z;
+            v[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < kSub; ++t) v[t] = t < ql ? p[t] : 0.f;
+    }
+}
+
+__device__ __forceinline__ void fetch_g(const float2 *p, int ql, float (&gr)[kSub], float (&gi)[kSub]) {
+    if (ql == kSub) {
+#pragma unroll
+        for (int i = 0; i < kSub / 2; ++i) {
+            const f4u q = *reinterpret_cast<const f4u *>(p + 2 * i);
+            gr[2 * i] = q.x;
+            gi[2 * i] = q.y;
+            gr[2 * i + 1] = q.z;
+            gi[2 * i + 1] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < kSub; ++t) {
+            const float2 g = t < ql ? p[t] : make_float2(0.f, 0.f);
+            gr[t] = g.x;
+            gi[t] = g.y;
+        }
+    }
+}
+
+// conj(a^l - fl32(a)^l): the part of an l-step lambda carry that a recursion
+// with fl32(a) misses (added as times lambda entering the chunk).
+__device__ __forceinline__ float2 lam_drift(const SlotArrays &s, int64_t slot, int l, int L, float ar, float ai) {
+    double2 dl;
+    if (l == L) {
+        dl = s.dL[slot];
+    } else {
+        const double2 al = cpow64(s.a64[slot], l);
+        const double2 ah = cpow64(make_double2((double)ar, (double)ai), l);
+        dl = make_double2(al.x - ah.x, al.y - ah.y);
+    }
+    return make_float2((float)dl.x, (float)dl.y);
+}
+
+struct BwdWave {
+    int g, wave, lane;
+    RowInfo ri;
+};
+
+__device__ __forceinline__ BwdWave bwd_wave(const BwdArgs &p) {
+    BwdWave w;
+    w.lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    w.g = gw / p.wpg;
+    w.wave = gw % p.wpg;
+    w.ri = p.rows[(int64_t)w.g * 4 * p.wpg + w.wave * 4 + (w.lane >> 4)];
+    return w;
+}
+
+// lambda[m] = G[m] + conj(a) lambda[m+1] over one sub-chunk, last step first
+// (FULL: all kSub steps, no per-step guard).
+template <int FL, bool FULL>
+__device__ __forceinline__ void lam_steps(float (&lr)[FL], float (&li)[FL], const float (&ar)[FL],
+                                          const float (&ai)[FL], const float (&gr)[kSub], const float (&gi)[kSub],
+                                          int ql) {
+#pragma unroll
+    for (int t = kSub - 1; t >= 0; --t) {
+        if (FULL || t < ql) {
+#pragma unroll
+            for (int f = 0; f < FL; ++f) {
+                const float nr = fmaf(ar[f], lr[f], fmaf(ai[f], li[f], gr[t]));
+                const float ni = fmaf(ar[f], li[f], fmaf(-ai[f], lr[f], gi[t]));
+                lr[f] = nr;
+                li[f] = ni;
+            }
+        }
+    }
+}
+
+// Forward recursion over one sub-chunk from (yr, yi).
+template <bool FULL>
+__device__ __forceinline__ void y_steps(float &yr, float &yi, float ar, float ai, float br, float bi,
+                                        const float (&xv)[kSub], int ql) {
+#pragma unroll
+    for (int t = 0; t < kSub; ++t) {
+        if (FULL || t < ql) {
+            const float nr = fmaf(-ai, yi, fmaf(ar, yr, br * xv[t]));
+            const float ni = fmaf(ai, yr, fmaf(ar, yi, bi * xv[t]));
+            yr = nr;
+            yi = ni;
+        }
+    }
+}
+
+// Reverse sweep of one sub-chunk: lambda, and the gradient sums
+// sb += lambda x[m - d], sa += lambda conj(y[m - 1]); hr/hi hold y[m - 1].
+template <bool FULL>
+__device__ __forceinline__ void adj_steps(float &lr, float &li, float ar, float ai, const float (&xv)[kSub],
+                                          const float (&gr)[kSub], const float (&gi)[kSub],
+                                          const float (&hr)[kSub + 1], const float (&hi)[kSub + 1], float &sar,
+                                          float &sai, float &sbr, float &sbi, int ql) {
+#pragma unroll
+    for (int t = kSub - 1; t >= 0; --t) {
+        if (FULL || t < ql) {
+            const float nr = fmaf(ar, lr, fmaf(ai, li, gr[t]));
+            const float ni = fmaf(ar, li, fmaf(-ai, lr, gi[t]));
+            lr = nr;
+            li = ni;
+            sbr = fmaf(lr, xv[t], sbr);
+            sbi = fmaf(li, xv[t], sbi);
+            sar = fmaf(lr, hr[t], fmaf(li, hi[t], sar));
+            sai = fmaf(li, hr[t], fmaf(-lr, hi[t], sai));
+        }
+    }
+}
+
+// Segment-local lambda at the start of segment blockIdx.y + 1. The FL filters
+// of a lane share their template's G and run side by side.
 template <int FL>
-__global__ void __launch_bounds__(256) bwd_kernel(BwdArgs p) {
-    const int tid = threadIdx.x, lane = tid & 63, wave_in_block = tid >> 6;
-    const int waves_per_block = blockDim.x >> 6;
-    const int gw = blockIdx.x * waves_per_block + wave_in_block;  // global wave
-    const int g = gw / p.wpg, wave = gw % p.wpg;
-    const RowInfo ri = p.rows[(int64_t)g * 4 * p.wpg + wave * 4 + (lane >> 4)];
-    if (ri.tpl < 0) return;
-    const int64_t n = p.n;
-    const int64_t nch = (n + p.L - 1) / p.L;
-    const float2 *gz = p.gz + (int64_t)ri.tpl * n;
+__global__ void __launch_bounds__(256) bwd_scan_kernel(BwdArgs p) {
+    const BwdWave w = bwd_wave(p);
+    if (w.ri.tpl < 0) return;
+    const int seg = blockIdx.y + 1;
+    const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
+    const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
+    const float2 *gz = p.gz + (int64_t)w.ri.tpl * n;
+    float ar[FL], ai[FL], lr[FL], li[FL];
+    int64_t slot[FL];
+#pragma unroll
     for (int f = 0; f < FL; ++f) {
-        const int64_t slot = slot_index(g, p.wpg, wave, f, FL, lane);
-        const int k = p.slot_filter[slot];
-        if (k < 0) continue;
+        slot[f] = slot_index(w.g, p.wpg, w.wave, f, FL, w.lane);
+        const float2 a = p.s.a32[slot[f]];
+        ar[f] = a.x;
+        ai[f] = a.y;
+        lr[f] = 0.f;
+        li[f] = 0.f;
+    }
+    for (int64_t c = ce - 1; c >= cs; --c) {
+        const int64_t c0 = c * p.L;
+        const int l = (int)min((int64_t)p.L, n - c0);
+        const int nq = (l + kSub - 1) / kSub;
+        float lin_r[FL], lin_i[FL];
+#pragma unroll
+        for (int f = 0; f < FL; ++f) {
+            lin_r[f] = lr[f];
+            lin_i[f] = li[f];
+        }
+        for (int q = nq - 1; q >= 0; --q) {
+            const int qs = q * kSub, ql = min(kSub, l - qs);
+            float gr[kSub], gi[kSub];
+            fetch_g(gz + c0 + qs, ql, gr, gi);
+            if (ql == kSub)
+                lam_steps<FL, true>(lr, li, ar, ai, gr, gi, ql);
+            else
+                lam_steps<FL, false>(lr, li, ar, ai, gr, gi, ql);
+        }
+        if (p.prec != kPrecFp32) {
+#pragma unroll
+            for (int f = 0; f < FL; ++f) {
+                const float2 d = lam_drift(p.s, slot[f], l, p.L, ar[f], ai[f]);
+                lr[f] = fmaf(d.x, lin_r[f], fmaf(d.y, lin_i[f], lr[f]));
+                li[f] = fmaf(d.x, lin_i[f], fmaf(-d.y, lin_r[f], li[f]));
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FL; ++f) p.lam_loc[(int64_t)seg * p.nslots + slot[f]] = make_float2(lr[f], li[f]);
+}
+
+// True lambda entering every segment from the right (zero for the last one):
+// lambda[s0] = lambda_loc[s0] + conj(a)^(e - s0) lambda[e], in FP64 (with
+// fl32(a) in the all-FP32 mode).
+__global__ void __launch_bounds__(256) bwd_chain_kernel(BwdArgs p) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= p.nslots) return;
+    const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
+    double2 a = p.s.a64[slot];
+    if (p.prec == kPrecFp32) {
+        const float2 a32 = p.s.a32[slot];
+        a = make_double2((double)a32.x, (double)a32.y);
+    }
+    double lr = 0.0, li = 0.0;
+    for (int seg = p.nseg - 1; seg >= 0; --seg) {
+        p.lam_in[(int64_t)seg * p.nslots + slot] = make_float2((float)lr, (float)li);
+        if (seg == 0) break;
+        const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
+        const int64_t len = min(n, ce * p.L) - cs * p.L;
+        const double2 al = cpow64(a, len);            // conj(a)^len = conj(a^len)
+        const float2 loc = p.lam_loc[(int64_t)seg * p.nslots + slot];
+        const double nr = (double)loc.x + al.x * lr + al.y * li;
+        const double ni = (double)loc.y + al.x * li - al.y * lr;
+        lr = nr;
+        li = ni;
+    }
+}
+
+// Full backward of segment blockIdx.y from its true incoming lambda; one
+// filter slot after another per lane.
+template <int FL>
+__global__ void __launch_bounds__(256) bwd_seg_kernel(BwdArgs p) {
+    const BwdWave w = bwd_wave(p);
+    if (w.ri.tpl < 0) return;
+    const int seg = blockIdx.y;
+    const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
+    const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
+    const int nqmax = (p.L + kSub - 1) / kSub;
+    float2 *ysub = p.ysub + (int64_t)seg * nqmax * p.nslots;
+    const float2 *gz = p.gz + (int64_t)w.ri.tpl * n;
+    for (int f = 0; f < FL; ++f) {
+        const int64_t slot = slot_index(w.g, p.wpg, w.wave, f, FL, w.lane);
+        if (p.slot_filter[slot] < 0) continue;
         const float2 a = p.s.a32[slot], b = p.s.b32[slot];
         const float ar = a.x, ai = a.y, br = b.x, bi = b.y;
         const float *xw = p.xwin + p.s.xoff[slot];  // xw[m] = x[m - d]
         double gar = 0.0, gai = 0.0, gbr = 0.0, gbi = 0.0;
-        float lr = 0.f, li = 0.f;  // lambda at the sample after the current chunk
-        for (int64_t c = nch - 1; c >= 0; --c) {
+        const float2 lam = p.lam_in[(int64_t)seg * p.nslots + slot];
+        float lr = lam.x, li = lam.y;  // lambda at the sample after the current chunk
+        for (int64_t c = ce - 1; c >= cs; --c) {
             const int64_t c0 = c * p.L;
             const int l = (int)min((int64_t)p.L, n - c0);
             const int nq = (l + kSub - 1) / kSub;
@@ -608,77 +857,68 @@ __global__ void __launch_bounds__(256) bwd_kernel(BwdArgs p) {
             const float4 tp = p.tape[c * p.nslots + slot];
             float yr = tp.x, yi = tp.y;
             for (int q = 0; q < nq; ++q) {
-                p.ysub[(int64_t)q * p.nslots + slot] = make_float2(yr, yi);
+                ysub[(int64_t)q * p.nslots + slot] = make_float2(yr, yi);
                 const int qs = q * kSub, ql = min(kSub, l - qs);
-#pragma unroll
-                for (int t = 0; t < kSub; ++t) {
-                    if (t < ql) {
-                        const float xv = xw[c0 + qs + t];
-                        const float nr = fmaf(-ai, yi, fmaf(ar, yr, br * xv));
-                        const float ni = fmaf(ai, yr, fmaf(ar, yi, bi * xv));
-                        yr = nr;
-                        yi = ni;
-                    }
-                }
+                float xv[kSub];
+                fetch_x(xw + c0 + qs, ql, xv);
+                if (ql == kSub)
+                    y_steps<true>(yr, yi, ar, ai, br, bi, xv, ql);
+                else
+                    y_steps<false>(yr, yi, ar, ai, br, bi, xv, ql);
             }
             // pass 2: sub-chunks in reverse
             const float lin_r = lr, lin_i = li;
             float sar = 0.f, sai = 0.f, sbr = 0.f, sbi = 0.f;
             for (int q = nq - 1; q >= 0; --q) {
                 const int qs = q * kSub, ql = min(kSub, l - qs);
+                float xv[kSub], gr[kSub], gi[kSub];
+                fetch_x(xw + c0 + qs, ql, xv);
+                fetch_g(gz + c0 + qs, ql, gr, gi);
                 float hr[kSub + 1], hi[kSub + 1];  // hr[t] = y[m - 1] for m = c0 + qs + t
-                const float2 y0 = p.ysub[(int64_t)q * p.nslots + slot];
+                const float2 y0 = ysub[(int64_t)q * p.nslots + slot];
                 hr[0] = y0.x;
                 hi[0] = y0.y;
 #pragma unroll
                 for (int t = 0; t < kSub; ++t) {
-                    if (t < ql) {
-                        const float xv = xw[c0 + qs + t];
-                        hr[t + 1] = fmaf(-ai, hi[t], fmaf(ar, hr[t], br * xv));
-                        hi[t + 1] = fmaf(ai, hr[t], fmaf(ar, hi[t], bi * xv));
-                    }
+                    hr[t + 1] = fmaf(-ai, hi[t], fmaf(ar, hr[t], br * xv[t]));
+                    hi[t + 1] = fmaf(ai, hr[t], fmaf(ar, hi[t], bi * xv[t]));
                 }
-#pragma unroll
-                for (int t = kSub - 1; t >= 0; --t) {
-                    if (t < ql) {
-                        const int64_t m = c0 + qs + t;
-                        const float2 gm = gz[m];
-                        // lambda[m] = G[m] + conj(a) lambda[m+1]
-                        const float nr = gm.x + fmaf(ar, lr, ai * li);
-                        const float ni = gm.y + fmaf(ar, li, -ai * lr);
-                        lr = nr;
-                        li = ni;
-                        const float xv = xw[m];
-                        sbr = fmaf(lr, xv, sbr);
-                        sbi = fmaf(li, xv, sbi);
-                        // lambda * conj(y[m-1])
-                        sar = fmaf(lr, hr[t], fmaf(li, hi[t], sar));
-                        sai = fmaf(li, hr[t], fmaf(-lr, hi[t], sai));
-                    }
-                }
+                if (ql == kSub)
+                    adj_steps<true>(lr, li, ar, ai, xv, gr, gi, hr, hi, sar, sai, sbr, sbi, ql);
+                else
+                    adj_steps<false>(lr, li, ar, ai, xv, gr, gi, hr, hi, sar, sai, sbr, sbi, ql);
             }
             if (p.prec != kPrecFp32) {
-                // carry of lambda across the chunk used conj(fl32(a))^l; add conj(a^l - fl32(a)^l) lambda_in
-                double2 dl;
-                if (l == p.L) {
-                    dl = p.s.dL[slot];
-                } else {
-                    const double2 al = cpow64(p.s.a64[slot], l);
-                    const double2 ah = cpow64(make_double2((double)ar, (double)ai), l);
-                    dl = make_double2(al.x - ah.x, al.y - ah.y);
-                }
-                const float dr = (float)dl.x, di = (float)dl.y;
-                lr = fmaf(dr, lin_r, fmaf(di, lin_i, lr));
-                li = fmaf(dr, lin_i, fmaf(-di, lin_r, li));
+                const float2 d = lam_drift(p.s, slot, l, p.L, ar, ai);
+                lr = fmaf(d.x, lin_r, fmaf(d.y, lin_i, lr));
+                li = fmaf(d.x, lin_i, fmaf(-d.y, lin_r, li));
             }
             gar += (double)sar;
             gai += (double)sai;
             gbr += (double)sbr;
             gbi += (double)sbi;
         }
-        p.grad_a[k] = make_float2((float)gar, (float)gai);
-        p.grad_b[k] = make_float2((float)gbr, (float)gbi);
+        p.gpart[((int64_t)seg * 2 + 0) * p.nslots + slot] = make_double2(gar, gai);
+        p.gpart[((int64_t)seg * 2 + 1) * p.nslots + slot] = make_double2(gbr, gbi);
     }
+}
+
+__global__ void __launch_bounds__(256) bwd_reduce_kernel(BwdArgs p) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= p.nslots) return;
+    const int k = p.slot_filter[slot];
+    if (k < 0) return;
+    double gar = 0.0, gai = 0.0, gbr = 0.0, gbi = 0.0;
+    for (int seg = 0; seg < p.nseg; ++seg) {
+        const double2 ga = p.gpart[((int64_t)seg * 2 + 0) * p.nslots + slot];
+        const double2 gb = p.gpart[((int64_t)seg * 2 + 1) * p.nslots + slot];
+        gar += ga.x;
+        gai += ga.y;
+        gbr += gb.x;
+        gbi += gb.y;
+    }
+    p.grad_a[k] = make_float2((float)gar, (float)gai);
+    p.grad_b[k] = make_float2((float)gbr, (float)gbi);
 }
 
 // Batch bookkeeping.
@@ -720,36 +960,39 @@ __global__ void batch_advance_kernel(int64_t *pos, const BatchStream *streams, i
 }
 
 template <int FL, int TT, int MODE, bool XLDS>
-hipError_t launch_fwd_t(const FwdArgs &a, int groups, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS>), dim3(groups), dim3(a.wpg * 64), lds, st, a);
+hipError_t launch_fwd_t(const FwdArgs &a, int groups, size_t lds, hipStream_t st, KernelEvents ev) {
+    hipExtLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS>), dim3(groups), dim3(a.wpg * 64), (uint32_t)lds, st,
+                          ev.start, ev.stop, 0u, a);
     return hipGetLastError();
 }
 
 template <int TT, int MODE, bool XLDS>
-hipError_t launch_fwd_m(const FwdArgs &a, int fl, int groups, size_t lds, hipStream_t st) {
+hipError_t launch_fwd_m(const FwdArgs &a, int fl, int groups, size_t lds, hipStream_t st, KernelEvents ev) {
     switch (fl) {
-        case 1: return launch_fwd_t<1, TT, MODE, XLDS>(a, groups, lds, st);
-        case 2: return launch_fwd_t<2, TT, MODE, XLDS>(a, groups, lds, st);
-        case 3: return launch_fwd_t<3, TT, MODE, XLDS>(a, groups, lds, st);
-        case 4: return launch_fwd_t<4, TT, MODE, XLDS>(a, groups, lds, st);
+        case 1: return launch_fwd_t<1, TT, MODE, XLDS>(a, groups, lds, st, ev);
+        case 2: return launch_fwd_t<2, TT, MODE, XLDS>(a, groups, lds, st, ev);
+        case 3: return launch_fwd_t<3, TT, MODE, XLDS>(a, groups, lds, st, ev);
+        case 4: return launch_fwd_t<4, TT, MODE, XLDS>(a, groups, lds, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int TT, bool XLDS>
-hipError_t launch_fwd_x(const FwdArgs &a, int mode, int fl, int groups, size_t lds, hipStream_t st) {
+hipError_t launch_fwd_x(const FwdArgs &a, int mode, int fl, int groups, size_t lds, hipStream_t st,
+                        KernelEvents ev) {
     switch (mode) {
-        case kModeSnr: return launch_fwd_m<TT, kModeSnr, XLDS>(a, fl, groups, lds, st);
-        case kModeKeys: return launch_fwd_m<TT, kModeKeys, XLDS>(a, fl, groups, lds, st);
-        case kModeZ: return launch_fwd_m<TT, kModeZ, XLDS>(a, fl, groups, lds, st);
+        case kModeSnr: return launch_fwd_m<TT, kModeSnr, XLDS>(a, fl, groups, lds, st, ev);
+        case kModeKeys: return launch_fwd_m<TT, kModeKeys, XLDS>(a, fl, groups, lds, st, ev);
+        case kModeZ: return launch_fwd_m<TT, kModeZ, XLDS>(a, fl, groups, lds, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int FL, int TT, int MODE, bool XLDS>
 hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_carry, const int32_t *slot_filter,
-                          hipStream_t st) {
-    hipLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS>), dim3(a.groups * nseg), dim3(a.wpg * 64), lds, st, a);
+                          hipStream_t st, KernelEvents ev) {
+    hipExtLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS>), dim3(a.groups * nseg), dim3(a.wpg * 64),
+                          (uint32_t)lds, st, ev.start, (hipEvent_t) nullptr, 0u, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((a.nslots + 255) / 256);
@@ -757,28 +1000,29 @@ hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_car
                        slot_filter, a.nslots, nseg, a.seg_len, a.n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64), lds_carry, st,
-                       a);
+    hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),
+                          (uint32_t)lds_carry, st, (hipEvent_t) nullptr, ev.stop, 0u, a);
     return hipGetLastError();
 }
 
 template <int TT, int MODE, bool XLDS>
 hipError_t launch_split_m(const FwdArgs &a, int fl, int nseg, size_t lds, size_t ldc, const int32_t *sf,
-                          hipStream_t st) {
+                          hipStream_t st, KernelEvents ev) {
     switch (fl) {
-        case 1: return launch_split_t<1, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
-        case 2: return launch_split_t<2, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
-        case 3: return launch_split_t<3, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
-        case 4: return launch_split_t<4, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st);
+        case 1: return launch_split_t<1, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st, ev);
+        case 2: return launch_split_t<2, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st, ev);
+        case 3: return launch_split_t<3, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st, ev);
+        case 4: return launch_split_t<4, TT, MODE, XLDS>(a, nseg, lds, ldc, sf, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int TT, bool XLDS>
 hipError_t launch_split_x(const FwdArgs &a, int mode, int fl, int nseg, size_t lds, size_t ldc, const int32_t *sf,
-                          hipStream_t st) {
-    if (mode == kModeSnr) return launch_split_m<TT, kModeSnr, XLDS>(a, fl, nseg, lds, ldc, sf, st);
-    if (mode == kModeKeys) return launch_split_m<TT, kModeKeys, XLDS>(a, fl, nseg, lds, ldc, sf, st);
+                          hipStream_t st, KernelEvents ev) {
+    if (mode == kModeSnr) return launch_split_m<TT, kModeSnr, XLDS>(a, fl, nseg, lds, ldc, sf, st, ev);
+    if (mode == kModeKeys) return launch_split_m<TT, kModeKeys, XLDS>(a, fl, nseg, lds, ldc, sf, st, ev);
+    if (mode == kModeZ) return launch_split_m<TT, kModeZ, XLDS>(a, fl, nseg, lds, ldc, sf, st, ev);
     return hipErrorInvalidValue;
 }
 
@@ -801,26 +1045,27 @@ size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt) {
 }
 
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
-                          size_t lds, hipStream_t st) {
+                          size_t lds, hipStream_t st, KernelEvents ev) {
     if (groups <= 0) return hipSuccess;
     if (tt == 16)
-        return x_in_lds ? launch_fwd_x<16, true>(a, mode, fl, groups, lds, st)
-                        : launch_fwd_x<16, false>(a, mode, fl, groups, lds, st);
+        return x_in_lds ? launch_fwd_x<16, true>(a, mode, fl, groups, lds, st, ev)
+                        : launch_fwd_x<16, false>(a, mode, fl, groups, lds, st, ev);
     if (tt == 8)
-        return x_in_lds ? launch_fwd_x<8, true>(a, mode, fl, groups, lds, st)
-                        : launch_fwd_x<8, false>(a, mode, fl, groups, lds, st);
+        return x_in_lds ? launch_fwd_x<8, true>(a, mode, fl, groups, lds, st, ev)
+                        : launch_fwd_x<8, false>(a, mode, fl, groups, lds, st, ev);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int nseg, size_t lds,
-                                size_t lds_carry, const int32_t *slot_filter, hipStream_t st) {
+                                size_t lds_carry, const int32_t *slot_filter, hipStream_t st,
+                                KernelEvents ev) {
     if (a.groups <= 0 || nseg < 2) return hipErrorInvalidValue;
     if (tt == 16)
-        return x_in_lds ? launch_split_x<16, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st)
-                        : launch_split_x<16, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st);
+        return x_in_lds ? launch_split_x<16, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev)
+                        : launch_split_x<16, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev);
     if (tt == 8)
-        return x_in_lds ? launch_split_x<8, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st)
-                        : launch_split_x<8, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st);
+        return x_in_lds ? launch_split_x<8, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev)
+                        : launch_split_x<8, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev);
     return hipErrorInvalidValue;
 }
 
@@ -911,20 +1156,37 @@ hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int FL>
+hipError_t launch_backward_t(const BwdArgs &a, dim3 wgrid, dim3 block, hipStream_t st) {
+    if (a.nseg > 1) {
+        hipLaunchKernelGGL(bwd_scan_kernel<FL>, dim3(wgrid.x, a.nseg - 1), block, 0, st, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bwd_chain_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bwd_seg_kernel<FL>, dim3(wgrid.x, a.nseg), block, 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bwd_reduce_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t st) {
     const int total_waves = groups * a.wpg;
     if (total_waves <= 0) return hipSuccess;
+    if (a.nseg < 1 || a.nseg > 65535 || a.seg_chunks < 1) return hipErrorInvalidValue;
     // 4 waves per block; the wave count of a bank is a multiple of wpg, pad to 4
     const int wpb = (total_waves % 4 == 0) ? 4 : (total_waves % 2 == 0 ? 2 : 1);
     const dim3 grid(total_waves / wpb), block(64 * wpb);
     switch (fl) {
-        case 1: hipLaunchKernelGGL(bwd_kernel<1>, grid, block, 0, st, a); break;
-        case 2: hipLaunchKernelGGL(bwd_kernel<2>, grid, block, 0, st, a); break;
-        case 3: hipLaunchKernelGGL(bwd_kernel<3>, grid, block, 0, st, a); break;
-        case 4: hipLaunchKernelGGL(bwd_kernel<4>, grid, block, 0, st, a); break;
+        case 1: return launch_backward_t<1>(a, grid, block, st);
+        case 2: return launch_backward_t<2>(a, grid, block, st);
+        case 3: return launch_backward_t<3>(a, grid, block, st);
+        case 4: return launch_backward_t<4>(a, grid, block, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int FL, int TT>

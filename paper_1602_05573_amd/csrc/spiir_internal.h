@@ -67,10 +67,14 @@ struct BwdArgs {
     const float4 *tape;          // [nchunks][nslots]
     const float *xwin;           // xwin[dmax + m] = x[m] for m in [-dmax, n)
     const float2 *gz;            // [T][n]
-    float2 *ysub;                // scratch [ceil(L / kSub)][nslots]
+    float2 *ysub;                // scratch [nseg][ceil(L / kSub)][nslots]
+    float2 *lam_loc;             // scratch [nseg][nslots]: segment-local lambda at the segment start
+    float2 *lam_in;              // scratch [nseg][nslots]: true lambda entering each segment from the right
+    double2 *gpart;              // scratch [nseg][2][nslots]: per-segment grad_a, grad_b
     float2 *grad_a, *grad_b;     // [F] caller order
     int64_t n, nslots;
     int32_t dmax, L, prec, wpg;
+    int32_t nseg, seg_chunks;    // time segments of seg_chunks chunks each (the last may be shorter)
 };
 
 // One stream of a batch, as the persistent kernel sees it.
@@ -84,15 +88,26 @@ struct BatchStream {
 };
 
 // Launch helpers (kernels.hip). All enqueue on `stream` and return the launch error.
+// Optional kernel timestamps: when set, `start` takes the start time of the
+// first forward kernel of a launch and `stop` the end time of the last one
+// (recorded by the dispatch itself, so no packet is added between kernels).
+struct KernelEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt);
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
-                          size_t lds, hipStream_t stream);
-// Time-split launch (modes kModeSnr / kModeKeys): local pass over every
+                          size_t lds, hipStream_t stream, KernelEvents ev = KernelEvents());
+// Time-split launch (modes kModeSnr / kModeKeys / kModeZ): local pass over every
 // segment, FP64 carry chain, carry-only pass with the local z added.
 hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int nseg,
                                 size_t lds, size_t lds_carry, const int32_t *slot_filter,
-                                hipStream_t stream);
+                                hipStream_t stream, KernelEvents ev = KernelEvents());
 int forward_occupancy(int fl, int tt, int wpg, size_t lds);
+// Adjoint over nseg time segments: segment-local lambda scan, FP64 chain,
+// per-segment backward, FP64 reduction of the per-segment gradients.
+hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t stream);
 hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, float *mx,
@@ -103,7 +118,6 @@ hipError_t launch_window_fill(float *xwin, const float *hist, const float *x, in
                               int dmax, hipStream_t stream);
 int batch_occupancy(int fl, int tt, int wpg, size_t lds);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
-hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
 hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitems,
                         int *counter, const int64_t *pos, int block_len, int fl, int tt, int grid,
                         int wpg, size_t lds, hipStream_t stream);

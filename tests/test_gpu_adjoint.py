@@ -42,12 +42,13 @@ def grad_close(g_gpu, g_ref, off, tol=GRAD_TOL):
     return worst
 
 
-def test_forward_z_parity():
-    banner("forward_z")
+@pytest.mark.parametrize("tsplit,max_block", [(0, 0), (1, 0), (3, 4096), (8, 0)])
+def test_forward_z_parity(tsplit, max_block):
+    banner("forward_z time_split=%d max_block=%d" % (tsplit, max_block))
     bank = random_bank(60, 0, 6, 30, 500, 0.99, 1 - 1e-5, 800)
     x = strain(9001, 60)
     ref = oracle.z(bank, x)
-    with mk(bank, chunk_len=128) as bk:
+    with mk(bank, chunk_len=128, time_split=tsplit, max_block=max_block) as bk:
         z = bk.forward_z(torch.from_numpy(x).cuda()).cpu().numpy()
         # forward_z leaves the streaming state alone: a streaming call still starts cold
         s = bk.filter_block(torch.from_numpy(x).cuda()).cpu().numpy()
@@ -75,6 +76,38 @@ def test_backward_matches_oracle_random_upstream(L, fl):
     ea = grad_close(ga, ga_ref, bank.offsets)
     eb = grad_close(gb, gb_ref, bank.offsets)
     print("grad err a %.3g b %.3g" % (ea, eb))
+
+
+@pytest.mark.parametrize("tsplit,prec", [(1, 0), (2, 0), (5, 0), (8, 2), (3, 1)])
+def test_backward_time_segments(tsplit, prec):
+    """The adjoint cut into time segments (segment-local lambda, FP64 chain,
+    per-segment gradients) against the oracle and against the unsplit run;
+    ragged last chunk and sub-chunk."""
+    banner("backward time_split=%d precision=%d" % (tsplit, prec))
+    bank = random_bank(62, 0, 7, 40, 200, 0.99, 1 - 1e-5, 900)
+    n = 7777
+    x = strain(n, 62)
+    rng = np.random.default_rng(8)
+    G = (rng.standard_normal((7, n)) + 1j * rng.standard_normal((7, n))) * 1e-2
+    ga_ref, gb_ref = oracle.backward(bank, x, G)
+    out = {}
+    for ts in (1, tsplit):
+        with mk(bank, chunk_len=128, filters_per_lane=2, time_split=ts, precision=prec) as bk:
+            xd = torch.from_numpy(x).cuda()
+            z, tape = bk.forward_z(xd, want_tape=True)
+            ga, gb = bk.backward(tape, torch.from_numpy(G.astype(np.complex64)).cuda())
+            out[ts] = (ga.cpu().numpy(), gb.cpu().numpy())
+            tape.close()
+    tol = GRAD_TOL if prec != 1 else 2e-2
+    ga, gb = out[tsplit]
+    ea = grad_close(ga, ga_ref, bank.offsets, tol)
+    eb = grad_close(gb, gb_ref, bank.offsets, tol)
+    # split and unsplit runs differ only by FP32 rounding order
+    ga1, gb1 = out[1]
+    da = np.linalg.norm(ga - ga1) / np.linalg.norm(ga1)
+    db = np.linalg.norm(gb - gb1) / np.linalg.norm(gb1)
+    print("grad err a %.3g b %.3g; split vs unsplit %.3g %.3g" % (ea, eb, da, db))
+    assert da <= tol and db <= tol
 
 
 def test_backward_of_overlap_loss_on_chirps():
