@@ -27,6 +27,7 @@ METRIC = "complex IIR filter-updates/s + % FP32 vector peak; fused vs plain at 1
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed FP32 issue), FLOP/s
 FLOP_UPDATE = 12              # a*y 6 + b*x 2 + add 2 + template accumulation 2
 FLOP_SAMPLE = 4               # |z|^2 3 + compare 1, per template and sample
+FLOP_ADJ = 30                 # adjoint per update: y recompute 10, lambda 8, grad_b 4, grad_a 8
 
 
 def log(*a):
@@ -60,6 +61,7 @@ def main():
     ap.add_argument("--chunk-len", type=int, default=256)
     ap.add_argument("--fl", type=int, default=0, help="filters per lane (0 = library choice)")
     ap.add_argument("--wpg", type=int, default=0)
+    ap.add_argument("--time-split", type=int, default=0, help="time segments (0 = library choice, 1 = off)")
     ap.add_argument("--plain-blocks", type=int, default=4)
     ap.add_argument("--check-blocks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,7 +111,7 @@ def run_bank(args, torch):
     nblk = (N + B - 1) // B
     log("workload: T=%d F=%d N=%d blocks=%d (gen %.1fs)" % (T, F, N, nblk, time.time() - t0))
 
-    bk = SpiirBank.from_bank(bank, chunk_len=args.chunk_len, filters_per_lane=args.fl,
+    bk = SpiirBank.from_bank(bank, chunk_len=args.chunk_len, filters_per_lane=args.fl, time_split=args.time_split,
                              waves_per_group=args.wpg, max_block=max(B, 4096))
     info = bk.info
     log("bank:", info)
@@ -318,7 +320,10 @@ def run_adjoint(args, torch):
 
     bank, x, gs, _ = config3()
     F, T, N = bank.n_filters, bank.n_templates, len(x)
-    bk = SpiirBank.from_bank(bank)
+    bk = SpiirBank.from_bank(bank, filters_per_lane=args.fl, waves_per_group=args.wpg,
+                             time_split=args.time_split)
+    info = bk.info
+    log("bank:", info)
     xd = torch.from_numpy(x).cuda()
     gt = torch.from_numpy(gs.astype(np.complex64)).cuda()
     stream = torch.cuda.current_stream()
@@ -363,10 +368,22 @@ def run_adjoint(args, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (leading-order chirps, chirp masses U[1,30])",
         "config": {"workload": "adjoint fit: %d templates x 400 filters, %d samples, unit impulse input" % (T, N),
-                   "chunk_len": bk.info["chunk_len"], "filters_per_lane": bk.info["filters_per_lane"]},
+                   "chunk_len": info["chunk_len"], "filters_per_lane": info["filters_per_lane"],
+                   "waves_per_group": info["waves_per_group"], "workgroups": info["n_groups"],
+                   "time_split": info["time_split"]},
         "forward_ms": fwd, "loss_ms": loss, "backward_ms": bwd,
         "forward_updates_per_s": updates / (fwd * 1e-3), "backward_updates_per_s": updates / (bwd * 1e-3),
-        "backward_tflops": 30.0 * updates / (bwd * 1e-3) / 1e12,
+        # backward call = lambda scan + FP64 chain + per-segment backward + reduction kernels,
+        # timed with events on the stream they run on
+        "roofline": {"bound": "alu", "achieved": FLOP_ADJ * updates / (bwd * 1e-3) / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": FLOP_ADJ * updates / (bwd * 1e-3) / PEAK_FP32, "traffic": None,
+                     "kernel": "spiir_backward (bwd_scan, bwd_chain, bwd_seg, bwd_reduce)",
+                     "launch_us": bwd * 1e3, "flop_per_launch": FLOP_ADJ * updates},
+        "roofline_forward": {"bound": "alu", "achieved": FLOP_UPDATE * updates / (fwd * 1e-3) / 1e12,
+                             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                             "frac": FLOP_UPDATE * updates / (fwd * 1e-3) / PEAK_FP32,
+                             "kernel": "spiir_forward_z with tape", "launch_us": fwd * 1e3},
     }
     log("adjoint: forward %.2f ms, loss %.2f ms, backward %.2f ms" % (fwd, loss, bwd))
     bk.close()

@@ -235,8 +235,23 @@ int spiir_batch_create(spiir_batch **out, int32_t n_streams, spiir_bank *const *
                        float *const *max_dev, int32_t *const *argmax_dev,
                        int32_t block_len, void *stream);
 
-/* One graph replay on stream: one block of every live stream. */
+/* One graph replay on stream: one block of every live stream.
+ *
+ * A batch holds two graphs. The plain one runs each (stream, workgroup) item
+ * over the whole block. The time-split one cuts each live stream's block into
+ * segments of whole chunks (as spiir_bank_opts.time_split does for one bank:
+ * segment-local pass, FP64 carry chain, carry-only pass), which multiplies the
+ * parallelism of the streams still running. By default a replay uses the
+ * time-split graph when the live streams' workgroups fill at most half of the
+ * device's resident workgroup slots (e.g. the tail of uneven streams); the
+ * results agree with the plain graph to FP32 rounding. */
 int spiir_batch_step(spiir_batch *batch, void *stream);
+
+/* Graph choice of later replays: mode 0 = automatic (above), 1 = always the
+ * plain graph (bitwise equal to per-bank streaming with time_split = 1),
+ * 2 = always the time-split graph. EINVAL for another mode, or for mode 2 when
+ * no stream's block holds two chunks (then no time-split graph exists). */
+int spiir_batch_set_time_split(spiir_batch *batch, int32_t mode);
 
 /* Number of steps until every stream has ended (host-side count). */
 int spiir_batch_steps_total(const spiir_batch *batch, int64_t *steps);

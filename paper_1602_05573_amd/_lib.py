@@ -22,7 +22,7 @@ EXPORTS = (
     "spiir_bank_set_state", "spiir_filter_block", "spiir_trigger_max",
     "spiir_trigger_max_per_template", "spiir_forward_z", "spiir_backward", "spiir_tape_destroy",
     "spiir_batch_create", "spiir_batch_step", "spiir_batch_steps_total", "spiir_batch_reset",
-    "spiir_batch_destroy", "spiir_autotune", "spiir_bank_time_kernels", "spiir_bank_kernel_time",
+    "spiir_batch_destroy", "spiir_batch_set_time_split", "spiir_autotune", "spiir_bank_time_kernels", "spiir_bank_kernel_time",
     "spiir_last_error", "spiir_version",
 )
 
@@ -89,6 +89,7 @@ def load():
         "spiir_batch_steps_total": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
         "spiir_batch_reset": (ctypes.c_int, [P, P]),
         "spiir_batch_destroy": (ctypes.c_int, [P]),
+        "spiir_batch_set_time_split": (ctypes.c_int, [P, I32]),
         "spiir_autotune": (ctypes.c_int, [I32, P, P, P, P, P, I32, I32, I32,
                                           ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "spiir_bank_time_kernels": (ctypes.c_int, [P, I32]),

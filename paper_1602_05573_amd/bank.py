@@ -241,6 +241,10 @@ class SpiirBatch:
     def step(self, stream=None):
         call("spiir_batch_step", self._h, _stream_ptr(stream))
 
+    def set_time_split(self, mode: int):
+        """0 = automatic graph choice, 1 = plain graph only, 2 = time-split graph only."""
+        call("spiir_batch_set_time_split", self._h, int(mode))
+
     def steps_total(self) -> int:
         v = ctypes.c_int64()
         call("spiir_batch_steps_total", self._h, ctypes.byref(v))

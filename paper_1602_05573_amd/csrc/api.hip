@@ -295,6 +295,17 @@ struct spiir_batch {
     int64_t key_stride = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // time-split graph for steps where the live streams alone cannot fill the device
+    // sgraph[k - 1]: the k longest streams live (streams end in order of length)
+    std::vector<hipGraph_t> sgraph;
+    std::vector<hipGraphExec_t> sexec;
+    int2 *seg_items = nullptr, *carry_items = nullptr;
+    std::vector<float4 *> seg_bufs;
+    std::vector<float2 *> zl_bufs;
+    std::vector<int> groups;
+    int64_t slots_dev = 0;   // resident workgroups on the device
+    int split_mode = 0;      // 0 auto, 1 never, 2 always
+    int64_t host_step = 0;   // replays since creation / reset
 };
 
 namespace {
@@ -1123,6 +1134,69 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
     }
     const int occ = std::max(1, batch_occupancy(bt->fl, bt->tt, bt->wpg, bt->lds));
     bt->grid = std::min(bt->nitems, banks[0]->dev.n_cu * occ);
+    bt->slots_dev = (int64_t)banks[0]->dev.n_cu * occ;
+    // time-split plan per stream: segments of whole chunks, enough to fill the
+    // device with this stream alone (at most 8 and at most one per chunk)
+    // Items of the time-split step are grouped by stream, longest stream first,
+    // so that the items of the k live streams are a prefix of the list.
+    std::vector<int> order(ns);
+    for (int s = 0; s < ns; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return lengths[p] > lengths[q]; });
+    std::vector<int2> si, ci;
+    std::vector<int> sp(ns + 1, 0), cp(ns + 1, 0);   // prefix item counts over `order`
+    int64_t max_slots = 0;
+    bool any_split = false;
+    for (int s = 0; s < ns; ++s) bt->groups.push_back(banks[s]->lay.groups);
+    for (int oi = 0; oi < ns; ++oi) {
+        const int s = order[oi];
+        const spiir_bank *bk = banks[s];
+        max_slots = std::max(max_slots, bk->lay.nslots);
+        const int L = bk->L;
+        int want = (int)std::min<int64_t>(8, bt->slots_dev / std::max(1, bk->lay.groups));
+        want = std::max(1, std::min(want, (B + L - 1) / L));
+        const int64_t seg_len = ((B + want - 1) / want + L - 1) / L * L;
+        const int nseg = (int)((B + seg_len - 1) / seg_len);
+        hs[s].args.seg_len = seg_len;
+        any_split = any_split || nseg >= 2;
+        // every stream takes part in the split step (a single segment needs only its end state)
+        float4 *se = nullptr, *ss = nullptr;
+        float2 *zl = nullptr;
+        A(dalloc(&se, (size_t)nseg * bk->lay.nslots));
+        A(dalloc(&ss, (size_t)nseg * bk->lay.nslots));
+        if (nseg >= 2) A(dalloc(&zl, (size_t)(nseg - 1) * bk->T * seg_len));
+        bt->seg_bufs.push_back(se);
+        bt->seg_bufs.push_back(ss);
+        if (zl) bt->zl_bufs.push_back(zl);
+        hs[s].args.seg_end = se;
+        hs[s].args.seg_start = ss;
+        hs[s].args.zl = zl;
+        // this stream's items, largest workgroups first
+        std::vector<int64_t> gf(bk->lay.groups, 0);
+        for (int j = 0; j < bk->T; ++j) gf[bk->lay.tpl_group[j]] += bk->off[j + 1] - bk->off[j];
+        std::vector<int> gord(bk->lay.groups);
+        for (int g = 0; g < bk->lay.groups; ++g) gord[g] = g;
+        std::stable_sort(gord.begin(), gord.end(), [&](int p, int q) { return gf[p] > gf[q]; });
+        for (int k = 0; k < nseg; ++k)
+            for (int g : gord) {
+                si.push_back(make_int2(s, (g << 4) | k));
+                if (k > 0) ci.push_back(make_int2(s, (g << 4) | k));
+            }
+        sp[oi + 1] = (int)si.size();
+        cp[oi + 1] = (int)ci.size();
+    }
+    if (!any_split) {
+        si.clear();
+        ci.clear();
+    }
+    if (!si.empty() && e == hipSuccess) {
+        A(dalloc(&bt->seg_items, si.size()));
+        A(dalloc(&bt->carry_items, std::max<size_t>(1, ci.size())));
+        if (e == hipSuccess) A(hipMemcpy(bt->seg_items, si.data(), si.size() * sizeof(int2), hipMemcpyHostToDevice));
+        if (e == hipSuccess && !ci.empty())
+            A(hipMemcpy(bt->carry_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    // segment plans are part of the stream descriptors
+    if (e == hipSuccess) A(hipMemcpy(bt->streams, hs.data(), ns * sizeof(BatchStream), hipMemcpyHostToDevice));
     hipStream_t cap = nullptr;
     if (e == hipSuccess) A(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     if (e == hipSuccess) {
@@ -1138,6 +1212,23 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
             bt->graph = g;
         }
         if (e == hipSuccess) A(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+    }
+    for (int k = 1; k <= ns && e == hipSuccess && !si.empty(); ++k) {
+        const size_t lds_carry = fwd_lds_bytes(bt->wpg, 0, 0, false, bt->tt);
+        A(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        if (e == hipSuccess) {
+            A(launch_batch_split(bt->streams, bt->seg_items, sp[k], bt->carry_items, cp[k], bt->pos, B, ns,
+                                 max_slots, bt->fl, bt->tt, bt->wpg, bt->lds, lds_carry, cap));
+            A(launch_batch_finalize(bt->streams, ns, bt->keys, bt->key_stride, bt->pos, B, max_groups, cap));
+            A(launch_batch_advance(bt->pos, bt->streams, ns, bt->counter, B, cap));
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(cap, &g);
+            A(ee);
+            bt->sgraph.push_back(g);
+        }
+        hipGraphExec_t x = nullptr;
+        if (e == hipSuccess) A(hipGraphInstantiate(&x, bt->sgraph.back(), nullptr, nullptr, 0));
+        bt->sexec.push_back(x);
     }
     if (cap) (void)hipStreamDestroy(cap);
     for (int s = 0; s < ns && e == hipSuccess; ++s) {
@@ -1155,7 +1246,28 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
 int spiir_batch_step(spiir_batch *bt, void *stream) {
     if (!bt) return fail(SPIIR_EINVAL, "batch is null");
     DeviceGuard guard(bt->device);
-    HIPCHK(hipGraphLaunch(bt->exec, as_stream(stream)));
+    // the device positions follow the replay count, so the host knows which streams are live
+    int nlive = 0;
+    int64_t live = 0;
+    for (int s = 0; s < bt->ns; ++s)
+        if (bt->len[s] > bt->host_step * bt->B) {
+            ++nlive;
+            live += bt->groups[s];
+        }
+    bool split = false;
+    if (!bt->sexec.empty() && nlive > 0 && bt->split_mode != 1)
+        split = bt->split_mode == 2 || 2 * live <= bt->slots_dev;
+    HIPCHK(hipGraphLaunch(split ? bt->sexec[nlive - 1] : bt->exec, as_stream(stream)));
+    ++bt->host_step;
+    return SPIIR_OK;
+}
+
+int spiir_batch_set_time_split(spiir_batch *bt, int32_t mode) {
+    if (!bt) return fail(SPIIR_EINVAL, "batch is null");
+    if (mode < 0 || mode > 2) return fail(SPIIR_EINVAL, "mode must be 0 (auto), 1 (never) or 2 (always)");
+    if (mode == 2 && bt->sexec.empty())
+        return fail(SPIIR_EINVAL, "this batch has no time-split step (blocks shorter than two chunks)");
+    bt->split_mode = mode;
     return SPIIR_OK;
 }
 
@@ -1172,6 +1284,7 @@ int spiir_batch_reset(spiir_batch *bt, void *stream) {
     DeviceGuard guard(bt->device);
     hipStream_t st = as_stream(stream);
     HIPCHK(launch_fill_zero(bt->pos, bt->ns * sizeof(int64_t), st));
+    bt->host_step = 0;
     HIPCHK(launch_fill_zero(bt->counter, sizeof(int), st));
     for (spiir_bank *bk : bt->banks) HIPCHK(launch_fill_zero(bk->state, bk->lay.nslots * sizeof(float4), st));
     return SPIIR_OK;
@@ -1184,6 +1297,14 @@ int spiir_batch_destroy(spiir_batch *bt) {
         (void)hipDeviceSynchronize();
         if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
         if (bt->graph) (void)hipGraphDestroy(bt->graph);
+        for (auto x : bt->sexec)
+            if (x) (void)hipGraphExecDestroy(x);
+        for (auto g : bt->sgraph)
+            if (g) (void)hipGraphDestroy(g);
+        dfree(bt->seg_items);
+        dfree(bt->carry_items);
+        for (auto &p : bt->seg_bufs) dfree(p);
+        for (auto &p : bt->zl_bufs) dfree(p);
         dfree(bt->streams);
         dfree(bt->items);
         dfree(bt->counter);

@@ -55,6 +55,9 @@ __device__ __forceinline__ int64_t slot_index(int g, int wpg, int wave, int f, i
     return ((int64_t)(g * wpg + wave) * fl + f) * 64 + lane;
 }
 
+// Four floats at a 4-byte aligned address (global loads accept this alignment).
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
 // Per-lane register state of FL filter slots.
 template <int FL>
 struct Lane {
@@ -89,15 +92,50 @@ __device__ __forceinline__ void load_ahead(float (&xv)[TT][FL], const float *xw,
     }
 }
 
+// Window in global memory: steps t0 .. t0 + AH - 1 as 16-byte loads.
+template <int FL, int TT, int AH>
+__device__ __forceinline__ void load_ahead_vec(float (&xv)[TT][FL], const float *xw, const Lane<FL> &s, int t0) {
+#pragma unroll
+    for (int f = 0; f < FL; ++f) {
+#pragma unroll
+        for (int u = 0; u < AH; u += 4) {
+            const f4u q = *reinterpret_cast<const f4u *>(xw + (s.xo[f] + t0 + u));
+            xv[u][f] = q.x;
+            xv[u + 1][f] = q.y;
+            xv[u + 2][f] = q.z;
+            xv[u + 3][f] = q.w;
+        }
+    }
+}
+
 // One tile: FL filter updates per step and per lane, the lane's partial
 // template sum of every step written to the wave's LDS tile [TT][64]. x for
 // step t + AH is read while step t computes (xv[0..AH) arrive loaded).
-template <int FL, int TT, bool FULL, bool CARRY, int AH>
+// VEC (window in global memory): every 4 steps, 4 consecutive samples of each
+// filter are read with one 16-byte load; reads for steps past the tile go to
+// the slots of the next tile's first AH steps (already consumed here) when
+// `more` says a next tile follows.
+template <int FL, int TT, bool FULL, bool CARRY, int AH, bool VEC>
 __device__ __forceinline__ void compute_tile(Lane<FL> &s, float (&xv)[TT][FL], const float *xw, int t0,
-                                             int steps, float2 *wt, int lane) {
+                                             int steps, float2 *wt, int lane, bool more) {
+    static_assert(!VEC || (AH % 4 == 0 && TT % 4 == 0 && AH < TT), "vector read-ahead layout");
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-        if (!CARRY && t + AH < TT) {
+        if (!CARRY && VEC && t % 4 == 0) {
+            const int u = t + AH;
+            if (u < TT || more) {
+                const int k = u < TT ? u : u - TT;
+#pragma unroll
+                for (int f = 0; f < FL; ++f) {
+                    const f4u q = *reinterpret_cast<const f4u *>(xw + (s.xo[f] + t0 + u));
+                    xv[k][f] = q.x;
+                    xv[k + 1][f] = q.y;
+                    xv[k + 2][f] = q.z;
+                    xv[k + 3][f] = q.w;
+                }
+            }
+        }
+        if (!CARRY && !VEC && t + AH < TT) {
 #pragma unroll
             for (int f = 0; f < FL; ++f) xv[t + AH][f] = xw[s.xo[f] + t0 + t + AH];
         }
@@ -329,18 +367,24 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
         } else {
             xw = p.xwin + (xbase + s0);
         }
-        if (!CARRY && wact) load_ahead<FL, TT, AH>(xv, xw, s, 0);
+        if (!CARRY && wact) {
+            if (XLDS)
+                load_ahead<FL, TT, AH>(xv, xw, s, 0);
+            else
+                load_ahead_vec<FL, TT, AH>(xv, xw, s, 0);
+        }
 
         for (int t0 = 0; t0 < nbs; t0 += TT) {
             const int steps = min(TT, nbs - t0);
+            const bool more = t0 + TT < nbs;
             if (wact) {
                 if (steps == TT)
-                    compute_tile<FL, TT, true, CARRY, AH>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, true, CARRY, AH, !XLDS>(s, xv, xw, t0, steps, wt, lane, more);
                 else
-                    compute_tile<FL, TT, false, CARRY, AH>(s, xv, xw, t0, steps, wt, lane);
+                    compute_tile<FL, TT, false, CARRY, AH, !XLDS>(s, xv, xw, t0, steps, wt, lane, more);
                 wave_lds_sync();
                 row_sums<TT>(wt, rsp, wsum + buf * TT * Rp, Rp, wave, lane);
-                if (!CARRY && t0 + TT < nbs) load_ahead<FL, TT, AH>(xv, xw, s, t0 + TT);
+                if (XLDS && !CARRY && more) load_ahead<FL, TT, AH>(xv, xw, s, t0 + TT);
             }
             __syncthreads();
             if (keys_out && pending && wave == 0 && lane < pend_steps) {
@@ -538,6 +582,101 @@ __global__ void __launch_bounds__(512) batch_kernel(const BatchStream *streams, 
     }
 }
 
+// Batch with each live stream's block cut into time segments (used while the
+// live streams alone cannot fill the device). Items are (stream, group << 4 |
+// segment), one workgroup each; items of ended streams or of segments past the
+// block's end exit at once. Per-stream segment buffers hang off the stream's
+// FwdArgs (seg_end, seg_start, zl, seg_len).
+__device__ __forceinline__ bool batch_item(const BatchStream *streams, const int2 *items, const int64_t *pos,
+                                           int block_len, int &sidx, int &g, int &seg, int64_t &p0,
+                                           int64_t &n) {
+    const int2 item = items[blockIdx.x];
+    sidx = __builtin_amdgcn_readfirstlane(item.x);
+    g = __builtin_amdgcn_readfirstlane(item.y >> 4);
+    seg = __builtin_amdgcn_readfirstlane(item.y & 15);
+    p0 = pos[sidx];
+    const int64_t len = streams[sidx].len;
+    if (p0 >= len) return false;
+    n = min((int64_t)block_len, len - p0);
+    return (int64_t)seg * streams[sidx].args.seg_len < n;
+}
+
+template <int FL, int TT>
+__global__ void __launch_bounds__(512) batch_seg_kernel(const BatchStream *streams, const int2 *items,
+                                                        const int64_t *pos, int block_len) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int sidx, g, seg;
+    int64_t p0, n;
+    if (!batch_item(streams, items, pos, block_len, sidx, g, seg, p0, n)) return;
+    FwdArgs a = streams[sidx].args;
+    a.xbase = p0;
+    a.n = n;
+    a.ld = block_len;
+    SegCtx sc;
+    sc.tb = (int64_t)seg * a.seg_len;
+    sc.tn = min(a.seg_len, n - sc.tb);
+    sc.st_in = seg == 0 ? a.state : nullptr;
+    sc.st_out = a.seg_end + (int64_t)seg * a.nslots;
+    sc.zl_out = seg == 0 ? nullptr : a.zl + (int64_t)(seg - 1) * a.n_templates * a.seg_len;
+    sc.zl_in = nullptr;
+    sc.ld_zl = a.seg_len;
+    fwd_group<FL, TT, kModeKeys, true, false>(a, g, smem, sc);
+}
+
+template <int FL, int TT>
+__global__ void __launch_bounds__(512) batch_carry_kernel(const BatchStream *streams, const int2 *items,
+                                                          const int64_t *pos, int block_len) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int sidx, g, seg;
+    int64_t p0, n;
+    if (!batch_item(streams, items, pos, block_len, sidx, g, seg, p0, n)) return;
+    FwdArgs a = streams[sidx].args;
+    a.xbase = p0;
+    a.n = n;
+    a.ld = block_len;
+    SegCtx sc;
+    sc.tb = (int64_t)seg * a.seg_len;
+    sc.tn = min(a.seg_len, n - sc.tb);
+    sc.st_in = a.seg_start + (int64_t)seg * a.nslots;
+    sc.st_out = nullptr;
+    sc.zl_out = nullptr;
+    sc.zl_in = a.zl + (int64_t)(seg - 1) * a.n_templates * a.seg_len;
+    sc.ld_zl = a.seg_len;
+    fwd_group<FL, TT, kModeKeys, false, true>(a, g, smem, sc);
+}
+
+// FP64 carry chain of every live stream (grid.y = stream): the same
+// composition as seg_chain_kernel over the segments the block actually has.
+__global__ void __launch_bounds__(256) batch_chain_kernel(const BatchStream *streams, const int64_t *pos,
+                                                          int block_len) {
+    const int sidx = blockIdx.y;
+    const FwdArgs &a = streams[sidx].args;
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= a.nslots) return;
+    const int64_t p0 = pos[sidx], len = streams[sidx].len;
+    if (p0 >= len) return;
+    const int64_t n = min((int64_t)block_len, len - p0);
+    const int nv = (int)((n + a.seg_len - 1) / a.seg_len);
+    const float4 e0 = a.seg_end[sl];
+    double cr = (double)e0.x + (double)e0.z, ci = (double)e0.y + (double)e0.w;
+    const double2 av = a.s.a64[sl];
+    for (int k = 1; k < nv; ++k) {
+        const float hr = (float)cr, hi = (float)ci;
+        a.seg_start[(int64_t)k * a.nslots + sl] =
+            make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+        const int ln = (int)min(a.seg_len, n - (int64_t)k * a.seg_len);
+        const double2 al = cpow64(av, ln);
+        const float4 e = a.seg_end[(int64_t)k * a.nslots + sl];
+        const double er = (double)e.x + (double)e.z, ei = (double)e.y + (double)e.w;
+        const double nr = al.x * cr - al.y * ci + er;
+        const double ni = al.x * ci + al.y * cr + ei;
+        cr = nr;
+        ci = ni;
+    }
+    const float hr = (float)cr, hi = (float)ci;
+    a.state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+}
+
 // Max over workgroup partial keys: 16 samples x 16 group slices per block.
 __global__ void __launch_bounds__(256) finalize_keys_kernel(const uint64_t *keys, int groups, int64_t ld,
                                                             int64_t n, float *mx, int32_t *am) {
@@ -622,7 +761,6 @@ __global__ void noise_fill_kernel(float *x, int64_t n, uint32_t seed) {
 // per-segment gradients in FP64 in segment order.
 // ---------------------------------------------------------------------------
 
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // v[t] = p[t] for t < ql, else 0; full runs use 16-byte loads (p is only
 // 4-byte aligned, which global loads accept).
@@ -1211,6 +1349,44 @@ hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitem
         case 416: return launch_batch_t<4, 16>(streams, items, nitems, counter, pos, block_len, grid, wpg, lds, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int FL, int TT>
+hipError_t launch_batch_split_t(const BatchStream *streams, const int2 *seg_items, int n_seg_items,
+                                const int2 *carry_items, int n_carry_items, const int64_t *pos, int block_len,
+                                int nstreams, int64_t max_slots, int wpg, size_t lds, size_t lds_carry,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((batch_seg_kernel<FL, TT>), dim3(n_seg_items), dim3(wpg * 64), lds, st, streams, seg_items,
+                       pos, block_len);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_chain_kernel, dim3(nblocks(max_slots, 256), nstreams), dim3(256), 0, st, streams, pos,
+                       block_len);
+    e = hipGetLastError();
+    if (e != hipSuccess || n_carry_items == 0) return e;
+    hipLaunchKernelGGL((batch_carry_kernel<FL, TT>), dim3(n_carry_items), dim3(wpg * 64), lds_carry, st, streams,
+                       carry_items, pos, block_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(const BatchStream *streams, const int2 *seg_items, int n_seg_items,
+                              const int2 *carry_items, int n_carry_items, const int64_t *pos, int block_len,
+                              int nstreams, int64_t max_slots, int fl, int tt, int wpg, size_t lds,
+                              size_t lds_carry, hipStream_t st) {
+#define SPIIR_SPLIT_ARGS streams, seg_items, n_seg_items, carry_items, n_carry_items, pos, block_len, nstreams, \
+                         max_slots, wpg, lds, lds_carry, st
+    switch (fl * 100 + tt) {
+        case 108: return launch_batch_split_t<1, 8>(SPIIR_SPLIT_ARGS);
+        case 208: return launch_batch_split_t<2, 8>(SPIIR_SPLIT_ARGS);
+        case 308: return launch_batch_split_t<3, 8>(SPIIR_SPLIT_ARGS);
+        case 408: return launch_batch_split_t<4, 8>(SPIIR_SPLIT_ARGS);
+        case 116: return launch_batch_split_t<1, 16>(SPIIR_SPLIT_ARGS);
+        case 216: return launch_batch_split_t<2, 16>(SPIIR_SPLIT_ARGS);
+        case 316: return launch_batch_split_t<3, 16>(SPIIR_SPLIT_ARGS);
+        case 416: return launch_batch_split_t<4, 16>(SPIIR_SPLIT_ARGS);
+        default: return hipErrorInvalidValue;
+    }
+#undef SPIIR_SPLIT_ARGS
 }
 
 hipError_t launch_batch_finalize(const BatchStream *streams, int nstreams, const uint64_t *keys,

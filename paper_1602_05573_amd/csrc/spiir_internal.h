@@ -121,6 +121,12 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 hipError_t launch_batch(const BatchStream *streams, const int2 *items, int nitems,
                         int *counter, const int64_t *pos, int block_len, int fl, int tt, int grid,
                         int wpg, size_t lds, hipStream_t stream);
+// Time-split batch step: local pass over (stream, group << 4 | segment) items,
+// per-stream FP64 carry chain, carry-only pass over the items of segments >= 1.
+hipError_t launch_batch_split(const BatchStream *streams, const int2 *seg_items, int n_seg_items,
+                              const int2 *carry_items, int n_carry_items, const int64_t *pos, int block_len,
+                              int nstreams, int64_t max_slots, int fl, int tt, int wpg, size_t lds,
+                              size_t lds_carry, hipStream_t stream);
 hipError_t launch_batch_finalize(const BatchStream *streams, int nstreams, const uint64_t *keys,
                                  int64_t key_stride, const int64_t *pos, int block_len,
                                  int max_groups, hipStream_t stream);

@@ -107,6 +107,7 @@ def test_null_arguments(lib):
     assert lib.spiir_backward(None, None, None, None, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_bank_get_info(None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_bank_time_kernels(None, 1) == _lib.SPIIR_EINVAL
+    assert lib.spiir_batch_set_time_split(None, 0) == _lib.SPIIR_EINVAL
     assert lib.spiir_bank_kernel_time(None, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_batch_create(None, 1, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
     bh = ctypes.c_void_p()

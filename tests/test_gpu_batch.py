@@ -37,6 +37,7 @@ def test_batch_matches_streaming_and_oracle():
     banks, xs, bks = make()
     xd = [torch.from_numpy(x).cuda() for x in xs]
     bt = SpiirBatch(bks, xd, block_len=4096)
+    bt.set_time_split(1)   # plain graph: bitwise equal to unsplit streaming
     steps = bt.steps_total()
     assert steps == (25001 + 4095) // 4096
     for _ in range(steps):
@@ -44,7 +45,7 @@ def test_batch_matches_streaming_and_oracle():
     bt.step()   # every stream has ended: a no-op replay
     torch.cuda.synchronize()
     for s, (b, x) in enumerate(zip(banks, xs)):
-        with SpiirBank.from_bank(b, filters_per_lane=2, chunk_len=256, waves_per_group=4) as ref_bk:
+        with SpiirBank.from_bank(b, filters_per_lane=2, chunk_len=256, waves_per_group=4, time_split=1) as ref_bk:
             m, a = ref_bk.trigger_max(xd[s])
         assert torch.equal(bt.max[s], m), "stream %d max differs" % s
         assert torch.equal(bt.argmax[s], a), "stream %d argmax differs" % s
@@ -59,6 +60,36 @@ def test_batch_matches_streaming_and_oracle():
     for s in range(len(xs)):
         assert torch.equal(first[s], bt.max[s])
     bt.close()
+    for bk in bks:
+        bk.close()
+
+
+@pytest.mark.parametrize("mode", [2, 0])
+def test_batch_time_split_graph(mode):
+    """Blocks cut into time segments inside the batch graph (always, or
+    automatically for the tail where one stream is left) agree with the plain
+    graph to rounding and pass the oracle's gate; ragged last blocks."""
+    from paper_1602_05573_amd import SpiirBatch
+    banner("batch time split mode %d" % mode)
+    banks, xs, bks = make(lengths=(10000, 29001, 4097))
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    out = {}
+    for m in (1, mode):
+        bt = SpiirBatch(bks, xd, block_len=4096)
+        bt.set_time_split(m)
+        for _ in range(bt.steps_total()):
+            bt.step()
+        torch.cuda.synchronize()
+        out[m] = ([t.clone() for t in bt.max], [t.clone() for t in bt.argmax])
+        bt.close()
+    for s, (b, x) in enumerate(zip(banks, xs)):
+        ref = oracle.snr(b, x)
+        P = ref.max()
+        mx, am = out[mode][0][s].cpu().numpy(), out[mode][1][s].cpu().numpy()
+        assert np.max(np.abs(mx - ref.max(axis=0))) <= 1e-4 * P, "stream %d" % s
+        check_argmax(mx, am, ref)
+        d = (out[mode][0][s] - out[1][0][s]).abs().max().item()
+        assert d <= 1e-4 * P, "stream %d: split vs plain %.3g" % (s, d)
     for bk in bks:
         bk.close()
 
