@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("bank", "batch", "adjoint"), default="bank",
+    ap.add_argument("--workload", choices=("bank", "batch", "adjoint", "precision"), default="bank",
                     help="bank: the 1,024-template bank (default, the headline); "
                          "batch: 8 uneven streams with their own banks in one graph replay per block")
     ap.add_argument("--length-scale", type=float, default=1.0, help="batch: scale of the stream lengths")
@@ -93,6 +93,8 @@ def main():
         del src, dst
     if args.workload == "batch":
         return run_batch(args, torch)
+    if args.workload == "precision":
+        return run_precision(args, torch)
     if args.workload == "adjoint":
         return run_adjoint(args, torch)
     return run_bank(args, torch)
@@ -387,6 +389,75 @@ def run_adjoint(args, torch):
     }
     log("adjoint: forward %.2f ms, loss %.2f ms, backward %.2f ms" % (fwd, loss, bwd))
     bk.close()
+    print(json.dumps(res), flush=True)
+
+
+def run_precision(args, torch):
+    """64 templates x 1,000 filters with r ~ U[1-1e-4, 1-1e-6] over 16,777,216
+    samples: throughput of the fused trigger per precision mode, and the max
+    relative SNR error of two sampled templates against the FP64 oracle."""
+    from paper_1602_05573_amd import SpiirBank
+    from workloads import config4
+    import oracle
+
+    pick = [5, 42]
+    bank, x = config4()
+    F, T, N = bank.n_filters, bank.n_templates, len(x)
+    xd = torch.from_numpy(x).cuda()
+    C = 1 << 20   # samples per call
+    t0 = time.perf_counter()
+    ref = oracle.snr(bank.subset(pick), x, nthreads=oracle.max_threads())
+    log("oracle on templates %s: %.1fs" % (pick, time.perf_counter() - t0))
+    P = ref.max(axis=1)
+    modes = {}
+    for prec, name in ((0, "fp32 + fp64 carries for |a| > 1-1e-5"), (2, "fp32 + fp64 carries for all"),
+                       (1, "all fp32")):
+        with SpiirBank.from_bank(bank, precision=prec) as bk:
+            mx = torch.empty(C, dtype=torch.float32, device="cuda")
+            am = torch.empty(C, dtype=torch.int32, device="cuda")
+
+            def one_pass():
+                bk.reset()
+                for c0 in range(0, N, C):
+                    c1 = min(N, c0 + C)
+                    bk.trigger_max(xd[c0:c1], out=(mx[: c1 - c0], am[: c1 - c0]))
+
+            for _ in range(args.warmup):
+                one_pass()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(args.steps):
+                one_pass()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - ts) / args.steps
+            # error of the sampled templates (separate pass keeping their SNR rows)
+            bk.reset()
+            rows = np.empty((len(pick), N), np.float32)
+            snr = torch.empty((T, C), dtype=torch.float32, device="cuda")
+            for c0 in range(0, N, C):
+                c1 = min(N, c0 + C)
+                s = bk.filter_block(xd[c0:c1], snr=snr[:, : c1 - c0] if c1 - c0 == C else None)
+                rows[:, c0:c1] = s[pick].cpu().numpy()
+            err = float(np.max(np.max(np.abs(rows - ref), axis=1) / P))
+            info = bk.info
+            modes[prec] = {"mode": name, "filter_updates_per_s": F * N / dt, "ms_per_pass": dt * 1e3,
+                           "max_rel_snr_err": err, "time_split": info["time_split"],
+                           "filters_per_lane": info["filters_per_lane"],
+                           "waves_per_group": info["waves_per_group"], "workgroups": info["n_groups"]}
+            log("precision %d (%s): %.3e updates/s, %.1f ms per pass, max rel SNR err %.3g"
+                % (prec, name, F * N / dt, dt * 1e3, err))
+    res = {
+        "metric": METRIC, "value": modes[0]["filter_updates_per_s"], "unit": "filter-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": modes[0]["ms_per_pass"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded white noise and random banks)",
+        "config": {"workload": "precision stress: %d templates x 1000 filters, r in [1-1e-4, 1-1e-6], "
+                               "%d samples in %d-sample calls, fused max/argmax" % (T, N, C)},
+        "pct_fp32_peak": 100.0 * FLOP_UPDATE * modes[0]["filter_updates_per_s"] / PEAK_FP32,
+        "precision_modes": modes,
+        "error_sample": "templates %s over the whole stream against the FP64 oracle; error = "
+                        "max |SNR - SNR_ref| / max SNR_ref per template" % pick,
+    }
     print(json.dumps(res), flush=True)
 
 

@@ -81,12 +81,16 @@ typedef struct {
     int32_t waves_per_group;  /* 64-lane waves per workgroup, 1..8; 0 = automatic */
     int32_t autotune;         /* 1: time the candidate (chunk_len, filters_per_lane)
                                  pairs on this bank and keep the fastest */
-    int32_t time_split;       /* segments each streaming launch is cut into when the bank
-                                 alone cannot fill the device: every segment is filtered
-                                 from rest in parallel, then the true segment-start states
-                                 follow from an FP64 carry chain and their free response is
-                                 added. 0 = automatic, 1 = off, 2..8 = forced. Not used in
-                                 SPIIR_PREC_FP32 mode nor by the per-template comparator. */
+    int32_t time_split;       /* segments each launch (spiir_filter_block,
+                                 spiir_trigger_max, spiir_forward_z) is cut into when the
+                                 bank alone cannot fill the device: every segment is
+                                 filtered from rest in parallel, then the true
+                                 segment-start states follow from a carry chain in FP64
+                                 (with fl32(a) in SPIIR_PREC_FP32 mode) and their free
+                                 response is added. spiir_backward likewise cuts the
+                                 reverse scan into segments (automatic count up to 16
+                                 for 0, the given count for 2..8). 0 = automatic, 1 = off,
+                                 2..8 = forced. Not used by the per-template comparator. */
 } spiir_bank_opts;
 
 /* Layout facts of a created bank (for tests, tuning reports and benchmarks). */

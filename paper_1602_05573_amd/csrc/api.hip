@@ -538,7 +538,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     bk->lds_carry = fwd_lds_bytes(wpg, 0, 0, false, gm.tt);
     bk->tsplit_opt = o.time_split;
     // time split: only when the bank's workgroups fill at most half the device
-    if (o.precision != SPIIR_PREC_FP32 && o.time_split != 1) {
+    if (o.time_split != 1) {
         if (o.time_split >= 2) {
             bk->nseg = o.time_split;
         } else {

@@ -529,14 +529,17 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
 // the true end of segment 0; writes every segment's true start state and the
 // launch's final state.
 __global__ void seg_chain_kernel(const float4 *seg_end, float4 *seg_start, float4 *state, const double2 *a64,
-                                 const int32_t *slot_filter, int64_t nslots, int nseg, int64_t seg_len,
+                                 const float2 *a32, int prec, int64_t nslots, int nseg, int64_t seg_len,
                                  int64_t n) {
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    (void)slot_filter;
     if (sl >= nslots) return;  // every slot, padding included (its states stay zero)
     const float4 e0 = seg_end[sl];
     double cr = (double)e0.x + (double)e0.z, ci = (double)e0.y + (double)e0.w;
-    const double2 a = a64[sl];
+    double2 a = a64[sl];
+    if (prec == kPrecFp32) {  // the all-FP32 mode propagates with the rounded coefficient
+        const float2 r = a32[sl];
+        a = make_double2((double)r.x, (double)r.y);
+    }
     for (int k = 1; k < nseg; ++k) {
         const float hr = (float)cr, hi = (float)ci;
         seg_start[(int64_t)k * nslots + sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
@@ -659,7 +662,11 @@ __global__ void __launch_bounds__(256) batch_chain_kernel(const BatchStream *str
     const int nv = (int)((n + a.seg_len - 1) / a.seg_len);
     const float4 e0 = a.seg_end[sl];
     double cr = (double)e0.x + (double)e0.z, ci = (double)e0.y + (double)e0.w;
-    const double2 av = a.s.a64[sl];
+    double2 av = a.s.a64[sl];
+    if (a.prec == kPrecFp32) {
+        const float2 r = a.s.a32[sl];
+        av = make_double2((double)r.x, (double)r.y);
+    }
     for (int k = 1; k < nv; ++k) {
         const float hr = (float)cr, hi = (float)ci;
         a.seg_start[(int64_t)k * a.nslots + sl] =
@@ -1134,8 +1141,9 @@ hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_car
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((a.nslots + 255) / 256);
+    (void)slot_filter;
     hipLaunchKernelGGL(seg_chain_kernel, dim3(nb), dim3(256), 0, st, a.seg_end, a.seg_start, a.state, a.s.a64,
-                       slot_filter, a.nslots, nseg, a.seg_len, a.n);
+                       a.s.a32, a.prec, a.nslots, nseg, a.seg_len, a.n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),

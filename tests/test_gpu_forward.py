@@ -223,6 +223,14 @@ def test_all_fp32_mode_runs(mid):
     err, _ = snr_err(snr, ref)
     print("all-fp32 err=%.3g" % err)
     assert np.isfinite(snr).all() and err < 0.05
+    # the time split keeps the mode's arithmetic (rounded coefficient, no correction)
+    out = {}
+    for ts in (1, 6):
+        with mk(bank, precision=1, time_split=ts) as bk:
+            out[ts] = bk.filter_block(dev(x)).cpu().numpy()
+    d, _ = snr_err(out[6], out[1])
+    print("all-fp32 split vs unsplit %.3g" % d)
+    assert d <= 1e-4
 
 
 def test_multi_piece_calls(mid):
