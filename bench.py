@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--wpg", type=int, default=0)
     ap.add_argument("--time-split", type=int, default=0, help="time segments (0 = library choice, 1 = off)")
     ap.add_argument("--plain-blocks", type=int, default=4)
-    ap.add_argument("--check-blocks", type=int, default=16)
+    ap.add_argument("--check-blocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
