@@ -94,6 +94,29 @@ def test_batch_time_split_graph(mode):
         bk.close()
 
 
+def test_batch_time_split_mode_errors():
+    from paper_1602_05573_amd import SpiirBank, SpiirBatch, SpiirError
+    banner("batch time split modes")
+    b0 = random_bank(73, 0, 3, 40, 100, 0.99, 0.999, 100)
+    x = torch.from_numpy(strain(5000, 73)).cuda()
+    with SpiirBank.from_bank(b0, filters_per_lane=1, chunk_len=512) as k1:
+        # 512-sample blocks hold one chunk: no time-split graph exists
+        bt = SpiirBatch([k1], [x], block_len=512)
+        with pytest.raises(SpiirError, match="no time-split"):
+            bt.set_time_split(2)
+        with pytest.raises(SpiirError, match="mode"):
+            bt.set_time_split(3)
+        bt.set_time_split(0)
+        for _ in range(bt.steps_total()):
+            bt.step()
+        torch.cuda.synchronize()
+        m, a = bt.max[0].clone(), bt.argmax[0].clone()
+        bt.close()
+    with SpiirBank.from_bank(b0, filters_per_lane=1, chunk_len=512, time_split=1) as ref:
+        rm, ra = ref.trigger_max(x)
+    assert torch.equal(m, rm) and torch.equal(a, ra)
+
+
 def test_batch_rejects_mixed_layouts():
     from paper_1602_05573_amd import SpiirBank, SpiirBatch, SpiirError
     banner("batch mixed layouts")

@@ -332,3 +332,52 @@ def test_impulse_response_on_gpu():
         s = bk.filter_block(dev(x)).cpu().numpy()
     err, _ = snr_err(s, ref)
     assert err <= SNR_TOL
+
+
+def test_kernel_timing_api(c0):
+    """spiir_bank_time_kernels / spiir_bank_kernel_time: one timed launch per
+    block call, positive durations, totals cleared on read, ESTATE when off."""
+    from paper_1602_05573_amd import SpiirError
+    bank, x, _ = c0
+    banner("kernel timing")
+    with mk(bank) as bk:
+        with pytest.raises(SpiirError, match="timing is off"):
+            bk.kernel_time()
+        xd = dev(x)
+        bk.time_kernels(True)
+        for i in range(0, len(x), 4096):
+            bk.trigger_max(xd[i:i + 4096])
+        ms, n = bk.kernel_time()
+        assert n == (len(x) + 4095) // 4096 and ms > 0
+        assert bk.kernel_time() == (0.0, 0)
+        # more launches than the event ring holds: the oldest pairs are collected on reuse
+        for _ in range(300):
+            bk.trigger_max(xd[:256])
+        ms, n = bk.kernel_time()
+        assert n == 300 and ms > 0
+        bk.time_kernels(False)
+        with pytest.raises(SpiirError, match="timing is off"):
+            bk.kernel_time()
+
+
+@pytest.mark.parametrize("tsplit", [1, 0])
+def test_irregular_call_sizes(mid, tsplit):
+    """The stream fed in calls of 1, 2, 3, 7, 15, 16, 17, 100, 1000 samples and
+    the rest (partial tiles, partial chunks, calls shorter than a segment):
+    SNR and fused outputs against the oracle."""
+    bank, x, ref = mid
+    banner("irregular calls time_split=%d" % tsplit)
+    cuts = np.cumsum([0, 1, 1, 2, 3, 7, 15, 16, 17, 100, 1000])
+    cuts = np.append(cuts, len(x))
+    with mk(bank, time_split=tsplit) as bk:
+        parts = [bk.filter_block(dev(x[c0:c1])).cpu().numpy() for c0, c1 in zip(cuts[:-1], cuts[1:])]
+    snr = np.concatenate(parts, axis=1)
+    err, _ = snr_err(snr, ref)
+    print("irregular calls err=%.3g" % err)
+    assert err <= SNR_TOL
+    with mk(bank, time_split=tsplit) as bk:
+        outs = [bk.trigger_max(dev(x[c0:c1])) for c0, c1 in zip(cuts[:-1], cuts[1:])]
+    mx = torch.cat([o[0] for o in outs]).cpu().numpy()
+    am = torch.cat([o[1] for o in outs]).cpu().numpy()
+    check_argmax(mx, am, ref)
+
