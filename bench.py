@@ -75,7 +75,7 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(templates would shard across GPUs with one max-key all-reduce per block)",
               file=sys.stderr)
         sys.exit(2)
@@ -102,10 +102,10 @@ def main():
 
 def run_bank(args, torch):
     from paper_1602_05573_amd import SpiirBank
-    from workloads import config1
+    from workloads import bank_1024
 
     t0 = time.time()
-    bank, x = config1(n=args.samples, n_templates=args.templates)
+    bank, x = bank_1024(n=args.samples, n_templates=args.templates)
     F = bank.n_filters
     T = bank.n_templates
     N = len(x)
@@ -238,10 +238,10 @@ def run_batch(args, torch):
     bank of U{200..600} filters, advanced one 4,096-sample block per graph
     replay; chunk length and filters per lane from the autotuner."""
     from paper_1602_05573_amd import SpiirBatch, autotune, batch_banks
-    from workloads import config2
+    from workloads import batch_streams
 
     t0 = time.time()
-    banks, xs = config2(length_scale=args.length_scale)
+    banks, xs = batch_streams(length_scale=args.length_scale)
     lengths = [len(x) for x in xs]
     updates = float(sum(b.n_filters * len(x) for b, x in zip(banks, xs)))
     log("batch workload: %d streams, lengths %s, %.3e updates (gen %.1fs)"
@@ -318,9 +318,9 @@ def run_adjoint(args, torch):
     samples: forward_z with its carry tape, the overlap loss and its gradient
     (torch, on the device), and the reverse-time adjoint (spiir_backward)."""
     from paper_1602_05573_amd import SpiirBank
-    from workloads import config3
+    from workloads import chirp_fit
 
-    bank, x, gs, _ = config3()
+    bank, x, gs, _ = chirp_fit()
     F, T, N = bank.n_filters, bank.n_templates, len(x)
     bk = SpiirBank.from_bank(bank, filters_per_lane=args.fl, waves_per_group=args.wpg,
                              time_split=args.time_split)
@@ -397,11 +397,11 @@ def run_precision(args, torch):
     samples: throughput of the fused trigger per precision mode, and the max
     relative SNR error of two sampled templates against the FP64 oracle."""
     from paper_1602_05573_amd import SpiirBank
-    from workloads import config4
+    from workloads import precision_bank
     import oracle
 
     pick = [5, 42]
-    bank, x = config4()
+    bank, x = precision_bank()
     F, T, N = bank.n_filters, bank.n_templates, len(x)
     xd = torch.from_numpy(x).cuda()
     C = 1 << 20   # samples per call

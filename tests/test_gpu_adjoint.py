@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import Bank, chirp_target, config3, random_bank, strain
+from workloads import Bank, chirp_target, chirp_fit, random_bank, strain
 
 pytestmark = pytest.mark.gpu
 
@@ -201,11 +201,11 @@ def test_stale_tape_is_rejected():
         tape.close()
 
 
-def test_config3_full_size_sampled_templates():
+def test_chirp_fit_full_size_sampled_templates():
     """256 templates x 400 filters, 65,536 samples: GPU forward + adjoint over the
     whole bank, compared with the oracle on sampled templates."""
-    banner("config3 full size")
-    bank, x, gs, _ = config3()
+    banner("chirp_fit full size")
+    bank, x, gs, _ = chirp_fit()
     T = bank.n_templates
     with mk(bank) as bk:
         xd = torch.from_numpy(x).cuda()

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from helpers import SNR_TOL, check_argmax, snr_err
-from workloads import Bank, config0, random_bank, strain
+from workloads import Bank, bank_4x128, random_bank, strain
 
 pytestmark = pytest.mark.gpu
 
@@ -34,35 +34,35 @@ def banner(msg):
 
 
 # ---------------------------------------------------------------------------
-# config 0: 4 templates x 128 filters, 16,384 samples
+# 4 templates x 128 filters, 16,384 samples
 # ---------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
 def c0():
-    bank, x = config0()
+    bank, x = bank_4x128()
     ref = oracle.snr(bank, x)
     return bank, x, ref
 
 
 @pytest.mark.parametrize("fl", [0, 1, 2, 4])
-def test_config0_snr_parity(c0, fl):
+def test_bank4x128_snr_parity(c0, fl):
     bank, x, ref = c0
-    banner("config0 snr fl=%d" % fl)
+    banner("bank_4x128 snr fl=%d" % fl)
     with mk(bank, filters_per_lane=fl) as bk:
         snr = bk.filter_block(dev(x)).cpu().numpy()
     err, _ = snr_err(snr, ref)
-    print("config0 fl=%d err=%.3g" % (fl, err))
+    print("bank_4x128 fl=%d err=%.3g" % (fl, err))
     assert err <= SNR_TOL
 
 
-def test_config0_trigger_parity(c0):
+def test_bank4x128_trigger_parity(c0):
     bank, x, ref = c0
-    banner("config0 trigger")
+    banner("bank_4x128 trigger")
     with mk(bank) as bk:
         mx, am = bk.trigger_max(dev(x))
         mx, am = mx.cpu().numpy(), am.cpu().numpy()
     ties = check_argmax(mx, am, ref)
-    print("config0 documented ties: %d of %d" % (ties, len(x)))
+    print("bank_4x128 documented ties: %d of %d" % (ties, len(x)))
 
 
 def test_fused_equals_max_of_plain_rows(c0):

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from helpers import SNR_TOL, check_argmax, snr_err
-from workloads import config1, config2
+from workloads import bank_1024, batch_streams
 
 pytestmark = pytest.mark.gpu
 
@@ -29,12 +29,12 @@ def banner(msg):
     print("[case] " + msg, flush=True)
 
 
-def test_config1_full_size():
+def test_bank1024_full_size():
     """1,024 templates x U{100..800} filters over 4,194,304 samples in
     4,096-sample blocks (the bench.py configuration)."""
     from paper_1602_05573_amd import SpiirBank
-    banner("config1 full size")
-    bank, x = config1()
+    banner("bank_1024 full size")
+    bank, x = bank_1024()
     N, T = len(x), bank.n_templates
     xd = torch.from_numpy(x).cuda()
     with SpiirBank.from_bank(bank, chunk_len=256, max_block=B) as bk:
@@ -59,11 +59,11 @@ def test_config1_full_size():
                 first = torch.argmax((s == m[None, :]).to(torch.int8), dim=0).to(torch.int32)
                 assert torch.equal(first, am[sl]), "block %d: argmax is not the lowest maximal row" % i
         torch.cuda.synchronize()
-    banner("config1 oracle on templates %s" % PICK1)
+    banner("bank_1024 oracle on templates %s" % PICK1)
     ref = oracle.snr(bank.subset(PICK1), x)
     got = rows.cpu().numpy()
     err, per = snr_err(got, ref)
-    print("config1 sampled-template SNR error %.3g (per template %s)" % (err, per))
+    print("bank_1024 sampled-template SNR error %.3g (per template %s)" % (err, per))
     assert err <= SNR_TOL
     # wherever the fused argmax is a sampled template, the fused max is its oracle SNR
     m, a = mx.cpu().numpy(), am.cpu().numpy()
@@ -76,13 +76,13 @@ def test_config1_full_size():
         assert np.all(m >= ref[r] - SNR_TOL * P[r])
 
 
-def test_config2_full_size_batch():
+def test_batch_streams_full_size():
     """8 uneven streams (2^18..2^22 samples), 256-template banks of U{200..600}
     filters, autotuned L and filters per lane, automatic graph choice (the
     bench.py configuration)."""
     from paper_1602_05573_amd import SpiirBank, SpiirBatch, autotune, batch_banks
-    banner("config2 full size")
-    banks, xs = config2()
+    banner("batch_streams full size")
+    banks, xs = batch_streams()
     L, F, _ = autotune(banks, block_len=B)
     bks = batch_banks(banks, L, F)
     xd = [torch.from_numpy(x).cuda() for x in xs]

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from helpers import SNR_TOL, snr_err
-from workloads import config4
+from workloads import precision_bank
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +23,8 @@ def need_gpu():
 
 @pytest.fixture(scope="module")
 def c4():
-    bank, x = config4()
-    print("[case] config4 oracle on templates %s" % PICK, flush=True)
+    bank, x = precision_bank()
+    print("[case] precision_bank oracle on templates %s" % PICK, flush=True)
     ref = oracle.snr(bank.subset(PICK), x)
     return bank, x, ref
 
@@ -44,9 +44,9 @@ def run(bank, x, precision):
 
 
 @pytest.mark.parametrize("precision,must_pass", [(0, True), (2, True), (1, False)])
-def test_config4_precision(c4, precision, must_pass):
+def test_precision_bank_modes(c4, precision, must_pass):
     bank, x, ref = c4
-    print("[case] config4 precision=%d" % precision, flush=True)
+    print("[case] precision_bank precision=%d" % precision, flush=True)
     got = run(bank, x, precision)
     err, per = snr_err(got, ref)
     print("precision %d: max relative SNR error %.3g (per template %s)" % (precision, err, per))

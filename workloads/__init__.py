@@ -9,11 +9,11 @@ from .gen import (  # noqa: F401
     SEED_ROOT,
     strain,
     random_bank,
-    config0,
-    config1,
-    config2,
-    config3,
-    config4,
+    bank_4x128,
+    bank_1024,
+    batch_streams,
+    chirp_fit,
+    precision_bank,
     chirp_target,
     chirp_init_bank,
 )

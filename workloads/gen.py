@@ -5,7 +5,7 @@ subsection "Experimental results") ran on real pipeline data and real
 template banks that are not public. These generators stand in for them with
 banks of first-order complex IIR filters of the shapes the workloads name.
 
-Seeds: ``numpy.random.default_rng([1602, cfg, role, idx])`` with role 0 =
+Seeds: ``numpy.random.default_rng([1602, family, role, idx])`` with role 0 =
 strain, 1 = bank, 2 = chirp parameters, and idx = stream / template index.
 The float32 strain array is canonical; bank coefficients are canonical in
 complex128 (the library rounds them itself).
@@ -24,8 +24,8 @@ FS = 4096.0                 # sample rate of the chirp workloads (Hz)
 T_SUN = 4.925491025543576e-06  # G * M_sun / c^3 in seconds
 
 
-def _rng(cfg: int, role: int, idx: int = 0) -> np.random.Generator:
-    return np.random.default_rng([SEED_ROOT, cfg, role, idx])
+def _rng(family: int, role: int, idx: int = 0) -> np.random.Generator:
+    return np.random.default_rng([SEED_ROOT, family, role, idx])
 
 
 @dataclass
@@ -65,12 +65,12 @@ class Bank:
         return Bank(off, cat(self.a), cat(self.b), cat(self.d).astype(np.int32), self.dmax)
 
 
-def strain(n: int, cfg: int, idx: int = 0) -> np.ndarray:
+def strain(n: int, family: int, idx: int = 0) -> np.ndarray:
     """Whitened strain stand-in: seeded white Gaussian noise, sigma = 1, float32."""
-    return _rng(cfg, ROLE_STRAIN, idx).standard_normal(int(n)).astype(np.float32)
+    return _rng(family, ROLE_STRAIN, idx).standard_normal(int(n)).astype(np.float32)
 
 
-def random_bank(cfg: int, idx: int, n_templates: int, k_lo: int, k_hi: int,
+def random_bank(family: int, idx: int, n_templates: int, k_lo: int, k_hi: int,
                 r_lo: float, r_hi: float, dmax: int,
                 w_lo: float = 0.001 * math.pi, w_hi: float = 0.5 * math.pi) -> Bank:
     """Random bank: K_j ~ U{k_lo..k_hi}; per filter r ~ U[r_lo, r_hi],
@@ -79,7 +79,7 @@ def random_bank(cfg: int, idx: int, n_templates: int, k_lo: int, k_hi: int,
 
     Draw order: all K_j first, then per template r, omega, Re b, Im b, d.
     """
-    rng = _rng(cfg, ROLE_BANK, idx)
+    rng = _rng(family, ROLE_BANK, idx)
     k = rng.integers(k_lo, k_hi + 1, size=n_templates).astype(np.int64)
     off = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
     nf = int(off[-1])
@@ -106,29 +106,29 @@ def random_bank(cfg: int, idx: int, n_templates: int, k_lo: int, k_hi: int,
 # smaller n is asked for (tests use prefixes or reduced template counts).
 # ---------------------------------------------------------------------------
 
-def config0(n: int = 16384):
+def bank_4x128(n: int = 16384):
     """4 templates x 128 filters, r ~ U[0.99, 0.9999], d ~ U{0..2047}, 16,384 samples."""
     bank = random_bank(0, 0, 4, 128, 128, 0.99, 0.9999, 2047)
     return bank, strain(n, 0)
 
 
-def config1(n: int = 4194304, n_templates: int = 1024):
+def bank_1024(n: int = 4194304, n_templates: int = 1024):
     """1,024 templates, K_j ~ U{100..800}, r ~ U[0.99, 1-1e-5], d ~ U{0..16384},
     4,194,304 samples at 4,096 Hz, processed in 4,096-sample blocks."""
     bank = random_bank(1, 0, n_templates, 100, 800, 0.99, 1.0 - 1e-5, 16384)
     return bank, strain(n, 1)
 
 
-def config2_lengths(n_streams: int = 8) -> np.ndarray:
+def batch_stream_lengths(n_streams: int = 8) -> np.ndarray:
     """Stream lengths round(2^u), u ~ U[18, 22]."""
     u = _rng(2, ROLE_STRAIN, 1000).uniform(18.0, 22.0, n_streams)
     return np.round(2.0 ** u).astype(np.int64)
 
 
-def config2(n_streams: int = 8, n_templates: int = 256, length_scale: float = 1.0):
+def batch_streams(n_streams: int = 8, n_templates: int = 256, length_scale: float = 1.0):
     """8 streams of uneven length, each with its own 256-template bank of
-    U{200..600} filters (coefficients as config 1, d <= 16,384)."""
-    lengths = config2_lengths(n_streams)
+    U{200..600} filters (coefficients as the 1,024-template bank, d <= 16,384)."""
+    lengths = batch_stream_lengths(n_streams)
     if length_scale != 1.0:
         lengths = np.maximum(1, np.round(lengths * length_scale)).astype(np.int64)
     banks = [random_bank(2, s, n_templates, 200, 600, 0.99, 1.0 - 1e-5, 16384)
@@ -137,7 +137,7 @@ def config2(n_streams: int = 8, n_templates: int = 256, length_scale: float = 1.
     return banks, xs
 
 
-def config4(n: int = 16777216, n_templates: int = 64):
+def precision_bank(n: int = 16777216, n_templates: int = 64):
     """64 templates x 1,000 filters with poles between 1-1e-4 and 1-1e-6 in
     radius (the interval is stated as [1-1e-6, 1-1e-4]; read as its sorted
     form), d ~ U{0..2047}, 16,777,216 samples."""
@@ -146,7 +146,7 @@ def config4(n: int = 16777216, n_templates: int = 64):
 
 
 # ---------------------------------------------------------------------------
-# Chirp targets for the adjoint fit (config 3).
+# Chirp targets for the adjoint fit (256 templates x 400 filters).
 # ---------------------------------------------------------------------------
 
 def _chirp_tau_of_f(f, mc):
@@ -174,7 +174,7 @@ def chirp_target(mc: float, n: int = 65536, fs: float = FS,
     return np.conj(h)
 
 
-def config3_masses(n_templates: int = 256) -> np.ndarray:
+def chirp_fit_masses(n_templates: int = 256) -> np.ndarray:
     return _rng(3, ROLE_CHIRP, 0).uniform(1.0, 30.0, n_templates)
 
 
@@ -201,13 +201,13 @@ def chirp_init_bank(g: np.ndarray, k: int, fs: float = FS):
     return a.astype(np.complex128), b.astype(np.complex128), starts.astype(np.int32)
 
 
-def config3(n: int = 65536, n_templates: int = 256, k: int = 400):
+def chirp_fit(n: int = 65536, n_templates: int = 256, k: int = 400):
     """256 templates x 400 filters fitted to time-reversed Newtonian chirps with
     chirp masses ~ U[1, 30] M_sun, 30-1,000 Hz, 65,536 samples at 4,096 Hz.
     Input x is a unit impulse, so the bank output is its impulse response.
 
     Returns (initial bank, x, targets g [T, n] complex128, chirp masses)."""
-    mcs = config3_masses(n_templates)
+    mcs = chirp_fit_masses(n_templates)
     gs = np.empty((n_templates, n), np.complex128)
     a = np.empty(n_templates * k, np.complex128)
     b = np.empty_like(a)
