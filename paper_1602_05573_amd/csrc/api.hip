@@ -491,7 +491,15 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     const int L = o.chunk_len ? o.chunk_len : 256;
     int max_block = o.max_block ? o.max_block : 16384;
     max_block = std::max(L, (max_block / L) * L);
-    int fl = o.filters_per_lane ? o.filters_per_lane : choose_fl(T, off, df.n_cu);
+    int fl = o.filters_per_lane;
+    if (fl == 0) {
+        // A delay window too long for LDS (even beside a single wave's tiles) leaves the strain
+        // in global memory; there four filters per lane give each wave more independent loads
+        // in flight, and the time split supplies the parallelism a small bank lacks.
+        const bool global_window = !plan_geometry(1, dmax, L, max_block, df.lds_cap).xlds;
+        fl = choose_fl(T, off, df.n_cu);
+        if (global_window && plan_rows(T, off, 4).max_nr <= 4 * kMaxWaves) fl = 4;
+    }
     const Plan plan = plan_rows(T, off, fl);
     if (plan.max_nr > 4 * kMaxWaves)
         return fail(SPIIR_EINVAL, "a template has more than %d filters; use more filters per lane",
@@ -1003,6 +1011,8 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     if (bk->tsplit_opt >= 2) {
         want = bk->tsplit_opt;
     } else if (bk->tsplit_opt == 0) {
+        // counted in layout waves (the per-segment kernel runs FL times as many): on the
+        // chirp-fit bank 16 segments of 4-filter lanes ran faster than 4
         const int64_t waves = std::max<int64_t>(1, (int64_t)bk->lay.groups * bk->lay.wpg);
         const int64_t target = (int64_t)32 * bk->dev.n_cu;
         want = (int)std::min<int64_t>(16, (target + waves - 1) / waves);

@@ -204,9 +204,9 @@ __device__ __forceinline__ void row_sums(const float2 *wt, const RowSumPlan<TT> 
                                          int Rp, int wave, int lane) {
     const char *base = reinterpret_cast<const char *>(wt);
     const bool lo = (lane & 1) == 0;
-    float4 v[pl.kReads];
+    float4 v[RowSumPlan<TT>::kReads];
 #pragma unroll
-    for (int i = 0; i < pl.kReads; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
+    for (int i = 0; i < RowSumPlan<TT>::kReads; ++i) v[i] = *reinterpret_cast<const float4 *>(base + pl.off[i]);
     const float2 s0 = sum_chunks4(v[0], v[1], v[2], v[3]);
     const float o0r = dpp_swap_pairs(s0.x), o0i = dpp_swap_pairs(s0.y);
     if (TT == 16) {
@@ -836,6 +836,20 @@ __device__ __forceinline__ BwdWave bwd_wave(const BwdArgs &p) {
     return w;
 }
 
+// One wave per slot column f of a wave of the layout (FL of them per layout
+// wave), so that the per-filter backward has FL times the waves of the layout.
+__device__ __forceinline__ BwdWave bwd_slot_wave(const BwdArgs &p, int fl, int &f) {
+    BwdWave w;
+    w.lane = threadIdx.x & 63;
+    const int gs = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    f = gs % fl;
+    const int gw = gs / fl;
+    w.g = gw / p.wpg;
+    w.wave = gw % p.wpg;
+    w.ri = p.rows[(int64_t)w.g * 4 * p.wpg + w.wave * 4 + (w.lane >> 4)];
+    return w;
+}
+
 // lambda[m] = G[m] + conj(a) lambda[m+1] over one sub-chunk, last step first
 // (FULL: all kSub steps, no per-step guard).
 template <int FL, bool FULL>
@@ -974,10 +988,11 @@ __global__ void __launch_bounds__(256) bwd_chain_kernel(BwdArgs p) {
 }
 
 // Full backward of segment blockIdx.y from its true incoming lambda; one
-// filter slot after another per lane.
+// filter slot per lane (grid: one wave per slot column).
 template <int FL>
 __global__ void __launch_bounds__(256) bwd_seg_kernel(BwdArgs p) {
-    const BwdWave w = bwd_wave(p);
+    int fcol = 0;
+    const BwdWave w = bwd_slot_wave(p, FL, fcol);
     if (w.ri.tpl < 0) return;
     const int seg = blockIdx.y;
     const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
@@ -985,9 +1000,9 @@ __global__ void __launch_bounds__(256) bwd_seg_kernel(BwdArgs p) {
     const int nqmax = (p.L + kSub - 1) / kSub;
     float2 *ysub = p.ysub + (int64_t)seg * nqmax * p.nslots;
     const float2 *gz = p.gz + (int64_t)w.ri.tpl * n;
-    for (int f = 0; f < FL; ++f) {
-        const int64_t slot = slot_index(w.g, p.wpg, w.wave, f, FL, w.lane);
-        if (p.slot_filter[slot] < 0) continue;
+    {
+        const int64_t slot = slot_index(w.g, p.wpg, w.wave, fcol, FL, w.lane);
+        if (p.slot_filter[slot] < 0) return;
         const float2 a = p.s.a32[slot], b = p.s.b32[slot];
         const float ar = a.x, ai = a.y, br = b.x, bi = b.y;
         const float *xw = p.xwin + p.s.xoff[slot];  // xw[m] = x[m - d]
@@ -1312,7 +1327,7 @@ hipError_t launch_backward_t(const BwdArgs &a, dim3 wgrid, dim3 block, hipStream
     hipLaunchKernelGGL(bwd_chain_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bwd_seg_kernel<FL>, dim3(wgrid.x, a.nseg), block, 0, st, a);
+    hipLaunchKernelGGL(bwd_seg_kernel<FL>, dim3(wgrid.x * FL, a.nseg), block, 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bwd_reduce_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
