@@ -118,6 +118,92 @@ int auto_wpg(int64_t total_rows, int max_nr, int n_cu) {
 // of a column have distinct d mod 32 (a residue class holds about K/32 < C
 // filters) and read from distinct banks. Padding lanes take the window offset
 // of a real lane of their column (same address: a broadcast, not a conflict).
+// Places the filters [k0, k1) of one template into its rows r0 .. r0+nr-1 of
+// workgroup g. A ds_read_b32 of the strain window x[m - d] is served 32 lanes
+// per LDS cycle with bank = (dword address mod 32), i.e. by d mod 32; the 32
+// lanes are the two rows 2q, 2q+1 of a wave at one filter column f. Where both
+// rows of such a pair belong to this template, the pair is one 32-lane column
+// that takes each residue class at most once while it can; a row whose partner
+// row belongs to another template takes residues 0..15 (even row) or 16..31
+// (odd row), so the two templates of the pair stay apart. Classes are placed
+// in order of decreasing count; a filter that finds every allowed column
+// already holding its class goes where its class is rarest, preferring
+// columns that already hold a double, so that the unavoidable extra cycles
+// gather in few passes. Padding lanes read the address of their row's first
+// lane (a broadcast).
+void deal_template(int64_t k0, int64_t k1, const int32_t *d, int g, int wpg, int fl, int r0, int nr, Layout &lay) {
+    struct Col {
+        int cap, lo, hi, rows[2], nparts, f, dbl;
+        std::vector<int32_t> items;
+        uint8_t has[32];
+    };
+    std::vector<Col> cols;
+    for (int r = r0; r < r0 + nr; ++r) {
+        const int p = r ^ 1;
+        const bool internal = p >= r0 && p < r0 + nr;
+        if (internal && p < r) continue;
+        for (int f = 0; f < fl; ++f) {
+            Col c{};
+            c.f = f;
+            c.rows[0] = r;
+            if (internal) {
+                c.cap = 2 * kRowLanes;
+                c.lo = 0;
+                c.hi = 32;
+                c.rows[1] = p;
+                c.nparts = 2;
+            } else {
+                c.cap = kRowLanes;
+                c.lo = (r & 1) ? 16 : 0;
+                c.hi = c.lo + 16;
+                c.nparts = 1;
+            }
+            cols.push_back(c);
+        }
+    }
+    std::vector<std::vector<int32_t>> bycls(32);
+    for (int64_t k = k0; k < k1; ++k) bycls[d[k] & 31].push_back((int32_t)k);
+    std::vector<int> corder(32);
+    for (int c = 0; c < 32; ++c) corder[c] = c;
+    std::stable_sort(corder.begin(), corder.end(),
+                     [&](int a, int b) { return bycls[a].size() > bycls[b].size(); });
+    // rank of a candidate column for a filter of class cls (lower is better): fewest of
+    // the class already there; among columns that already hold it, one with a double;
+    // then the least filled
+    auto key = [](const Col &c, int cls) {
+        const double fill = (double)c.items.size() / c.cap;
+        const int again = c.has[cls] > 0 && c.dbl == 0 ? 1 : 0;
+        return std::make_tuple((int)c.has[cls], again, fill);
+    };
+    for (int cls : corder) {
+        for (int32_t k : bycls[cls]) {
+            Col *best = nullptr;
+            for (int pass = 0; pass < 2 && !best; ++pass)   // allowed classes first, then any room
+                for (Col &c : cols) {
+                    if ((int)c.items.size() >= c.cap) continue;
+                    if (pass == 0 && (cls < c.lo || cls >= c.hi)) continue;
+                    if (!best || key(c, cls) < key(*best, cls)) best = &c;
+                }
+            if (best->has[cls]) ++best->dbl;
+            ++best->has[cls];
+            best->items.push_back(k);
+        }
+    }
+    for (const Col &c : cols) {
+        if (c.items.empty()) continue;
+        int64_t first = -1;   // slot of the column's first filter: padding lanes read its address
+        for (int part = 0; part < c.nparts; ++part) {
+            const int row = c.rows[part];
+            const int64_t base = ((int64_t)(g * wpg + row / 4) * fl + c.f) * 64 + (row % 4) * kRowLanes;
+            if (part == 0) first = base;
+            const int n0 = part * kRowLanes;
+            const int n = std::max(0, std::min<int>(kRowLanes, (int)c.items.size() - n0));
+            for (int l = 0; l < n; ++l) lay.slot_filter[(size_t)(base + l)] = c.items[(size_t)(n0 + l)];
+            for (int l = n; l < kRowLanes; ++l) lay.pad_src[(size_t)(base + l)] = first;
+        }
+    }
+}
+
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
     const int R = 4 * wpg;
     std::vector<int> nr(T);
@@ -153,7 +239,6 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
     lay.slot_filter.assign((size_t)lay.nslots, -1);
     lay.pad_src.assign((size_t)lay.nslots, -1);
     lay.tpl_group.assign(T, -1);
-    std::vector<int32_t> ks;
     for (int g = 0; g < lay.groups; ++g) {
         std::vector<int> &mem = members[g];
         std::sort(mem.begin(), mem.end());
@@ -161,22 +246,7 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
         for (int j : mem) {
             lay.tpl_group[j] = g;
             for (int r = 0; r < nr[j]; ++r) lay.rows[(size_t)g * R + r0 + r] = RowInfo{j, r0, nr[j], 0};
-            ks.clear();
-            for (int64_t k = off[j]; k < off[j + 1]; ++k) ks.push_back((int32_t)k);
-            std::stable_sort(ks.begin(), ks.end(), [&](int32_t x, int32_t y) { return (d[x] & 31) < (d[y] & 31); });
-            const int cols = nr[j] * fl;
-            auto slot_of = [&](int c, int lane16) {
-                const int row = r0 + c % nr[j], f = c / nr[j];
-                return ((int64_t)(g * wpg + row / 4) * fl + f) * 64 + (row % 4) * kRowLanes + lane16;
-            };
-            for (size_t i = 0; i < ks.size(); ++i)
-                lay.slot_filter[(size_t)slot_of((int)(i % cols), (int)(i / cols))] = ks[i];
-            for (int c = 0; c < cols; ++c) {
-                const int64_t first = slot_of(c, 0);   // filled whenever the column holds any filter
-                if (lay.slot_filter[(size_t)first] < 0) continue;
-                for (int l = 1; l < kRowLanes; ++l)
-                    if (lay.slot_filter[(size_t)slot_of(c, l)] < 0) lay.pad_src[(size_t)slot_of(c, l)] = first;
-            }
+            deal_template(off[j], off[j + 1], d, g, wpg, fl, r0, nr[j], lay);
             r0 += nr[j];
         }
     }
