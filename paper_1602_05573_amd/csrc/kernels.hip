@@ -221,6 +221,44 @@ __device__ __forceinline__ void row_sums(const float2 *wt, const RowSumPlan<TT> 
     }
 }
 
+// Template sum over its nr row sums of one step: N reads issued together
+// (rows past nr read other rows or the buffer's slack and are zeroed), then a
+// fixed pairwise tree; templates of more than 16 rows loop.
+template <int N>
+__device__ __forceinline__ void sum_rows(const float2 *ws, int nr, float &zr, float &zi) {
+    float vr[N], vi[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float2 v = ws[i];
+        vr[i] = i < nr ? v.x : 0.f;
+        vi[i] = i < nr ? v.y : 0.f;
+    }
+#pragma unroll
+    for (int w = 1; w < N; w *= 2)
+#pragma unroll
+        for (int i = 0; i < N; i += 2 * w) {
+            vr[i] += vr[i + w];
+            vi[i] += vi[i + w];
+        }
+    zr = vr[0];
+    zi = vi[0];
+}
+
+__device__ __forceinline__ void sum_rows_loop(const float2 *ws, int nr, float &zr, float &zi) {
+    zr = 0.f;
+    zi = 0.f;
+    int r = 0;
+    for (; r + 4 <= nr; r += 4) {
+        const float2 v0 = ws[r], v1 = ws[r + 1], v2 = ws[r + 2], v3 = ws[r + 3];
+        zr += (v0.x + v1.x) + (v2.x + v3.x);
+        zi += (v0.y + v1.y) + (v2.y + v3.y);
+    }
+    for (; r < nr; ++r) {
+        zr += ws[r].x;
+        zi += ws[r].y;
+    }
+}
+
 // Chunk-end correction of the carried state (len = samples in the chunk).
 template <int FL>
 __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa, int prec,
@@ -298,7 +336,8 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
     float *xs = reinterpret_cast<float *>(smem);
     float2 *wt = reinterpret_cast<float2 *>(smem + win_bytes) + wave * TT * 64;
     float2 *wsum = reinterpret_cast<float2 *>(smem + win_bytes) + W * TT * 64;  // [2][TT][Rp]
-    unsigned long long *kmax = reinterpret_cast<unsigned long long *>(wsum + 2 * TT * Rp);  // [2][TT]
+    // [2][TT] after wsum and 16 float2 of slack (row-sum reads past a template's last row)
+    unsigned long long *kmax = reinterpret_cast<unsigned long long *>(wsum + 2 * TT * Rp + 16);
     const RowSumPlan<TT> rsp = row_sum_plan<TT>(lane);
     constexpr int AH = Ahead<XLDS, TT>::value;
 
@@ -394,17 +433,13 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
             }
             if (leader && tl16 < steps) {
                 const float2 *ws = wsum + (buf * TT + tl16) * Rp + ri.r0;
-                float zr = 0.f, zi = 0.f;
-                int r = 0;
-                for (; r + 4 <= ri.nr; r += 4) {
-                    const float2 v0 = ws[r], v1 = ws[r + 1], v2 = ws[r + 2], v3 = ws[r + 3];
-                    zr += (v0.x + v1.x) + (v2.x + v3.x);
-                    zi += (v0.y + v1.y) + (v2.y + v3.y);
-                }
-                for (; r < ri.nr; ++r) {
-                    zr += ws[r].x;
-                    zi += ws[r].y;
-                }
+                float zr, zi;
+                if (ri.nr <= 8)
+                    sum_rows<8>(ws, ri.nr, zr, zi);
+                else if (ri.nr <= 16)
+                    sum_rows<16>(ws, ri.nr, zr, zi);
+                else
+                    sum_rows_loop(ws, ri.nr, zr, zi);
                 const int64_t tl = s0 + t0 + tl16;
                 if (sc.zl_in) {
                     const float2 zl = sc.zl_in[(int64_t)ri.tpl * sc.ld_zl + tl];
@@ -1202,7 +1237,7 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt) {
     const size_t win = x_in_lds ? (size_t)((dmax + nb + tt + 3) & ~3) * 4 : 0;
-    return win + (size_t)wpg * tt * 64 * 8 + (size_t)2 * tt * (4 * wpg + 1) * 8 + (size_t)2 * tt * 8;
+    return win + (size_t)wpg * tt * 64 * 8 + ((size_t)2 * tt * (4 * wpg + 1) + 16) * 8 + (size_t)2 * tt * 8;
 }
 
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
