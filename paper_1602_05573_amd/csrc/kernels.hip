@@ -221,6 +221,36 @@ __device__ __forceinline__ void row_sums(const float2 *wt, const RowSumPlan<TT> 
     }
 }
 
+// xs[i] = src[off + i] (0 if ZERO) for i in [i0, i1), by the whole workgroup:
+// a scalar head up to a 16-byte LDS boundary, then 16-byte global loads (4-byte
+// aligned) with four per thread in flight and 16-byte LDS stores, then a scalar
+// tail. Indices off + i are in range for every i in [i0, i1).
+template <bool ZERO>
+__device__ __forceinline__ void stage_range(float *xs, const float *src, int64_t off, int i0, int i1) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ia = min(i1, (i0 + 3) & ~3);
+    for (int i = i0 + tid; i < ia; i += nt) xs[i] = ZERO ? 0.f : src[off + i];
+    const int nv = (i1 - ia) >> 2;
+    for (int v0 = tid; v0 < nv; v0 += 4 * nt) {
+        float4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + u * nt;
+            q[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (!ZERO && v < nv) {
+                const f4u w = *reinterpret_cast<const f4u *>(src + (off + ia + 4 * (int64_t)v));
+                q[u] = make_float4(w.x, w.y, w.z, w.w);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + u * nt;
+            if (v < nv) *reinterpret_cast<float4 *>(xs + ia + 4 * v) = q[u];
+        }
+    }
+    for (int i = ia + 4 * nv + tid; i < i1; i += nt) xs[i] = ZERO ? 0.f : src[off + i];
+}
+
 // Template sum over its nr row sums of one step: N reads issued together
 // (rows past nr read other rows or the buffer's slack and are zeroed), then a
 // fixed pairwise tree; templates of more than 16 rows loop.
@@ -396,11 +426,13 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
         } else if (XLDS) {
             __syncthreads();
             const int cnt = p.dmax + nbs;
-            const int64_t m0 = xbase + s0 - p.dmax;
-            for (int i = tid; i < cnt; i += blockDim.x) {
-                const int64_t m = m0 + i;
-                xs[i] = m >= 0 ? p.x[m] : (p.hist ? p.hist[p.dmax + m] : 0.f);
-            }
+            const int64_t m0 = xbase + s0 - p.dmax;   // xs[i] = x[m0 + i]; m < 0 from the history
+            const int nneg = (int)min((int64_t)cnt, max((int64_t)0, -m0));
+            if (p.hist)
+                stage_range<false>(xs, p.hist, p.dmax + m0, 0, nneg);
+            else
+                stage_range<true>(xs, nullptr, 0, 0, nneg);
+            stage_range<false>(xs, p.x, m0, nneg, cnt);
             __syncthreads();
             xw = xs;
         } else {
