@@ -1445,10 +1445,17 @@ int spiir_autotune(int32_t nbk, const int32_t *T, const int64_t *const *off, con
     float best = 1e30f;
     int bestL = 256, bestF = 1;
     hipStream_t st = nullptr;
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    {
+        hipError_t ce = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (ce == hipSuccess) ce = hipEventCreate(&e0);
+        if (ce == hipSuccess) ce = hipEventCreate(&e1);
+        if (ce != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (st) (void)hipStreamDestroy(st);
+            return fail(SPIIR_EHIP, "autotune stream/event: %s", hipGetErrorString(ce));
+        }
+    }
     const int warm = 2, iters = 6;
     const int64_t len = (int64_t)B * (warm + iters);
     std::vector<float *> xs(nbk, nullptr), ms(nbk, nullptr);

@@ -381,3 +381,40 @@ def test_irregular_call_sizes(mid, tsplit):
     am = torch.cat([o[1] for o in outs]).cpu().numpy()
     check_argmax(mx, am, ref)
 
+
+def test_degenerate_coefficients_and_largest_template():
+    """a = 0 (a pure delayed tap), b = 0 (a silent filter), d = max_delay, and a
+    template that fills a whole workgroup (8 waves x 4 rows x 16 lanes x 4
+    filters = 2,048 filters) beside a one-filter template."""
+    banner("degenerate coefficients, largest template")
+    rng = np.random.default_rng(11)
+    K0, dmax = 2048, 1200
+    off = np.array([0, K0, K0 + 1, K0 + 4], np.int64)
+    F = int(off[-1])
+    a = 0.999 * np.exp(1j * rng.uniform(0.01, 1.5, F))
+    b = (rng.standard_normal(F) + 1j * rng.standard_normal(F)) / 40
+    d = rng.integers(0, dmax + 1, F).astype(np.int32)
+    a[5] = 0.0            # y = b x[n - d]
+    b[6] = 0.0            # contributes nothing
+    d[7] = dmax
+    a[K0] = 0.0           # one-filter template that is a pure tap at the longest delay
+    d[K0] = dmax
+    a[K0 + 1:] = 0.5 - 0.25j
+    bank = Bank(off, a, b, d, dmax)
+    x = strain(6007, 57)
+    ref = oracle.snr(bank, x)
+    for tsplit in (1, 0):
+        with mk(bank, filters_per_lane=4, time_split=tsplit) as bk:
+            assert bk.info["waves_per_group"] == 8
+            s = bk.filter_block(dev(x)).cpu().numpy()
+            bk.reset()
+            mx, am = bk.trigger_max(dev(x))
+        err, _ = snr_err(s, ref)
+        print("degenerate time_split=%d err=%.3g" % (tsplit, err))
+        assert err <= SNR_TOL
+        check_argmax(mx.cpu().numpy(), am.cpu().numpy(), ref)
+    # the one-tap template is exactly |b|^2 x[n - dmax]^2 (x = 0 before the stream)
+    tap = np.zeros(len(x))
+    tap[dmax:] = np.abs(b[K0]) ** 2 * x[:-dmax].astype(np.float64) ** 2
+    assert np.allclose(ref[1], tap, rtol=1e-12, atol=1e-300)
+
