@@ -34,6 +34,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measured_traffic():
     """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (scaled by a device copy of known size), or None when the
@@ -62,6 +73,8 @@ def main():
     ap.add_argument("--fl", type=int, default=0, help="filters per lane (0 = library choice)")
     ap.add_argument("--wpg", type=int, default=0)
     ap.add_argument("--time-split", type=int, default=0, help="time segments (0 = library choice, 1 = off)")
+    ap.add_argument("--fit-steps", type=int, default=5, help="adjoint: optimiser steps of the chirp fit")
+    ap.add_argument("--fit-lr", type=float, default=1e-4, help="adjoint: Adam learning rate of the fit")
     ap.add_argument("--plain-blocks", type=int, default=4)
     ap.add_argument("--check-blocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -215,10 +228,16 @@ def run_bank(args, torch):
         log("check: max|dM|/peak %.3g argmax agree %.6f (%d documented ties, %d outside) (oracle %.1fs)"
             % (rel, agree, diff.size, bad, t_or))
         if not args.no_cpu_baseline:
+            from workloads import bank_4x128
+            small, xs_small = bank_4x128()
+            t2 = time.perf_counter()
+            oracle.trigger(small, xs_small, nthreads=1)
+            rate1 = float(small.n_filters) * len(xs_small) / (time.perf_counter() - t2)
             result["cpu_baseline"] = {
                 "value": oracle_rate, "unit": "filter-updates/s", "cores": nth, "kind": "oracle",
                 "sample": "FP64 oracle trigger over the first %d samples of the same bank "
-                          "(all %d templates, %.2e updates), %.1f s" % (nchk, T, float(F) * nchk, t_or)}
+                          "(all %d templates, %.2e updates), %.1f s" % (nchk, T, float(F) * nchk, t_or),
+                "one_thread_4x128_bank": rate1, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
     if not args.no_plain and args.plain_blocks > 0:
         nb = min(args.plain_blocks, nblk)
@@ -403,6 +422,37 @@ def run_adjoint(args, torch):
                              "kernel": "spiir_forward_z with tape", "launch_us": fwd * 1e3},
     }
     log("adjoint: forward %.2f ms, loss %.2f ms, backward %.2f ms" % (fwd, loss, bwd))
+
+    # a short fit through the autograd Function: loss before and after (fit quality is not a gate)
+    from paper_1602_05573_amd import SpiirFn
+    a = torch.tensor(bank.a, dtype=torch.complex128, requires_grad=True)
+    b = torch.tensor(bank.b, dtype=torch.complex128, requires_grad=True)
+    Gn = torch.linalg.norm(gt, dim=1)
+
+    def overlap_loss(z):
+        c = torch.sum(z * torch.conj(gt), dim=1)
+        return torch.mean(1 - torch.abs(c) / (torch.linalg.norm(z, dim=1) * Gn))
+
+    opt = torch.optim.Adam([a, b], lr=args.fit_lr)
+    losses = []
+    tf = time.perf_counter()
+    for _ in range(args.fit_steps + 1):
+        opt.zero_grad()
+        lval = overlap_loss(SpiirFn.apply(a, b, bk, xd))
+        losses.append(float(lval))
+        if len(losses) > args.fit_steps:
+            break
+        lval.backward()
+        opt.step()
+        with torch.no_grad():   # keep every pole inside the unit circle
+            r = torch.abs(a)
+            a.mul_(torch.where(r > 1 - 1e-6, (1 - 1e-6) / r, torch.ones_like(r)))
+    tf = time.perf_counter() - tf
+    res["fit"] = {"steps": args.fit_steps, "optimizer": "Adam lr %g" % args.fit_lr,
+                  "mean_loss_before": losses[0], "mean_loss_after": losses[-1],
+                  "s_per_step": tf / max(1, args.fit_steps)}
+    log("fit: mean overlap loss %.4f -> %.4f over %d steps (%.3f s/step incl. coefficient upload)"
+        % (losses[0], losses[-1], args.fit_steps, tf / max(1, args.fit_steps)))
     bk.close()
     print(json.dumps(res), flush=True)
 
