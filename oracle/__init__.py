@@ -10,6 +10,7 @@ Functions (all double precision; see the C source for the definitions):
   trigger(bank, x)               (float64 max [n], int32 argmax [n])
   backward(bank, x, G)           (grad_a, grad_b) complex128 [F]
   overlap_loss(z, g)             per-template loss and its gradient G
+  clusters(M, J, threshold, W)   (index int64, template int32, value float32) of the triggers
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_pins.py`` against closed forms, a library IIR routine,
@@ -55,6 +56,8 @@ def _load():
         for f in (lib.oracle_z, lib.oracle_snr, lib.oracle_trigger, lib.oracle_backward):
             f.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_clusters.argtypes = [P, P, i64, ctypes.c_float, i32, P, P, P, i64]
+        lib.oracle_clusters.restype = i64
         _lib = lib
     return _lib
 
@@ -121,6 +124,24 @@ def trigger(bank, x, nthreads=None):
     if rc:
         raise RuntimeError("oracle_trigger failed (%d)" % rc)
     return mx, am
+
+
+def clusters(M, J, threshold, window):
+    """Triggers of a fused max/argmax series: the loudest sample of every
+    +-window neighbourhood at or above the threshold (earliest on ties)."""
+    lib = _load()
+    M = np.ascontiguousarray(M, np.float32)
+    J = np.ascontiguousarray(J, np.int32)
+    n = len(M)
+    cap = n // (int(window) + 1) + 1   # triggers are more than `window` apart
+    idx = np.zeros(cap, np.int64)
+    tpl = np.zeros(cap, np.int32)
+    val = np.zeros(cap, np.float32)
+    cnt = lib.oracle_clusters(_p(M), _p(J), n, ctypes.c_float(threshold), int(window), _p(idx), _p(tpl),
+                              _p(val), cap)
+    if cnt > cap:
+        raise RuntimeError("oracle_clusters: %d triggers exceed the bound %d" % (cnt, cap))
+    return idx[:cnt], tpl[:cnt], val[:cnt]
 
 
 def backward(bank, x, G, nthreads=None):

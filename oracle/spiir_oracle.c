@@ -244,3 +244,44 @@ int oracle_backward(const int64_t *off, const double *a, const double *b, const 
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/*
+ * Trigger clustering, the step after the per-sample max (Sect. "GPU
+ * accelerated SPIIR method", subsection "SPIIR method": the search identifies
+ * the presence of a signal in noisy data; Sect. "Multimessenger astronomy",
+ * subsection on the event timescale: low-latency searches must generate
+ * triggers quickly). The paper states no clustering rule; the reading used
+ * here keeps the loudest sample of every window: sample m is a trigger when
+ *
+ *   M[m] >= threshold,
+ *   M[i] <  M[m] for every i in [m - W, m)      (inside [0, n)),
+ *   M[i] <= M[m] for every i in (m, m + W]      (inside [0, n)),
+ *
+ * so equal values go to the earliest sample and triggers are more than W
+ * apart. M is the float32 fused maximum; comparisons are made on those float32
+ * values. Triggers are listed in increasing m with J[m] and M[m]; at most cap
+ * are written, the return value is their total number.
+ */
+int64_t oracle_clusters(const float *M, const int32_t *J, int64_t n, float threshold, int32_t W,
+                        int64_t *idx, int32_t *tpl, float *val, int64_t cap) {
+    int64_t cnt = 0;
+    for (int64_t m = 0; m < n; ++m) {
+        const float v = M[m];
+        if (!(v >= threshold)) continue;
+        int keep = 1;
+        const int64_t lo = m - W < 0 ? 0 : m - W;
+        for (int64_t i = lo; i < m && keep; ++i)
+            if (!(M[i] < v)) keep = 0;
+        const int64_t hi = m + W >= n ? n - 1 : m + W;
+        for (int64_t i = m + 1; i <= hi && keep; ++i)
+            if (!(M[i] <= v)) keep = 0;
+        if (!keep) continue;
+        if (cnt < cap) {
+            idx[cnt] = m;
+            tpl[cnt] = J[m];
+            val[cnt] = v;
+        }
+        ++cnt;
+    }
+    return cnt;
+}

@@ -349,3 +349,76 @@ def test_generators_are_deterministic_and_in_range():
     x1, x2 = strain(1000, 1), strain(1000, 1)
     assert x1.dtype == np.float32 and np.array_equal(x1, x2)
     assert not np.array_equal(strain(1000, 1), strain(1000, 0))
+
+
+# --- trigger clustering ----------------------------------------------------
+
+def _clusters_brute(M, J, threshold, W):
+    """Independent restatement: keep m when it is at or above the threshold and
+    no sample within W before it reaches its value, none within W after exceeds it."""
+    n = len(M)
+    out = []
+    for m in range(n):
+        v = float(M[m])
+        if v < threshold:
+            continue
+        left = [float(u) for u in M[max(0, m - W):m]]
+        right = [float(u) for u in M[m + 1:min(n, m + W + 1)]]
+        if (not left or max(left) < v) and (not right or max(right) <= v):
+            out.append(m)
+    return np.array(out, np.int64)
+
+
+@pytest.mark.parametrize("W,threshold", [(1, 0.0), (3, 2.0), (7, 5.0), (50, 0.0)])
+def test_clusters_brute_force_with_ties(W, threshold):
+    rng = np.random.default_rng(40 + W)
+    M = rng.integers(0, 9, 3000).astype(np.float32)   # many exact ties
+    J = rng.integers(0, 100, 3000).astype(np.int32)
+    idx, tpl, val = oracle.clusters(M, J, threshold, W)
+    ref = _clusters_brute(M, J, threshold, W)
+    assert np.array_equal(idx, ref)
+    assert np.array_equal(tpl, J[ref]) and np.array_equal(val, M[ref])
+    assert np.all(np.diff(idx) > W)   # triggers are more than W apart
+
+
+def test_clusters_match_maximum_filter_for_distinct_values():
+    import scipy.ndimage
+    from workloads import trigger_series
+    M, J = trigger_series(200000, 1)
+    # distinct values with the same ordering (ranks, exact in float32), where the
+    # tie rule plays no part
+    rank = np.empty(len(M), np.int64)
+    rank[np.argsort(M, kind="stable")] = np.arange(len(M))
+    M = rank.astype(np.float32)
+    assert len(np.unique(M)) == len(M)
+    for W in (5, 200, 4096):
+        mf = scipy.ndimage.maximum_filter(M, size=2 * W + 1, mode="constant", cval=-np.inf)
+        thr = float(np.quantile(M, 0.999))
+        ref = np.nonzero((M >= thr) & (M == mf))[0]
+        idx, _, _ = oracle.clusters(M, J, thr, W)
+        assert np.array_equal(idx, ref), W
+
+
+def test_clusters_closed_form_cases():
+    J = np.arange(40, dtype=np.int32)
+    # one triangular bump: its apex
+    M = np.array([0, 1, 2, 3, 4, 3, 2, 1, 0] + [0] * 31, np.float32)
+    assert oracle.clusters(M, J, 0.5, 10)[0].tolist() == [4]
+    # a flat top: its first sample
+    M = np.zeros(40, np.float32)
+    M[10:15] = 7.0
+    assert oracle.clusters(M, J, 1.0, 3)[0].tolist() == [10]
+    # a value exactly at the threshold counts
+    assert oracle.clusters(M, J, 7.0, 3)[0].tolist() == [10]
+    # two bumps further apart than W: both; within W: the larger one
+    M = np.zeros(40, np.float32)
+    M[5], M[20] = 3.0, 4.0
+    assert oracle.clusters(M, J, 1.0, 14)[0].tolist() == [5, 20]
+    assert oracle.clusters(M, J, 1.0, 15)[0].tolist() == [20]
+    # windows are clipped at both ends of the series
+    M = np.zeros(40, np.float32)
+    M[0], M[39] = 2.0, 2.0
+    assert oracle.clusters(M, J, 1.0, 5)[0].tolist() == [0, 39]
+    # nothing at or above the threshold; an empty series
+    assert len(oracle.clusters(M, J, 3.0, 5)[0]) == 0
+    assert len(oracle.clusters(np.zeros(0, np.float32), np.zeros(0, np.int32), 0.0, 5)[0]) == 0

@@ -16,4 +16,5 @@ from .gen import (  # noqa: F401
     precision_bank,
     chirp_target,
     chirp_init_bank,
+    trigger_series,
 )

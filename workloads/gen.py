@@ -223,3 +223,30 @@ def chirp_fit(n: int = 65536, n_templates: int = 256, k: int = 400):
     x = np.zeros(n, np.float32)
     x[0] = 1.0
     return Bank(off, a, b, d, int(n - 1)), x, gs, mcs
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the trigger clustering step: a fused max/argmax series.
+# ---------------------------------------------------------------------------
+
+def trigger_series(n: int, idx: int = 0, n_templates: int = 1024, peaks: int = 64,
+                   plateau: int = 8):
+    """A float32 max series shaped like the fused output over noise (chi-square
+    background) with `peaks` injected bumps, some of them flat-topped plateaus of
+    exactly equal values, and an int32 template index per sample (family 5)."""
+    rng = _rng(5, ROLE_STRAIN, idx)
+    M = rng.chisquare(2.0, n).astype(np.float64)
+    J = rng.integers(0, n_templates, n).astype(np.int32)
+    if n > 0:
+        at = rng.integers(0, n, peaks)
+        amp = rng.uniform(10.0, 100.0, peaks)
+        width = rng.integers(1, 200, peaks)
+        for c, h, w in zip(at, amp, width):
+            lo, hi = max(0, c - 3 * w), min(n, c + 3 * w + 1)
+            t = np.arange(lo, hi)
+            M[lo:hi] = np.maximum(M[lo:hi], h * np.exp(-0.5 * ((t - c) / w) ** 2))
+        for c in rng.integers(0, n, max(1, peaks // 4)):   # flat tops: runs of equal values
+            lo, hi = max(0, c), min(n, c + plateau)
+            M[lo:hi] = M[lo:hi].max() + 1.0
+    return M.astype(np.float32), J
+
