@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "complex IIR filter-updates/s + % FP32 vector peak; fused vs plain at 1e-4 err"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed FP32 issue), FLOP/s
+PEAK_HBM = 8.0e12             # MI355X HBM3E bandwidth, bytes/s
 FLOP_UPDATE = 12              # a*y 6 + b*x 2 + add 2 + template accumulation 2
 FLOP_SAMPLE = 4               # |z|^2 3 + compare 1, per template and sample
 FLOP_ADJ = 30                 # adjoint per update: y recompute 10, lambda 8, grad_b 4, grad_a 8
@@ -80,6 +81,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-cluster", action="store_true", help="bank: skip the trigger clustering leg")
+    ap.add_argument("--cluster-window", type=int, default=4096,
+                    help="bank: clustering window W in samples (4096 = 1 s at 4096 Hz)")
+    ap.add_argument("--cluster-quantile", type=float, default=0.9999,
+                    help="bank: clustering threshold as a quantile of the step's max series")
     ap.add_argument("--workload", choices=("bank", "batch", "adjoint", "precision"), default="bank",
                     help="bank: the 1,024-template bank (default, the headline); "
                          "batch: 8 uneven streams with their own banks in one graph replay per block")
@@ -194,6 +200,9 @@ def run_bank(args, torch):
                      "block_call_us": blk_s * 1e6, "flop_per_launch": flops_launch},
     }
 
+    if not args.no_cluster:
+        result["triggers"] = bench_clustering(args, torch, mx, am, stream)
+
     # parity of the timed configuration on a prefix (oracle over all templates)
     oracle_rate = None
     if not args.no_check or not args.no_cpu_baseline:
@@ -265,6 +274,53 @@ def run_bank(args, torch):
 
     bk.close()
     print(json.dumps(result), flush=True)
+
+
+def bench_clustering(args, torch, mx, am, stream, reps=50):
+    """Trigger clustering of one step's fused max/argmax series (threshold = a
+    high quantile of the series, window W), timed over repeated calls on the
+    stream; the oracle's scan of the same series is the CPU baseline and the
+    check (identical triggers)."""
+    from paper_1602_05573_amd import TriggerClusterer
+    n = mx.numel()
+    W = args.cluster_window
+    m_host, a_host = mx.cpu().numpy(), am.cpu().numpy()
+    thr = float(np.quantile(m_host, args.cluster_quantile))
+    cl = TriggerClusterer(n, n // (W + 1) + 1)
+    for _ in range(3):
+        cl.run(mx, am, thr, W)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cl.run(mx, am, thr, W)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_call = e0.elapsed_time(e1) * 1e-3 / reps
+    gi, gt, gv, total = cl.result()
+    # algorithmic bytes: the max series read once, then argmax read and
+    # (index, template, snr) written per trigger
+    alg = 4.0 * n + 20.0 * total
+    out = {"samples": n, "window": W, "threshold": thr, "threshold_quantile": args.cluster_quantile,
+           "count": total, "us_per_call": t_call * 1e6, "samples_per_s": n / t_call,
+           "launches_per_call": 4,
+           "roofline": {"bound": "hbm", "achieved": alg / t_call / 1e9, "peak": PEAK_HBM / 1e9,
+                        "unit": "GB/s", "frac": alg / t_call / PEAK_HBM, "algorithmic_bytes": alg,
+                        "note": "whole call (4 launches); launch latency dominates at this size"}}
+    log("clustering: %d triggers (W=%d, threshold %.4g), %.1f us per call" % (total, W, thr, t_call * 1e6))
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        ri, rt, rv = oracle.clusters(m_host, a_host, thr, W)
+        rtotal = len(ri)
+        t_or = time.perf_counter() - t0
+        same = (total == rtotal and np.array_equal(gi.cpu().numpy(), ri)
+                and np.array_equal(gt.cpu().numpy(), rt) and np.array_equal(gv.cpu().numpy(), rv))
+        out["cpu_baseline"] = {"value": n / t_or, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                               "sample": "oracle window scan of the same %d-sample series, %.3f s" % (n, t_or)}
+        out["check"] = {"identical_to_oracle": bool(same), "oracle_count": int(rtotal)}
+        log("clustering check: identical to the oracle: %s (oracle %.3f s)" % (same, t_or))
+    return out
 
 
 def run_batch(args, torch):

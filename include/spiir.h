@@ -305,6 +305,55 @@ int spiir_autotune(int32_t n_banks, const int32_t *n_templates,
 int spiir_bank_time_kernels(spiir_bank *bank, int32_t enable);
 int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches);
 
+/*
+ * Trigger clustering over a per-sample max / argmax series such as the output
+ * of spiir_trigger_max: thresholding the detection statistic and keeping one
+ * peak (sample, template, SNR) per cluster. The paper uses the SNR output to
+ * decide whether a signal is present (Sect. "GPU accelerated SPIIR method",
+ * subsection "SPIIR method") and names low-latency trigger generation as the
+ * purpose (Sect. "Multimessenger astronomy"); it gives no clustering rule, so
+ * this library reads it as a peak finder over a window of W samples:
+ *
+ *   m is a trigger  <=>  max[m] >= threshold,
+ *                        max[i] <  max[m] for every i in [m - W, m),
+ *                        max[i] <= max[m] for every i in (m, m + W],
+ *
+ * with the windows clipped to [0, n). Among equal values the earliest sample
+ * wins, so triggers are more than W samples apart. Comparisons are float32;
+ * -0 equals +0, a NaN never triggers and suppresses every sample within W of
+ * it. Triggers are written in increasing sample order.
+ *
+ * The rule depends on the series only within W of each sample, so a stream can
+ * be clustered piecewise: a call on samples [s, e) of a longer series gives the
+ * whole series' answer for every m with s + W <= m < e - W (overlap calls by 2W).
+ *
+ *   max_dev, argmax_dev  float32 [n], int32 [n]; device memory (may be NULL when
+ *                        n = 0). Any alignment of 4 bytes.
+ *   threshold            SNR threshold (a NaN threshold selects nothing)
+ *   window               W >= 0; W = 0 keeps every sample at or above threshold
+ *   workspace_dev        device scratch of spiir_cluster_workspace_size(n) bytes or
+ *                        more, owned by the caller; contents need no clearing and
+ *                        are overwritten. NULL allowed when n = 0.
+ *   index_dev            int64 [capacity]: trigger sample indices, ascending
+ *   template_dev         int32 [capacity]: argmax[index]
+ *   snr_dev              float32 [capacity]: max[index]
+ *                        (all three may be NULL when capacity = 0)
+ *   count_dev            int64 [1], device memory: the total number of triggers,
+ *                        also when it exceeds capacity (then only the first
+ *                        capacity triggers are written)
+ *   device               HIP device ordinal of every buffer and of stream; -1 = current
+ * Everything is enqueued on stream (no host synchronisation, no allocation);
+ * calls sharing a workspace must be ordered on one stream. Errors: EINVAL for
+ * null pointers, n outside [0, 2^40], W < 0, capacity < 0 or a short workspace;
+ * ENODEV for a missing or non-gfx950 device.
+ */
+int spiir_cluster_workspace_size(int64_t n, size_t *nbytes);
+int spiir_cluster_triggers(const float *max_dev, const int32_t *argmax_dev, int64_t n,
+                           float threshold, int32_t window, void *workspace_dev,
+                           size_t workspace_bytes, int64_t *index_dev, int32_t *template_dev,
+                           float *snr_dev, int64_t capacity, int64_t *count_dev, int32_t device,
+                           void *stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *spiir_last_error(void);
 

@@ -22,7 +22,8 @@ EXPORTS = (
     "spiir_bank_set_state", "spiir_filter_block", "spiir_trigger_max",
     "spiir_trigger_max_per_template", "spiir_forward_z", "spiir_backward", "spiir_tape_destroy",
     "spiir_batch_create", "spiir_batch_step", "spiir_batch_steps_total", "spiir_batch_reset",
-    "spiir_batch_destroy", "spiir_batch_set_time_split", "spiir_autotune", "spiir_bank_time_kernels", "spiir_bank_kernel_time",
+    "spiir_batch_destroy", "spiir_batch_set_time_split", "spiir_autotune", "spiir_bank_time_kernels",
+    "spiir_bank_kernel_time", "spiir_cluster_workspace_size", "spiir_cluster_triggers",
     "spiir_last_error", "spiir_version",
 )
 
@@ -94,6 +95,9 @@ def load():
                                           ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "spiir_bank_time_kernels": (ctypes.c_int, [P, I32]),
         "spiir_bank_kernel_time": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
+        "spiir_cluster_workspace_size": (ctypes.c_int, [I64, ctypes.POINTER(SZ)]),
+        "spiir_cluster_triggers": (ctypes.c_int, [P, P, I64, ctypes.c_float, I32, P, SZ, P, P, P, I64,
+                                                  P, I32, P]),
         "spiir_last_error": (ctypes.c_char_p, []),
         "spiir_version": (ctypes.c_char_p, []),
     }

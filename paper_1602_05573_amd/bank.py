@@ -325,8 +325,59 @@ class SpiirFn(torch.autograd.Function):
                 None, None)
 
 
+class TriggerClusterer:
+    """Trigger clustering of max/argmax series of up to max_n samples with a
+    preallocated device workspace and outputs for `capacity` triggers
+    (spiir_cluster_triggers). run() only enqueues work; result() waits for it."""
+
+    def __init__(self, max_n: int, capacity: int, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nb = ctypes.c_size_t()
+        call("spiir_cluster_workspace_size", int(max_n), ctypes.byref(nb))
+        self.max_n, self.capacity, self.device = int(max_n), int(capacity), dev
+        self.workspace = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
+        self.index = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev)
+        self.template = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
+        self.snr = torch.empty(max(1, self.capacity), dtype=torch.float32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def run(self, mx: torch.Tensor, am: torch.Tensor, threshold: float, window: int, stream=None):
+        _require_cuda(mx, torch.float32, "max")
+        _require_cuda(am, torch.int32, "argmax")
+        n = mx.numel()
+        if am.numel() != n:
+            raise ValueError("max and argmax differ in length")
+        if n > self.max_n:
+            raise ValueError("series of %d samples exceeds max_n = %d" % (n, self.max_n))
+        if mx.device != self.device or am.device != self.device:
+            raise ValueError("series are not on %s" % self.device)
+        call("spiir_cluster_triggers", _ptr(mx), _ptr(am), n, float(threshold), int(window),
+             _ptr(self.workspace), self.workspace.numel(), _ptr(self.index), _ptr(self.template),
+             _ptr(self.snr), self.capacity, _ptr(self.count), self.device.index, _stream_ptr(stream))
+
+    def result(self):
+        """(index, template, snr, total): the first min(total, capacity)
+        triggers and the total count."""
+        total = int(self.count.item())
+        k = min(total, self.capacity)
+        return self.index[:k], self.template[:k], self.snr[:k], total
+
+
+def cluster_triggers(mx: torch.Tensor, am: torch.Tensor, threshold: float, window: int,
+                     capacity: int | None = None, stream=None):
+    """One-shot clustering of a max/argmax series; the default capacity holds
+    every possible trigger (they are more than `window` samples apart).
+    Returns (index int64, template int32, snr float32, total)."""
+    n = mx.numel()
+    cap = n // (int(window) + 1) + 1 if capacity is None else int(capacity)
+    c = TriggerClusterer(n, cap, device=mx.device)
+    c.run(mx, am, threshold, window, stream=stream)
+    return c.result()
+
+
 def version() -> str:
     return load().spiir_version().decode()
 
 
-__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "autotune", "batch_banks", "version", "_lib"]
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "TriggerClusterer", "autotune", "batch_banks",
+           "cluster_triggers", "version", "_lib"]

@@ -1537,6 +1537,66 @@ int spiir_autotune(int32_t nbk, const int32_t *T, const int64_t *const *off, con
 
 const char *spiir_last_error(void) { return g_err.c_str(); }
 
+namespace {
+
+constexpr int64_t kMaxClusterN = (int64_t)1 << 40;
+
+// gfx950 check of a device, cached per ordinal for the process.
+int cluster_device(int32_t device, int &dev) {
+    static std::mutex mu;
+    static std::map<int, int> checked;
+    dev = device;
+    if (dev < 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+            return fail(SPIIR_ENODEV, "no HIP device available");
+        HIPCHK(hipGetDevice(&dev));
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = checked.find(dev);
+    if (it != checked.end()) return it->second;
+    DeviceFacts df;
+    const int rc = device_facts(dev, df);
+    if (rc != SPIIR_ENODEV) checked[dev] = rc;
+    return rc;
+}
+
+}  // namespace
+
+int spiir_cluster_workspace_size(int64_t n, size_t *nbytes) {
+    if (!nbytes) return fail(SPIIR_EINVAL, "null argument");
+    if (n < 0 || n > kMaxClusterN) return fail(SPIIR_EINVAL, "n must be in [0, 2^40] (got %lld)", (long long)n);
+    *nbytes = cluster_workspace_bytes(n);
+    return SPIIR_OK;
+}
+
+int spiir_cluster_triggers(const float *max_dev, const int32_t *argmax_dev, int64_t n, float threshold,
+                           int32_t window, void *workspace_dev, size_t workspace_bytes, int64_t *index_dev,
+                           int32_t *template_dev, float *snr_dev, int64_t capacity, int64_t *count_dev,
+                           int32_t device, void *stream) {
+    if (!count_dev) return fail(SPIIR_EINVAL, "count_dev is null");
+    if (n < 0 || n > kMaxClusterN) return fail(SPIIR_EINVAL, "n must be in [0, 2^40] (got %lld)", (long long)n);
+    if (window < 0) return fail(SPIIR_EINVAL, "window must be >= 0 (got %d)", window);
+    if (capacity < 0) return fail(SPIIR_EINVAL, "capacity must be >= 0");
+    if (capacity > 0 && (!index_dev || !template_dev || !snr_dev))
+        return fail(SPIIR_EINVAL, "null output array with capacity %lld", (long long)capacity);
+    if (n > 0) {
+        if (!max_dev || !argmax_dev) return fail(SPIIR_EINVAL, "null max / argmax series");
+        if (!workspace_dev) return fail(SPIIR_EINVAL, "null workspace");
+        const size_t need = cluster_workspace_bytes(n);
+        if (workspace_bytes < need)
+            return fail(SPIIR_EINVAL, "workspace of %zu bytes is below the %zu bytes needed for n = %lld",
+                        workspace_bytes, need, (long long)n);
+    }
+    int dev = 0;
+    const int rc = cluster_device(device, dev);
+    if (rc) return rc;
+    DeviceGuard guard(dev);
+    HIPCHK(launch_cluster(max_dev, argmax_dev, n, threshold, window, workspace_dev, capacity, index_dev,
+                          template_dev, snr_dev, count_dev, static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 const char *spiir_version(void) { return "spiir-mi355x 0.1.0 (gfx950)"; }
 
 }  // extern "C"

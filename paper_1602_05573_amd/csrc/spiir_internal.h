@@ -135,4 +135,11 @@ hipError_t launch_batch_advance(int64_t *pos, const BatchStream *streams, int ns
 hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t stream);
 int forward_max_threads();
 
+// Trigger clustering over a max/argmax series (block maxima, window test,
+// ordered compaction); the workspace holds the block maxima, masks and counts.
+size_t cluster_workspace_bytes(int64_t n);
+hipError_t launch_cluster(const float *max, const int32_t *argmax, int64_t n, float threshold,
+                          int64_t window, void *workspace, int64_t capacity, int64_t *index,
+                          int32_t *tmpl, float *snr, int64_t *count, hipStream_t stream);
+
 }  // namespace spiir

@@ -117,6 +117,37 @@ def test_null_arguments(lib):
                               ctypes.byref(F), None) == _lib.SPIIR_EINVAL
 
 
+def test_cluster_arguments(lib):
+    """Clustering rejects bad sizes and null buffers on the host, and reports
+    a workspace that grows with n."""
+    nb = ctypes.c_size_t()
+    assert lib.spiir_cluster_workspace_size(-1, ctypes.byref(nb)) == _lib.SPIIR_EINVAL
+    assert lib.spiir_cluster_workspace_size(1 << 41, ctypes.byref(nb)) == _lib.SPIIR_EINVAL
+    assert lib.spiir_cluster_workspace_size(10, None) == _lib.SPIIR_EINVAL
+    sizes = []
+    for n in (0, 1, 4096, 4097, 1 << 22):
+        assert lib.spiir_cluster_workspace_size(n, ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes == sorted(sizes) and sizes[1] > 0
+    # (1<<22)/64 block maxima + masks and (1<<22)/4096 counts and offsets
+    assert sizes[-1] >= (1 << 16) * 12 + (1 << 10) * 16
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails on the host
+    C = lib.spiir_cluster_triggers
+    assert C(fake, fake, 10, 1.0, 4, fake, 1 << 20, fake, fake, fake, 4, None, -1, None) == _lib.SPIIR_EINVAL
+    assert "count" in lib.spiir_last_error().decode()
+    assert C(fake, fake, -1, 1.0, 4, fake, 1 << 20, fake, fake, fake, 4, fake, -1, None) == _lib.SPIIR_EINVAL
+    assert C(fake, fake, 10, 1.0, -1, fake, 1 << 20, fake, fake, fake, 4, fake, -1, None) == _lib.SPIIR_EINVAL
+    assert "window" in lib.spiir_last_error().decode()
+    assert C(fake, fake, 10, 1.0, 4, fake, 1 << 20, fake, fake, fake, -1, fake, -1, None) == _lib.SPIIR_EINVAL
+    assert C(fake, fake, 10, 1.0, 4, fake, 1 << 20, None, fake, fake, 4, fake, -1, None) == _lib.SPIIR_EINVAL
+    assert C(None, fake, 10, 1.0, 4, fake, 1 << 20, fake, fake, fake, 4, fake, -1, None) == _lib.SPIIR_EINVAL
+    assert C(fake, fake, 10, 1.0, 4, None, 1 << 20, fake, fake, fake, 4, fake, -1, None) == _lib.SPIIR_EINVAL
+    lib.spiir_cluster_workspace_size(10000, ctypes.byref(nb))
+    assert C(fake, fake, 10000, 1.0, 4, fake, nb.value - 1, fake, fake, fake, 4, fake, -1,
+             None) == _lib.SPIIR_EINVAL
+    assert "workspace" in lib.spiir_last_error().decode()
+
+
 def test_no_device_reported_cleanly(lib):
     """With valid arguments and no GPU, creation fails with ENODEV (never a fallback)."""
     import torch
@@ -125,6 +156,9 @@ def test_no_device_reported_cleanly(lib):
     rc, h = _create(lib, GOOD["T"], GOOD["off"], GOOD["a"], GOOD["b"], GOOD["d"])
     assert rc == _lib.SPIIR_ENODEV
     assert not h.value
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.spiir_cluster_triggers(None, None, 0, 1.0, 4, None, 0, None, None, None, 0, fake, -1,
+                                      None) == _lib.SPIIR_ENODEV
 
 
 def test_package_has_no_cpu_fallback():

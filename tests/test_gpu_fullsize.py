@@ -74,6 +74,16 @@ def test_bank1024_full_size():
             assert np.max(np.abs(m[at] - ref[r, at])) <= SNR_TOL * P[r]
         # and the max over all templates is never below a sampled template's SNR
         assert np.all(m >= ref[r] - SNR_TOL * P[r])
+    # trigger clustering of the fused output, as bench.py runs it
+    from paper_1602_05573_amd import cluster_triggers
+    thr, W = float(np.quantile(m, 0.9999)), 4096
+    banner("bank_1024 clustering threshold %.6g window %d" % (thr, W))
+    gi, gt, gv, total = cluster_triggers(mx, am, thr, W)
+    ri, rt, rv = oracle.clusters(m, a, thr, W)
+    rtotal = len(ri)
+    assert total == rtotal and total > 0
+    assert np.array_equal(gi.cpu().numpy(), ri) and np.array_equal(gt.cpu().numpy(), rt)
+    assert np.array_equal(gv.cpu().numpy(), rv)
 
 
 def test_batch_streams_full_size():
