@@ -9,15 +9,18 @@
 // windows clipped to the series. Triggers are therefore more than W apart and
 // each is the peak of the samples within W of it.
 //
-// Four launches, all linear in n:
+// Three launches (four for series of more than 8,192 4,096-blocks):
 //   reduce : order-preserving 32-bit keys, maxima of 64-sample blocks (one wave)
 //            and of 4,096-sample blocks (one workgroup)
-//   find   : per sample, threshold test, then the two window maxima taken
-//            nearest first from samples, 64-blocks and 4,096-blocks, stopping at
-//            the first larger key; a 64-bit ballot mask per 64-block and a count
-//            per 4,096-block
-//   scan   : one workgroup, exclusive prefix of the 4,096-block counts
-//   write  : triggers in increasing sample order, clipped to the capacity
+//   find   : per sample, threshold and direct-neighbour tests, then the two
+//            window maxima over samples, 64-blocks and 4,096-blocks (by the
+//            whole wave for a few survivors, by each lane otherwise); a 64-bit
+//            ballot mask per 64-block and a count per 4,096-block
+//   (scan) : long series only: one workgroup, exclusive prefix of the counts
+//   write  : triggers in increasing sample order, clipped to the capacity; for
+//            short series each 4,096-block with triggers sums the counts before
+//            it (the cost is the square of the block count, hence the limit)
+//            and the last block writes the total
 // A 64-block whose maximum is below the threshold is skipped by find without
 // reading its samples, so for a threshold well above the noise the only full
 // pass over max[] is the reduce launch.
@@ -29,6 +32,7 @@ namespace {
 constexpr int kB1 = 64;     // level-1 block: one wave, one mask word
 constexpr int kB2 = 4096;   // level-2 block: one workgroup
 constexpr int kThreads = 256;
+constexpr int64_t kInlinePrefix = 8192;  // most 4,096-blocks whose offsets the write launch sums itself
 
 typedef float f4 __attribute__((ext_vector_type(4), aligned(4)));
 
@@ -99,20 +103,17 @@ __global__ __launch_bounds__(kThreads) void clus_reduce_kernel(const float *__re
     }
 }
 
-// True when no key in [lo, m) reaches km and no key in (m, e) exceeds km, with
-// lo = max(0, m - W), e = min(n, m + W + 1). Every range is covered nearest
-// first by samples up to a 64-block boundary, then 64-blocks up to a
-// 4,096-block boundary, then 4,096-blocks, then 64-blocks and samples again;
-// a block is only used when it lies wholly inside the range, so partial blocks
-// at the end of the series are never read as blocks.
-__device__ bool is_peak(const float *__restrict__ M, int64_t n, int64_t m, uint32_t km, int64_t W,
-                        const uint32_t *__restrict__ bm1, const uint32_t *__restrict__ bm2) {
+// Per-lane test of sample m: no key in [lo, m) reaches km and no key in
+// (m, e) exceeds km, with lo = max(0, m - W), e = min(n, m + W + 1). Each range
+// is covered nearest first by samples up to a 64-block boundary, then 64-blocks
+// up to a 4,096-block boundary, then 4,096-blocks, then 64-blocks and samples
+// again, stopping at the first larger key; a block is only used when it lies
+// wholly inside the range, so partial blocks at the end of the series are
+// never read as blocks. Used when many lanes of a wave are candidates.
+__device__ bool is_peak_lane(const float *__restrict__ M, int64_t n, int64_t m, uint32_t km, int64_t W,
+                             const uint32_t *__restrict__ bm1, const uint32_t *__restrict__ bm2) {
     const int64_t lo = m - W > 0 ? m - W : 0;
     const int64_t e = m + W + 1 < n ? m + W + 1 : n;
-    // the direct neighbours first: a rising or falling edge fails here
-    if (m - 1 >= lo && okey(M[m - 1]) >= km) return false;
-    if (m + 1 < e && okey(M[m + 1]) > km) return false;
-
     int64_t p = m;
     const int64_t e1 = (m / kB1) * kB1 > lo ? (m / kB1) * kB1 : lo;
     for (; p > e1; --p)
@@ -140,46 +141,9 @@ __device__ bool is_peak(const float *__restrict__ M, int64_t n, int64_t m, uint3
     return true;
 }
 
-// One workgroup per 4,096-block c; wave w takes its 64-blocks c*64 + 16w .. +15,
-// one sample per lane.
-__global__ __launch_bounds__(kThreads) void clus_find_kernel(const float *__restrict__ M, int64_t n,
-                                                             float thr, uint32_t kthr, int64_t W,
-                                                             const uint32_t *__restrict__ bm1,
-                                                             const uint32_t *__restrict__ bm2,
-                                                             uint64_t *__restrict__ mask,
-                                                             uint32_t *__restrict__ cnt2) {
-    __shared__ uint32_t wc[kThreads / 64];
-    const int64_t c = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t nb1 = (n + kB1 - 1) / kB1;
-    uint32_t cnt = 0;
-    for (int it = 0; it < kB2 / kB1 / (kThreads / 64); ++it) {
-        const int64_t b = c * (kB2 / kB1) + w * (kB2 / kB1 / (kThreads / 64)) + it;
-        if (b >= nb1) break;
-        uint64_t bits = 0;
-        if (bm1[b] >= kthr) {
-            const int64_t m = b * kB1 + lane;
-            bool hit = false;
-            if (m < n) {
-                const float v = M[m];
-                if (v >= thr) hit = is_peak(M, n, m, okey(v), W, bm1, bm2);
-            }
-            bits = __ballot(hit);
-        }
-        if (lane == 0) mask[b] = bits;
-        cnt += (uint32_t)__popcll(bits);
-    }
-    if (lane == 0) wc[w] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int i = 0; i < kThreads / 64; ++i) s += wc[i];
-        cnt2[c] = s;
-    }
-}
-
 // Exclusive prefix of the nb2 block counts in one workgroup of 1,024 threads,
-// each owning a contiguous run; the total goes to *count.
+// each owning a contiguous run; the total goes to *count. Used for long series
+// (more than kInlinePrefix blocks).
 __global__ __launch_bounds__(1024) void clus_scan_kernel(const uint32_t *__restrict__ cnt2, int64_t nb2,
                                                          int64_t *__restrict__ off2,
                                                          int64_t *__restrict__ count) {
@@ -205,24 +169,163 @@ __global__ __launch_bounds__(1024) void clus_scan_kernel(const uint32_t *__restr
     if (t == 1023) *count = part[1023];
 }
 
+// Count of an empty series.
+__global__ void clus_zero_count_kernel(int64_t *count) { *count = 0; }
+
+__device__ inline uint32_t wave_max(uint32_t k) {
+    for (int o = 1; o < 64; o <<= 1) k = max(k, (uint32_t)__shfl_xor((int)k, o));
+    return k;
+}
+
+// This lane's share of the maximum key over samples [a, z) (a, z uniform across
+// the wave): samples up to the nearest 64-block boundaries, whole 64-blocks up
+// to the nearest 4,096-block boundaries and whole 4,096-blocks in between, each
+// piece one predicated load per lane, so the loads of every piece are in flight
+// together. Blocks are only read when they lie wholly inside [a, z).
+__device__ uint32_t range_max_part(const float *__restrict__ M, const uint32_t *__restrict__ bm1,
+                                   const uint32_t *__restrict__ bm2, int64_t a, int64_t z, int lane) {
+    uint32_t k = 0;
+    if (a >= z) return k;
+    const int64_t L1 = (a + kB1 - 1) / kB1 * kB1, H1 = z / kB1 * kB1;
+    if (L1 >= H1) {
+        // at most one 64-block boundary inside: fewer than 128 samples
+        for (int64_t i = a + lane; i < z; i += 64) k = max(k, okey(M[i]));
+        return k;
+    }
+    if (a + lane < L1) k = max(k, okey(M[a + lane]));
+    if (H1 + lane < z) k = max(k, okey(M[H1 + lane]));
+    const int64_t L2 = (a + kB2 - 1) / kB2 * kB2, H2 = z / kB2 * kB2;
+    if (L2 <= H2) {
+        if (L1 + kB1 * lane < L2) k = max(k, bm1[L1 / kB1 + lane]);
+        if (H2 + kB1 * lane < H1) k = max(k, bm1[H2 / kB1 + lane]);
+        for (int64_t j = L2 / kB2 + lane; j < H2 / kB2; j += 64) k = max(k, bm2[j]);
+    } else if (L1 + kB1 * lane < H1) {
+        // a and z in one 4,096-block: fewer than 64 whole 64-blocks
+        k = max(k, bm1[L1 / kB1 + lane]);
+    }
+    return k;
+}
+
+// One workgroup of 16 waves per 4,096-block c. Every wave reads the 64 block
+// maxima of c; blocks below the threshold are skipped without reading their
+// samples, and the live blocks are dealt round robin by rank to the waves (the
+// samples above a threshold come in runs, so neighbouring live blocks go to
+// different waves). In a live block each lane tests one sample: threshold and
+// the two direct neighbours (rising and falling edges fail there); the
+// survivors are tested on their whole windows, one at a time by the whole wave
+// when few, else each by its own lane.
+constexpr int kFindThreads = 1024;
+constexpr int kWaveTestMax = 4;
+
+__global__ __launch_bounds__(kFindThreads) void clus_find_kernel(const float *__restrict__ M, int64_t n,
+                                                                 float thr, uint32_t kthr, int64_t W,
+                                                                 const uint32_t *__restrict__ bm1,
+                                                                 const uint32_t *__restrict__ bm2,
+                                                                 uint64_t *__restrict__ mask,
+                                                                 uint32_t *__restrict__ cnt2) {
+    constexpr int kWaves = kFindThreads / 64;
+    __shared__ uint32_t wc[kWaves];
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nb1 = (n + kB1 - 1) / kB1;
+    const int64_t b0 = c * (kB2 / kB1);
+    const bool own = b0 + lane < nb1;
+    const bool live = own && bm1[b0 + lane] >= kthr;
+    if (w == 0 && own && !live) mask[b0 + lane] = 0;
+    uint64_t todo = __ballot(live);
+    uint32_t cnt = 0;
+    for (int r = 0; todo; ++r) {
+        const int i = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        if (r % kWaves != w) continue;
+        const int64_t b = b0 + i;
+        const int64_t m = b * kB1 + lane;
+        float v = 0.0f;
+        bool cand = false;
+        if (m < n) {
+            v = M[m];
+            cand = v >= thr;
+        }
+        if (cand && W >= 1) {
+            const uint32_t km = okey(v);
+            if (m >= 1 && okey(M[m - 1]) >= km) cand = false;
+            if (m + 1 < n && okey(M[m + 1]) > km) cand = false;
+        }
+        uint64_t cm = __ballot(cand);
+        uint64_t bits = 0;
+        if (W == 0) {
+            bits = cm;
+        } else if (__popcll(cm) <= kWaveTestMax) {
+            while (cm) {
+                const int l = __builtin_ctzll(cm);
+                cm &= cm - 1;
+                const int64_t mm = b * kB1 + l;
+                const uint32_t km = okey(__shfl(v, l));
+                const int64_t lo = mm - W > 0 ? mm - W : 0;
+                const int64_t e = mm + W + 1 < n ? mm + W + 1 : n;
+                const uint32_t pl = range_max_part(M, bm1, bm2, lo, mm, lane);
+                const uint32_t pr = range_max_part(M, bm1, bm2, mm + 1, e, lane);
+                if (wave_max(pl) < km && wave_max(pr) <= km) bits |= 1ull << l;
+            }
+        } else {
+            const bool hit = cand && is_peak_lane(M, n, m, okey(v), W, bm1, bm2);
+            bits = __ballot(hit);
+        }
+        if (lane == 0) mask[b] = bits;
+        cnt += (uint32_t)__popcll(bits);
+    }
+    if (lane == 0) wc[w] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int k = 0; k < kWaves; ++k) s += wc[k];
+        cnt2[c] = s;
+    }
+}
+
 // One workgroup per 4,096-block with triggers: the first wave ranks the 64 mask
 // words, then each wave writes whole words, lane = bit, so a word's triggers
-// land in consecutive slots.
+// land in consecutive slots. off2 = NULL: offsets and total summed here.
 __global__ __launch_bounds__(kThreads) void clus_write_kernel(const float *__restrict__ M,
                                                               const int32_t *__restrict__ J, int64_t n,
                                                               const uint64_t *__restrict__ mask,
                                                               const uint32_t *__restrict__ cnt2,
                                                               const int64_t *__restrict__ off2, int64_t cap,
+                                                              int64_t *__restrict__ count,
                                                               int64_t *__restrict__ idx,
                                                               int32_t *__restrict__ tpl,
                                                               float *__restrict__ val) {
     __shared__ uint64_t mk[kB2 / kB1];
     __shared__ uint32_t pre[kB2 / kB1];
+    __shared__ uint64_t red[kThreads / 64];
     const int64_t c = blockIdx.x;
-    if (cnt2[c] == 0) return;
-    const int64_t off = off2[c];
-    if (off >= cap) return;
+    const int64_t nb2 = gridDim.x;
     const int t = threadIdx.x;
+    int64_t off;
+    if (off2) {
+        if (cnt2[c] == 0) return;
+        off = off2[c];
+    } else {
+        // short series: this block's offset is the sum of the counts before it,
+        // and the last block also writes the total
+        const bool tail = c == nb2 - 1;
+        if (cnt2[c] == 0 && !tail) return;
+        const int64_t end = tail ? nb2 : c;
+        uint64_t s = 0;
+        for (int64_t i = t; i < end; i += kThreads) s += cnt2[i];
+        for (int o = 1; o < 64; o <<= 1) s += (uint64_t)__shfl_xor((long long)s, o);
+        if ((t & 63) == 0) red[t >> 6] = s;
+        __syncthreads();
+        s = 0;
+        for (int k = 0; k < kThreads / 64; ++k) s += red[k];
+        if (tail) {
+            if (t == 0) *count = (int64_t)s;
+            if (cnt2[c] == 0) return;
+            s -= cnt2[c];
+        }
+        off = (int64_t)s;
+    }
+    if (off >= cap) return;
     const int64_t nb1 = (n + kB1 - 1) / kB1;
     if (t < 64) {
         const int64_t b = c * (kB2 / kB1) + t;
@@ -287,15 +390,20 @@ hipError_t launch_cluster(const float *M, const int32_t *J, int64_t n, float thr
     ClusterWs w;
     carve(ws, n, &w);
     const int64_t nb2 = (n + kB2 - 1) / kB2;
-    if (nb2 > 0) {
-        hipLaunchKernelGGL(clus_reduce_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, n, w.bm1, w.bm2);
-        hipLaunchKernelGGL(clus_find_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, n, thr, okey(thr), W,
-                           w.bm1, w.bm2, w.mask, w.cnt2);
+    if (nb2 == 0) {
+        hipLaunchKernelGGL(clus_zero_count_kernel, dim3(1), dim3(1), 0, st, count);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(clus_scan_kernel, dim3(1), dim3(1024), 0, st, w.cnt2, nb2, w.off2, count);
-    if (nb2 > 0 && cap > 0)
-        hipLaunchKernelGGL(clus_write_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, J, n, w.mask,
-                           w.cnt2, w.off2, cap, idx, tpl, val);
+    hipLaunchKernelGGL(clus_reduce_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, n, w.bm1, w.bm2);
+    hipLaunchKernelGGL(clus_find_kernel, dim3((unsigned)nb2), dim3(kFindThreads), 0, st, M, n, thr, okey(thr), W,
+                       w.bm1, w.bm2, w.mask, w.cnt2);
+    int64_t *off2 = nullptr;
+    if (nb2 > kInlinePrefix) {
+        hipLaunchKernelGGL(clus_scan_kernel, dim3(1), dim3(1024), 0, st, w.cnt2, nb2, w.off2, count);
+        off2 = w.off2;
+    }
+    hipLaunchKernelGGL(clus_write_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, J, n, w.mask, w.cnt2,
+                       off2, cap, count, idx, tpl, val);
     return hipGetLastError();
 }
 

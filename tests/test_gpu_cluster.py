@@ -150,3 +150,58 @@ def test_cluster_rejects_bad_tensors():
         c.run(m[:50], j[:40], 1.0, 4)            # lengths differ
     with pytest.raises(SpiirError):
         c.run(m[:50], j[:50], 1.0, -3)           # negative window
+
+
+def test_cluster_graph_replay():
+    """The clustering call captured in a HIP graph: each replay, with eager
+    work (new series copied into the captured buffers) in between, equals the
+    oracle on the series the buffers hold at that replay."""
+    from paper_1602_05573_amd import TriggerClusterer
+    banner("cluster graph replay")
+    n, W = 300000, 512
+    series = [trigger_series(n, idx=k, peaks=48) for k in range(4)]
+    thr = 30.0
+    md = torch.empty(n, dtype=torch.float32, device="cuda")
+    jd = torch.empty(n, dtype=torch.int32, device="cuda")
+    md.copy_(torch.from_numpy(series[0][0]))
+    jd.copy_(torch.from_numpy(series[0][1]))
+    c = TriggerClusterer(n, n // (W + 1) + 1)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        c.run(md, jd, thr, W)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c.run(md, jd, thr, W)
+    for rep in range(6):
+        M, J = series[rep % 4]
+        md.copy_(torch.from_numpy(M))
+        jd.copy_(torch.from_numpy(J))
+        g.replay()
+        i, t, v, total = c.result()
+        ref = oracle_ref(M, J, thr, W)
+        assert ref[3] > 3
+        assert_same((i.cpu().numpy(), t.cpu().numpy(), v.cpu().numpy(), total), ref, "replay %d" % rep)
+        # eager call on another series between replays
+        M2, J2 = series[(rep + 1) % 4]
+        e = TriggerClusterer(n, 100)
+        e.run(torch.from_numpy(M2).cuda(), torch.from_numpy(J2).cuda(), thr, W)
+        assert e.result()[3] == oracle_ref(M2, J2, thr, W)[3]
+    del g
+
+
+def test_cluster_parity_scan_path():
+    """A series of more than 8,192 4,096-blocks (2^25 + 12,365 samples): block
+    offsets come from the separate one-workgroup scan instead of the write
+    launch."""
+    n = (1 << 25) + 3 * 4096 + 77
+    M, J = trigger_series(n, idx=4, peaks=512, plateau=8)
+    thr = float(np.quantile(M, 0.99995))
+    banner("cluster scan path n=%d" % n)
+    for W in (4096, 100000):
+        ref = oracle_ref(M, J, thr, W)
+        got = gpu_clusters(M, J, thr, W)
+        assert_same(got, ref, "scan path W=%d" % W)
+        assert ref[3] > 20
