@@ -11,6 +11,8 @@ Functions (all double precision; see the C source for the definitions):
   backward(bank, x, G)           (grad_a, grad_b) complex128 [F]
   overlap_loss(z, g)             per-template loss and its gradient G
   clusters(M, J, threshold, W)   (index int64, template int32, value float32) of the triggers
+  multirate_z(levels, h, g, x)   complex128 [T, n]: multi-rate bank, full-rate template sums
+  multirate_trigger(levels, h, g, x)  (float64 max [n], int32 argmax [n]) of |multirate_z|^2
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_pins.py`` against closed forms, a library IIR routine,
@@ -181,3 +183,67 @@ def overlap_loss(zs: np.ndarray, gs: np.ndarray):
     phase = np.where(ac > 0, c / np.where(ac > 0, ac, 1.0), 0.0)
     G = -(1.0 / (Z * Gn))[:, None] * (phase[:, None] * gs - (ac / Z ** 2)[:, None] * zs)
     return loss, G
+
+
+def decimate(x, h):
+    """One halving of the sample rate: x_r[q] = sum_i h[i] x[2q + 1 - i]
+    (causal FIR h, x[m < 0] = 0), len(x) // 2 outputs."""
+    x = np.asarray(x)
+    full = np.convolve(x, np.asarray(h, np.float64))
+    return full[1:len(x):2].copy()
+
+
+def upsample(w, g, n_out):
+    """One doubling of the sample rate: U(w)[p] = sum_q g[p - 2q] w[q] over
+    0 <= p - 2q < len(g), i.e. w zero-stuffed to the doubled rate and passed
+    through the causal FIR g, first n_out outputs."""
+    w = np.asarray(w)
+    s = np.zeros(n_out, w.dtype)
+    s[0::2] = w[:(n_out + 1) // 2]
+    return np.convolve(s, np.asarray(g, np.float64))[:n_out]
+
+
+def multirate_z(levels, h, g, x, nthreads=None) -> np.ndarray:
+    """Full-rate template sums of a multi-rate bank (the paper's remark that the
+    sampling rate of data and templates can be lowered where the signal
+    evolves slowly, Sect. "Multimessenger astronomy"; the steps are this
+    library's reading of it). levels[r] is a bank whose filters run at
+    1 / 2^r of the input rate, every level with the same templates (a
+    template may have no filters at a level); coefficients and delays are in
+    that level's samples.
+
+      x_0 = x,  x_r = decimate(x_{r-1}, h)                  (r = 1..R)
+      z_r[j] = sum over the level-r filters of template j of y_k, run on x_r
+      w_R = z_R,  w_r = z_r + upsample(w_{r+1}, g)           (r = R-1..0)
+      result = w_0
+
+    Cold start; len(x) must be a multiple of 2^R. FP64."""
+    R = len(levels) - 1
+    x = np.asarray(x, np.float64)
+    n = len(x)
+    if n % (1 << R):
+        raise ValueError("len(x) must be a multiple of 2^%d" % R)
+    T = levels[0].n_templates
+    xs = [x]
+    for r in range(1, R + 1):
+        xs.append(decimate(xs[-1], h))
+    w = None
+    for r in range(R, -1, -1):
+        lv = levels[r]
+        if lv.n_templates != T:
+            raise ValueError("every level needs the same templates")
+        nr = len(xs[r])
+        zr = z(lv, xs[r], nthreads=nthreads) if lv.n_filters > 0 else np.zeros((T, nr), np.complex128)
+        if w is not None:
+            for j in range(T):
+                zr[j] += upsample(w[j], g, nr)
+        w = zr
+    return w
+
+
+def multirate_trigger(levels, h, g, x, nthreads=None):
+    """Per-sample max over templates of |multirate_z|^2 and the smallest index
+    attaining it."""
+    zz = multirate_z(levels, h, g, x, nthreads=nthreads)
+    s = zz.real ** 2 + zz.imag ** 2
+    return s.max(axis=0), np.argmax(s, axis=0).astype(np.int32)

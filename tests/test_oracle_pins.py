@@ -422,3 +422,123 @@ def test_clusters_closed_form_cases():
     # nothing at or above the threshold; an empty series
     assert len(oracle.clusters(M, J, 3.0, 5)[0]) == 0
     assert len(oracle.clusters(np.zeros(0, np.float32), np.zeros(0, np.int32), 0.0, 5)[0]) == 0
+
+
+# --- multi-rate bank ---------------------------------------------------------
+
+def _mr_levels(T, per_level, R, seed=0, r_max=0.95):
+    """Random small multi-rate bank: per_level[r] = filters per template at level r."""
+    from workloads import Bank
+    rng = np.random.default_rng(900 + seed)
+    out = []
+    for r in range(R + 1):
+        k = per_level[r]
+        off = np.arange(T + 1, dtype=np.int64) * k
+        F = T * k
+        a = rng.uniform(0.3, r_max, F) * np.exp(1j * rng.uniform(0, np.pi / 2, F))
+        b = rng.standard_normal(F) + 1j * rng.standard_normal(F)
+        d = rng.integers(0, 5, F).astype(np.int32)
+        out.append(Bank(off, a, b, d, 8))
+    return out
+
+
+def test_multirate_resampling_matches_library_routines():
+    """A single pass-through filter (a = 0, b = 1, d = 0) at level R: the result
+    is x decimated R times and interpolated R times, built here from
+    scipy.signal.lfilter and scipy.signal.upfirdn."""
+    import scipy.signal
+    from workloads import Bank
+    rng = np.random.default_rng(5)
+    h, g = rng.standard_normal(13), rng.standard_normal(10)   # asymmetric: index direction matters
+    x = rng.standard_normal(512)
+    for R in (1, 2, 3):
+        levels = [Bank(np.zeros(2, np.int64), np.zeros(0, complex), np.zeros(0, complex),
+                       np.zeros(0, np.int32), 0) for _ in range(R)]
+        levels.append(Bank(np.array([0, 1], np.int64), np.array([0j]), np.array([1 + 0j]),
+                           np.array([0], np.int32), 0))
+        v = x.copy()
+        for _ in range(R):
+            v = scipy.signal.lfilter(h, [1.0], v)[1::2]
+        for r in range(R, 0, -1):
+            v = scipy.signal.upfirdn(g, v, up=2)[:len(x) >> (r - 1)]
+        got = oracle.multirate_z(levels, h, g, x)
+        assert got.shape == (1, len(x))
+        assert np.max(np.abs(got[0] - v)) < 1e-12, R
+
+
+def test_multirate_constant_input_steady_state():
+    """x = 1: decimation keeps the constant (h sums to 1), each filter settles at
+    b / (1 - a) in its own level's samples, interpolation keeps a constant
+    (each polyphase half of g sums to 1), so z_j settles at the sum of
+    b / (1 - a) over all of the template's filters at every level."""
+    from workloads import resample_taps
+    h, g = resample_taps(24)
+    R = 3
+    levels = _mr_levels(3, [2, 3, 1, 4], R, seed=1, r_max=0.8)
+    got = oracle.multirate_z(levels, h, g, np.ones(4096))
+    for j in range(3):
+        want = sum(np.sum(lv.b[lv.offsets[j]:lv.offsets[j + 1]] / (1 - lv.a[lv.offsets[j]:lv.offsets[j + 1]]))
+                   for lv in levels)
+        assert abs(got[j, -1] - want) < 1e-9 * abs(want)
+
+
+def _mr_brute(levels, h, g, x):
+    R = len(levels) - 1
+    xs = [list(map(float, x))]
+    for r in range(1, R + 1):
+        p = xs[-1]
+        xs.append([sum(h[i] * p[2 * q + 1 - i] for i in range(len(h)) if 0 <= 2 * q + 1 - i < len(p))
+                   for q in range(len(p) // 2)])
+    T = levels[0].n_templates
+    w = None
+    for r in range(R, -1, -1):
+        lv, xr = levels[r], xs[r]
+        zr = [[0j] * len(xr) for _ in range(T)]
+        for j in range(T):
+            for k in range(int(lv.offsets[j]), int(lv.offsets[j + 1])):
+                y = 0j
+                for m in range(len(xr)):
+                    y = lv.a[k] * y + lv.b[k] * (xr[m - lv.d[k]] if m - lv.d[k] >= 0 else 0.0)
+                    zr[j][m] += y
+            if w is not None:
+                for p in range(len(xr)):
+                    zr[j][p] += sum(g[p - 2 * q] * w[j][q] for q in range(len(w[j])) if 0 <= p - 2 * q < len(g))
+        w = zr
+    return np.array(w)
+
+
+def test_multirate_brute_force_tiny():
+    rng = np.random.default_rng(8)
+    h, g = rng.standard_normal(7), rng.standard_normal(6)   # asymmetric taps
+    levels = _mr_levels(2, [1, 2, 1], 2, seed=2)
+    levels[1].offsets = np.array([0, 0, 2], np.int64)      # template 0 has no level-1 filter
+    levels[1].a, levels[1].b, levels[1].d = levels[1].a[:2], levels[1].b[:2], levels[1].d[:2]
+    x = np.random.default_rng(6).standard_normal(48)
+    got = oracle.multirate_z(levels, h, g, x)
+    ref = _mr_brute(levels, h, g, x)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_multirate_shift_and_linearity():
+    from workloads import resample_taps
+    h, g = resample_taps(12)
+    R = 2
+    levels = _mr_levels(2, [2, 1, 3], R, seed=3)
+    rng = np.random.default_rng(7)
+    x, y = rng.standard_normal(256), rng.standard_normal(256)
+    zx, zy = oracle.multirate_z(levels, h, g, x), oracle.multirate_z(levels, h, g, y)
+    assert np.allclose(oracle.multirate_z(levels, h, g, 2.0 * x - 0.5 * y), 2.0 * zx - 0.5 * zy, atol=1e-10)
+    s = 3 << R   # shifts by whole multiples of 2^R keep the decimation phase
+    xs = np.concatenate([np.zeros(s), x])[:len(x)]
+    assert np.allclose(oracle.multirate_z(levels, h, g, xs)[:, s:], zx[:, :len(x) - s], atol=1e-10)
+
+
+def test_multirate_single_level_is_the_bank():
+    from workloads import random_bank, resample_taps, strain
+    h, g = resample_taps(8)
+    bank = random_bank(0, 3, 3, 10, 20, 0.9, 0.99, 16)
+    x = strain(300, 0, 3)
+    assert np.array_equal(oracle.multirate_z([bank], h, g, x), oracle.z(bank, x))
+    mx, am = oracle.multirate_trigger([bank], h, g, x)
+    m2, a2 = oracle.trigger(bank, x)
+    assert np.allclose(mx, m2, rtol=1e-12) and np.array_equal(am, a2)

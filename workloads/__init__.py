@@ -17,4 +17,6 @@ from .gen import (  # noqa: F401
     chirp_target,
     chirp_init_bank,
     trigger_series,
+    resample_taps,
+    multirate_bank,
 )

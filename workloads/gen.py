@@ -250,3 +250,69 @@ def trigger_series(n: int, idx: int = 0, n_templates: int = 1024, peaks: int = 6
             M[lo:hi] = M[lo:hi].max() + 1.0
     return M.astype(np.float32), J
 
+
+
+# ---------------------------------------------------------------------------
+# Multi-rate bank (family 6): filters placed on halved sample rates.
+# ---------------------------------------------------------------------------
+
+def resample_taps(n_taps: int = 24):
+    """FIR taps for halving (h) and doubling (g) the sample rate: a
+    Hann-windowed sinc with its cutoff at a quarter of the higher rate. h sums
+    to 1; each polyphase half of g (even and odd taps) sums to 1, so a constant
+    passes through decimation and interpolation unchanged. float64."""
+    i = np.arange(n_taps)
+    m = i - (n_taps - 1) / 2.0
+    win = 0.5 - 0.5 * np.cos(2.0 * np.pi * (i + 1) / (n_taps + 1))
+    base = 0.5 * np.sinc(0.5 * m) * win
+    h = base / base.sum()
+    g = np.empty(n_taps)
+    g[0::2] = base[0::2] / base[0::2].sum()
+    g[1::2] = base[1::2] / base[1::2].sum()
+    return h, g
+
+
+def multirate_bank(n_templates: int = 1024, k_lo: int = 100, k_hi: int = 800, levels: int = 5,
+                   f_lo: float = 20.0, f_hi: float = 1024.0, r_lo: float = 0.98, r_hi: float = 0.999,
+                   dmax: int = 2047, idx: int = 0):
+    """Chirp-like bank for a multi-rate filter bank (family 6). Template j has
+    K_j ~ U{k_lo..k_hi} filters whose frequencies follow p(f) ~ f^(-11/3) on
+    [f_lo, f_hi] Hz (the time an inspiral chirp spends per frequency band, so
+    most filters are slow). A filter of frequency f goes to the lowest rate
+    FS / 2^r (r < levels) at which f stays below a quarter of the rate, and is
+    drawn at that rate: omega = 2 pi f 2^r / FS, |a| ~ U[r_lo, r_hi], b
+    circular complex normal / sqrt(K_j), d ~ U{0..dmax >> r}.
+
+    Draw order: all K_j, then per template u (frequency), |a|, Re b, Im b, v
+    (delay). Returns the list of per-level Banks (same templates at every
+    level; a template may have no filters at a level)."""
+    rng = _rng(6, ROLE_BANK, idx)
+    K = rng.integers(k_lo, k_hi + 1, n_templates)
+    e = -8.0 / 3.0
+    lo, hi = f_lo ** e, f_hi ** e
+    per = [[[] for _ in range(n_templates)] for _ in range(levels)]
+    for j in range(n_templates):
+        k = int(K[j])
+        u = rng.random(k)
+        r = rng.uniform(r_lo, r_hi, k)
+        br = rng.standard_normal(k) * math.sqrt(0.5 / k)
+        bi = rng.standard_normal(k) * math.sqrt(0.5 / k)
+        v = rng.random(k)
+        f = (lo - u * (lo - hi)) ** (1.0 / e)
+        for q in range(k):
+            lev = 0
+            while lev + 1 < levels and f[q] < FS / 2.0 ** (lev + 3):
+                lev += 1
+            om = 2.0 * math.pi * f[q] * 2.0 ** lev / FS
+            dm = dmax >> lev
+            per[lev][j].append((r[q] * np.exp(1j * om), br[q] + 1j * bi[q], int(v[q] * (dm + 1))))
+    banks = []
+    for lev in range(levels):
+        cnt = np.array([len(per[lev][j]) for j in range(n_templates)], np.int64)
+        off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+        flat = [t for j in range(n_templates) for t in per[lev][j]]
+        a = np.array([t[0] for t in flat], np.complex128)
+        b = np.array([t[1] for t in flat], np.complex128)
+        d = np.array([t[2] for t in flat], np.int32)
+        banks.append(Bank(off, a, b, d, dmax >> lev))
+    return banks
