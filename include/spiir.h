@@ -45,6 +45,7 @@ extern "C" {
 typedef struct spiir_bank spiir_bank;
 typedef struct spiir_tape spiir_tape;
 typedef struct spiir_batch spiir_batch;
+typedef struct spiir_multirate spiir_multirate;
 
 typedef enum {
     SPIIR_OK = 0,
@@ -169,6 +170,15 @@ int spiir_bank_set_state(spiir_bank *bank, const void *host_buf, size_t nbytes);
  */
 int spiir_filter_block(spiir_bank *bank, const float *x_dev, int64_t n,
                        float *snr_dev, int64_t ld_snr, void *stream);
+
+/*
+ * Filters the next n samples of the stream and writes every template's
+ * complex sum z_j (the quantity whose squared modulus is the SNR).
+ *   z_dev  complex64, row-major [T][ld_z] (interleaved), ld_z >= n
+ * n = 0 is a no-op. Continues the same stream as spiir_filter_block.
+ */
+int spiir_filter_block_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_dev,
+                         int64_t ld_z, void *stream);
 
 /*
  * Filters the next n samples and writes only the per-sample maximum of the
@@ -304,6 +314,68 @@ int spiir_autotune(int32_t n_banks, const int32_t *n_templates,
  */
 int spiir_bank_time_kernels(spiir_bank *bank, int32_t enable);
 int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches);
+
+/*
+ * Multi-rate bank. The paper notes that the slow frequency evolution of an
+ * inspiral lets the data and the templates run at a reduced sampling rate
+ * (Sect. "Multimessenger astronomy"). This library's reading: the filters
+ * of every template are split over levels r = 0..R; level r runs at 1/2^r of
+ * the input rate, on the stream decimated r times by two, and its template
+ * sums are interpolated back one halving at a time and added:
+ *
+ *   x_0 = x,  x_r[q] = sum_i h[i] x_{r-1}[2q + 1 - i]             (decimation)
+ *   z_r[j] = sum over template j's level-r filters of y_k, run on x_r
+ *   w_R = z_R,  w_r[p] = z_r[p] + sum_q g[p - 2q] w_{r+1}[q]     (interpolation)
+ *   z = w_0,  snr_j = |z_j|^2,  max / argmax over templates as spiir_trigger_max
+ *
+ * h and g are causal FIR filters given by the caller (a lowpass for each;
+ * g with each polyphase half summing to 1 keeps a constant's level).
+ * Samples before the stream start are 0. All arithmetic is FP32 apart from
+ * the banks' FP64 chunk carries.
+ *
+ *   n_levels         R + 1, 1..8
+ *   n_templates      T >= 1, the same templates at every level
+ *   filter_offsets   [n_levels] pointers to int64 [T+1], non-decreasing (a
+ *                    template may have no filters at a level; at least one
+ *                    level must hold a filter)
+ *   a, b, d          [n_levels] pointers as in spiir_bank_create, coefficients
+ *                    and delays in that level's samples (NULL for a level
+ *                    without filters)
+ *   decim_taps       float64 [n_decim_taps], 1..64 taps (h)
+ *   interp_taps      float64 [n_interp_taps], 1..64 taps (g)
+ *   opts             applied to every level's bank; max_block counts full-rate
+ *                    samples (rounded down to a multiple of 2^R; level r gets
+ *                    max_block / 2^r)
+ * Calls take n a multiple of 2^R and continue one stream. Device memory held:
+ * the level banks, the decimated streams, the level sums and T x max_block
+ * complex64 of full-rate z.
+ */
+int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_templates,
+                           const int64_t *const *filter_offsets, const double *const *a,
+                           const double *const *b, const int32_t *const *d,
+                           const double *decim_taps, int32_t n_decim_taps,
+                           const double *interp_taps, int32_t n_interp_taps,
+                           const spiir_bank_opts *opts);
+int spiir_multirate_destroy(spiir_multirate *mr);
+
+/* Cold start: every level's bank and every resampling history. */
+int spiir_multirate_reset(spiir_multirate *mr, void *stream);
+
+/* The next n samples (n a multiple of 2^R): full-rate z into z_dev, complex64
+ * row-major [T][ld_z], ld_z >= n. */
+int spiir_multirate_filter_block_z(spiir_multirate *mr, const float *x_dev, int64_t n,
+                                   float *z_dev, int64_t ld_z, void *stream);
+
+/* The next n samples: per-sample max over templates of |z_j|^2 and the
+ * smallest attaining template (float32 max_dev [n], int32 argmax_dev [n]). */
+int spiir_multirate_trigger_max(spiir_multirate *mr, const float *x_dev, int64_t n,
+                                float *max_dev, int32_t *argmax_dev, void *stream);
+
+/* The bank that runs level `level` (NULL when the level holds no filters),
+ * owned by the multi-rate bank: for spiir_bank_get_info and kernel timing
+ * only; filtering through it directly would desynchronise the levels. Its
+ * templates are the templates with filters at that level, in order. */
+int spiir_multirate_level_bank(spiir_multirate *mr, int32_t level, spiir_bank **bank);
 
 /*
  * Trigger clustering over a per-sample max / argmax series such as the output

@@ -24,6 +24,8 @@ EXPORTS = (
     "spiir_batch_create", "spiir_batch_step", "spiir_batch_steps_total", "spiir_batch_reset",
     "spiir_batch_destroy", "spiir_batch_set_time_split", "spiir_autotune", "spiir_bank_time_kernels",
     "spiir_bank_kernel_time", "spiir_cluster_workspace_size", "spiir_cluster_triggers",
+    "spiir_filter_block_z", "spiir_multirate_create", "spiir_multirate_destroy", "spiir_multirate_reset",
+    "spiir_multirate_filter_block_z", "spiir_multirate_trigger_max", "spiir_multirate_level_bank",
     "spiir_last_error", "spiir_version",
 )
 
@@ -98,6 +100,14 @@ def load():
         "spiir_cluster_workspace_size": (ctypes.c_int, [I64, ctypes.POINTER(SZ)]),
         "spiir_cluster_triggers": (ctypes.c_int, [P, P, I64, ctypes.c_float, I32, P, SZ, P, P, P, I64,
                                                   P, I32, P]),
+        "spiir_filter_block_z": (ctypes.c_int, [P, P, I64, P, I64, P]),
+        "spiir_multirate_create": (ctypes.c_int, [PP, I32, I32, P, P, P, P, P, I32, P, I32,
+                                                  ctypes.POINTER(BankOpts)]),
+        "spiir_multirate_destroy": (ctypes.c_int, [P]),
+        "spiir_multirate_reset": (ctypes.c_int, [P, P]),
+        "spiir_multirate_filter_block_z": (ctypes.c_int, [P, P, I64, P, I64, P]),
+        "spiir_multirate_trigger_max": (ctypes.c_int, [P, P, I64, P, P, P]),
+        "spiir_multirate_level_bank": (ctypes.c_int, [P, I32, PP]),
         "spiir_last_error": (ctypes.c_char_p, []),
         "spiir_version": (ctypes.c_char_p, []),
     }

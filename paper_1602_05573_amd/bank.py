@@ -145,6 +145,16 @@ class SpiirBank:
         call("spiir_filter_block", self._h, _ptr(x), n, _ptr(snr), snr.shape[-1], _stream_ptr(stream))
         return snr
 
+    def filter_block_z(self, x: torch.Tensor, z: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Next len(x) samples -> complex template sums, complex64 [T, n]."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if z is None:
+            z = torch.empty((self.n_templates, n), dtype=torch.complex64, device=x.device)
+        _require_cuda(z, torch.complex64, "z")
+        call("spiir_filter_block_z", self._h, _ptr(x), n, _ptr(z), z.shape[-1], _stream_ptr(stream))
+        return z
+
     def trigger_max(self, x: torch.Tensor, out=None, stream=None):
         """Next len(x) samples -> (max SNR over templates float32 [n], argmax int32 [n])."""
         _require_cuda(x, torch.float32, "x")
@@ -325,6 +335,95 @@ class SpiirFn(torch.autograd.Function):
                 None, None)
 
 
+class SpiirMultiRate:
+    """Multi-rate bank (spiir_multirate_*): `levels` is a list of
+    workloads.Bank-like objects, level r running at 1 / 2^r of the input
+    rate, all with the same templates (a template may have no filters at a
+    level); h and g are the decimation and interpolation taps."""
+
+    def __init__(self, levels, h, g, **opts):
+        o = default_opts()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.n_levels = len(levels)
+        T = levels[0].n_templates
+        self._keep = []
+        offs, aas, bbs, dds = [], [], [], []
+        for lv in levels:
+            off = np.ascontiguousarray(lv.offsets, dtype=np.int64)
+            a, b = _c128(lv.a), _c128(lv.b)
+            d = np.ascontiguousarray(lv.d, dtype=np.int32)
+            self._keep += [off, a, b, d]
+            offs.append(off.ctypes.data)
+            empty = int(off[-1]) == 0
+            aas.append(None if empty else a.ctypes.data)
+            bbs.append(None if empty else b.ctypes.data)
+            dds.append(None if empty else d.ctypes.data)
+        VP = ctypes.c_void_p * self.n_levels
+        hh = np.ascontiguousarray(h, dtype=np.float64)
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        self._h = ctypes.c_void_p()
+        call("spiir_multirate_create", ctypes.byref(self._h), self.n_levels, T, VP(*offs), VP(*aas), VP(*bbs),
+             VP(*dds), hh.ctypes.data_as(ctypes.c_void_p), len(hh), gg.ctypes.data_as(ctypes.c_void_p), len(gg),
+             ctypes.byref(o))
+        self.n_templates = T
+        self.block_multiple = 1 << (self.n_levels - 1)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().spiir_multirate_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self, stream=None):
+        call("spiir_multirate_reset", self._h, _stream_ptr(stream))
+
+    def filter_block_z(self, x: torch.Tensor, z: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Full-rate template sums, complex64 [T, n]."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if z is None:
+            z = torch.empty((self.n_templates, n), dtype=torch.complex64, device=x.device)
+        call("spiir_multirate_filter_block_z", self._h, _ptr(x), n, _ptr(z), z.shape[-1], _stream_ptr(stream))
+        return z
+
+    def trigger_max(self, x: torch.Tensor, out=None, stream=None):
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float32, device=x.device),
+                   torch.empty(n, dtype=torch.int32, device=x.device))
+        mx, am = out
+        call("spiir_multirate_trigger_max", self._h, _ptr(x), n, _ptr(mx), _ptr(am), _stream_ptr(stream))
+        return mx, am
+
+    def level_info(self, level: int):
+        """Layout facts of the bank running `level`, or None when it holds no filters."""
+        bh = ctypes.c_void_p()
+        call("spiir_multirate_level_bank", self._h, int(level), ctypes.byref(bh))
+        if not bh.value:
+            return None
+        info = BankInfo()
+        call("spiir_bank_get_info", bh, ctypes.byref(info))
+        return info.as_dict()
+
+    def level_bank_handle(self, level: int):
+        bh = ctypes.c_void_p()
+        call("spiir_multirate_level_bank", self._h, int(level), ctypes.byref(bh))
+        return bh if bh.value else None
+
+
 class TriggerClusterer:
     """Trigger clustering of max/argmax series of up to max_n samples with a
     preallocated device workspace and outputs for `capacity` triggers
@@ -379,5 +478,6 @@ def version() -> str:
     return load().spiir_version().decode()
 
 
-__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "Tape", "TriggerClusterer", "autotune", "batch_banks",
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "autotune",
+           "batch_banks",
            "cluster_triggers", "version", "_lib"]

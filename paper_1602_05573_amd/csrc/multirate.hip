@@ -1,0 +1,148 @@
+// Multi-rate filter bank: the resampling and recombination around the
+// per-level filter banks. The paper remarks that a slowly evolving chirp lets
+// both the data and the templates run at a lower sampling rate (Sect.
+// "Multimessenger astronomy"); this library's reading:
+//   x_r[q]  = sum_i h[i] x_{r-1}[2q + 1 - i]                 (decimation, causal FIR)
+//   z_r     = level-r template sums of filters run on x_r      (ordinary bank, z mode)
+//   w_R     = z_R,  w_r[p] = z_r[p] + sum_q g[p - 2q] w_{r+1}[q]   (interpolation, causal FIR)
+//   z       = w_0, then |z|^2 and the per-sample max / argmax over templates.
+// All kernels here are streaming: each level keeps the last samples of its
+// resampling input as history, so consecutive calls continue one stream.
+#include "spiir_internal.h"
+
+namespace spiir {
+namespace {
+
+constexpr int kThreads = 256;
+
+int64_t nblk(int64_t n, int64_t b) { return (n + b - 1) / b; }
+
+// dst[q] = sum_i h[i] v(2q + 1 - i) for q < n_src / 2, with v(m) = src[m] for
+// m >= 0 and hist[lh - 1 + m] (the previous lh - 1 samples) for m < 0. Block 0
+// also writes the next call's history (the last lh - 1 samples of v) to
+// hist_new, a different buffer than hist.
+__global__ __launch_bounds__(kThreads) void mr_decimate_kernel(const float *__restrict__ src, int64_t n_src,
+                                                               const float *__restrict__ hist,
+                                                               float *__restrict__ hist_new,
+                                                               const float *__restrict__ h, int lh,
+                                                               float *__restrict__ dst) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t nq = n_src / 2;
+    if (q < nq) {
+        float acc = 0.0f;
+        for (int i = 0; i < lh; ++i) {
+            const int64_t m = 2 * q + 1 - i;
+            const float v = m >= 0 ? src[m] : hist[lh - 1 + m];
+            acc = fmaf(h[i], v, acc);
+        }
+        dst[q] = acc;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < lh - 1) {
+        const int64_t m = n_src - (lh - 1) + threadIdx.x;
+        hist_new[threadIdx.x] = m >= 0 ? src[m] : hist[lh - 1 + m];
+    }
+}
+
+// One template row j per blockIdx.x / tiles, 256 output samples per block:
+//   out[j][p] = Z(j, p) + sum_{i < lg, p - i even} g[i] W(j, (p - i) / 2)
+// Z(j, p) = z[zrow[j]][p] (0 if z is NULL or zrow[j] < 0); W(j, q) =
+// w[wrow(j)][q] for q >= 0 (wrow = identity if NULL; 0 if wrow[j] < 0) and
+// whist[j][hh + q] for -hh <= q < 0. w == NULL: no interpolation term. The
+// first block of a row writes the row's next history (the last hh samples of
+// W) to whist_new.
+__global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
+    const float2 *__restrict__ z, int64_t ld_z, const int32_t *__restrict__ zrow, const float2 *__restrict__ w,
+    int64_t ld_w, const int32_t *__restrict__ wrow, int64_t n_w, const float2 *__restrict__ whist,
+    float2 *__restrict__ whist_new, int hh, const float *__restrict__ g, int lg, float2 *__restrict__ out,
+    int64_t ld_out, int64_t n_out, int64_t tiles) {
+    const int64_t j = blockIdx.x / tiles;
+    const int64_t tile = blockIdx.x % tiles;
+    const int64_t p = tile * kThreads + threadIdx.x;
+    const int zr = (z && zrow) ? zrow[j] : -1;
+    const int wr = w ? (wrow ? wrow[j] : (int)j) : -1;
+    const float2 *wj = wr >= 0 ? w + (int64_t)wr * ld_w : nullptr;
+    const float2 *hj = whist + j * hh;
+    if (p < n_out) {
+        float2 acc = zr >= 0 ? z[(int64_t)zr * ld_z + p] : make_float2(0.0f, 0.0f);
+        if (w) {
+            for (int i = (int)(p & 1); i < lg; i += 2) {
+                const int64_t q = (p - i) / 2;   // p - i is even
+                float2 v = make_float2(0.0f, 0.0f);
+                if (q >= 0) {
+                    if (wj) v = wj[q];
+                } else {
+                    v = hj[hh + q];
+                }
+                acc.x = fmaf(g[i], v.x, acc.x);
+                acc.y = fmaf(g[i], v.y, acc.y);
+            }
+        }
+        out[j * ld_out + p] = acc;
+    }
+    if (w && tile == 0 && threadIdx.x < hh) {
+        const int64_t q = n_w - hh + threadIdx.x;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (q >= 0) {
+            if (wj) v = wj[q];
+        } else {
+            v = hj[hh + q];
+        }
+        whist_new[j * hh + threadIdx.x] = v;
+    }
+}
+
+// Per-sample 64-bit keys (|z|^2 bits << 32 | ~j) of a chunk of 16 template
+// rows: block = 256 samples of one chunk; keys[chunk][p] = max over the chunk.
+constexpr int kKeyChunk = 16;
+
+__global__ __launch_bounds__(kThreads) void mr_row_keys_kernel(const float2 *__restrict__ zz, int64_t ld, int T,
+                                                               int64_t n, uint64_t *__restrict__ keys,
+                                                               int64_t ld_keys, int64_t tiles) {
+    const int64_t chunk = blockIdx.x / tiles;
+    const int64_t p = (blockIdx.x % tiles) * kThreads + threadIdx.x;
+    if (p >= n) return;
+    const int j0 = (int)chunk * kKeyChunk;
+    const int j1 = min(T, j0 + kKeyChunk);
+    uint64_t best = 0;
+    for (int j = j0; j < j1; ++j) {
+        const float2 v = zz[(int64_t)j * ld + p];
+        const float s = v.x * v.x + v.y * v.y;
+        const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)j);
+        best = key > best ? key : best;
+    }
+    keys[chunk * ld_keys + p] = best;
+}
+
+}  // namespace
+
+hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
+                              const float *h, int lh, float *dst, hipStream_t st) {
+    const int64_t nq = n_src / 2;
+    const int64_t blocks = std::max<int64_t>(1, nblk(nq, kThreads));
+    hipLaunchKernelGGL(mr_decimate_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, src, n_src, hist,
+                       hist_new, h, lh, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w,
+                                  int64_t ld_w, const int32_t *wrow, int64_t n_w, const float2 *whist,
+                                  float2 *whist_new, int hh, const float *g, int lg, float2 *out,
+                                  int64_t ld_out, int64_t n_out, int T, hipStream_t st) {
+    const int64_t tiles = std::max<int64_t>(1, nblk(n_out, kThreads));
+    hipLaunchKernelGGL(mr_upsample_add_kernel, dim3((unsigned)(tiles * T)), dim3(kThreads), 0, st, z, ld_z, zrow,
+                       w, ld_w, wrow, n_w, whist, whist_new, hh, g, lg, out, ld_out, n_out, tiles);
+    return hipGetLastError();
+}
+
+int mr_key_chunks(int T) { return (T + kKeyChunk - 1) / kKeyChunk; }
+
+hipError_t launch_mr_row_keys(const float2 *zz, int64_t ld, int T, int64_t n, uint64_t *keys, int64_t ld_keys,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = nblk(n, kThreads);
+    hipLaunchKernelGGL(mr_row_keys_kernel, dim3((unsigned)(tiles * mr_key_chunks(T))), dim3(kThreads), 0, st, zz,
+                       ld, T, n, keys, ld_keys, tiles);
+    return hipGetLastError();
+}
+
+}  // namespace spiir

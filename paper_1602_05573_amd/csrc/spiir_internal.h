@@ -135,6 +135,19 @@ hipError_t launch_batch_advance(int64_t *pos, const BatchStream *streams, int ns
 hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t stream);
 int forward_max_threads();
 
+// Multi-rate bank: decimation by two with history, interpolation by two added
+// to the level below (template rows through row maps, with history), and
+// per-sample keys over chunks of template rows for finalize_keys.
+hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
+                              const float *h, int lh, float *dst, hipStream_t stream);
+hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w,
+                                  int64_t ld_w, const int32_t *wrow, int64_t n_w, const float2 *whist,
+                                  float2 *whist_new, int hh, const float *g, int lg, float2 *out,
+                                  int64_t ld_out, int64_t n_out, int T, hipStream_t stream);
+int mr_key_chunks(int T);
+hipError_t launch_mr_row_keys(const float2 *z, int64_t ld, int T, int64_t n, uint64_t *keys, int64_t ld_keys,
+                              hipStream_t stream);
+
 // Trigger clustering over a max/argmax series (block maxima, window test,
 // ordered compaction); the workspace holds the block maxima, masks and counts.
 size_t cluster_workspace_bytes(int64_t n);

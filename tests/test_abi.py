@@ -109,6 +109,18 @@ def test_null_arguments(lib):
     assert lib.spiir_bank_time_kernels(None, 1) == _lib.SPIIR_EINVAL
     assert lib.spiir_batch_set_time_split(None, 0) == _lib.SPIIR_EINVAL
     assert lib.spiir_bank_kernel_time(None, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_filter_block_z(None, None, 0, None, 0, None) == _lib.SPIIR_EINVAL
+    mh = ctypes.c_void_p()
+    assert lib.spiir_multirate_create(None, 2, 1, None, None, None, None, None, 4, None, 4, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_multirate_create(ctypes.byref(mh), 0, 1, None, None, None, None, None, 4, None, 4,
+                                      None) == _lib.SPIIR_EINVAL
+    assert "n_levels" in lib.spiir_last_error().decode()
+    assert not mh.value
+    assert lib.spiir_multirate_destroy(None) == 0
+    assert lib.spiir_multirate_reset(None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_multirate_filter_block_z(None, None, 0, None, 0, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_multirate_trigger_max(None, None, 0, None, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_multirate_level_bank(None, 0, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_batch_create(None, 1, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
     bh = ctypes.c_void_p()
     assert lib.spiir_batch_create(ctypes.byref(bh), 0, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
@@ -146,6 +158,43 @@ def test_cluster_arguments(lib):
     assert C(fake, fake, 10000, 1.0, 4, fake, nb.value - 1, fake, fake, fake, 4, fake, -1,
              None) == _lib.SPIIR_EINVAL
     assert "workspace" in lib.spiir_last_error().decode()
+
+
+def test_multirate_create_arguments(lib):
+    """Argument errors of the multi-rate bank are found on the host."""
+    T = 2
+    off0 = np.array([0, 1, 2], np.int64)
+    off1 = np.array([0, 0, 1], np.int64)
+    a = np.array([0.5, 0.3j, 0.1], np.complex128)
+    b = np.ones(3, np.complex128)
+    d = np.zeros(3, np.int32)
+    h = np.ones(4) / 4
+    VP = ctypes.c_void_p * 2
+    offs = VP(off0.ctypes.data, off1.ctypes.data)
+    aa = VP(a.ctypes.data, a.ctypes.data)
+    bb = VP(b.ctypes.data, b.ctypes.data)
+    dd = VP(d.ctypes.data, d.ctypes.data)
+    hp = h.ctypes.data_as(ctypes.c_void_p)
+    mh = ctypes.c_void_p()
+    C = lib.spiir_multirate_create
+    assert C(ctypes.byref(mh), 2, T, offs, aa, bb, dd, hp, 0, hp, 4, None) == _lib.SPIIR_EINVAL
+    assert "taps" in lib.spiir_last_error().decode()
+    assert C(ctypes.byref(mh), 2, T, offs, aa, bb, dd, hp, 4, hp, 65, None) == _lib.SPIIR_EINVAL
+    hn = np.array([1.0, np.nan, 0.0, 0.0])
+    assert C(ctypes.byref(mh), 2, T, offs, aa, bb, dd, hn.ctypes.data_as(ctypes.c_void_p), 4, hp, 4,
+             None) == _lib.SPIIR_EINVAL
+    assert "non-finite" in lib.spiir_last_error().decode()
+    bad = np.array([0, 2, 1], np.int64)
+    assert C(ctypes.byref(mh), 2, T, VP(off0.ctypes.data, bad.ctypes.data), aa, bb, dd, hp, 4, hp, 4,
+             None) == _lib.SPIIR_EINVAL
+    assert "decrease" in lib.spiir_last_error().decode()
+    zero = np.zeros(3, np.int64)
+    assert C(ctypes.byref(mh), 2, T, VP(zero.ctypes.data, zero.ctypes.data), aa, bb, dd, hp, 4, hp, 4,
+             None) == _lib.SPIIR_EINVAL
+    assert "no level" in lib.spiir_last_error().decode()
+    assert C(ctypes.byref(mh), 2, T, offs, VP(a.ctypes.data, None), bb, dd, hp, 4, hp, 4,
+             None) == _lib.SPIIR_EINVAL
+    assert not mh.value
 
 
 def test_no_device_reported_cleanly(lib):
