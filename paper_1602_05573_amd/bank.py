@@ -423,6 +423,24 @@ class SpiirMultiRate:
         call("spiir_multirate_level_bank", self._h, int(level), ctypes.byref(bh))
         return bh if bh.value else None
 
+    def time_kernels(self, enable: bool = True):
+        """Forward-kernel timing of every level's bank (spiir_bank_time_kernels)."""
+        for r in range(self.n_levels):
+            bh = self.level_bank_handle(r)
+            if bh is not None:
+                call("spiir_bank_time_kernels", bh, 1 if enable else 0)
+
+    def kernel_time(self):
+        """{level: (total ms, launches)} of the level banks' forward kernels since the last read."""
+        out = {}
+        for r in range(self.n_levels):
+            bh = self.level_bank_handle(r)
+            if bh is not None:
+                ms, n = ctypes.c_double(), ctypes.c_int64()
+                call("spiir_bank_kernel_time", bh, ctypes.byref(ms), ctypes.byref(n))
+                out[r] = (ms.value, n.value)
+        return out
+
 
 class TriggerClusterer:
     """Trigger clustering of max/argmax series of up to max_n samples with a

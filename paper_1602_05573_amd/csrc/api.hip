@@ -751,11 +751,24 @@ struct spiir_multirate {
     float2 *w0 = nullptr;                // [T][B]: full-rate z for the max / argmax
     uint64_t *keys = nullptr;            // [chunks][B]
     float *h = nullptr, *g = nullptr;
+    // the level banks run concurrently: each on its own stream, forked from the
+    // caller's stream after the decimation and joined before the interpolation
+    std::vector<hipStream_t> lstream;
+    std::vector<hipEvent_t> ldone;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
 
 void mr_free(spiir_multirate *mr) {
+    for (auto s : mr->lstream)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto e : mr->ldone)
+        if (e) (void)hipEventDestroy(e);
+    if (mr->fork) (void)hipEventDestroy(mr->fork);
+    mr->lstream.clear();
+    mr->ldone.clear();
+    mr->fork = nullptr;
     for (auto *bk : mr->bank)
         if (bk) spiir_bank_destroy(bk);
     for (auto *p : mr->zrow) dfree(p);
@@ -798,11 +811,15 @@ int mr_run(spiir_multirate *mr, const float *x, int64_t n, float2 *zout, int64_t
                                       mr->xbuf[r], st));
             xs[r] = mr->xbuf[r];
         }
-        for (int r = 0; r <= top; ++r)
+        HIPCHK(hipEventRecord(mr->fork, st));
+        for (int r = top; r >= 0; --r)   // the top level holds the most filters: start it first
             if (mr->bank[r]) {
+                HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->fork, 0));
                 const int rc = stream_call(mr->bank[r], xs[r], np >> r, kModeZ, reinterpret_cast<float *>(mr->z[r]),
-                                           mr->B >> r, nullptr, nullptr, st);
+                                           mr->B >> r, nullptr, nullptr, mr->lstream[r]);
                 if (rc) return rc;
+                HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
+                HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
             }
         float2 *out0 = zout ? zout + P : mr->w0;
         const int64_t ld0 = zout ? ldz : mr->B;
@@ -1832,6 +1849,17 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         if (e == hipSuccess) e = dalloc(&mr->h, (size_t)mr->lh);
         if (e == hipSuccess) e = dalloc(&mr->g, (size_t)mr->lg);
         if (e != hipSuccess) return alloc_fail(e);
+    }
+    mr->lstream.assign(R + 1, nullptr);
+    mr->ldone.assign(R + 1, nullptr);
+    {
+        hipError_t e = hipEventCreateWithFlags(&mr->fork, hipEventDisableTiming);
+        for (int r = 0; r <= R && e == hipSuccess; ++r)
+            if (mr->bank[r]) {
+                e = hipStreamCreateWithFlags(&mr->lstream[r], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&mr->ldone[r], hipEventDisableTiming);
+            }
+        if (e != hipSuccess) return hip_fail(e, "level streams");
     }
     std::vector<float> hf(decim_taps, decim_taps + mr->lh), gf(interp_taps, interp_taps + mr->lg);
     hipError_t e = hipMemcpy(mr->h, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice);

@@ -43,52 +43,69 @@ __global__ __launch_bounds__(kThreads) void mr_decimate_kernel(const float *__re
     }
 }
 
-// One template row j per blockIdx.x / tiles, 256 output samples per block:
+// One template row j per blockIdx.x / tiles, kOut = 1,024 output samples per
+// block of 256 threads (4 per thread, kThreads apart):
 //   out[j][p] = Z(j, p) + sum_{i < lg, p - i even} g[i] W(j, (p - i) / 2)
 // Z(j, p) = z[zrow[j]][p] (0 if z is NULL or zrow[j] < 0); W(j, q) =
 // w[wrow(j)][q] for q >= 0 (wrow = identity if NULL; 0 if wrow[j] < 0) and
-// whist[j][hh + q] for -hh <= q < 0. w == NULL: no interpolation term. The
+// whist[j][hh + q] for -hh <= q < 0, hh = lg / 2. w == NULL: no interpolation
+// term. The block first stages the W samples its outputs need (at most
+// kOut / 2 + hh + 1) and the taps in LDS, so the tap loop reads LDS only. The
 // first block of a row writes the row's next history (the last hh samples of
 // W) to whist_new.
+constexpr int kMaxTaps = 64;
+constexpr int kOut = 4 * kThreads;
+
+__device__ inline float2 w_at(const float2 *wj, const float2 *hj, int hh, int64_t q) {
+    if (q >= 0) return wj ? wj[q] : make_float2(0.0f, 0.0f);
+    return hj[hh + q];
+}
+
 __global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
     const float2 *__restrict__ z, int64_t ld_z, const int32_t *__restrict__ zrow, const float2 *__restrict__ w,
     int64_t ld_w, const int32_t *__restrict__ wrow, int64_t n_w, const float2 *__restrict__ whist,
     float2 *__restrict__ whist_new, int hh, const float *__restrict__ g, int lg, float2 *__restrict__ out,
     int64_t ld_out, int64_t n_out, int64_t tiles) {
+    __shared__ float2 sw[kOut / 2 + kMaxTaps / 2 + 2];
+    __shared__ float sg[kMaxTaps];
     const int64_t j = blockIdx.x / tiles;
     const int64_t tile = blockIdx.x % tiles;
-    const int64_t p = tile * kThreads + threadIdx.x;
+    const int64_t p0 = tile * kOut;
     const int zr = (z && zrow) ? zrow[j] : -1;
     const int wr = w ? (wrow ? wrow[j] : (int)j) : -1;
     const float2 *wj = wr >= 0 ? w + (int64_t)wr * ld_w : nullptr;
-    const float2 *hj = whist + j * hh;
-    if (p < n_out) {
-        float2 acc = zr >= 0 ? z[(int64_t)zr * ld_z + p] : make_float2(0.0f, 0.0f);
+    const float2 *hj = whist ? whist + j * hh : nullptr;
+    // staged W(j, q) for q in [q_lo, q_lo + cnt): q_lo = floor((p0 - lg + 1) / 2) >= -hh
+    const int64_t v = p0 - lg + 1;
+    const int64_t q_lo = v >= 0 ? v / 2 : -((-v + 1) / 2);
+    const int cnt = (int)((p0 + kOut - 1) / 2 - q_lo + 1);
+    if (w) {
+        for (int k = threadIdx.x; k < cnt; k += kThreads) {
+            const int64_t q = q_lo + k;
+            sw[k] = q < n_w ? w_at(wj, hj, hh, q) : make_float2(0.0f, 0.0f);
+        }
+        if (threadIdx.x < lg) sg[threadIdx.x] = g[threadIdx.x];
+    }
+    __syncthreads();
+    const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
+    float2 *oj = out + j * ld_out;
+#pragma unroll
+    for (int u = 0; u < kOut / kThreads; ++u) {
+        const int t = u * kThreads + (int)threadIdx.x;   // offset inside the tile
+        const int64_t p = p0 + t;
+        if (p >= n_out) break;
+        float2 acc = zj ? zj[p] : make_float2(0.0f, 0.0f);
         if (w) {
-            for (int i = (int)(p & 1); i < lg; i += 2) {
-                const int64_t q = (p - i) / 2;   // p - i is even
-                float2 v = make_float2(0.0f, 0.0f);
-                if (q >= 0) {
-                    if (wj) v = wj[q];
-                } else {
-                    v = hj[hh + q];
-                }
-                acc.x = fmaf(g[i], v.x, acc.x);
-                acc.y = fmaf(g[i], v.y, acc.y);
+            const int base = (int)(p0 / 2 - q_lo) + (t >> 1);   // sw index of q = p / 2
+            for (int i = t & 1, k = 0; i < lg; i += 2, ++k) {
+                const float2 x = sw[base - k];                     // q = (p - i) / 2 = p / 2 - k
+                acc.x = fmaf(sg[i], x.x, acc.x);
+                acc.y = fmaf(sg[i], x.y, acc.y);
             }
         }
-        out[j * ld_out + p] = acc;
+        oj[p] = acc;
     }
-    if (w && tile == 0 && threadIdx.x < hh) {
-        const int64_t q = n_w - hh + threadIdx.x;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (q >= 0) {
-            if (wj) v = wj[q];
-        } else {
-            v = hj[hh + q];
-        }
-        whist_new[j * hh + threadIdx.x] = v;
-    }
+    if (w && tile == 0 && threadIdx.x < hh) whist_new[j * hh + threadIdx.x] = w_at(wj, hj, hh, n_w - hh + threadIdx.x);
 }
 
 // Per-sample 64-bit keys (|z|^2 bits << 32 | ~j) of a chunk of 16 template
@@ -128,7 +145,7 @@ hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *
                                   int64_t ld_w, const int32_t *wrow, int64_t n_w, const float2 *whist,
                                   float2 *whist_new, int hh, const float *g, int lg, float2 *out,
                                   int64_t ld_out, int64_t n_out, int T, hipStream_t st) {
-    const int64_t tiles = std::max<int64_t>(1, nblk(n_out, kThreads));
+    const int64_t tiles = std::max<int64_t>(1, nblk(n_out, kOut));
     hipLaunchKernelGGL(mr_upsample_add_kernel, dim3((unsigned)(tiles * T)), dim3(kThreads), 0, st, z, ld_z, zrow,
                        w, ld_w, wrow, n_w, whist, whist_new, hh, g, lg, out, ld_out, n_out, tiles);
     return hipGetLastError();
