@@ -13,6 +13,8 @@ Functions (all double precision; see the C source for the definitions):
   clusters(M, J, threshold, W)   (index int64, template int32, value float32) of the triggers
   multirate_z(levels, h, g, x)   complex128 [T, n]: multi-rate bank, full-rate template sums
   multirate_trigger(levels, h, g, x)  (float64 max [n], int32 argmax [n]) of |multirate_z|^2
+  welch_psd(s, N)                float64 [N/2+1]: averaged windowed periodogram
+  whiten(x, S, N)                float64 [n]: frame-wise division by sqrt(S), overlap-added
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_pins.py`` against closed forms, a library IIR routine,
@@ -247,3 +249,55 @@ def multirate_trigger(levels, h, g, x, nthreads=None):
     zz = multirate_z(levels, h, g, x, nthreads=nthreads)
     s = zz.real ** 2 + zz.imag ** 2
     return s.max(axis=0), np.argmax(s, axis=0).astype(np.int32)
+
+
+def hann(N):
+    """Periodic Hann window w[t] = sin^2(pi t / N); w[t] + w[t + N/2] = 1."""
+    t = np.arange(N)
+    return np.sin(np.pi * t / N) ** 2
+
+
+def welch_psd(s, N):
+    """Noise power spectral density of a training stretch, the whitening
+    filter's input (the path filters whitened strain; the paper's SPIIR
+    section takes noisy detector data as its input, "SPIIR method"). Frames
+    of N samples at hop N/2 (as many as fit), periodic Hann window w:
+    S[f] = mean over frames of |sum_t w[t] s[kH + t] e^{-2 pi i f t / N}|^2
+    divided by sum_t w[t]^2, for f = 0..N/2 (white noise of variance v gives
+    S = v)."""
+    s = np.asarray(s, np.float64)
+    H = N // 2
+    K = (len(s) - N) // H + 1
+    if K < 1:
+        raise ValueError("need at least N samples")
+    w = hann(N)
+    acc = np.zeros(N)
+    for k in range(K):
+        X = np.fft.fft(w * s[k * H:k * H + N])
+        acc += X.real ** 2 + X.imag ** 2
+    return acc[:H + 1] / K / np.sum(w * w)
+
+
+def whiten(x, S, N):
+    """Whitened stream, delayed by H = N/2 samples: with xp = H zeros followed
+    by x, frame j covers xp[jH, jH + N); its windowed DFT is divided by
+    sqrt(S[f]) (f and N - f share S[f]; bins with S <= 0 are zeroed), the
+    inverse DFT is overlap-added at jH; frames j = 0 .. len(x)/H - 1, first
+    len(x) outputs. With S = 1 the output is x delayed by H exactly (the
+    window sums to 1 over overlapping frames)."""
+    x = np.asarray(x, np.float64)
+    S = np.asarray(S, np.float64)
+    H = N // 2
+    n = len(x)
+    if n % H:
+        raise ValueError("len(x) must be a multiple of N/2")
+    xp = np.concatenate([np.zeros(H), x])
+    inv = np.where(S > 0, 1.0 / np.sqrt(np.where(S > 0, S, 1.0)), 0.0)
+    f = np.arange(N)
+    inv_full = inv[np.minimum(f, N - f)]
+    w = hann(N)
+    out = np.zeros(n + N)
+    for j in range(n // H):
+        X = np.fft.fft(w * xp[j * H:j * H + N])
+        out[j * H:j * H + N] += np.fft.ifft(X * inv_full).real
+    return out[:n]

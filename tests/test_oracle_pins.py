@@ -542,3 +542,82 @@ def test_multirate_single_level_is_the_bank():
     mx, am = oracle.multirate_trigger([bank], h, g, x)
     m2, a2 = oracle.trigger(bank, x)
     assert np.allclose(mx, m2, rtol=1e-12) and np.array_equal(am, a2)
+
+
+# --- whitening front end -----------------------------------------------------
+
+def test_welch_psd_matches_scipy():
+    """scipy.signal.welch with the same frames and window, density scaling at
+    fs = 1, one-sided: its bins 1..N/2-1 are doubled, DC and Nyquist are not."""
+    import scipy.signal
+    from workloads import coloured_noise
+    x = coloured_noise(40000, 1).astype(np.float64)
+    for N in (64, 512, 2048):
+        S = oracle.welch_psd(x, N)
+        f, P = scipy.signal.welch(x, fs=1.0, window="hann", nperseg=N, noverlap=N // 2, detrend=False,
+                                  return_onesided=True, scaling="density", average="mean")
+        want = P.copy()
+        want[1:N // 2] /= 2.0
+        assert np.allclose(S, want, rtol=1e-10, atol=0), N
+
+
+def test_whiten_unit_psd_is_a_delay():
+    """S = 1: the Hann frames sum to 1 at 50% overlap, so the output is x
+    delayed by N/2 exactly; S = c scales it by 1/sqrt(c)."""
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(4096)
+    for N in (16, 256, 1024):
+        H = N // 2
+        y = oracle.whiten(x, np.ones(H + 1), N)
+        assert np.max(np.abs(y[H:] - x[:-H])) < 1e-12 and np.max(np.abs(y[:H])) < 1e-12
+        y4 = oracle.whiten(x, np.full(H + 1, 4.0), N)
+        assert np.max(np.abs(y4[H:] - x[:-H] / 2.0)) < 1e-12
+
+
+def _whiten_brute(x, S, N):
+    H = N // 2
+    xp = [0.0] * H + list(map(float, x))
+    n = len(x)
+    out = [0.0] * (n + N)
+    w = [np.sin(np.pi * t / N) ** 2 for t in range(N)]
+    inv = [0.0 if S[min(f, N - f)] <= 0 else 1.0 / np.sqrt(S[min(f, N - f)]) for f in range(N)]
+    for j in range(n // H):
+        X = [sum(w[t] * xp[j * H + t] * np.exp(-2j * np.pi * f * t / N) for t in range(N)) for f in range(N)]
+        for t in range(N):
+            out[j * H + t] += (sum(X[f] * inv[f] * np.exp(2j * np.pi * f * t / N) for f in range(N)) / N).real
+    return np.array(out[:n])
+
+
+def test_whiten_brute_force_tiny():
+    rng = np.random.default_rng(12)
+    N = 8
+    S = rng.uniform(0.2, 3.0, N // 2 + 1)
+    S[2] = 0.0                       # a zeroed bin
+    x = rng.standard_normal(40)
+    assert np.max(np.abs(oracle.whiten(x, S, N) - _whiten_brute(x, S, N))) < 1e-12
+
+
+def test_whiten_flattens_coloured_noise():
+    """Coloured noise whose PSD spans four decades comes out with a flat PSD
+    of unit level (statistical: 50 frames per estimate)."""
+    from workloads import coloured_noise
+    N = 512
+    x = coloured_noise(1 << 16, 2)
+    S = oracle.welch_psd(x, N)
+    assert S.max() / S.min() > 1e3
+    y = oracle.whiten(x, S, N)
+    S2 = oracle.welch_psd(y[N:], N)
+    assert abs(S2.mean() - 1.0) < 0.02 and S2.min() > 0.75 and S2.max() < 1.3
+
+
+def test_whiten_zero_bin_removes_a_tone():
+    """A tone exactly on bin f0 disappears when S[f0] = 0 (after the first frame)."""
+    N = 256
+    f0 = 20
+    t = np.arange(8192)
+    x = np.cos(2 * np.pi * f0 * t / N)
+    S = np.ones(N // 2 + 1)
+    S[f0] = 0.0
+    y = oracle.whiten(x, S, N)
+    assert np.max(np.abs(y[N:])) < 1e-9
+    assert np.max(np.abs(oracle.whiten(x, np.ones(N // 2 + 1), N)[N:])) > 0.99

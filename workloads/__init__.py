@@ -19,4 +19,5 @@ from .gen import (  # noqa: F401
     trigger_series,
     resample_taps,
     multirate_bank,
+    coloured_noise,
 )

@@ -316,3 +316,23 @@ def multirate_bank(n_templates: int = 1024, k_lo: int = 100, k_hi: int = 800, le
         d = np.array([t[2] for t in flat], np.int32)
         banks.append(Bank(off, a, b, d, dmax >> lev))
     return banks
+
+
+
+# ---------------------------------------------------------------------------
+# Coloured noise for the whitening front end (family 7).
+# ---------------------------------------------------------------------------
+
+COLOUR_B = (1.0,)
+COLOUR_A = (1.0, -1.8, 0.85)   # a resonant low-pass: power rises ~100x towards low frequencies
+
+
+def coloured_noise(n: int, idx: int = 0, floor: float = 0.1) -> np.ndarray:
+    """Raw-strain stand-in: white Gaussian noise through the resonant low-pass
+    1 / (1 - 1.8 z^-1 + 0.85 z^-2) plus a white floor of standard deviation
+    `floor`, float32 (family 7)."""
+    import scipy.signal
+    rng = _rng(7, ROLE_STRAIN, idx)
+    w = rng.standard_normal(int(n))
+    v = rng.standard_normal(int(n))
+    return (scipy.signal.lfilter(COLOUR_B, COLOUR_A, w) + floor * v).astype(np.float32)
