@@ -46,6 +46,7 @@ typedef struct spiir_bank spiir_bank;
 typedef struct spiir_tape spiir_tape;
 typedef struct spiir_batch spiir_batch;
 typedef struct spiir_multirate spiir_multirate;
+typedef struct spiir_whitener spiir_whitener;
 
 typedef enum {
     SPIIR_OK = 0,
@@ -376,6 +377,51 @@ int spiir_multirate_trigger_max(spiir_multirate *mr, const float *x_dev, int64_t
  * only; filtering through it directly would desynchronise the levels. Its
  * templates are the templates with filters at that level, in order. */
 int spiir_multirate_level_bank(spiir_multirate *mr, int32_t level, spiir_bank **bank);
+
+/*
+ * Whitening front end. The bank filters whitened strain; the paper's SPIIR
+ * section starts from noisy detector data ("SPIIR method"), so this is the
+ * step before the bank. This library's reading, with frames of N samples at
+ * hop H = N/2 and the periodic Hann window w[t] = sin^2(pi t / N) (which sums
+ * to 1 over overlapping frames):
+ *
+ *   PSD        S[f] = mean over the frames k of a training stretch of
+ *                     |sum_t w[t] s[kH + t] exp(-2 pi i f t / N)|^2 / sum_t w[t]^2,
+ *                     f = 0..N/2 (white noise of variance v gives S = v)
+ *   whitening  with xp = H zeros followed by the stream x, frame j covers
+ *              xp[jH, jH + N); its windowed DFT is divided by sqrt(S[min(f, N-f)])
+ *              (bins with S = 0 are zeroed) and the inverse DFT is added into
+ *              the output at jH. The output is the whitened stream delayed by H
+ *              samples; with S = 1 it is x delayed by H exactly.
+ *
+ * Transforms run in FP32 on the device (radix-2 FFT per frame in LDS); the
+ * PSD average is accumulated in FP64.
+ *
+ *   frame_len   N, a power of two in [16, 8192]
+ *   max_block   most samples per internal piece (0 = 65536; rounded to a
+ *               multiple of H); longer calls are split
+ *   device      HIP device ordinal; -1 = current
+ */
+int spiir_whitener_create(spiir_whitener **out, int32_t frame_len, int32_t max_block, int32_t device);
+int spiir_whitener_destroy(spiir_whitener *wh);
+
+/* PSD from train_dev float32 [n] (n >= N: (n - N) / H + 1 frames), enqueued on
+ * stream. Grows its frame buffer on demand (allocation: not for use under
+ * graph capture). */
+int spiir_whitener_estimate_psd(spiir_whitener *wh, const float *train_dev, int64_t n, void *stream);
+
+/* Host PSD float64 [N/2 + 1], finite and >= 0; synchronous. */
+int spiir_whitener_set_psd(spiir_whitener *wh, const double *psd);
+int spiir_whitener_get_psd(spiir_whitener *wh, double *psd);
+
+/* Whitens the next n samples (n a multiple of N/2) into out_dev float32 [n]
+ * (out_dev must not overlap x_dev); the stream continues across calls.
+ * SPIIR_ESTATE until a PSD has been set or estimated. */
+int spiir_whitener_process(spiir_whitener *wh, const float *x_dev, int64_t n, float *out_dev,
+                           void *stream);
+
+/* Cold start: zero history and pending output (the PSD is kept). */
+int spiir_whitener_reset(spiir_whitener *wh, void *stream);
 
 /*
  * Trigger clustering over a per-sample max / argmax series such as the output

@@ -442,6 +442,61 @@ class SpiirMultiRate:
         return out
 
 
+class Whitener:
+    """Whitening front end (spiir_whitener_*): Welch PSD of a training
+    stretch and frame-wise whitening with overlap-add; the output is the
+    whitened stream delayed by frame_len / 2 samples."""
+
+    def __init__(self, frame_len: int = 4096, max_block: int = 0, device: int = -1):
+        self._h = ctypes.c_void_p()
+        call("spiir_whitener_create", ctypes.byref(self._h), int(frame_len), int(max_block), int(device))
+        self.frame_len = int(frame_len)
+        self.hop = self.frame_len // 2
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().spiir_whitener_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def estimate_psd(self, train: torch.Tensor, stream=None):
+        _require_cuda(train, torch.float32, "train")
+        call("spiir_whitener_estimate_psd", self._h, _ptr(train), train.numel(), _stream_ptr(stream))
+
+    def set_psd(self, psd):
+        p = np.ascontiguousarray(psd, dtype=np.float64)
+        if p.shape != (self.hop + 1,):
+            raise ValueError("psd must have frame_len / 2 + 1 values")
+        call("spiir_whitener_set_psd", self._h, p.ctypes.data_as(ctypes.c_void_p))
+
+    def psd(self) -> np.ndarray:
+        p = np.zeros(self.hop + 1, np.float64)
+        call("spiir_whitener_get_psd", self._h, p.ctypes.data_as(ctypes.c_void_p))
+        return p
+
+    def process(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _require_cuda(x, torch.float32, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _require_cuda(out, torch.float32, "out")
+        call("spiir_whitener_process", self._h, _ptr(x), x.numel(), _ptr(out), _stream_ptr(stream))
+        return out
+
+    def reset(self, stream=None):
+        call("spiir_whitener_reset", self._h, _stream_ptr(stream))
+
+
 class TriggerClusterer:
     """Trigger clustering of max/argmax series of up to max_n samples with a
     preallocated device workspace and outputs for `capacity` triggers
@@ -496,6 +551,6 @@ def version() -> str:
     return load().spiir_version().decode()
 
 
-__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "autotune",
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "Whitener", "autotune",
            "batch_banks",
            "cluster_triggers", "version", "_lib"]

@@ -148,6 +148,17 @@ int mr_key_chunks(int T);
 hipError_t launch_mr_row_keys(const float2 *z, int64_t ld, int T, int64_t n, uint64_t *keys, int64_t ld_keys,
                               hipStream_t stream);
 
+// Whitening front end: frame FFTs (PSD or whitening mode), PSD average,
+// 1/sqrt(S) from a given PSD, overlap-add with history and pending half-frame.
+hipError_t launch_wh_frames(bool psd, const float *hist, int64_t hlen, const float *x, const float *wtab,
+                            const float2 *tw, int n, int logn, const float *inv, float *y, float *pw,
+                            int64_t frames, hipStream_t stream);
+hipError_t launch_wh_psd_reduce(const float *pw, int64_t frames, int H, double wsum2, double *S, float *inv,
+                                hipStream_t stream);
+hipError_t launch_wh_inv(const double *S, int H, float *inv, hipStream_t stream);
+hipError_t launch_wh_ola(const float *y, int64_t nf, int n, const float *pend, float *pend_new, const float *x,
+                         int64_t nx, float *hist_new, float *out, hipStream_t stream);
+
 // Trigger clustering over a max/argmax series (block maxima, window test,
 // ordered compaction); the workspace holds the block maxima, masks and counts.
 size_t cluster_workspace_bytes(int64_t n);

@@ -1,0 +1,169 @@
+// Whitening front end: the filter bank's input is whitened strain; this is
+// the step that makes it from raw detector data (the paper's SPIIR section
+// takes noisy detector data as input, "SPIIR method"). Frames of N samples at
+// hop H = N/2 with a periodic Hann window w[t] = sin^2(pi t / N):
+//   PSD estimate : S[f] = mean over frames of |DFT(w . s_k)[f]|^2 / sum_t w[t]^2, f = 0..N/2
+//   whitening    : y_k = IDFT(DFT(w . x_k) / sqrt(S)), overlap-added at hop H
+// The stream is whitened with a delay of H samples (H zeros precede it).
+// Each frame is one workgroup: a radix-2 FFT of N complex points in LDS
+// (bit-reversed load, in-place butterflies, FP64-computed twiddles); the
+// inverse transform is the forward one applied to the conjugate.
+#include "spiir_internal.h"
+
+namespace spiir {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline int bitrev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
+
+// In-place radix-2 decimation-in-time stages over bit-reversed input:
+// stage s combines pairs half = 2^s apart with twiddles exp(-2 pi i pos / (2 half)).
+__device__ void fft_stages(float2 *buf, const float2 *__restrict__ tw, int n, int logn) {
+    for (int s = 0; s < logn; ++s) {
+        const int half = 1 << s;
+        const int step = n >> (s + 1);
+        for (int b = threadIdx.x; b < n / 2; b += kThreads) {
+            const int pos = b & (half - 1);
+            const int i0 = ((b >> s) << (s + 1)) + pos;
+            const int i1 = i0 + half;
+            const float2 wv = tw[pos * step];
+            const float2 u = buf[i0], v = buf[i1];
+            const float2 t = make_float2(v.x * wv.x - v.y * wv.y, v.x * wv.y + v.y * wv.x);
+            buf[i0] = make_float2(u.x + t.x, u.y + t.y);
+            buf[i1] = make_float2(u.x - t.x, u.y - t.y);
+        }
+        __syncthreads();
+    }
+}
+
+// Frame j covers samples jH .. jH + N - 1 of the concatenation hist[0..hlen) ++ x.
+// PSD mode: pw[j][f] = |X_j[f]|^2 for f = 0..H. Whitening mode: y[j][t] = the
+// inverse DFT of X_j[f] * inv[min(f, N - f)], t = 0..N-1.
+template <bool PSD>
+__global__ __launch_bounds__(kThreads) void wh_frames_kernel(const float *__restrict__ hist, int64_t hlen,
+                                                             const float *__restrict__ x,
+                                                             const float *__restrict__ wtab,
+                                                             const float2 *__restrict__ tw, int n, int logn,
+                                                             const float *__restrict__ inv,
+                                                             float *__restrict__ y, float *__restrict__ pw) {
+    extern __shared__ float2 buf[];
+    const int H = n / 2;
+    const int64_t base = (int64_t)blockIdx.x * H;
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const int64_t gi = base + i;
+        const float v = gi < hlen ? hist[gi] : x[gi - hlen];
+        buf[bitrev(i, logn)] = make_float2(wtab[i] * v, 0.0f);
+    }
+    __syncthreads();
+    fft_stages(buf, tw, n, logn);
+    if (PSD) {
+        for (int f = threadIdx.x; f <= H; f += kThreads) {
+            const float2 X = buf[f];
+            pw[(int64_t)blockIdx.x * (H + 1) + f] = X.x * X.x + X.y * X.y;
+        }
+        return;
+    }
+    // conj(X * inv), then bit-reversed order for the second forward transform
+    for (int f = threadIdx.x; f < n; f += kThreads) {
+        const float s = inv[min(f, n - f)];
+        const float2 X = buf[f];
+        buf[f] = make_float2(X.x * s, -X.y * s);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const int r = bitrev(i, logn);
+        if (i < r) {
+            const float2 t = buf[i];
+            buf[i] = buf[r];
+            buf[r] = t;
+        }
+    }
+    __syncthreads();
+    fft_stages(buf, tw, n, logn);
+    const float scale = 1.0f / (float)n;
+    for (int t = threadIdx.x; t < n; t += kThreads) y[(int64_t)blockIdx.x * n + t] = buf[t].x * scale;
+}
+
+// S[f] = sum_j pw[j][f] / (frames * wsum2) in FP64; inv[f] = 1 / sqrt(S[f]), 0 where S <= 0.
+__global__ void wh_psd_reduce_kernel(const float *__restrict__ pw, int64_t frames, int H, double wsum2,
+                                     double *__restrict__ S, float *__restrict__ inv) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f > H) return;
+    double acc = 0.0;
+    for (int64_t j = 0; j < frames; ++j) acc += (double)pw[j * (H + 1) + f];
+    const double v = acc / ((double)frames * wsum2);
+    S[f] = v;
+    inv[f] = v > 0.0 ? (float)(1.0 / sqrt(v)) : 0.0f;
+}
+
+// inv[f] from a given S (host-set PSD).
+__global__ void wh_inv_kernel(const double *__restrict__ S, int H, float *__restrict__ inv) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f > H) return;
+    const double v = S[f];
+    inv[f] = v > 0.0 ? (float)(1.0 / sqrt(v)) : 0.0f;
+}
+
+// out[jH + t] = y[j][t] + (j == 0 ? pend[t] : y[j - 1][H + t]) for the nf frames;
+// block 0 also stores the last frame's second half (pending for the next call)
+// and the last H input samples (the next call's history).
+__global__ __launch_bounds__(kThreads) void wh_ola_kernel(const float *__restrict__ y, int64_t nf, int n,
+                                                          const float *__restrict__ pend,
+                                                          float *__restrict__ pend_new,
+                                                          const float *__restrict__ x, int64_t nx,
+                                                          float *__restrict__ hist_new, float *__restrict__ out) {
+    const int H = n / 2;
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (m < nf * H) {
+        const int64_t j = m / H;
+        const int t = (int)(m - j * H);
+        const float prev = j == 0 ? pend[t] : y[(j - 1) * n + H + t];
+        out[m] = y[j * n + t] + prev;
+    }
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < H; t += kThreads) {
+            pend_new[t] = y[(nf - 1) * n + H + t];
+            hist_new[t] = x[nx - H + t];
+        }
+}
+
+}  // namespace
+
+hipError_t launch_wh_frames(bool psd, const float *hist, int64_t hlen, const float *x, const float *wtab,
+                            const float2 *tw, int n, int logn, const float *inv, float *y, float *pw,
+                            int64_t frames, hipStream_t st) {
+    if (frames <= 0) return hipSuccess;
+    const size_t lds = (size_t)n * sizeof(float2);
+    if (psd)
+        hipLaunchKernelGGL(wh_frames_kernel<true>, dim3((unsigned)frames), dim3(kThreads), lds, st, hist, hlen, x,
+                           wtab, tw, n, logn, inv, y, pw);
+    else
+        hipLaunchKernelGGL(wh_frames_kernel<false>, dim3((unsigned)frames), dim3(kThreads), lds, st, hist, hlen, x,
+                           wtab, tw, n, logn, inv, y, pw);
+    return hipGetLastError();
+}
+
+hipError_t launch_wh_psd_reduce(const float *pw, int64_t frames, int H, double wsum2, double *S, float *inv,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(wh_psd_reduce_kernel, dim3((unsigned)((H + 1 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       st, pw, frames, H, wsum2, S, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_wh_inv(const double *S, int H, float *inv, hipStream_t st) {
+    hipLaunchKernelGGL(wh_inv_kernel, dim3((unsigned)((H + 1 + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, S,
+                       H, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_wh_ola(const float *y, int64_t nf, int n, const float *pend, float *pend_new, const float *x,
+                         int64_t nx, float *hist_new, float *out, hipStream_t st) {
+    const int64_t total = nf * (n / 2);
+    const int64_t blocks = std::max<int64_t>(1, (total + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(wh_ola_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, y, nf, n, pend, pend_new, x, nx,
+                       hist_new, out);
+    return hipGetLastError();
+}
+
+}  // namespace spiir

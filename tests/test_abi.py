@@ -121,6 +121,19 @@ def test_null_arguments(lib):
     assert lib.spiir_multirate_filter_block_z(None, None, 0, None, 0, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_multirate_trigger_max(None, None, 0, None, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_multirate_level_bank(None, 0, None) == _lib.SPIIR_EINVAL
+    wh = ctypes.c_void_p()
+    assert lib.spiir_whitener_create(None, 64, 0, -1) == _lib.SPIIR_EINVAL
+    for bad in (0, 8, 100, 16384):
+        assert lib.spiir_whitener_create(ctypes.byref(wh), bad, 0, -1) == _lib.SPIIR_EINVAL
+        assert "power of two" in lib.spiir_last_error().decode()
+    assert lib.spiir_whitener_create(ctypes.byref(wh), 64, -1, -1) == _lib.SPIIR_EINVAL
+    assert not wh.value
+    assert lib.spiir_whitener_destroy(None) == 0
+    assert lib.spiir_whitener_estimate_psd(None, None, 0, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_whitener_set_psd(None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_whitener_get_psd(None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_whitener_process(None, None, 0, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_whitener_reset(None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_batch_create(None, 1, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
     bh = ctypes.c_void_p()
     assert lib.spiir_batch_create(ctypes.byref(bh), 0, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
