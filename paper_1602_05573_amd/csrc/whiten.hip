@@ -5,25 +5,29 @@
 //   PSD estimate : S[f] = mean over frames of |DFT(w . s_k)[f]|^2 / sum_t w[t]^2, f = 0..N/2
 //   whitening    : y_k = IDFT(DFT(w . x_k) / sqrt(S)), overlap-added at hop H
 // The stream is whitened with a delay of H samples (H zeros precede it).
-// Each frame is one workgroup: a radix-2 FFT of N complex points in LDS
-// (bit-reversed load, in-place butterflies, FP64-computed twiddles); the
-// inverse transform is the forward one applied to the conjugate.
+// Each frame is one workgroup of 1,024 threads: a radix-2 FFT of N complex
+// points in LDS (bit-reversed load, in-place butterflies; the FP64-computed
+// twiddle table is staged in LDS once per frame, so no stage waits on global
+// memory); the inverse transform is the forward one applied to the conjugate.
 #include "spiir_internal.h"
+
+#include <atomic>
 
 namespace spiir {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // overlap-add and PSD launches
+constexpr int kFftThreads = 1024;  // one frame per workgroup
 
 __device__ inline int bitrev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
 
 // In-place radix-2 decimation-in-time stages over bit-reversed input:
 // stage s combines pairs half = 2^s apart with twiddles exp(-2 pi i pos / (2 half)).
-__device__ void fft_stages(float2 *buf, const float2 *__restrict__ tw, int n, int logn) {
+__device__ void fft_stages(float2 *buf, const float2 *tw, int n, int logn) {
     for (int s = 0; s < logn; ++s) {
         const int half = 1 << s;
         const int step = n >> (s + 1);
-        for (int b = threadIdx.x; b < n / 2; b += kThreads) {
+        for (int b = threadIdx.x; b < n / 2; b += kFftThreads) {
             const int pos = b & (half - 1);
             const int i0 = ((b >> s) << (s + 1)) + pos;
             const int i1 = i0 + half;
@@ -41,16 +45,18 @@ __device__ void fft_stages(float2 *buf, const float2 *__restrict__ tw, int n, in
 // PSD mode: pw[j][f] = |X_j[f]|^2 for f = 0..H. Whitening mode: y[j][t] = the
 // inverse DFT of X_j[f] * inv[min(f, N - f)], t = 0..N-1.
 template <bool PSD>
-__global__ __launch_bounds__(kThreads) void wh_frames_kernel(const float *__restrict__ hist, int64_t hlen,
-                                                             const float *__restrict__ x,
-                                                             const float *__restrict__ wtab,
-                                                             const float2 *__restrict__ tw, int n, int logn,
-                                                             const float *__restrict__ inv,
-                                                             float *__restrict__ y, float *__restrict__ pw) {
-    extern __shared__ float2 buf[];
+__global__ __launch_bounds__(kFftThreads) void wh_frames_kernel(const float *__restrict__ hist, int64_t hlen,
+                                                                const float *__restrict__ x,
+                                                                const float *__restrict__ wtab,
+                                                                const float2 *__restrict__ tw_g, int n, int logn,
+                                                                const float *__restrict__ inv,
+                                                                float *__restrict__ y, float *__restrict__ pw) {
+    extern __shared__ float2 buf[];   // [n] data, then [n/2] twiddles
+    float2 *tw = buf + n;
     const int H = n / 2;
     const int64_t base = (int64_t)blockIdx.x * H;
-    for (int i = threadIdx.x; i < n; i += kThreads) {
+    for (int k = threadIdx.x; k < H; k += kFftThreads) tw[k] = tw_g[k];
+    for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const int64_t gi = base + i;
         const float v = gi < hlen ? hist[gi] : x[gi - hlen];
         buf[bitrev(i, logn)] = make_float2(wtab[i] * v, 0.0f);
@@ -58,20 +64,20 @@ __global__ __launch_bounds__(kThreads) void wh_frames_kernel(const float *__rest
     __syncthreads();
     fft_stages(buf, tw, n, logn);
     if (PSD) {
-        for (int f = threadIdx.x; f <= H; f += kThreads) {
+        for (int f = threadIdx.x; f <= H; f += kFftThreads) {
             const float2 X = buf[f];
             pw[(int64_t)blockIdx.x * (H + 1) + f] = X.x * X.x + X.y * X.y;
         }
         return;
     }
     // conj(X * inv), then bit-reversed order for the second forward transform
-    for (int f = threadIdx.x; f < n; f += kThreads) {
+    for (int f = threadIdx.x; f < n; f += kFftThreads) {
         const float s = inv[min(f, n - f)];
         const float2 X = buf[f];
         buf[f] = make_float2(X.x * s, -X.y * s);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kThreads) {
+    for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const int r = bitrev(i, logn);
         if (i < r) {
             const float2 t = buf[i];
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void wh_frames_kernel(const float *__rest
     __syncthreads();
     fft_stages(buf, tw, n, logn);
     const float scale = 1.0f / (float)n;
-    for (int t = threadIdx.x; t < n; t += kThreads) y[(int64_t)blockIdx.x * n + t] = buf[t].x * scale;
+    for (int t = threadIdx.x; t < n; t += kFftThreads) y[(int64_t)blockIdx.x * n + t] = buf[t].x * scale;
 }
 
 // S[f] = sum_j pw[j][f] / (frames * wsum2) in FP64; inv[f] = 1 / sqrt(S[f]), 0 where S <= 0.
@@ -134,13 +140,29 @@ hipError_t launch_wh_frames(bool psd, const float *hist, int64_t hlen, const flo
                             const float2 *tw, int n, int logn, const float *inv, float *y, float *pw,
                             int64_t frames, hipStream_t st) {
     if (frames <= 0) return hipSuccess;
-    const size_t lds = (size_t)n * sizeof(float2);
+    const size_t lds = (size_t)n * sizeof(float2) + (size_t)(n / 2) * sizeof(float2);   // at most 96 KB
+    // the frame kernels may use more than the default 64 KB of dynamic LDS:
+    // raise their limit once per device
+    static std::atomic<uint64_t> attr_done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_done.load() & bit)) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wh_frames_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wh_frames_kernel<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        if (e != hipSuccess) return e;
+        attr_done.fetch_or(bit);
+    }
     if (psd)
-        hipLaunchKernelGGL(wh_frames_kernel<true>, dim3((unsigned)frames), dim3(kThreads), lds, st, hist, hlen, x,
-                           wtab, tw, n, logn, inv, y, pw);
+        hipLaunchKernelGGL(wh_frames_kernel<true>, dim3((unsigned)frames), dim3(kFftThreads), lds, st, hist, hlen,
+                           x, wtab, tw, n, logn, inv, y, pw);
     else
-        hipLaunchKernelGGL(wh_frames_kernel<false>, dim3((unsigned)frames), dim3(kThreads), lds, st, hist, hlen, x,
-                           wtab, tw, n, logn, inv, y, pw);
+        hipLaunchKernelGGL(wh_frames_kernel<false>, dim3((unsigned)frames), dim3(kFftThreads), lds, st, hist, hlen,
+                           x, wtab, tw, n, logn, inv, y, pw);
     return hipGetLastError();
 }
 
