@@ -575,16 +575,27 @@ def run_multirate(args, torch):
         step()
         torch.cuda.synchronize()
         log("warmup %d done" % w)
-    mr.time_kernels(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    t_step = t_total / args.steps
+    # the same step without graphs (every piece enqueued call by call)
+    mr.set_graph(False)
+    torch.cuda.synchronize()
+    t0e = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0e
+    # one more step with the level banks' forward kernels timed (eager path)
+    mr.time_kernels(True)
+    step()
+    torch.cuda.synchronize()
     kt = mr.kernel_time()
     mr.time_kernels(False)
-    t_step = t_total / args.steps
+    mr.set_graph(True)
     value = upd_eff / t_step
     per_level = {}
     for r, (ms, nl) in kt.items():
@@ -598,9 +609,10 @@ def run_multirate(args, torch):
     fl_dom = FLOP_UPDATE * float(F[dom]) * (B >> dom) + FLOP_SAMPLE * float(d["templates"]) * (B >> dom)
     achieved = fl_dom / (d["forward_us"] * 1e-6)
     fwd_sum_us = sum(v["forward_us"] for v in per_level.values())
-    log("multirate: %.1f ms per step, %.3e effective / %.3e actual updates/s; per block %.1f us, forward kernels "
-        "%.1f us (dominant level %d: %.1f us)" % (t_step * 1e3, value, upd_act / t_step, t_step / nblk * 1e6,
-                                                   fwd_sum_us, dom, d["forward_us"]))
+    log("multirate: %.1f ms per step, %.3e effective / %.3e actual updates/s; per block %.1f us (graph replay; "
+        "%.1f us enqueued call by call), forward kernels %.1f us (dominant level %d: %.1f us)"
+        % (t_step * 1e3, value, upd_act / t_step, t_step / nblk * 1e6, t_eager / nblk * 1e6, fwd_sum_us, dom,
+           d["forward_us"]))
 
     # the same filters as one single-rate bank (every filter at the input rate), timed on a prefix
     off = np.zeros(T + 1, np.int64)
@@ -635,7 +647,7 @@ def run_multirate(args, torch):
                                % (T, N, B),
                    "filters_per_level": F, "global_batch": T, "seq_len": N, "parallelism": "single GPU"},
         "actual_updates_per_s": upd_act / t_step, "update_fraction": upd_act / upd_eff,
-        "block_us": t_step / nblk * 1e6, "per_level": per_level,
+        "block_us": t_step / nblk * 1e6, "block_us_without_graph": t_eager / nblk * 1e6, "per_level": per_level,
         "single_rate_same_filters": {"updates_per_s": single_rate, "block_us": t_single * 1e6,
                                      "blocks_timed": nb_single, "multirate_speedup": value / single_rate},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",

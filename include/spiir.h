@@ -372,6 +372,16 @@ int spiir_multirate_filter_block_z(spiir_multirate *mr, const float *x_dev, int6
 int spiir_multirate_trigger_max(spiir_multirate *mr, const float *x_dev, int64_t n,
                                 float *max_dev, int32_t *argmax_dev, void *stream);
 
+/* Graph replay of trigger calls (on by default): once a piece has run
+ * eagerly, every spiir_multirate_trigger_max piece of exactly max_block
+ * samples replays a HIP graph of the whole piece (decimation, level banks,
+ * interpolation, max / argmax), captured on first use for each history
+ * parity; the block is copied into an internal buffer and the results out
+ * of one. Results are identical to the eager path. Other piece lengths,
+ * spiir_multirate_filter_block_z and runs with kernel timing enabled on a
+ * level bank take the eager path. 0 switches the graphs off. */
+int spiir_multirate_set_graph(spiir_multirate *mr, int32_t enable);
+
 /* The bank that runs level `level` (NULL when the level holds no filters),
  * owned by the multi-rate bank: for spiir_bank_get_info and kernel timing
  * only; filtering through it directly would desynchronise the levels. Its

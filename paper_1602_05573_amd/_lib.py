@@ -26,6 +26,7 @@ EXPORTS = (
     "spiir_bank_kernel_time", "spiir_cluster_workspace_size", "spiir_cluster_triggers",
     "spiir_filter_block_z", "spiir_multirate_create", "spiir_multirate_destroy", "spiir_multirate_reset",
     "spiir_multirate_filter_block_z", "spiir_multirate_trigger_max", "spiir_multirate_level_bank",
+    "spiir_multirate_set_graph",
     "spiir_whitener_create", "spiir_whitener_destroy", "spiir_whitener_estimate_psd", "spiir_whitener_set_psd",
     "spiir_whitener_get_psd", "spiir_whitener_process", "spiir_whitener_reset",
     "spiir_last_error", "spiir_version",
@@ -110,6 +111,7 @@ def load():
         "spiir_multirate_filter_block_z": (ctypes.c_int, [P, P, I64, P, I64, P]),
         "spiir_multirate_trigger_max": (ctypes.c_int, [P, P, I64, P, P, P]),
         "spiir_multirate_level_bank": (ctypes.c_int, [P, I32, PP]),
+        "spiir_multirate_set_graph": (ctypes.c_int, [P, I32]),
         "spiir_whitener_create": (ctypes.c_int, [PP, I32, I32, I32]),
         "spiir_whitener_destroy": (ctypes.c_int, [P]),
         "spiir_whitener_estimate_psd": (ctypes.c_int, [P, P, I64, P]),

@@ -408,6 +408,10 @@ class SpiirMultiRate:
         call("spiir_multirate_trigger_max", self._h, _ptr(x), n, _ptr(mx), _ptr(am), _stream_ptr(stream))
         return mx, am
 
+    def set_graph(self, enable: bool):
+        """Graph replay of trigger pieces of exactly max_block samples (on by default)."""
+        call("spiir_multirate_set_graph", self._h, 1 if enable else 0)
+
     def level_info(self, level: int):
         """Layout facts of the bank running `level`, or None when it holds no filters."""
         bh = ctypes.c_void_p()

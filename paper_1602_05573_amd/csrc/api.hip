@@ -756,11 +756,35 @@ struct spiir_multirate {
     std::vector<hipStream_t> lstream;
     std::vector<hipEvent_t> ldone;
     hipEvent_t fork = nullptr;
+    // trigger calls in pieces of exactly B samples replay a captured graph of
+    // the whole piece (one per history parity): the block is copied into xin,
+    // the max / argmax out of mxo / amo
+    bool use_graph = true;
+    bool graph_failed = false;
+    int64_t eager_pieces = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    float *xin = nullptr, *mxo = nullptr;
+    int32_t *amo = nullptr;
 };
 
 namespace {
 
+void mr_free_graphs(spiir_multirate *mr) {
+    for (auto &g : mr->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
 void mr_free(spiir_multirate *mr) {
+    mr_free_graphs(mr);
+    if (mr->cap) (void)hipStreamDestroy(mr->cap);
+    mr->cap = nullptr;
+    dfree(mr->xin);
+    dfree(mr->mxo);
+    dfree(mr->amo);
     for (auto s : mr->lstream)
         if (s) (void)hipStreamDestroy(s);
     for (auto e : mr->ldone)
@@ -795,57 +819,137 @@ int mr_clear_history(spiir_multirate *mr, hipStream_t st) {
     return SPIIR_OK;
 }
 
+// One piece (np <= B samples) of the multi-rate bank: decimation, the level
+// banks forked onto their streams, interpolation and sums, and the full-rate
+// z (out0, row stride ld0) or the max / argmax (mx, am).
+int mr_piece(spiir_multirate *mr, const float *x0, int64_t np, float2 *out0, int64_t ld0, float *mx, int32_t *am,
+             hipStream_t st) {
+    const int top = mr->top;
+    const int c = mr->cur;
+    std::vector<const float *> xs(top + 1);
+    xs[0] = x0;
+    for (int r = 1; r <= top; ++r) {
+        HIPCHK(launch_mr_decimate(xs[r - 1], np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh,
+                                  mr->xbuf[r], st));
+        xs[r] = mr->xbuf[r];
+    }
+    HIPCHK(hipEventRecord(mr->fork, st));
+    for (int r = top; r >= 0; --r)   // the top level holds the most filters: start it first
+        if (mr->bank[r]) {
+            HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->fork, 0));
+            const int rc = stream_call(mr->bank[r], xs[r], np >> r, kModeZ, reinterpret_cast<float *>(mr->z[r]),
+                                       mr->B >> r, nullptr, nullptr, mr->lstream[r]);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
+            HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
+        }
+    if (!out0) {
+        out0 = mr->w0;
+        ld0 = mr->B;
+    }
+    if (top == 0) {
+        HIPCHK(launch_mr_upsample_add(mr->z[0], mr->B, mr->zrow[0], nullptr, 0, nullptr, 0, nullptr, nullptr, 0,
+                                      mr->g, mr->lg, out0, ld0, np, mr->T, st));
+    } else {
+        const float2 *src = mr->z[top];
+        int64_t ld_src = mr->B >> top;
+        const int32_t *srow = mr->zrow[top];
+        for (int r = top - 1; r >= 0; --r) {
+            float2 *dst = r == 0 ? out0 : mr->w[r];
+            const int64_t ld_dst = r == 0 ? ld0 : (mr->B >> r);
+            HIPCHK(launch_mr_upsample_add(mr->bank[r] ? mr->z[r] : nullptr, mr->B >> r, mr->zrow[r], src, ld_src,
+                                          srow, np >> (r + 1), mr->wh[c][r + 1], mr->wh[c ^ 1][r + 1], mr->hh,
+                                          mr->g, mr->lg, dst, ld_dst, np >> r, mr->T, st));
+            src = dst;
+            ld_src = ld_dst;
+            srow = nullptr;
+        }
+    }
+    if (mx) {
+        HIPCHK(launch_mr_row_keys(mr->w0, mr->B, mr->T, np, mr->keys, mr->B, st));
+        HIPCHK(launch_finalize_keys(mr->keys, mr_key_chunks(mr->T), mr->B, np, mx, am, st));
+    }
+    mr->cur ^= 1;
+    return SPIIR_OK;
+}
+
+bool mr_timing_on(const spiir_multirate *mr) {
+    for (auto *bk : mr->bank)
+        if (bk && !bk->tev0.empty()) return true;
+    return false;
+}
+
+// Captures a trigger piece of B samples for each history parity. The host-side
+// parity flags (mr->cur and every level bank's history index) toggle once per
+// captured piece, so after the two captures they are back where they were;
+// on failure they are restored and graphs stay off.
+int mr_build_graphs(spiir_multirate *mr) {
+    std::vector<int> hc;
+    for (auto *bk : mr->bank) hc.push_back(bk ? bk->hist_cur : 0);
+    const int cur0 = mr->cur;
+    auto restore = [&]() {
+        mr->cur = cur0;
+        for (size_t r = 0; r < mr->bank.size(); ++r)
+            if (mr->bank[r]) mr->bank[r]->hist_cur = hc[r];
+        mr_free_graphs(mr);
+        mr->graph_failed = true;
+    };
+    hipError_t e = hipSuccess;
+    if (!mr->cap) e = hipStreamCreateWithFlags(&mr->cap, hipStreamNonBlocking);
+    if (e == hipSuccess && !mr->xin) e = dalloc(&mr->xin, (size_t)mr->B);
+    if (e == hipSuccess && !mr->mxo) e = dalloc(&mr->mxo, (size_t)mr->B);
+    if (e == hipSuccess && !mr->amo) e = dalloc(&mr->amo, (size_t)mr->B);
+    if (e != hipSuccess) {
+        restore();
+        return fail(SPIIR_EHIP, "graph set-up: %s", hipGetErrorString(e));
+    }
+    for (int k = 0; k < 2; ++k) {
+        const int parity = mr->cur;
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(mr->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            restore();
+            return fail(SPIIR_EHIP, "graph capture: %s", hipGetErrorString(e));
+        }
+        const int rc = mr_piece(mr, mr->xin, mr->B, nullptr, 0, mr->mxo, mr->amo, mr->cap);
+        e = hipStreamEndCapture(mr->cap, &g);
+        if (rc == SPIIR_OK && e == hipSuccess) e = hipGraphInstantiate(&mr->gexec[parity], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (rc || e != hipSuccess) {
+            restore();
+            return rc ? rc : fail(SPIIR_EHIP, "graph capture: %s", hipGetErrorString(e));
+        }
+    }
+    return SPIIR_OK;
+}
+
 // One pass of the multi-rate bank over x[0..n), written as the full-rate z
 // (zout, row stride ldz) or as max / argmax.
 int mr_run(spiir_multirate *mr, const float *x, int64_t n, float2 *zout, int64_t ldz, float *mx, int32_t *am,
            hipStream_t st) {
     DeviceGuard guard(mr->device);
-    const int top = mr->top;
     for (int64_t P = 0; P < n; P += mr->B) {
         const int64_t np = std::min<int64_t>(mr->B, n - P);
-        const int c = mr->cur;
-        std::vector<const float *> xs(top + 1);
-        xs[0] = x + P;
-        for (int r = 1; r <= top; ++r) {
-            HIPCHK(launch_mr_decimate(xs[r - 1], np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh,
-                                      mr->xbuf[r], st));
-            xs[r] = mr->xbuf[r];
+        const bool graph = mx && np == mr->B && mr->use_graph && !mr->graph_failed && mr->eager_pieces > 0 &&
+                           !mr_timing_on(mr);
+        if (graph && !mr->gexec[mr->cur]) {
+            const int rc = mr_build_graphs(mr);
+            if (rc) return rc;
         }
-        HIPCHK(hipEventRecord(mr->fork, st));
-        for (int r = top; r >= 0; --r)   // the top level holds the most filters: start it first
-            if (mr->bank[r]) {
-                HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->fork, 0));
-                const int rc = stream_call(mr->bank[r], xs[r], np >> r, kModeZ, reinterpret_cast<float *>(mr->z[r]),
-                                           mr->B >> r, nullptr, nullptr, mr->lstream[r]);
-                if (rc) return rc;
-                HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
-                HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
-            }
-        float2 *out0 = zout ? zout + P : mr->w0;
-        const int64_t ld0 = zout ? ldz : mr->B;
-        if (top == 0) {
-            HIPCHK(launch_mr_upsample_add(mr->z[0], mr->B, mr->zrow[0], nullptr, 0, nullptr, 0, nullptr, nullptr, 0,
-                                          mr->g, mr->lg, out0, ld0, np, mr->T, st));
-        } else {
-            const float2 *src = mr->z[top];
-            int64_t ld_src = mr->B >> top;
-            const int32_t *srow = mr->zrow[top];
-            for (int r = top - 1; r >= 0; --r) {
-                float2 *dst = r == 0 ? out0 : mr->w[r];
-                const int64_t ld_dst = r == 0 ? ld0 : (mr->B >> r);
-                HIPCHK(launch_mr_upsample_add(mr->bank[r] ? mr->z[r] : nullptr, mr->B >> r, mr->zrow[r], src, ld_src,
-                                              srow, np >> (r + 1), mr->wh[c][r + 1], mr->wh[c ^ 1][r + 1], mr->hh,
-                                              mr->g, mr->lg, dst, ld_dst, np >> r, mr->T, st));
-                src = dst;
-                ld_src = ld_dst;
-                srow = nullptr;
-            }
+        if (graph) {
+            HIPCHK(hipMemcpyAsync(mr->xin, x + P, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipGraphLaunch(mr->gexec[mr->cur], st));
+            HIPCHK(hipMemcpyAsync(mx + P, mr->mxo, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(am + P, mr->amo, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            mr->cur ^= 1;
+            for (auto *bk : mr->bank)
+                if (bk) bk->hist_cur ^= 1;   // as the captured stream calls did
+            continue;
         }
-        if (mx) {
-            HIPCHK(launch_mr_row_keys(mr->w0, mr->B, mr->T, np, mr->keys, mr->B, st));
-            HIPCHK(launch_finalize_keys(mr->keys, mr_key_chunks(mr->T), mr->B, np, mx + P, am + P, st));
-        }
-        mr->cur ^= 1;
+        const int rc = mr_piece(mr, x + P, np, zout ? zout + P : nullptr, ldz, mx ? mx + P : nullptr,
+                                am ? am + P : nullptr, st);
+        if (rc) return rc;
+        ++mr->eager_pieces;
     }
     return SPIIR_OK;
 }
@@ -1954,6 +2058,12 @@ int spiir_multirate_trigger_max(spiir_multirate *mr, const float *x, int64_t n, 
     if (rc || n == 0) return rc;
     if (!mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
     return mr_run(mr, x, n, nullptr, 0, mx, am, as_stream(stream));
+}
+
+int spiir_multirate_set_graph(spiir_multirate *mr, int32_t enable) {
+    if (!mr) return fail(SPIIR_EINVAL, "multi-rate bank is null");
+    mr->use_graph = enable != 0;
+    return SPIIR_OK;
 }
 
 int spiir_multirate_level_bank(spiir_multirate *mr, int32_t level, spiir_bank **bank) {

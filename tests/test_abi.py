@@ -121,6 +121,7 @@ def test_null_arguments(lib):
     assert lib.spiir_multirate_filter_block_z(None, None, 0, None, 0, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_multirate_trigger_max(None, None, 0, None, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_multirate_level_bank(None, 0, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_multirate_set_graph(None, 1) == _lib.SPIIR_EINVAL
     wh = ctypes.c_void_p()
     assert lib.spiir_whitener_create(None, 64, 0, -1) == _lib.SPIIR_EINVAL
     for bad in (0, 8, 100, 16384):

@@ -127,6 +127,49 @@ def test_multirate_streaming_and_reset():
         check_argmax(mx.cpu().numpy(), am.cpu().numpy(), s)
 
 
+def test_multirate_graph_replay_equals_eager():
+    """Trigger pieces replayed from the captured graphs equal the eager path
+    bitwise, across mixed call lengths (graph pieces, shorter eager pieces),
+    a reset, timing switched on and off, and many replays of both parities."""
+    from paper_1602_05573_amd import SpiirMultiRate
+    T, per = 9, [5, 8, 0, 24]
+    levels = rand_levels(T, per, 40)
+    h, g = resample_taps(24)
+    B = 1024
+    n = 40 * B
+    x = strain(n, 6, 40)
+    banner("multirate graph replay")
+    xd = torch.from_numpy(x).cuda()
+    cuts = [0, B, 2 * B, 2 * B + 256, 3 * B + 256, 7 * B + 256, 7 * B + 512, 20 * B, n]
+
+    def run(graph, timing_at=None):
+        mx = torch.empty(n, dtype=torch.float32, device="cuda")
+        am = torch.empty(n, dtype=torch.int32, device="cuda")
+        with SpiirMultiRate(levels, h, g, max_block=B) as mr:
+            mr.set_graph(graph)
+            for k, (a, b) in enumerate(zip(cuts[:-1], cuts[1:])):
+                if timing_at is not None and k == timing_at:
+                    mr.time_kernels(True)
+                if timing_at is not None and k == timing_at + 2:
+                    mr.kernel_time()
+                    mr.time_kernels(False)
+                mr.trigger_max(xd[a:b], out=(mx[a:b], am[a:b]))
+            torch.cuda.synchronize()
+            first = (mx.clone(), am.clone())
+            mr.reset()
+            mr.trigger_max(xd, out=(mx, am))
+            torch.cuda.synchronize()
+        return first, (mx, am)
+
+    (e1, e2) = run(False)
+    (g1, g2) = run(True, timing_at=4)
+    assert torch.equal(e1[0], g1[0]) and torch.equal(e1[1], g1[1])
+    assert torch.equal(e2[0], g2[0]) and torch.equal(e2[1], g2[1])
+    zz = oracle.multirate_z(levels, h, g, x)
+    s = zz.real ** 2 + zz.imag ** 2
+    assert np.max(np.abs(g2[0].cpu().numpy() - s.max(axis=0))) <= SNR_TOL * s.max()
+
+
 def test_multirate_rejects_bad_arguments():
     from paper_1602_05573_amd import SpiirError, SpiirMultiRate
     levels = rand_levels(3, [4, 4], 30)
