@@ -346,7 +346,10 @@ int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches
  *   interp_taps      float64 [n_interp_taps], 1..64 taps (g)
  *   opts             applied to every level's bank; max_block counts full-rate
  *                    samples (rounded down to a multiple of 2^R; level r gets
- *                    max_block / 2^r)
+ *                    max_block / 2^r). With time_split = 0, a level of at most
+ *                    128 filters per compute unit (a short serial recursion
+ *                    per call) uses 64-sample chunks and up to 32 time
+ *                    segments instead of chunk_len and 8.
  * Calls take n a multiple of 2^R and continue one stream. Device memory held:
  * the level banks, the decimated streams, the level sums and T x max_block
  * complex64 of full-rate z.

@@ -541,8 +541,11 @@ Geometry plan_geometry(int wpg, int dmax, int L, int max_block, size_t lds_cap) 
     return best;
 }
 
+// seg_cap: most time segments the automatic time split may choose (8 for
+// banks created through the ABI; the multi-rate object allows more for its
+// small levels, whose calls are short serial recursions).
 int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a, const double *b,
-                const int32_t *d, const spiir_bank_opts &o) {
+                const int32_t *d, const spiir_bank_opts &o, int seg_cap = 8) {
     int dmax = 0;
     int rc = check_bank_args(T, off, a, b, d, o, dmax);
     if (rc) return rc;
@@ -623,7 +626,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
             const int occ = std::max(1, forward_occupancy(fl, gm.tt, wpg, gm.lds));
             const int64_t slots_dev = (int64_t)df.n_cu * occ;
             if (2 * (int64_t)bk->lay.groups <= slots_dev)
-                bk->nseg = (int)std::min<int64_t>(8, slots_dev / std::max(1, bk->lay.groups));
+                bk->nseg = (int)std::min<int64_t>(seg_cap, slots_dev / std::max(1, bk->lay.groups));
         }
         bk->nseg = std::min(bk->nseg, std::max(1, max_block / L));
     }
@@ -1963,8 +1966,15 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         spiir_bank_opts orr = o;
         orr.device = dev;
         orr.max_block = (int32_t)std::max<int64_t>(8, B >> r);
+        // a level whose filters leave most of the device idle is a short serial
+        // recursion per call: let the automatic time split cut it into up to 32
+        // segments, with 64-sample chunks so that segments can be that short
+        const bool small = o.time_split == 0 && off[T] <= 128 * (int64_t)df.n_cu;
+        if (small) orr.chunk_len = 64;
         spiir_bank *bk = nullptr;
-        rc = spiir_bank_create(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], &orr);
+        rc = orr.autotune ? spiir_bank_create(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], &orr)
+                          : create_bank(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], orr,
+                                        small ? 32 : 8);
         if (rc) {
             g_err = "level " + std::to_string(r) + ": " + g_err;
             return bail(rc);
