@@ -1905,6 +1905,9 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
     if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
     int64_t B = o.max_block ? o.max_block : 16384;
     B = std::max<int64_t>((B >> R) << R, (int64_t)1 << R);
+    // interpolation launches one workgroup per (template, 1,024 outputs)
+    if (((B + 1023) / 1024) * (int64_t)T > INT32_MAX)
+        return fail(SPIIR_EINVAL, "n_templates x max_block too large (%d x %lld)", T, (long long)B);
     int dev = o.device;
     if (dev < 0) {
         int count = 0;
@@ -2173,6 +2176,7 @@ int spiir_whitener_estimate_psd(spiir_whitener *wh, const float *train, int64_t 
     DeviceGuard guard(wh->device);
     hipStream_t st = as_stream(stream);
     const int64_t K = (n - wh->N) / wh->H + 1;
+    if (K > INT32_MAX) return fail(SPIIR_EINVAL, "training stretch of %lld frames is too long", (long long)K);
     if (K > wh->pw_frames) {
         HIPCHK(hipStreamSynchronize(st));
         dfree(wh->pw);
