@@ -91,8 +91,8 @@ typedef struct {
                                  (with fl32(a) in SPIIR_PREC_FP32 mode) and their free
                                  response is added. spiir_backward likewise cuts the
                                  reverse scan into segments (automatic count up to 16
-                                 for 0, the given count for 2..8). 0 = automatic, 1 = off,
-                                 2..8 = forced. Not used by the per-template comparator. */
+                                 for 0, the given count for 2..32). 0 = automatic, 1 = off,
+                                 2..32 = forced. Not used by the per-template comparator. */
 } spiir_bank_opts;
 
 /* Layout facts of a created bank (for tests, tuning reports and benchmarks). */

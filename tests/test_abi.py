@@ -79,7 +79,7 @@ GOOD = dict(T=2, off=[0, 2, 3], a=[0.5, 0.9j, -0.3 + 0.1j], b=[1, 1j, 0.5], d=[0
     (dict(filters_per_lane=5), "filters_per_lane"),
     (dict(precision=3), "precision"),
     (dict(waves_per_group=17), "waves_per_group"),
-    (dict(time_split=9), "time_split"),
+    (dict(time_split=33), "time_split"),
 ])
 def test_create_rejects_bad_arguments(lib, change, needle):
     args = dict(GOOD)
