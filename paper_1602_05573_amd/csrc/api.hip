@@ -1506,7 +1506,8 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
         const spiir_bank *bk = banks[s];
         max_slots = std::max(max_slots, bk->lay.nslots);
         const int L = bk->L;
-        int want = (int)std::min<int64_t>(8, bt->slots_dev / std::max(1, bk->lay.groups));
+        // as in a bank's automatic split: twice the resident slots over the workgroups, at most 8
+        int want = (int)std::min<int64_t>(8, 2 * bt->slots_dev / std::max(1, bk->lay.groups));
         want = std::max(1, std::min(want, (B + L - 1) / L));
         const int64_t seg_len = ((B + want - 1) / want + L - 1) / L * L;
         const int nseg = (int)((B + seg_len - 1) / seg_len);
