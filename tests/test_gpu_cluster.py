@@ -205,3 +205,29 @@ def test_cluster_parity_scan_path():
         got = gpu_clusters(M, J, thr, W)
         assert_same(got, ref, "scan path W=%d" % W)
         assert ref[3] > 20
+
+
+def test_cluster_piecewise_with_overlap():
+    """The rule reaches W samples either side, so calls on [s, e) overlapping by
+    2W give the whole series' triggers for every m with s + W <= m < e - W:
+    stitching those ranges reproduces the whole-series result."""
+    from paper_1602_05573_amd import cluster_triggers
+    n, W, piece = 300000, 777, 40000
+    M, J = trigger_series(n, idx=2, peaks=64, plateau=6)
+    thr = float(np.quantile(M, 0.99))
+    banner("cluster piecewise")
+    whole = gpu_clusters(M, J, thr, W)
+    md, jd = torch.from_numpy(M).cuda(), torch.from_numpy(J).cuda()
+    got = []
+    start = 0
+    while start < n:
+        s = max(0, start - W)
+        e = min(n, start + piece + W)
+        i, t, v, total = cluster_triggers(md[s:e], jd[s:e], thr, W)
+        i = i.cpu().numpy() + s
+        keep = (i >= start) & (i < min(n, start + piece))
+        got.append(i[keep])
+        start += piece
+    stitched = np.concatenate(got)
+    assert np.array_equal(stitched, whole[0])
+    assert len(stitched) > 20
