@@ -6,9 +6,10 @@
 //   whitening    : y_k = IDFT(DFT(w . x_k) / sqrt(S)), overlap-added at hop H
 // The stream is whitened with a delay of H samples (H zeros precede it).
 // Each frame is one workgroup of 1,024 threads: a radix-2 FFT of N complex
-// points in LDS (bit-reversed load, in-place butterflies; the FP64-computed
-// twiddle table is staged in LDS once per frame, so no stage waits on global
-// memory); the inverse transform is the forward one applied to the conjugate.
+// points in LDS (bit-reversed load, in-place butterflies taken two stages per
+// pass; the FP64-computed twiddle table is staged in LDS once per frame, so no
+// stage waits on global memory); the inverse transform is the forward one
+// applied to the conjugate.
 #include "spiir_internal.h"
 
 #include <atomic>
@@ -21,21 +22,47 @@ constexpr int kFftThreads = 1024;  // one frame per workgroup
 
 __device__ inline int bitrev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
 
-// In-place radix-2 decimation-in-time stages over bit-reversed input:
-// stage s combines pairs half = 2^s apart with twiddles exp(-2 pi i pos / (2 half)).
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place radix-2 decimation-in-time over bit-reversed input, two stages per
+// pass: stage s combines pairs h = 2^s apart with exp(-2 pi i pos / 2h), stage
+// s+1 pairs 2h apart with exp(-2 pi i pos' / 4h). The four elements
+// b, b+h, b+2h, b+3h of a group (b = its 4h-block start + pos, pos < h) are
+// closed under both stages, so each thread takes whole groups through both in
+// registers: one LDS exchange and one barrier per two stages. An odd stage
+// count ends with one plain radix-2 stage.
 __device__ void fft_stages(float2 *buf, const float2 *tw, int n, int logn) {
-    for (int s = 0; s < logn; ++s) {
-        const int half = 1 << s;
+    int s = 0;
+    for (; s + 1 < logn; s += 2) {
+        const int h = 1 << s;
+        const int st1 = n >> (s + 1), st2 = n >> (s + 2);
+        for (int q = threadIdx.x; q < n / 4; q += kFftThreads) {
+            const int pos = q & (h - 1);
+            const int b = ((q >> s) << (s + 2)) + pos;
+            const float2 w1 = tw[pos * st1];
+            const float2 w2a = tw[pos * st2], w2b = tw[(pos + h) * st2];
+            const float2 a0 = buf[b], a1 = cmul(buf[b + h], w1), a2 = buf[b + 2 * h], a3 = cmul(buf[b + 3 * h], w1);
+            const float2 b0 = make_float2(a0.x + a1.x, a0.y + a1.y), b1 = make_float2(a0.x - a1.x, a0.y - a1.y);
+            const float2 c2 = cmul(make_float2(a2.x + a3.x, a2.y + a3.y), w2a);
+            const float2 c3 = cmul(make_float2(a2.x - a3.x, a2.y - a3.y), w2b);
+            buf[b] = make_float2(b0.x + c2.x, b0.y + c2.y);
+            buf[b + 2 * h] = make_float2(b0.x - c2.x, b0.y - c2.y);
+            buf[b + h] = make_float2(b1.x + c3.x, b1.y + c3.y);
+            buf[b + 3 * h] = make_float2(b1.x - c3.x, b1.y - c3.y);
+        }
+        __syncthreads();
+    }
+    if (s < logn) {
+        const int h = 1 << s;
         const int step = n >> (s + 1);
-        for (int b = threadIdx.x; b < n / 2; b += kFftThreads) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> s) << (s + 1)) + pos;
-            const int i1 = i0 + half;
-            const float2 wv = tw[pos * step];
-            const float2 u = buf[i0], v = buf[i1];
-            const float2 t = make_float2(v.x * wv.x - v.y * wv.y, v.x * wv.y + v.y * wv.x);
-            buf[i0] = make_float2(u.x + t.x, u.y + t.y);
-            buf[i1] = make_float2(u.x - t.x, u.y - t.y);
+        for (int q = threadIdx.x; q < n / 2; q += kFftThreads) {
+            const int pos = q & (h - 1);
+            const int i0 = ((q >> s) << (s + 1)) + pos;
+            const float2 u = buf[i0], v = cmul(buf[i0 + h], tw[pos * step]);
+            buf[i0] = make_float2(u.x + v.x, u.y + v.y);
+            buf[i0 + h] = make_float2(u.x - v.x, u.y - v.y);
         }
         __syncthreads();
     }
