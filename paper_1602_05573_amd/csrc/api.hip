@@ -2047,8 +2047,11 @@ int spiir_multirate_reset(spiir_multirate *mr, void *stream) {
         if (bk) {
             const int rc = spiir_bank_reset(bk, stream);
             if (rc) return rc;
+            // every piece toggles the object's parity and each level bank's history
+            // index together, so they stay equal; the captured graphs rely on it
+            bk->hist_cur = 0;
         }
-    return mr_clear_history(mr, as_stream(stream));
+    return mr_clear_history(mr, as_stream(stream));   // sets mr->cur = 0
 }
 
 static int mr_check_call(const spiir_multirate *mr, const float *x, int64_t n) {

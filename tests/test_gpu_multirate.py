@@ -170,6 +170,39 @@ def test_multirate_graph_replay_equals_eager():
     assert np.max(np.abs(g2[0].cpu().numpy() - s.max(axis=0))) <= SNR_TOL * s.max()
 
 
+def test_multirate_graph_after_odd_reset():
+    """Reset after an odd number of pieces, then graph replays mixed with eager
+    pieces: equal to the same calls with graphs off (the graphs bake in which
+    history buffer of each level bank is current)."""
+    from paper_1602_05573_amd import SpiirMultiRate
+    levels = rand_levels(6, [4, 6, 12], 41)
+    h, g = resample_taps(16)
+    B = 1024
+    x = strain(40 * B, 6, 41)
+    xd = torch.from_numpy(x).cuda()
+    banner("multirate graph after odd reset")
+    plan = [(0, 3 * B), "reset", (3 * B, 5 * B), (5 * B, 5 * B + 256), (5 * B + 256, 9 * B + 256), "reset",
+            (0, B), (B, B + 512), (B + 512, 12 * B + 512)]
+
+    def run(graph):
+        outs = []
+        with SpiirMultiRate(levels, h, g, max_block=B) as mr:
+            mr.set_graph(graph)
+            for step in plan:
+                if step == "reset":
+                    mr.reset()
+                    continue
+                a, b = step
+                mx, am = mr.trigger_max(xd[a:b])
+                outs.append((mx.clone(), am.clone()))
+            torch.cuda.synchronize()
+        return outs
+
+    eager, graph = run(False), run(True)
+    for (em, ea), (gm, ga) in zip(eager, graph):
+        assert torch.equal(em, gm) and torch.equal(ea, ga)
+
+
 def test_multirate_rejects_bad_arguments():
     from paper_1602_05573_amd import SpiirError, SpiirMultiRate
     levels = rand_levels(3, [4, 4], 30)
