@@ -47,6 +47,7 @@ typedef struct spiir_tape spiir_tape;
 typedef struct spiir_batch spiir_batch;
 typedef struct spiir_multirate spiir_multirate;
 typedef struct spiir_whitener spiir_whitener;
+typedef struct spiir_trigger_stream spiir_trigger_stream;
 
 typedef enum {
     SPIIR_OK = 0,
@@ -484,6 +485,39 @@ int spiir_cluster_triggers(const float *max_dev, const int32_t *argmax_dev, int6
                            size_t workspace_bytes, int64_t *index_dev, int32_t *template_dev,
                            float *snr_dev, int64_t capacity, int64_t *count_dev, int32_t device,
                            void *stream);
+
+/*
+ * Streaming trigger clustering (the rule of spiir_cluster_triggers) for a
+ * max / argmax series that arrives block by block, as spiir_trigger_max
+ * produces it. A sample's triggers are final once the W samples after it have
+ * arrived, so each push emits, in increasing order and with absolute sample
+ * indices, the triggers among the samples that became final with it: the
+ * latency is W samples. Across all pushes and the final flush the output is
+ * exactly spiir_cluster_triggers on the whole series.
+ *
+ *   create   threshold and window W >= 0 as in spiir_cluster_triggers;
+ *            max_block = most samples per push (1 .. 2^32). Device memory:
+ *            two windows of 2W + max_block samples and a clustering workspace.
+ *   push     max_dev float32 [n], argmax_dev int32 [n], 0 <= n <= max_block;
+ *            writes up to capacity triggers (index_dev int64, template_dev
+ *            int32, snr_dev float32; NULL allowed with capacity 0) and their
+ *            count (also when above capacity) to count_dev int64 [1].
+ *   flush    end of the stream: emits the triggers of the last W samples (their
+ *            windows clipped at the end). Push after flush only after reset.
+ *   reset    starts a new stream at sample 0.
+ * Everything is enqueued on stream; the object keeps host-side positions, so
+ * its calls must be made from one thread in stream order.
+ */
+int spiir_trigger_stream_create(spiir_trigger_stream **out, float threshold, int32_t window,
+                                int64_t max_block, int32_t device);
+int spiir_trigger_stream_push(spiir_trigger_stream *ts, const float *max_dev,
+                              const int32_t *argmax_dev, int64_t n, int64_t *index_dev,
+                              int32_t *template_dev, float *snr_dev, int64_t capacity,
+                              int64_t *count_dev, void *stream);
+int spiir_trigger_stream_flush(spiir_trigger_stream *ts, int64_t *index_dev, int32_t *template_dev,
+                               float *snr_dev, int64_t capacity, int64_t *count_dev, void *stream);
+int spiir_trigger_stream_reset(spiir_trigger_stream *ts, void *stream);
+int spiir_trigger_stream_destroy(spiir_trigger_stream *ts);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *spiir_last_error(void);

@@ -17,7 +17,7 @@ from ._lib import (  # noqa: F401
 def __getattr__(name):
     # torch-dependent classes are imported lazily so that the ABI checks run
     # without initialising any GPU runtime
-    if name in ("SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "Whitener", "autotune",
+    if name in ("SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "TriggerStream", "Whitener", "autotune",
                 "batch_banks", "cluster_triggers", "version"):
         from . import bank
         return getattr(bank, name)

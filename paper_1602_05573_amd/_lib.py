@@ -29,6 +29,8 @@ EXPORTS = (
     "spiir_multirate_set_graph",
     "spiir_whitener_create", "spiir_whitener_destroy", "spiir_whitener_estimate_psd", "spiir_whitener_set_psd",
     "spiir_whitener_get_psd", "spiir_whitener_process", "spiir_whitener_reset",
+    "spiir_trigger_stream_create", "spiir_trigger_stream_push", "spiir_trigger_stream_flush",
+    "spiir_trigger_stream_reset", "spiir_trigger_stream_destroy",
     "spiir_last_error", "spiir_version",
 )
 
@@ -119,6 +121,11 @@ def load():
         "spiir_whitener_get_psd": (ctypes.c_int, [P, P]),
         "spiir_whitener_process": (ctypes.c_int, [P, P, I64, P, P]),
         "spiir_whitener_reset": (ctypes.c_int, [P, P]),
+        "spiir_trigger_stream_create": (ctypes.c_int, [PP, ctypes.c_float, I32, I64, I32]),
+        "spiir_trigger_stream_push": (ctypes.c_int, [P, P, P, I64, P, P, P, I64, P, P]),
+        "spiir_trigger_stream_flush": (ctypes.c_int, [P, P, P, P, I64, P, P]),
+        "spiir_trigger_stream_reset": (ctypes.c_int, [P, P]),
+        "spiir_trigger_stream_destroy": (ctypes.c_int, [P]),
         "spiir_last_error": (ctypes.c_char_p, []),
         "spiir_version": (ctypes.c_char_p, []),
     }

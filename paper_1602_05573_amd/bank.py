@@ -539,6 +539,80 @@ class TriggerClusterer:
         return self.index[:k], self.template[:k], self.snr[:k], total
 
 
+class TriggerStream:
+    """Streaming trigger clustering (spiir_trigger_stream_*): push each block's
+    max / argmax; every push returns the triggers that became final (W samples
+    of latency), flush() returns the rest at the end of the stream."""
+
+    def __init__(self, threshold: float, window: int, max_block: int, capacity: int | None = None,
+                 device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._h = ctypes.c_void_p()
+        call("spiir_trigger_stream_create", ctypes.byref(self._h), float(threshold), int(window), int(max_block),
+             dev.index)
+        self.device = dev
+        self.capacity = int(capacity) if capacity is not None else (max_block + window) // (window + 1) + 2
+        self.index = torch.empty(max(1, self.capacity), dtype=torch.int64, device=dev)
+        self.template = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
+        self.snr = torch.empty(max(1, self.capacity), dtype=torch.float32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().spiir_trigger_stream_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _result(self):
+        total = int(self.count.item())
+        k = min(total, self.capacity)
+        return self.index[:k].clone(), self.template[:k].clone(), self.snr[:k].clone(), total
+
+    def push(self, mx: torch.Tensor, am: torch.Tensor, stream=None):
+        """(index, template, snr, total) of the triggers that became final."""
+        _require_cuda(mx, torch.float32, "max")
+        _require_cuda(am, torch.int32, "argmax")
+        if mx.numel() != am.numel():
+            raise ValueError("max and argmax differ in length")
+        call("spiir_trigger_stream_push", self._h, _ptr(mx), _ptr(am), mx.numel(), _ptr(self.index),
+             _ptr(self.template), _ptr(self.snr), self.capacity, _ptr(self.count), _stream_ptr(stream))
+        return self._result()
+
+    def push_into(self, mx: torch.Tensor, am: torch.Tensor, index: torch.Tensor, template: torch.Tensor,
+                  snr: torch.Tensor, count: torch.Tensor, stream=None):
+        """Enqueues a push writing into caller tensors (no host synchronisation):
+        up to index.numel() triggers, their total to count[0]."""
+        _require_cuda(mx, torch.float32, "max")
+        _require_cuda(am, torch.int32, "argmax")
+        cap = index.numel()
+        if template.numel() < cap or snr.numel() < cap or count.numel() < 1:
+            raise ValueError("output tensors too small")
+        call("spiir_trigger_stream_push", self._h, _ptr(mx), _ptr(am), mx.numel(), _ptr(index), _ptr(template),
+             _ptr(snr), cap, _ptr(count), _stream_ptr(stream))
+
+    def flush_into(self, index: torch.Tensor, template: torch.Tensor, snr: torch.Tensor, count: torch.Tensor,
+                   stream=None):
+        """Enqueues the end-of-stream flush writing into caller tensors."""
+        cap = index.numel()
+        if template.numel() < cap or snr.numel() < cap or count.numel() < 1:
+            raise ValueError("output tensors too small")
+        call("spiir_trigger_stream_flush", self._h, _ptr(index), _ptr(template), _ptr(snr), cap, _ptr(count),
+             _stream_ptr(stream))
+
+    def flush(self, stream=None):
+        call("spiir_trigger_stream_flush", self._h, _ptr(self.index), _ptr(self.template), _ptr(self.snr),
+             self.capacity, _ptr(self.count), _stream_ptr(stream))
+        return self._result()
+
+    def reset(self, stream=None):
+        call("spiir_trigger_stream_reset", self._h, _stream_ptr(stream))
+
+
 def cluster_triggers(mx: torch.Tensor, am: torch.Tensor, threshold: float, window: int,
                      capacity: int | None = None, stream=None):
     """One-shot clustering of a max/argmax series; the default capacity holds
@@ -555,6 +629,6 @@ def version() -> str:
     return load().spiir_version().decode()
 
 
-__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "Whitener", "autotune",
+__all__ = ["SpiirBank", "SpiirBatch", "SpiirFn", "SpiirMultiRate", "Tape", "TriggerClusterer", "TriggerStream", "Whitener", "autotune",
            "batch_banks",
            "cluster_triggers", "version", "_lib"]

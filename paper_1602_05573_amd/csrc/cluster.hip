@@ -210,7 +210,8 @@ __device__ uint32_t range_max_part(const float *__restrict__ M, const uint32_t *
 // maxima of c; blocks below the threshold are skipped without reading their
 // samples, and the live blocks are dealt round robin by rank to the waves (the
 // samples above a threshold come in runs, so neighbouring live blocks go to
-// different waves). In a live block each lane tests one sample: threshold and
+// different waves). Only samples in [c_lo, c_hi) can trigger; the others serve
+// as window neighbours. In a live block each lane tests one sample: threshold and
 // the two direct neighbours (rising and falling edges fail there); the
 // survivors are tested on their whole windows, one at a time by the whole wave
 // when few, else each by its own lane.
@@ -219,6 +220,7 @@ constexpr int kWaveTestMax = 4;
 
 __global__ __launch_bounds__(kFindThreads) void clus_find_kernel(const float *__restrict__ M, int64_t n,
                                                                  float thr, uint32_t kthr, int64_t W,
+                                                                 int64_t c_lo, int64_t c_hi,
                                                                  const uint32_t *__restrict__ bm1,
                                                                  const uint32_t *__restrict__ bm2,
                                                                  uint64_t *__restrict__ mask,
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(kFindThreads) void clus_find_kernel(const float *__
         bool cand = false;
         if (m < n) {
             v = M[m];
-            cand = v >= thr;
+            cand = m >= c_lo && m < c_hi && v >= thr;   // outside [c_lo, c_hi): neighbours only
         }
         if (cand && W >= 1) {
             const uint32_t km = okey(v);
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void clus_write_kernel(const float *__res
                                                               const uint64_t *__restrict__ mask,
                                                               const uint32_t *__restrict__ cnt2,
                                                               const int64_t *__restrict__ off2, int64_t cap,
-                                                              int64_t *__restrict__ count,
+                                                              int64_t *__restrict__ count, int64_t index_base,
                                                               int64_t *__restrict__ idx,
                                                               int32_t *__restrict__ tpl,
                                                               float *__restrict__ val) {
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(kThreads) void clus_write_kernel(const float *__res
         const int64_t pos = off + pre[i] + __popcll(mm & ((1ull << lane) - 1));
         if (pos >= cap) continue;
         const int64_t m = (c * (kB2 / kB1) + i) * kB1 + lane;
-        idx[pos] = m;
+        idx[pos] = index_base + m;
         tpl[pos] = J[m];
         val[pos] = M[m];
     }
@@ -386,7 +388,7 @@ size_t cluster_workspace_bytes(int64_t n) { return carve(nullptr, n, nullptr); }
 
 hipError_t launch_cluster(const float *M, const int32_t *J, int64_t n, float thr, int64_t W, void *ws,
                           int64_t cap, int64_t *idx, int32_t *tpl, float *val, int64_t *count,
-                          hipStream_t st) {
+                          hipStream_t st, int64_t c_lo, int64_t c_hi, int64_t index_base) {
     ClusterWs w;
     carve(ws, n, &w);
     const int64_t nb2 = (n + kB2 - 1) / kB2;
@@ -396,14 +398,14 @@ hipError_t launch_cluster(const float *M, const int32_t *J, int64_t n, float thr
     }
     hipLaunchKernelGGL(clus_reduce_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, n, w.bm1, w.bm2);
     hipLaunchKernelGGL(clus_find_kernel, dim3((unsigned)nb2), dim3(kFindThreads), 0, st, M, n, thr, okey(thr), W,
-                       w.bm1, w.bm2, w.mask, w.cnt2);
+                       c_lo, c_hi < 0 ? n : c_hi, w.bm1, w.bm2, w.mask, w.cnt2);
     int64_t *off2 = nullptr;
     if (nb2 > kInlinePrefix) {
         hipLaunchKernelGGL(clus_scan_kernel, dim3(1), dim3(1024), 0, st, w.cnt2, nb2, w.off2, count);
         off2 = w.off2;
     }
     hipLaunchKernelGGL(clus_write_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, J, n, w.mask, w.cnt2,
-                       off2, cap, count, idx, tpl, val);
+                       off2, cap, count, index_base, idx, tpl, val);
     return hipGetLastError();
 }
 

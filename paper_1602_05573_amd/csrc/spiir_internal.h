@@ -162,8 +162,11 @@ hipError_t launch_wh_ola(const float *y, int64_t nf, int n, const float *pend, f
 // Trigger clustering over a max/argmax series (block maxima, window test,
 // ordered compaction); the workspace holds the block maxima, masks and counts.
 size_t cluster_workspace_bytes(int64_t n);
+// Candidates are limited to samples [c_lo, c_hi) (c_hi < 0: up to n; the rest
+// are window neighbours only) and written indices are offset by index_base.
 hipError_t launch_cluster(const float *max, const int32_t *argmax, int64_t n, float threshold,
                           int64_t window, void *workspace, int64_t capacity, int64_t *index,
-                          int32_t *tmpl, float *snr, int64_t *count, hipStream_t stream);
+                          int32_t *tmpl, float *snr, int64_t *count, hipStream_t stream,
+                          int64_t c_lo = 0, int64_t c_hi = -1, int64_t index_base = 0);
 
 }  // namespace spiir

@@ -135,6 +135,15 @@ def test_null_arguments(lib):
     assert lib.spiir_whitener_get_psd(None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_whitener_process(None, None, 0, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_whitener_reset(None, None) == _lib.SPIIR_EINVAL
+    th = ctypes.c_void_p()
+    assert lib.spiir_trigger_stream_create(None, 1.0, 4, 16, -1) == _lib.SPIIR_EINVAL
+    assert lib.spiir_trigger_stream_create(ctypes.byref(th), 1.0, -1, 16, -1) == _lib.SPIIR_EINVAL
+    assert lib.spiir_trigger_stream_create(ctypes.byref(th), 1.0, 4, 0, -1) == _lib.SPIIR_EINVAL
+    assert not th.value
+    assert lib.spiir_trigger_stream_destroy(None) == 0
+    assert lib.spiir_trigger_stream_reset(None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_trigger_stream_push(None, None, None, 0, None, None, None, 0, None, None) == _lib.SPIIR_EINVAL
+    assert lib.spiir_trigger_stream_flush(None, None, None, None, 0, None, None) == _lib.SPIIR_EINVAL
     assert lib.spiir_batch_create(None, 1, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL
     bh = ctypes.c_void_p()
     assert lib.spiir_batch_create(ctypes.byref(bh), 0, None, None, None, None, None, 4096, None) == _lib.SPIIR_EINVAL

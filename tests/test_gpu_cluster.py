@@ -231,3 +231,34 @@ def test_cluster_piecewise_with_overlap():
     stitched = np.concatenate(got)
     assert np.array_equal(stitched, whole[0])
     assert len(stitched) > 20
+
+
+@pytest.mark.parametrize("W,block,q", [(0, 4096, 0.99), (1, 1000, 0.5), (777, 5000, 0.99), (5000, 2048, 0.999),
+                                       (20000, 8192, 0.99)])
+def test_trigger_stream_equals_whole_series(W, block, q):
+    """Pushes of irregular lengths (at most max_block) and a flush give exactly
+    the whole series' triggers; reset starts over."""
+    from paper_1602_05573_amd import TriggerStream
+    n = 120007
+    M, J = trigger_series(n, idx=W % 4, peaks=48, plateau=6)
+    thr = float(np.quantile(M, q))
+    banner("trigger stream W=%d block=%d q=%g" % (W, block, q))
+    ref = oracle_ref(M, J, thr, W)
+    md, jd = torch.from_numpy(M).cuda(), torch.from_numpy(J).cuda()
+    rng = np.random.default_rng(W)
+    ts = TriggerStream(thr, W, block, capacity=n // (W + 1) + 2)
+    for rep in range(2):
+        got_i, got_t, got_v = [], [], []
+        pos = 0
+        while pos < n:
+            k = int(min(n - pos, rng.integers(0, block + 1)))
+            i, t, v, total = ts.push(md[pos:pos + k], jd[pos:pos + k])
+            assert total == len(i)
+            got_i.append(i.cpu().numpy()); got_t.append(t.cpu().numpy()); got_v.append(v.cpu().numpy())
+            pos += k
+        i, t, v, total = ts.flush()
+        got_i.append(i.cpu().numpy()); got_t.append(t.cpu().numpy()); got_v.append(v.cpu().numpy())
+        got = (np.concatenate(got_i), np.concatenate(got_t), np.concatenate(got_v))
+        assert_same(got + (len(got[0]),), ref, "stream W=%d rep %d" % (W, rep))
+        ts.reset()
+    ts.close()
