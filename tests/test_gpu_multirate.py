@@ -203,6 +203,22 @@ def test_multirate_graph_after_odd_reset():
         assert torch.equal(em, gm) and torch.equal(ea, ga)
 
 
+def test_multirate_level_banks():
+    """Each level runs a bank of exactly the templates that have filters there;
+    a level without filters has no bank."""
+    from paper_1602_05573_amd import SpiirMultiRate
+    levels = rand_levels(8, [3, 0, 9, 5], 42)
+    h, g = resample_taps(8)
+    with SpiirMultiRate(levels, h, g, max_block=2048) as mr:
+        for r, lv in enumerate(levels):
+            info = mr.level_info(r)
+            present = int(np.count_nonzero(np.diff(lv.offsets)))
+            if lv.n_filters == 0:
+                assert info is None and mr.level_bank_handle(r) is None
+            else:
+                assert info["n_templates"] == present and info["n_filters"] == lv.n_filters
+
+
 def test_multirate_rejects_bad_arguments():
     from paper_1602_05573_amd import SpiirError, SpiirMultiRate
     levels = rand_levels(3, [4, 4], 30)
