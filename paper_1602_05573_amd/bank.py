@@ -335,6 +335,14 @@ class SpiirFn(torch.autograd.Function):
                 None, None)
 
 
+def _cuda_device(device=None) -> torch.device:
+    """torch.device with an explicit index (the current device when none is given)."""
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    if dev.type != "cuda":
+        raise ValueError("a CUDA device is required (got %s)" % dev)
+    return torch.device("cuda", torch.cuda.current_device() if dev.index is None else dev.index)
+
+
 class SpiirMultiRate:
     """Multi-rate bank (spiir_multirate_*): `levels` is a list of
     workloads.Bank-like objects, level r running at 1 / 2^r of the input
@@ -507,7 +515,7 @@ class TriggerClusterer:
     (spiir_cluster_triggers). run() only enqueues work; result() waits for it."""
 
     def __init__(self, max_n: int, capacity: int, device=None):
-        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        dev = _cuda_device(device)
         nb = ctypes.c_size_t()
         call("spiir_cluster_workspace_size", int(max_n), ctypes.byref(nb))
         self.max_n, self.capacity, self.device = int(max_n), int(capacity), dev
@@ -546,7 +554,7 @@ class TriggerStream:
 
     def __init__(self, threshold: float, window: int, max_block: int, capacity: int | None = None,
                  device=None):
-        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        dev = _cuda_device(device)
         self._h = ctypes.c_void_p()
         call("spiir_trigger_stream_create", ctypes.byref(self._h), float(threshold), int(window), int(max_block),
              dev.index)
