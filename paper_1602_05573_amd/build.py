@@ -8,8 +8,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspiir.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "cluster.hip", "multirate.hip", "whiten.hip", "api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "spiir_internal.h"), os.path.join(ROOT, "include", "spiir.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "cluster.hip", "multirate.hip", "whiten.hip", "api.hip",
+                                                   "multirate_api.hip", "whiten_api.hip", "cluster_api.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "spiir_internal.h"), os.path.join(HERE, "csrc", "host_common.h"),
+           os.path.join(ROOT, "include", "spiir.h")]
 
 # Packed FP32 instructions are switched off for the device code: ordinary
 # float code is compiled to scalar VALU instructions only.

@@ -1,8 +1,9 @@
-// Host side of libspiir: argument checking, bank layout, FP64 precomputation,
-// launches, streaming state, the adjoint tape, batches in a HIP graph and the
-// autotuner. Declared in include/spiir.h.
-#include "spiir.h"
-#include "spiir_internal.h"
+// Host side of libspiir's filter banks: argument checking, bank layout, FP64
+// precomputation, launches, streaming state, the adjoint tape, batches in a
+// HIP graph and the autotuner; also the shared error and device helpers of
+// host_common.h. The multi-rate bank, the whitener and the clustering objects
+// have their own host sources. Declared in include/spiir.h.
+#include "host_common.h"
 
 #include <algorithm>
 #include <cmath>
@@ -16,8 +17,10 @@
 #include <vector>
 
 using namespace spiir;
+using namespace spiir::host;
 
-namespace {
+namespace spiir {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -31,35 +34,29 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPCHK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return fail(SPIIR_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename T>
-hipError_t dalloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+int device_facts(int dev, DeviceFacts &f) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(SPIIR_ENODEV, "no HIP device available");
+    if (dev < 0 || dev >= count) return fail(SPIIR_ENODEV, "device %d out of range (%d devices)", dev, count);
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SPIIR_ENODEV, "device %d is %s; this library is built for gfx950 only", dev,
+                    prop.gcnArchName);
+    f.n_cu = prop.multiProcessorCount;
+    f.lds_cap = prop.sharedMemPerBlock;
+    return SPIIR_OK;
 }
 
-template <typename T>
-void dfree(T *&p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
+}  // namespace host
+}  // namespace spiir
+
+namespace {
+
+
+
+
 
 std::pair<double, double> cpow(double re, double im, long e) {
     double rr = 1.0, ri = 0.0;
@@ -253,25 +250,6 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
     return SPIIR_OK;
 }
 
-struct DeviceFacts {
-    int n_cu = 0;
-    size_t lds_cap = 0;
-};
-
-int device_facts(int dev, DeviceFacts &f) {
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
-        return fail(SPIIR_ENODEV, "no HIP device available");
-    if (dev < 0 || dev >= count) return fail(SPIIR_ENODEV, "device %d out of range (%d devices)", dev, count);
-    hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, dev));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(SPIIR_ENODEV, "device %d is %s; this library is built for gfx950 only", dev,
-                    prop.gcnArchName);
-    f.n_cu = prop.multiProcessorCount;
-    f.lds_cap = prop.sharedMemPerBlock;
-    return SPIIR_OK;
-}
 
 }  // namespace
 
@@ -677,7 +655,6 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     return SPIIR_OK;
 }
 
-inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 int ensure_xwin(spiir_bank *bk, int64_t need) {
     if (need <= bk->xwin_cap) return SPIIR_OK;
@@ -741,261 +718,45 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
 
 }  // namespace
 
-struct spiir_multirate {
-    int device = 0;
-    int T = 0, R = 0, top = 0;  // levels 0..R; top = highest level holding filters
-    int lh = 0, lg = 0, hh = 0;  // decimation / interpolation taps, interpolation history
-    int64_t B = 0;               // most full-rate samples per piece (a multiple of 2^R)
-    std::vector<spiir_bank *> bank;      // per level; NULL where the level holds no filters
-    std::vector<int32_t *> zrow;         // per level, device [T]: row of template j in z, or -1
-    std::vector<float *> xbuf;           // per level >= 1: the decimated stream [B >> r]
-    std::vector<float *> dh[2];          // per level >= 1: decimation history [lh - 1] (double-buffered)
-    std::vector<float2 *> z;             // per level with filters: template sums [T_r][B >> r]
-    std::vector<float2 *> w;             // 1 <= r < top: w_r [T][B >> r]
-    std::vector<float2 *> wh[2];         // 1 <= r <= top: interpolation history of w_r [T][hh]
-    int cur = 0;
-    float2 *w0 = nullptr;                // [T][B]: full-rate z for the max / argmax
-    uint64_t *keys = nullptr;            // [chunks][B]
-    float *h = nullptr, *g = nullptr;
-    // the level banks run concurrently: each on its own stream, forked from the
-    // caller's stream after the decimation and joined before the interpolation
-    std::vector<hipStream_t> lstream;
-    std::vector<hipEvent_t> ldone;
-    hipEvent_t fork = nullptr;
-    // trigger calls in pieces of exactly B samples replay a captured graph of
-    // the whole piece (one per history parity): the block is copied into xin,
-    // the max / argmax out of mxo / amo
-    bool use_graph = true;
-    bool graph_failed = false;
-    int64_t eager_pieces = 0;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    float *xin = nullptr, *mxo = nullptr;
-    int32_t *amo = nullptr;
-};
+namespace spiir {
+namespace host {
 
-namespace {
-
-void mr_free_graphs(spiir_multirate *mr) {
-    for (auto &g : mr->gexec)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+int bank_stream_z(spiir_bank *bk, const float *x, int64_t n, float *z, int64_t ld, hipStream_t st) {
+    return stream_call(bk, x, n, kModeZ, z, ld, nullptr, nullptr, st);
 }
 
-void mr_free(spiir_multirate *mr) {
-    mr_free_graphs(mr);
-    if (mr->cap) (void)hipStreamDestroy(mr->cap);
-    mr->cap = nullptr;
-    dfree(mr->xin);
-    dfree(mr->mxo);
-    dfree(mr->amo);
-    for (auto s : mr->lstream)
-        if (s) (void)hipStreamDestroy(s);
-    for (auto e : mr->ldone)
-        if (e) (void)hipEventDestroy(e);
-    if (mr->fork) (void)hipEventDestroy(mr->fork);
-    mr->lstream.clear();
-    mr->ldone.clear();
-    mr->fork = nullptr;
-    for (auto *bk : mr->bank)
-        if (bk) spiir_bank_destroy(bk);
-    for (auto *p : mr->zrow) dfree(p);
-    for (auto *p : mr->xbuf) dfree(p);
-    for (int c = 0; c < 2; ++c) {
-        for (auto *p : mr->dh[c]) dfree(p);
-        for (auto *p : mr->wh[c]) dfree(p);
-    }
-    for (auto *p : mr->z) dfree(p);
-    for (auto *p : mr->w) dfree(p);
-    dfree(mr->w0);
-    dfree(mr->keys);
-    dfree(mr->h);
-    dfree(mr->g);
+int bank_create_capped(spiir_bank **out, int32_t T, const int64_t *off, const double *a, const double *b,
+                       const int32_t *d, const spiir_bank_opts &o, int seg_cap) {
+    return create_bank(out, T, off, a, b, d, o, seg_cap);
 }
 
-int mr_clear_history(spiir_multirate *mr, hipStream_t st) {
-    for (int c = 0; c < 2; ++c)
-        for (int r = 1; r <= mr->top; ++r) {
-            HIPCHK(launch_fill_zero(mr->dh[c][r], (size_t)std::max(1, mr->lh - 1) * sizeof(float), st));
-            HIPCHK(launch_fill_zero(mr->wh[c][r], (size_t)mr->T * std::max(1, mr->hh) * sizeof(float2), st));
-        }
-    mr->cur = 0;
-    return SPIIR_OK;
+int bank_hist_cur(const spiir_bank *bk) { return bk->hist_cur; }
+void bank_set_hist_cur(spiir_bank *bk, int v) { bk->hist_cur = v; }
+bool bank_timing_on(const spiir_bank *bk) { return !bk->tev0.empty(); }
+
+// gfx950 check of a device, cached per ordinal for the process.
+int resolve_device(int32_t device, int &dev) {
+    static std::mutex mu;
+    static std::map<int, int> checked;
+    dev = device;
+    if (dev < 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+            return fail(SPIIR_ENODEV, "no HIP device available");
+        HIPCHK(hipGetDevice(&dev));
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = checked.find(dev);
+    if (it != checked.end()) return it->second;
+    DeviceFacts df;
+    const int rc = device_facts(dev, df);
+    if (rc != SPIIR_ENODEV) checked[dev] = rc;
+    return rc;
 }
 
-// One piece (np <= B samples) of the multi-rate bank: decimation, the level
-// banks forked onto their streams, interpolation and sums, and the full-rate
-// z (out0, row stride ld0) or the max / argmax (mx, am).
-int mr_piece(spiir_multirate *mr, const float *x0, int64_t np, float2 *out0, int64_t ld0, float *mx, int32_t *am,
-             hipStream_t st) {
-    const int top = mr->top;
-    const int c = mr->cur;
-    std::vector<const float *> xs(top + 1);
-    xs[0] = x0;
-    for (int r = 1; r <= top; ++r) {
-        HIPCHK(launch_mr_decimate(xs[r - 1], np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh,
-                                  mr->xbuf[r], st));
-        xs[r] = mr->xbuf[r];
-    }
-    HIPCHK(hipEventRecord(mr->fork, st));
-    for (int r = top; r >= 0; --r)   // the top level holds the most filters: start it first
-        if (mr->bank[r]) {
-            HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->fork, 0));
-            const int rc = stream_call(mr->bank[r], xs[r], np >> r, kModeZ, reinterpret_cast<float *>(mr->z[r]),
-                                       mr->B >> r, nullptr, nullptr, mr->lstream[r]);
-            if (rc) return rc;
-            HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
-            HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
-        }
-    if (!out0) {
-        out0 = mr->w0;
-        ld0 = mr->B;
-    }
-    if (top == 0) {
-        HIPCHK(launch_mr_upsample_add(mr->z[0], mr->B, mr->zrow[0], nullptr, 0, nullptr, 0, nullptr, nullptr, 0,
-                                      mr->g, mr->lg, out0, ld0, np, mr->T, st));
-    } else {
-        const float2 *src = mr->z[top];
-        int64_t ld_src = mr->B >> top;
-        const int32_t *srow = mr->zrow[top];
-        for (int r = top - 1; r >= 0; --r) {
-            float2 *dst = r == 0 ? out0 : mr->w[r];
-            const int64_t ld_dst = r == 0 ? ld0 : (mr->B >> r);
-            HIPCHK(launch_mr_upsample_add(mr->bank[r] ? mr->z[r] : nullptr, mr->B >> r, mr->zrow[r], src, ld_src,
-                                          srow, np >> (r + 1), mr->wh[c][r + 1], mr->wh[c ^ 1][r + 1], mr->hh,
-                                          mr->g, mr->lg, dst, ld_dst, np >> r, mr->T, st));
-            src = dst;
-            ld_src = ld_dst;
-            srow = nullptr;
-        }
-    }
-    if (mx) {
-        HIPCHK(launch_mr_row_keys(mr->w0, mr->B, mr->T, np, mr->keys, mr->B, st));
-        HIPCHK(launch_finalize_keys(mr->keys, mr_key_chunks(mr->T), mr->B, np, mx, am, st));
-    }
-    mr->cur ^= 1;
-    return SPIIR_OK;
-}
 
-bool mr_timing_on(const spiir_multirate *mr) {
-    for (auto *bk : mr->bank)
-        if (bk && !bk->tev0.empty()) return true;
-    return false;
-}
-
-// Captures a trigger piece of B samples for each history parity. The host-side
-// parity flags (mr->cur and every level bank's history index) toggle once per
-// captured piece, so after the two captures they are back where they were;
-// on failure they are restored and graphs stay off.
-int mr_build_graphs(spiir_multirate *mr) {
-    std::vector<int> hc;
-    for (auto *bk : mr->bank) hc.push_back(bk ? bk->hist_cur : 0);
-    const int cur0 = mr->cur;
-    auto restore = [&]() {
-        mr->cur = cur0;
-        for (size_t r = 0; r < mr->bank.size(); ++r)
-            if (mr->bank[r]) mr->bank[r]->hist_cur = hc[r];
-        mr_free_graphs(mr);
-        mr->graph_failed = true;
-    };
-    hipError_t e = hipSuccess;
-    if (!mr->cap) e = hipStreamCreateWithFlags(&mr->cap, hipStreamNonBlocking);
-    if (e == hipSuccess && !mr->xin) e = dalloc(&mr->xin, (size_t)mr->B);
-    if (e == hipSuccess && !mr->mxo) e = dalloc(&mr->mxo, (size_t)mr->B);
-    if (e == hipSuccess && !mr->amo) e = dalloc(&mr->amo, (size_t)mr->B);
-    if (e != hipSuccess) {
-        restore();
-        return fail(SPIIR_EHIP, "graph set-up: %s", hipGetErrorString(e));
-    }
-    for (int k = 0; k < 2; ++k) {
-        const int parity = mr->cur;
-        hipGraph_t g = nullptr;
-        e = hipStreamBeginCapture(mr->cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            restore();
-            return fail(SPIIR_EHIP, "graph capture: %s", hipGetErrorString(e));
-        }
-        const int rc = mr_piece(mr, mr->xin, mr->B, nullptr, 0, mr->mxo, mr->amo, mr->cap);
-        e = hipStreamEndCapture(mr->cap, &g);
-        if (rc == SPIIR_OK && e == hipSuccess) e = hipGraphInstantiate(&mr->gexec[parity], g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
-        if (rc || e != hipSuccess) {
-            restore();
-            return rc ? rc : fail(SPIIR_EHIP, "graph capture: %s", hipGetErrorString(e));
-        }
-    }
-    return SPIIR_OK;
-}
-
-// One pass of the multi-rate bank over x[0..n), written as the full-rate z
-// (zout, row stride ldz) or as max / argmax.
-int mr_run(spiir_multirate *mr, const float *x, int64_t n, float2 *zout, int64_t ldz, float *mx, int32_t *am,
-           hipStream_t st) {
-    DeviceGuard guard(mr->device);
-    for (int64_t P = 0; P < n; P += mr->B) {
-        const int64_t np = std::min<int64_t>(mr->B, n - P);
-        const bool graph = mx && np == mr->B && mr->use_graph && !mr->graph_failed && mr->eager_pieces > 0 &&
-                           !mr_timing_on(mr);
-        if (graph && !mr->gexec[mr->cur]) {
-            const int rc = mr_build_graphs(mr);
-            if (rc) return rc;
-        }
-        if (graph) {
-            HIPCHK(hipMemcpyAsync(mr->xin, x + P, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipGraphLaunch(mr->gexec[mr->cur], st));
-            HIPCHK(hipMemcpyAsync(mx + P, mr->mxo, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(am + P, mr->amo, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-            mr->cur ^= 1;
-            for (auto *bk : mr->bank)
-                if (bk) bk->hist_cur ^= 1;   // as the captured stream calls did
-            continue;
-        }
-        const int rc = mr_piece(mr, x + P, np, zout ? zout + P : nullptr, ldz, mx ? mx + P : nullptr,
-                                am ? am + P : nullptr, st);
-        if (rc) return rc;
-        ++mr->eager_pieces;
-    }
-    return SPIIR_OK;
-}
-
-}  // namespace
-
-struct spiir_whitener {
-    int device = 0;
-    int N = 0, logN = 0, H = 0;
-    int64_t B = 0;                 // most samples per piece (a multiple of H)
-    double wsum2 = 0.0;            // sum of the squared window
-    float *wtab = nullptr;         // [N] periodic Hann window
-    float2 *tw = nullptr;          // [N/2] exp(-2 pi i k / N)
-    double *S = nullptr;           // [H+1] PSD
-    float *inv = nullptr;          // [H+1] 1 / sqrt(S)
-    float *hist[2] = {nullptr, nullptr};  // last H input samples (double-buffered)
-    float *pend[2] = {nullptr, nullptr};  // second half of the last frame's output
-    int cur = 0;
-    float *y = nullptr;            // [B/H][N] frame outputs
-    float *pw = nullptr;           // [frames][H+1] power spectra of the PSD training frames
-    int64_t pw_frames = 0;
-    bool has_psd = false;
-};
-
-namespace {
-
-void wh_free(spiir_whitener *wh) {
-    dfree(wh->wtab);
-    dfree(wh->tw);
-    dfree(wh->S);
-    dfree(wh->inv);
-    for (int c = 0; c < 2; ++c) {
-        dfree(wh->hist[c]);
-        dfree(wh->pend[c]);
-    }
-    dfree(wh->y);
-    dfree(wh->pw);
-}
-
-}  // namespace
+}  // namespace host
+}  // namespace spiir
 
 extern "C" {
 
@@ -1811,596 +1572,6 @@ int spiir_autotune(int32_t nbk, const int32_t *T, const int64_t *const *off, con
 }
 
 const char *spiir_last_error(void) { return g_err.c_str(); }
-
-namespace {
-
-constexpr int64_t kMaxClusterN = (int64_t)1 << 40;
-
-// gfx950 check of a device, cached per ordinal for the process.
-int cluster_device(int32_t device, int &dev) {
-    static std::mutex mu;
-    static std::map<int, int> checked;
-    dev = device;
-    if (dev < 0) {
-        int count = 0;
-        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
-            return fail(SPIIR_ENODEV, "no HIP device available");
-        HIPCHK(hipGetDevice(&dev));
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = checked.find(dev);
-    if (it != checked.end()) return it->second;
-    DeviceFacts df;
-    const int rc = device_facts(dev, df);
-    if (rc != SPIIR_ENODEV) checked[dev] = rc;
-    return rc;
-}
-
-}  // namespace
-
-}  // extern "C"
-
-// Streaming trigger clustering: a window of the series, [base, base + len),
-// holds the samples whose triggers are not final yet plus W samples before
-// them; each push appends a block, clusters the window with candidates
-// limited to the newly final samples [final_end, total - W) and keeps the
-// last W samples before the new final_end (ping-pong buffers).
-struct spiir_trigger_stream {
-    int device = 0;
-    float thr = 0.0f;
-    int64_t W = 0, B = 0;
-    float *wm[2] = {nullptr, nullptr};
-    int32_t *wj[2] = {nullptr, nullptr};
-    int cur = 0;
-    int64_t base = 0, len = 0, total = 0, final_end = 0;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-};
-
-namespace {
-
-void ts_free(spiir_trigger_stream *ts) {
-    for (int c = 0; c < 2; ++c) {
-        dfree(ts->wm[c]);
-        dfree(ts->wj[c]);
-    }
-    if (ts->ws) (void)hipFree(ts->ws);
-    ts->ws = nullptr;
-}
-
-// Clusters the window with candidates [final_end, new_end) and slides it.
-int ts_step(spiir_trigger_stream *ts, int64_t new_end, int64_t *idx, int32_t *tpl, float *val, int64_t cap,
-            int64_t *count, hipStream_t st) {
-    const int c = ts->cur;
-    HIPCHK(launch_cluster(ts->wm[c], ts->wj[c], ts->len, ts->thr, ts->W, ts->ws, cap, idx, tpl, val, count, st,
-                          ts->final_end - ts->base, new_end - ts->base, ts->base));
-    ts->final_end = new_end;
-    const int64_t keep_from = std::max(ts->base, ts->final_end - ts->W) - ts->base;
-    const int64_t keep = ts->len - keep_from;
-    if (keep > 0) {
-        HIPCHK(hipMemcpyAsync(ts->wm[c ^ 1], ts->wm[c] + keep_from, (size_t)keep * sizeof(float),
-                              hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ts->wj[c ^ 1], ts->wj[c] + keep_from, (size_t)keep * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, st));
-    }
-    ts->cur ^= 1;
-    ts->base += keep_from;
-    ts->len = keep;
-    return SPIIR_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int spiir_trigger_stream_create(spiir_trigger_stream **out, float threshold, int32_t window, int64_t max_block,
-                                int32_t device) {
-    if (!out) return fail(SPIIR_EINVAL, "out is null");
-    *out = nullptr;
-    if (window < 0) return fail(SPIIR_EINVAL, "window must be >= 0 (got %d)", window);
-    if (max_block < 1 || max_block > ((int64_t)1 << 32))
-        return fail(SPIIR_EINVAL, "max_block must be in [1, 2^32] (got %lld)", (long long)max_block);
-    int dev = 0;
-    int rc = cluster_device(device, dev);
-    if (rc) return rc;
-    DeviceGuard guard(dev);
-    spiir_trigger_stream *ts = new (std::nothrow) spiir_trigger_stream();
-    if (!ts) return fail(SPIIR_ENOMEM, "out of host memory");
-    ts->device = dev;
-    ts->thr = threshold;
-    ts->W = window;
-    ts->B = max_block;
-    const int64_t cap = 2 * (int64_t)window + max_block;   // the window never holds more
-    ts->ws_bytes = cluster_workspace_bytes(cap);
-    hipError_t e = hipSuccess;
-    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-        e = dalloc(&ts->wm[c], (size_t)cap);
-        if (e == hipSuccess) e = dalloc(&ts->wj[c], (size_t)cap);
-    }
-    if (e == hipSuccess) e = hipMalloc(&ts->ws, std::max<size_t>(256, ts->ws_bytes));
-    if (e != hipSuccess) {
-        ts_free(ts);
-        delete ts;
-        return fail(SPIIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
-    }
-    *out = ts;
-    return SPIIR_OK;
-}
-
-int spiir_trigger_stream_destroy(spiir_trigger_stream *ts) {
-    if (!ts) return SPIIR_OK;
-    {
-        DeviceGuard guard(ts->device);
-        (void)hipDeviceSynchronize();
-        ts_free(ts);
-    }
-    delete ts;
-    return SPIIR_OK;
-}
-
-int spiir_trigger_stream_reset(spiir_trigger_stream *ts, void *stream) {
-    if (!ts) return fail(SPIIR_EINVAL, "trigger stream is null");
-    (void)stream;   // no device state to clear: the window is rebuilt from the next push
-    ts->cur = 0;
-    ts->base = ts->len = ts->total = ts->final_end = 0;
-    return SPIIR_OK;
-}
-
-static int ts_check_out(int64_t *idx, int32_t *tpl, float *val, int64_t cap, int64_t *count) {
-    if (!count) return fail(SPIIR_EINVAL, "count_dev is null");
-    if (cap < 0) return fail(SPIIR_EINVAL, "capacity must be >= 0");
-    if (cap > 0 && (!idx || !tpl || !val)) return fail(SPIIR_EINVAL, "null output array with capacity %lld",
-                                                     (long long)cap);
-    return SPIIR_OK;
-}
-
-int spiir_trigger_stream_push(spiir_trigger_stream *ts, const float *max_dev, const int32_t *argmax_dev, int64_t n,
-                              int64_t *index_dev, int32_t *template_dev, float *snr_dev, int64_t capacity,
-                              int64_t *count_dev, void *stream) {
-    if (!ts) return fail(SPIIR_EINVAL, "trigger stream is null");
-    int rc = ts_check_out(index_dev, template_dev, snr_dev, capacity, count_dev);
-    if (rc) return rc;
-    if (n < 0 || n > ts->B) return fail(SPIIR_EINVAL, "n must be in [0, max_block = %lld] (got %lld)",
-                                        (long long)ts->B, (long long)n);
-    if (n > 0 && (!max_dev || !argmax_dev)) return fail(SPIIR_EINVAL, "null max / argmax block");
-    DeviceGuard guard(ts->device);
-    hipStream_t st = as_stream(stream);
-    const int c = ts->cur;
-    if (n > 0) {
-        HIPCHK(hipMemcpyAsync(ts->wm[c] + ts->len, max_dev, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ts->wj[c] + ts->len, argmax_dev, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                              st));
-    }
-    ts->len += n;
-    ts->total += n;
-    const int64_t new_end = std::max(ts->final_end, ts->total - ts->W);
-    return ts_step(ts, new_end, index_dev, template_dev, snr_dev, capacity, count_dev, st);
-}
-
-int spiir_trigger_stream_flush(spiir_trigger_stream *ts, int64_t *index_dev, int32_t *template_dev, float *snr_dev,
-                               int64_t capacity, int64_t *count_dev, void *stream) {
-    if (!ts) return fail(SPIIR_EINVAL, "trigger stream is null");
-    int rc = ts_check_out(index_dev, template_dev, snr_dev, capacity, count_dev);
-    if (rc) return rc;
-    DeviceGuard guard(ts->device);
-    return ts_step(ts, ts->total, index_dev, template_dev, snr_dev, capacity, count_dev, as_stream(stream));
-}
-
-int spiir_cluster_workspace_size(int64_t n, size_t *nbytes) {
-    if (!nbytes) return fail(SPIIR_EINVAL, "null argument");
-    if (n < 0 || n > kMaxClusterN) return fail(SPIIR_EINVAL, "n must be in [0, 2^40] (got %lld)", (long long)n);
-    *nbytes = cluster_workspace_bytes(n);
-    return SPIIR_OK;
-}
-
-int spiir_cluster_triggers(const float *max_dev, const int32_t *argmax_dev, int64_t n, float threshold,
-                           int32_t window, void *workspace_dev, size_t workspace_bytes, int64_t *index_dev,
-                           int32_t *template_dev, float *snr_dev, int64_t capacity, int64_t *count_dev,
-                           int32_t device, void *stream) {
-    if (!count_dev) return fail(SPIIR_EINVAL, "count_dev is null");
-    if (n < 0 || n > kMaxClusterN) return fail(SPIIR_EINVAL, "n must be in [0, 2^40] (got %lld)", (long long)n);
-    if (window < 0) return fail(SPIIR_EINVAL, "window must be >= 0 (got %d)", window);
-    if (capacity < 0) return fail(SPIIR_EINVAL, "capacity must be >= 0");
-    if (capacity > 0 && (!index_dev || !template_dev || !snr_dev))
-        return fail(SPIIR_EINVAL, "null output array with capacity %lld", (long long)capacity);
-    if (n > 0) {
-        if (!max_dev || !argmax_dev) return fail(SPIIR_EINVAL, "null max / argmax series");
-        if (!workspace_dev) return fail(SPIIR_EINVAL, "null workspace");
-        const size_t need = cluster_workspace_bytes(n);
-        if (workspace_bytes < need)
-            return fail(SPIIR_EINVAL, "workspace of %zu bytes is below the %zu bytes needed for n = %lld",
-                        workspace_bytes, need, (long long)n);
-    }
-    int dev = 0;
-    const int rc = cluster_device(device, dev);
-    if (rc) return rc;
-    DeviceGuard guard(dev);
-    HIPCHK(launch_cluster(max_dev, argmax_dev, n, threshold, window, workspace_dev, capacity, index_dev,
-                          template_dev, snr_dev, count_dev, static_cast<hipStream_t>(stream)));
-    return SPIIR_OK;
-}
-
-int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_templates,
-                           const int64_t *const *filter_offsets, const double *const *a, const double *const *b,
-                           const int32_t *const *d, const double *decim_taps, int32_t n_decim_taps,
-                           const double *interp_taps, int32_t n_interp_taps, const spiir_bank_opts *opts) {
-    if (!out) return fail(SPIIR_EINVAL, "out is null");
-    *out = nullptr;
-    if (n_levels < 1 || n_levels > 8) return fail(SPIIR_EINVAL, "n_levels must be 1..8 (got %d)", n_levels);
-    const int T = n_templates;
-    if (T < 1) return fail(SPIIR_EINVAL, "n_templates must be >= 1 (got %d)", T);
-    if (!filter_offsets || !a || !b || !d) return fail(SPIIR_EINVAL, "null per-level array");
-    if (!decim_taps || !interp_taps) return fail(SPIIR_EINVAL, "null taps");
-    if (n_decim_taps < 1 || n_decim_taps > 64 || n_interp_taps < 1 || n_interp_taps > 64)
-        return fail(SPIIR_EINVAL, "taps: counts must be 1..64 (got %d, %d)", n_decim_taps, n_interp_taps);
-    for (int i = 0; i < n_decim_taps; ++i)
-        if (!std::isfinite(decim_taps[i])) return fail(SPIIR_EINVAL, "non-finite decimation tap");
-    for (int i = 0; i < n_interp_taps; ++i)
-        if (!std::isfinite(interp_taps[i])) return fail(SPIIR_EINVAL, "non-finite interpolation tap");
-    const int R = n_levels - 1;
-    int top = -1;
-    for (int r = 0; r <= R; ++r) {
-        const int64_t *off = filter_offsets[r];
-        if (!off) return fail(SPIIR_EINVAL, "level %d: null filter_offsets", r);
-        if (off[0] != 0) return fail(SPIIR_EINVAL, "level %d: filter_offsets[0] must be 0", r);
-        for (int j = 0; j < T; ++j)
-            if (off[j + 1] < off[j]) return fail(SPIIR_EINVAL, "level %d: filter_offsets decrease at %d", r, j);
-        if (off[T] > 0) {
-            if (!a[r] || !b[r] || !d[r]) return fail(SPIIR_EINVAL, "level %d: null coefficient / delay array", r);
-            top = r;
-        }
-    }
-    if (top < 0) return fail(SPIIR_EINVAL, "no level holds a filter");
-    spiir_bank_opts o;
-    spiir_bank_opts_default(&o);
-    if (opts) o = *opts;
-    if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
-    int64_t B = o.max_block ? o.max_block : 16384;
-    B = std::max<int64_t>((B >> R) << R, (int64_t)1 << R);
-    // interpolation launches one workgroup per (template, 1,024 outputs)
-    if (((B + 1023) / 1024) * (int64_t)T > INT32_MAX)
-        return fail(SPIIR_EINVAL, "n_templates x max_block too large (%d x %lld)", T, (long long)B);
-    int dev = o.device;
-    if (dev < 0) {
-        int count = 0;
-        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SPIIR_ENODEV, "no HIP device available");
-        HIPCHK(hipGetDevice(&dev));
-    }
-    DeviceFacts df;
-    int rc = device_facts(dev, df);
-    if (rc) return rc;
-    DeviceGuard guard(dev);
-
-    spiir_multirate *mr = new (std::nothrow) spiir_multirate();
-    if (!mr) return fail(SPIIR_ENOMEM, "out of host memory");
-    mr->device = dev;
-    mr->T = T;
-    mr->R = R;
-    mr->top = top;
-    mr->lh = n_decim_taps;
-    mr->lg = n_interp_taps;
-    mr->hh = n_interp_taps / 2;
-    mr->B = B;
-    mr->bank.assign(R + 1, nullptr);
-    mr->zrow.assign(R + 1, nullptr);
-    mr->xbuf.assign(R + 1, nullptr);
-    mr->z.assign(R + 1, nullptr);
-    mr->w.assign(R + 1, nullptr);
-    for (int c = 0; c < 2; ++c) {
-        mr->dh[c].assign(R + 1, nullptr);
-        mr->wh[c].assign(R + 1, nullptr);
-    }
-    auto bail = [&](int code) {
-        (void)hipDeviceSynchronize();
-        mr_free(mr);
-        delete mr;
-        return code;
-    };
-    auto alloc_fail = [&](hipError_t e) {
-        const int code = fail(SPIIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
-        return bail(code);
-    };
-    auto hip_fail = [&](hipError_t e, const char *what) {
-        const int code = fail(SPIIR_EHIP, "%s: %s", what, hipGetErrorString(e));
-        return bail(code);
-    };
-    for (int r = 0; r <= R; ++r) {
-        const int64_t *off = filter_offsets[r];
-        std::vector<int32_t> row(T, -1);
-        std::vector<int64_t> offc(1, 0);
-        for (int j = 0; j < T; ++j)
-            if (off[j + 1] > off[j]) {
-                row[j] = (int32_t)(offc.size() - 1);
-                offc.push_back(off[j + 1]);
-            }
-        hipError_t e = dalloc(&mr->zrow[r], (size_t)T);
-        if (e != hipSuccess) return alloc_fail(e);
-        e = hipMemcpy(mr->zrow[r], row.data(), T * sizeof(int32_t), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "row map upload");
-        if (off[T] == 0) continue;
-        spiir_bank_opts orr = o;
-        orr.device = dev;
-        orr.max_block = (int32_t)std::max<int64_t>(8, B >> r);
-        // a level whose filters leave most of the device idle is a short serial
-        // recursion per call: let the automatic time split cut it into up to 32
-        // segments, with 64-sample chunks so that segments can be that short
-        const bool small = o.time_split == 0 && off[T] <= 128 * (int64_t)df.n_cu;
-        if (small) orr.chunk_len = 64;
-        spiir_bank *bk = nullptr;
-        rc = orr.autotune ? spiir_bank_create(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], &orr)
-                          : create_bank(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], orr,
-                                        small ? 32 : 8);
-        if (rc) {
-            g_err = "level " + std::to_string(r) + ": " + g_err;
-            return bail(rc);
-        }
-        mr->bank[r] = bk;
-        e = dalloc(&mr->z[r], (size_t)(offc.size() - 1) * (size_t)(B >> r));
-        if (e != hipSuccess) return alloc_fail(e);
-    }
-    for (int r = 1; r <= top; ++r) {
-        hipError_t e = dalloc(&mr->xbuf[r], (size_t)(B >> r));
-        for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-            e = dalloc(&mr->dh[c][r], (size_t)std::max(1, mr->lh - 1));
-            if (e == hipSuccess) e = dalloc(&mr->wh[c][r], (size_t)T * std::max(1, mr->hh));
-        }
-        if (e == hipSuccess && r < top) e = dalloc(&mr->w[r], (size_t)T * (size_t)(B >> r));
-        if (e != hipSuccess) return alloc_fail(e);
-    }
-    {
-        hipError_t e = dalloc(&mr->w0, (size_t)T * (size_t)B);
-        if (e == hipSuccess) e = dalloc(&mr->keys, (size_t)mr_key_chunks(T) * (size_t)B);
-        if (e == hipSuccess) e = dalloc(&mr->h, (size_t)mr->lh);
-        if (e == hipSuccess) e = dalloc(&mr->g, (size_t)mr->lg);
-        if (e != hipSuccess) return alloc_fail(e);
-    }
-    mr->lstream.assign(R + 1, nullptr);
-    mr->ldone.assign(R + 1, nullptr);
-    {
-        hipError_t e = hipEventCreateWithFlags(&mr->fork, hipEventDisableTiming);
-        for (int r = 0; r <= R && e == hipSuccess; ++r)
-            if (mr->bank[r]) {
-                e = hipStreamCreateWithFlags(&mr->lstream[r], hipStreamNonBlocking);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&mr->ldone[r], hipEventDisableTiming);
-            }
-        if (e != hipSuccess) return hip_fail(e, "level streams");
-    }
-    std::vector<float> hf(decim_taps, decim_taps + mr->lh), gf(interp_taps, interp_taps + mr->lg);
-    hipError_t e = hipMemcpy(mr->h, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(mr->g, gf.data(), gf.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "taps upload");
-    rc = mr_clear_history(mr, nullptr);
-    if (rc) return bail(rc);
-    e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "multi-rate bank set-up");
-    *out = mr;
-    return SPIIR_OK;
-}
-
-int spiir_multirate_destroy(spiir_multirate *mr) {
-    if (!mr) return SPIIR_OK;
-    {
-        DeviceGuard guard(mr->device);
-        (void)hipDeviceSynchronize();
-        mr_free(mr);
-    }
-    delete mr;
-    return SPIIR_OK;
-}
-
-int spiir_multirate_reset(spiir_multirate *mr, void *stream) {
-    if (!mr) return fail(SPIIR_EINVAL, "multi-rate bank is null");
-    DeviceGuard guard(mr->device);
-    for (auto *bk : mr->bank)
-        if (bk) {
-            const int rc = spiir_bank_reset(bk, stream);
-            if (rc) return rc;
-            // every piece toggles the object's parity and each level bank's history
-            // index together, so they stay equal; the captured graphs rely on it
-            bk->hist_cur = 0;
-        }
-    return mr_clear_history(mr, as_stream(stream));   // sets mr->cur = 0
-}
-
-static int mr_check_call(const spiir_multirate *mr, const float *x, int64_t n) {
-    if (!mr) return fail(SPIIR_EINVAL, "multi-rate bank is null");
-    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
-    if (n % ((int64_t)1 << mr->R))
-        return fail(SPIIR_EINVAL, "n (%lld) must be a multiple of 2^%d", (long long)n, mr->R);
-    if (n > 0 && !x) return fail(SPIIR_EINVAL, "null device pointer");
-    return SPIIR_OK;
-}
-
-int spiir_multirate_filter_block_z(spiir_multirate *mr, const float *x, int64_t n, float *z, int64_t ld,
-                                   void *stream) {
-    int rc = mr_check_call(mr, x, n);
-    if (rc || n == 0) return rc;
-    if (!z) return fail(SPIIR_EINVAL, "null device pointer");
-    if (ld < n) return fail(SPIIR_EINVAL, "ld_z (%lld) < n (%lld)", (long long)ld, (long long)n);
-    return mr_run(mr, x, n, reinterpret_cast<float2 *>(z), ld, nullptr, nullptr, as_stream(stream));
-}
-
-int spiir_multirate_trigger_max(spiir_multirate *mr, const float *x, int64_t n, float *mx, int32_t *am,
-                                void *stream) {
-    int rc = mr_check_call(mr, x, n);
-    if (rc || n == 0) return rc;
-    if (!mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
-    return mr_run(mr, x, n, nullptr, 0, mx, am, as_stream(stream));
-}
-
-int spiir_multirate_set_graph(spiir_multirate *mr, int32_t enable) {
-    if (!mr) return fail(SPIIR_EINVAL, "multi-rate bank is null");
-    mr->use_graph = enable != 0;
-    return SPIIR_OK;
-}
-
-int spiir_multirate_level_bank(spiir_multirate *mr, int32_t level, spiir_bank **bank) {
-    if (!mr || !bank) return fail(SPIIR_EINVAL, "null argument");
-    if (level < 0 || level > mr->R) return fail(SPIIR_EINVAL, "level %d out of range 0..%d", level, mr->R);
-    *bank = mr->bank[level];
-    return SPIIR_OK;
-}
-
-int spiir_whitener_create(spiir_whitener **out, int32_t frame_len, int32_t max_block, int32_t device) {
-    if (!out) return fail(SPIIR_EINVAL, "out is null");
-    *out = nullptr;
-    int logn = 0;
-    while ((1 << logn) < frame_len) ++logn;
-    if (frame_len < 16 || frame_len > 8192 || (1 << logn) != frame_len)
-        return fail(SPIIR_EINVAL, "frame_len must be a power of two in [16, 8192] (got %d)", frame_len);
-    if (max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
-    const int H = frame_len / 2;
-    int64_t B = max_block ? max_block : 65536;
-    B = std::max<int64_t>(H, B / H * H);
-    int dev = device;
-    if (dev < 0) {
-        int count = 0;
-        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SPIIR_ENODEV, "no HIP device available");
-        HIPCHK(hipGetDevice(&dev));
-    }
-    DeviceFacts df;
-    int rc = device_facts(dev, df);
-    if (rc) return rc;
-    DeviceGuard guard(dev);
-    spiir_whitener *wh = new (std::nothrow) spiir_whitener();
-    if (!wh) return fail(SPIIR_ENOMEM, "out of host memory");
-    wh->device = dev;
-    wh->N = frame_len;
-    wh->logN = logn;
-    wh->H = H;
-    wh->B = B;
-    auto bail = [&](int code) {
-        (void)hipDeviceSynchronize();
-        wh_free(wh);
-        delete wh;
-        return code;
-    };
-    hipError_t e = dalloc(&wh->wtab, (size_t)frame_len);
-    if (e == hipSuccess) e = dalloc(&wh->tw, (size_t)H);
-    if (e == hipSuccess) e = dalloc(&wh->S, (size_t)H + 1);
-    if (e == hipSuccess) e = dalloc(&wh->inv, (size_t)H + 1);
-    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-        e = dalloc(&wh->hist[c], (size_t)H);
-        if (e == hipSuccess) e = dalloc(&wh->pend[c], (size_t)H);
-    }
-    if (e == hipSuccess) e = dalloc(&wh->y, (size_t)(B / H) * (size_t)frame_len);
-    if (e != hipSuccess) return bail(fail(SPIIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
-    std::vector<float> w(frame_len);
-    std::vector<float2> tw(H);
-    double ws = 0.0;
-    for (int t = 0; t < frame_len; ++t) {
-        const double s1 = std::sin(M_PI * t / frame_len);
-        w[t] = (float)(s1 * s1);
-        ws += (s1 * s1) * (s1 * s1);
-    }
-    for (int k = 0; k < H; ++k) {
-        const double ang = -2.0 * M_PI * k / frame_len;
-        tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    wh->wsum2 = ws;
-    e = hipMemcpy(wh->wtab, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(wh->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return bail(fail(SPIIR_EHIP, "window upload: %s", hipGetErrorString(e)));
-    for (int c = 0; c < 2; ++c) {
-        if (launch_fill_zero(wh->hist[c], (size_t)H * sizeof(float), nullptr) != hipSuccess ||
-            launch_fill_zero(wh->pend[c], (size_t)H * sizeof(float), nullptr) != hipSuccess)
-            return bail(fail(SPIIR_EHIP, "history clear failed"));
-    }
-    e = hipDeviceSynchronize();
-    if (e != hipSuccess) return bail(fail(SPIIR_EHIP, "whitener set-up: %s", hipGetErrorString(e)));
-    *out = wh;
-    return SPIIR_OK;
-}
-
-int spiir_whitener_destroy(spiir_whitener *wh) {
-    if (!wh) return SPIIR_OK;
-    {
-        DeviceGuard guard(wh->device);
-        (void)hipDeviceSynchronize();
-        wh_free(wh);
-    }
-    delete wh;
-    return SPIIR_OK;
-}
-
-int spiir_whitener_estimate_psd(spiir_whitener *wh, const float *train, int64_t n, void *stream) {
-    if (!wh) return fail(SPIIR_EINVAL, "whitener is null");
-    if (!train) return fail(SPIIR_EINVAL, "null device pointer");
-    if (n < wh->N) return fail(SPIIR_EINVAL, "training stretch of %lld samples is shorter than a frame (%d)",
-                               (long long)n, wh->N);
-    DeviceGuard guard(wh->device);
-    hipStream_t st = as_stream(stream);
-    const int64_t K = (n - wh->N) / wh->H + 1;
-    if (K > INT32_MAX) return fail(SPIIR_EINVAL, "training stretch of %lld frames is too long", (long long)K);
-    if (K > wh->pw_frames) {
-        HIPCHK(hipStreamSynchronize(st));
-        dfree(wh->pw);
-        wh->pw_frames = 0;
-        hipError_t e = dalloc(&wh->pw, (size_t)K * (size_t)(wh->H + 1));
-        if (e != hipSuccess) return fail(SPIIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
-        wh->pw_frames = K;
-    }
-    HIPCHK(launch_wh_frames(true, nullptr, 0, train, wh->wtab, wh->tw, wh->N, wh->logN, nullptr, nullptr, wh->pw, K,
-                            st));
-    HIPCHK(launch_wh_psd_reduce(wh->pw, K, wh->H, wh->wsum2, wh->S, wh->inv, st));
-    wh->has_psd = true;
-    return SPIIR_OK;
-}
-
-int spiir_whitener_set_psd(spiir_whitener *wh, const double *psd) {
-    if (!wh || !psd) return fail(SPIIR_EINVAL, "null argument");
-    for (int f = 0; f <= wh->H; ++f)
-        if (!std::isfinite(psd[f]) || psd[f] < 0.0) return fail(SPIIR_EINVAL, "psd[%d] is negative or not finite", f);
-    DeviceGuard guard(wh->device);
-    HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(wh->S, psd, (size_t)(wh->H + 1) * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(launch_wh_inv(wh->S, wh->H, wh->inv, nullptr));
-    HIPCHK(hipDeviceSynchronize());
-    wh->has_psd = true;
-    return SPIIR_OK;
-}
-
-int spiir_whitener_get_psd(spiir_whitener *wh, double *psd) {
-    if (!wh || !psd) return fail(SPIIR_EINVAL, "null argument");
-    if (!wh->has_psd) return fail(SPIIR_ESTATE, "no PSD set or estimated");
-    DeviceGuard guard(wh->device);
-    HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(psd, wh->S, (size_t)(wh->H + 1) * sizeof(double), hipMemcpyDeviceToHost));
-    return SPIIR_OK;
-}
-
-int spiir_whitener_reset(spiir_whitener *wh, void *stream) {
-    if (!wh) return fail(SPIIR_EINVAL, "whitener is null");
-    DeviceGuard guard(wh->device);
-    hipStream_t st = as_stream(stream);
-    for (int c = 0; c < 2; ++c) {
-        HIPCHK(launch_fill_zero(wh->hist[c], (size_t)wh->H * sizeof(float), st));
-        HIPCHK(launch_fill_zero(wh->pend[c], (size_t)wh->H * sizeof(float), st));
-    }
-    wh->cur = 0;
-    return SPIIR_OK;
-}
-
-int spiir_whitener_process(spiir_whitener *wh, const float *x, int64_t n, float *out, void *stream) {
-    if (!wh) return fail(SPIIR_EINVAL, "whitener is null");
-    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
-    if (n % wh->H) return fail(SPIIR_EINVAL, "n (%lld) must be a multiple of half the frame (%d)", (long long)n, wh->H);
-    if (!wh->has_psd) return fail(SPIIR_ESTATE, "no PSD set or estimated");
-    if (n == 0) return SPIIR_OK;
-    if (!x || !out) return fail(SPIIR_EINVAL, "null device pointer");
-    DeviceGuard guard(wh->device);
-    hipStream_t st = as_stream(stream);
-    for (int64_t P = 0; P < n; P += wh->B) {
-        const int64_t np = std::min<int64_t>(wh->B, n - P);
-        const int64_t nf = np / wh->H;
-        const int c = wh->cur;
-        HIPCHK(launch_wh_frames(false, wh->hist[c], wh->H, x + P, wh->wtab, wh->tw, wh->N, wh->logN, wh->inv, wh->y,
-                                nullptr, nf, st));
-        HIPCHK(launch_wh_ola(wh->y, nf, wh->N, wh->pend[c], wh->pend[c ^ 1], x + P, np, wh->hist[c ^ 1], out + P, st));
-        wh->cur ^= 1;
-    }
-    return SPIIR_OK;
-}
 
 const char *spiir_version(void) { return "spiir-mi355x 0.1.0 (gfx950)"; }
 
