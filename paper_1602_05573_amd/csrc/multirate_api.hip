@@ -32,8 +32,7 @@ struct spiir_multirate {
     // the level banks run concurrently: each on its own stream, forked from the
     // caller's stream after the decimation and joined before the interpolation
     std::vector<hipStream_t> lstream;
-    std::vector<hipEvent_t> ldone;
-    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> lfork, ldone;
     // trigger calls in pieces of exactly B samples replay a captured graph of
     // the whole piece (one per history parity): the block is copied into xin,
     // the max / argmax out of mxo / amo
@@ -67,10 +66,11 @@ void mr_free(spiir_multirate *mr) {
         if (s) (void)hipStreamDestroy(s);
     for (auto e : mr->ldone)
         if (e) (void)hipEventDestroy(e);
-    if (mr->fork) (void)hipEventDestroy(mr->fork);
+    for (auto e : mr->lfork)
+        if (e) (void)hipEventDestroy(e);
     mr->lstream.clear();
     mr->ldone.clear();
-    mr->fork = nullptr;
+    mr->lfork.clear();
     for (auto *bk : mr->bank)
         if (bk) spiir_bank_destroy(bk);
     for (auto *p : mr->zrow) dfree(p);
@@ -104,23 +104,26 @@ int mr_piece(spiir_multirate *mr, const float *x0, int64_t np, float2 *out0, int
              hipStream_t st) {
     const int top = mr->top;
     const int c = mr->cur;
-    std::vector<const float *> xs(top + 1);
-    xs[0] = x0;
-    for (int r = 1; r <= top; ++r) {
-        HIPCHK(launch_mr_decimate(xs[r - 1], np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh,
-                                  mr->xbuf[r], st));
-        xs[r] = mr->xbuf[r];
-    }
-    HIPCHK(hipEventRecord(mr->fork, st));
-    for (int r = top; r >= 0; --r)   // the top level holds the most filters: start it first
-        if (mr->bank[r]) {
-            HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->fork, 0));
-            const int rc = bank_stream_z(mr->bank[r], xs[r], np >> r, reinterpret_cast<float *>(mr->z[r]), mr->B >> r,
-                                        mr->lstream[r]);
-            if (rc) return rc;
-            HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
-            HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
+    // each level's bank is forked onto its stream as soon as its input exists
+    // (level 0 at once, level r after r decimations); the joins come after
+    // the whole decimation chain has been enqueued
+    const float *xr = x0;
+    for (int r = 0; r <= top; ++r) {
+        if (r > 0) {
+            HIPCHK(launch_mr_decimate(xr, np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh, mr->xbuf[r],
+                                      st));
+            xr = mr->xbuf[r];
         }
+        if (!mr->bank[r]) continue;
+        HIPCHK(hipEventRecord(mr->lfork[r], st));
+        HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->lfork[r], 0));
+        const int rc = bank_stream_z(mr->bank[r], xr, np >> r, reinterpret_cast<float *>(mr->z[r]), mr->B >> r,
+                                     mr->lstream[r]);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
+    }
+    for (int r = 0; r <= top; ++r)
+        if (mr->bank[r]) HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
     if (!out0) {
         out0 = mr->w0;
         ld0 = mr->B;
@@ -371,12 +374,14 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         if (e != hipSuccess) return alloc_fail(e);
     }
     mr->lstream.assign(R + 1, nullptr);
+    mr->lfork.assign(R + 1, nullptr);
     mr->ldone.assign(R + 1, nullptr);
     {
-        hipError_t e = hipEventCreateWithFlags(&mr->fork, hipEventDisableTiming);
+        hipError_t e = hipSuccess;
         for (int r = 0; r <= R && e == hipSuccess; ++r)
             if (mr->bank[r]) {
                 e = hipStreamCreateWithFlags(&mr->lstream[r], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&mr->lfork[r], hipEventDisableTiming);
                 if (e == hipSuccess) e = hipEventCreateWithFlags(&mr->ldone[r], hipEventDisableTiming);
             }
         if (e != hipSuccess) return hip_fail(e, "level streams");
