@@ -287,7 +287,8 @@ def test_single_filter_templates_and_zero_delay():
     assert err <= SNR_TOL
 
 
-@pytest.mark.parametrize("nseg,max_block,L", [(2, 4096, 256), (4, 2048, 128), (8, 16384, 64), (3, 5000, 8)])
+@pytest.mark.parametrize("nseg,max_block,L", [(2, 4096, 256), (4, 2048, 128), (8, 16384, 64), (3, 5000, 8),
+                                             (16, 8192, 64), (32, 16384, 64), (32, 4096, 256)])
 def test_time_split_parity(mid, nseg, max_block, L):
     """Launches cut into segments filtered in parallel, joined by the FP64 carry
     chain: SNR rows and the fused max against the oracle, over several calls."""
