@@ -708,10 +708,14 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
                                         bk->slot_filter, st, ev));
         else
             HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev));
+        // the last key finalisation of a call also writes the next history
+        const bool last = P + np >= n;
+        const HistCopy hc{hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax};
         if (mode == kModeKeys)
-            HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st));
+            HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st,
+                                        last ? &hc : nullptr));
     }
-    HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
+    if (mode != kModeKeys || n <= 0) HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
     bk->hist_cur ^= 1;
     return SPIIR_OK;
 }

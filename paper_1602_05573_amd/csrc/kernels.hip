@@ -592,6 +592,39 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     fwd_group<FL, TT, MODE, false, true>(p, g, smem, sc);
 }
 
+// Carries of one slot across the segments of a launch: c holds the true end
+// state of segment 0 on entry; for k >= 1 the true start of segment k is c,
+// then c <- a^{len_k} c + e_k (e_k = segment k's end state from rest), in
+// FP64. Full segments share one a^{seg_len}; the segment-end reads are issued
+// eight at a time ahead of the dependent chain.
+__device__ __forceinline__ void chain_segments(const float4 *seg_end, float4 *seg_start, int64_t nslots, int64_t sl,
+                                               double2 a, int nseg, int64_t seg_len, int64_t n, double &cr,
+                                               double &ci) {
+    const double2 a_full = cpow64(a, (int)seg_len);
+    for (int k0 = 1; k0 < nseg; k0 += 8) {
+        float4 eb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < nseg) eb[u] = seg_end[(int64_t)(k0 + u) * nslots + sl];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            if (k >= nseg) break;
+            const float hr = (float)cr, hi = (float)ci;
+            seg_start[(int64_t)k * nslots + sl] =
+                make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+            const int64_t len = min(seg_len, n - (int64_t)k * seg_len);
+            const double2 al = len == seg_len ? a_full : cpow64(a, (int)len);
+            const float4 e = eb[u];
+            const double er = (double)e.x + (double)e.z, ei = (double)e.y + (double)e.w;
+            const double nr = al.x * cr - al.y * ci + er;
+            const double ni = al.x * ci + al.y * cr + ei;
+            cr = nr;
+            ci = ni;
+        }
+    }
+}
+
 // Time split, carry chain: c_{s+1} = a^len_s c_s + e_s in FP64 per slot, from
 // the true end of segment 0; writes every segment's true start state and the
 // launch's final state.
@@ -607,18 +640,7 @@ __global__ void seg_chain_kernel(const float4 *seg_end, float4 *seg_start, float
         const float2 r = a32[sl];
         a = make_double2((double)r.x, (double)r.y);
     }
-    for (int k = 1; k < nseg; ++k) {
-        const float hr = (float)cr, hi = (float)ci;
-        seg_start[(int64_t)k * nslots + sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
-        const int len = (int)min(seg_len, n - (int64_t)k * seg_len);
-        const double2 al = cpow64(a, len);
-        const float4 e = seg_end[(int64_t)k * nslots + sl];
-        const double er = (double)e.x + (double)e.z, ei = (double)e.y + (double)e.w;
-        const double nr = al.x * cr - al.y * ci + er;
-        const double ni = al.x * ci + al.y * cr + ei;
-        cr = nr;
-        ci = ni;
-    }
+    chain_segments(seg_end, seg_start, nslots, sl, a, nseg, seg_len, n, cr, ci);
     const float hr = (float)cr, hi = (float)ci;
     state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
 }
@@ -734,26 +756,27 @@ __global__ void __launch_bounds__(256) batch_chain_kernel(const BatchStream *str
         const float2 r = a.s.a32[sl];
         av = make_double2((double)r.x, (double)r.y);
     }
-    for (int k = 1; k < nv; ++k) {
-        const float hr = (float)cr, hi = (float)ci;
-        a.seg_start[(int64_t)k * a.nslots + sl] =
-            make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
-        const int ln = (int)min(a.seg_len, n - (int64_t)k * a.seg_len);
-        const double2 al = cpow64(av, ln);
-        const float4 e = a.seg_end[(int64_t)k * a.nslots + sl];
-        const double er = (double)e.x + (double)e.z, ei = (double)e.y + (double)e.w;
-        const double nr = al.x * cr - al.y * ci + er;
-        const double ni = al.x * ci + al.y * cr + ei;
-        cr = nr;
-        ci = ni;
-    }
+    chain_segments(a.seg_end, a.seg_start, a.nslots, sl, av, nv, a.seg_len, n, cr, ci);
     const float hr = (float)cr, hi = (float)ci;
     a.state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
 }
 
+__device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
+    const int64_t m = hc.n - hc.dmax + i;
+    hc.new_h[i] = m >= 0 ? hc.x[m] : hc.old_h[hc.dmax + m];
+}
+
 // Max over workgroup partial keys: 16 samples x 16 group slices per block.
+// Blocks from key_blocks on write the history copy (hc.new_h set), 256
+// samples each.
 __global__ void __launch_bounds__(256) finalize_keys_kernel(const uint64_t *keys, int groups, int64_t ld,
-                                                            int64_t n, float *mx, int32_t *am) {
+                                                            int64_t n, float *mx, int32_t *am, HistCopy hc,
+                                                            unsigned key_blocks) {
+    if (blockIdx.x >= key_blocks) {   // uniform per block: no barrier below is reached
+        const int i = (int)(blockIdx.x - key_blocks) * 256 + (int)threadIdx.x;
+        if (i < hc.dmax) hist_copy_at(hc, i);
+        return;
+    }
     __shared__ uint64_t red[16][17];
     const int si = threadIdx.x & 15, q = threadIdx.x >> 4;
     const int64_t i = (int64_t)blockIdx.x * 16 + si;
@@ -789,12 +812,9 @@ __global__ void rows_argmax_kernel(const float *snr, int T, int64_t ld, int64_t 
     am[i] = bj;
 }
 
-__global__ void hist_update_kernel(const float *old_h, float *new_h, const float *x, int64_t n,
-                                   int dmax) {
+__global__ void hist_update_kernel(HistCopy hc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dmax) return;
-    const int64_t m = n - dmax + i;
-    new_h[i] = m >= 0 ? x[m] : old_h[dmax + m];
+    if (i < hc.dmax) hist_copy_at(hc, i);
 }
 
 __global__ void window_fill_kernel(float *xwin, const float *hist, const float *x, int64_t n,
@@ -1317,10 +1337,14 @@ int forward_occupancy(int fl, int tt, int wpg, size_t lds) {
 }
 
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
-                                float *mx, int32_t *am, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_keys_kernel, dim3(nblocks(n, 16)), dim3(256), 0, st, keys, groups,
-                       ld, n, mx, am);
+                                float *mx, int32_t *am, hipStream_t st, const HistCopy *hc) {
+    HistCopy h{nullptr, nullptr, nullptr, 0, 0};
+    if (hc && hc->dmax > 0) h = *hc;
+    const unsigned kb = n > 0 ? nblocks(n, 16) : 0u;
+    const unsigned hb = h.dmax > 0 ? nblocks(h.dmax, 256) : 0u;
+    if (kb + hb == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_keys_kernel, dim3(kb + hb), dim3(256), 0, st, keys, groups, ld, n, mx, am, h,
+                       kb);
     return hipGetLastError();
 }
 
@@ -1335,8 +1359,8 @@ hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, fl
 hipError_t launch_hist_update(const float *old_h, float *new_h, const float *x, int64_t n,
                               int dmax, hipStream_t st) {
     if (dmax <= 0) return hipSuccess;
-    hipLaunchKernelGGL(hist_update_kernel, dim3(nblocks(dmax, 256)), dim3(256), 0, st, old_h,
-                       new_h, x, n, dmax);
+    const HistCopy hc{old_h, new_h, x, n, dmax};
+    hipLaunchKernelGGL(hist_update_kernel, dim3(nblocks(dmax, 256)), dim3(256), 0, st, hc);
     return hipGetLastError();
 }
 

@@ -108,29 +108,90 @@ __global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
     if (w && tile == 0 && threadIdx.x < hh) whist_new[j * hh + threadIdx.x] = w_at(wj, hj, hh, n_w - hh + threadIdx.x);
 }
 
-// Per-sample 64-bit keys (|z|^2 bits << 32 | ~j) of a chunk of 16 template
-// rows: block = 256 samples of one chunk; keys[chunk][p] = max over the chunk.
+// Templates per key chunk (rows folded into one per-sample key).
 constexpr int kKeyChunk = 16;
 
-__global__ __launch_bounds__(kThreads) void mr_row_keys_kernel(const float2 *__restrict__ zz, int64_t ld, int T,
-                                                               int64_t n, uint64_t *__restrict__ keys,
-                                                               int64_t ld_keys, int64_t tiles) {
+// The last interpolation (into level 0) fused with the per-sample keys:
+// block = one chunk of kKeyChunk template rows x kOut samples, one wave per
+// row. Each wave stages its row's W samples in its own LDS slice, forms the
+// full-rate z of its kOut / 64 samples per lane as in mr_upsample_add_kernel
+// and folds its keys into the block's per-sample maximum (LDS atomics); the
+// full-rate z itself is never stored. Tile 0 also writes every row's next
+// interpolation history.
+constexpr int kSw = kOut / 2 + kMaxTaps / 2 + 2;
+constexpr int kFuseThreads = kKeyChunk * 64;
+
+__global__ __launch_bounds__(kFuseThreads) void mr_interp_keys_kernel(
+    const float2 *__restrict__ z, int64_t ld_z, const int32_t *__restrict__ zrow, const float2 *__restrict__ w,
+    int64_t ld_w, const int32_t *__restrict__ wrow, int64_t n_w, const float2 *__restrict__ whist,
+    float2 *__restrict__ whist_new, int hh, const float *__restrict__ g, int lg, int64_t n_out, int T,
+    uint64_t *__restrict__ keys, int64_t ld_keys, int64_t tiles) {
+    __shared__ float2 sw[kKeyChunk][kSw];
+    __shared__ float sg[kMaxTaps];
+    __shared__ unsigned long long kred[kOut];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t chunk = blockIdx.x / tiles;
-    const int64_t p = (blockIdx.x % tiles) * kThreads + threadIdx.x;
-    if (p >= n) return;
-    const int j0 = (int)chunk * kKeyChunk;
-    const int j1 = min(T, j0 + kKeyChunk);
-    uint64_t best = 0;
-    for (int j = j0; j < j1; ++j) {
-        const float2 v = zz[(int64_t)j * ld + p];
-        const float s = v.x * v.x + v.y * v.y;
-        const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)j);
-        best = key > best ? key : best;
+    const int64_t tile = blockIdx.x % tiles;
+    const int64_t p0 = tile * kOut;
+    const int64_t j = chunk * kKeyChunk + wv;
+    const bool live = j < T;
+    const int zr = (live && z && zrow) ? zrow[j] : -1;
+    const int wr = (live && w) ? (wrow ? wrow[j] : (int)j) : -1;
+    const float2 *wj = wr >= 0 ? w + (int64_t)wr * ld_w : nullptr;
+    const float2 *hj = (live && whist) ? whist + j * hh : nullptr;
+    const int64_t v = p0 - lg + 1;
+    const int64_t q_lo = v >= 0 ? v / 2 : -((-v + 1) / 2);
+    const int cnt = (int)((p0 + kOut - 1) / 2 - q_lo + 1);
+    for (int t = threadIdx.x; t < kOut; t += kFuseThreads) kred[t] = 0ull;
+    if (threadIdx.x < lg) sg[threadIdx.x] = g[threadIdx.x];
+    if (live && w)
+        for (int k = lane; k < cnt; k += 64) {
+            const int64_t q = q_lo + k;
+            sw[wv][k] = q < n_w ? w_at(wj, hj, hh, q) : make_float2(0.0f, 0.0f);
+        }
+    __syncthreads();
+    if (live) {
+        const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
+        const uint32_t jkey = 0xFFFFFFFFu - (uint32_t)j;
+        const int b0 = (int)(p0 / 2 - q_lo);
+        for (int u = 0; u < kOut / 64; ++u) {
+            const int t = u * 64 + lane;
+            const int64_t p = p0 + t;
+            if (p >= n_out) break;
+            float2 acc = zj ? zj[p] : make_float2(0.0f, 0.0f);
+            if (w) {
+                const int base = b0 + (t >> 1);
+                for (int i = t & 1, k = 0; i < lg; i += 2, ++k) {
+                    const float2 x = sw[wv][base - k];
+                    acc.x = fmaf(sg[i], x.x, acc.x);
+                    acc.y = fmaf(sg[i], x.y, acc.y);
+                }
+            }
+            const float s = acc.x * acc.x + acc.y * acc.y;
+            atomicMax(&kred[t], ((unsigned long long)__float_as_uint(s) << 32) | (unsigned long long)jkey);
+        }
+        if (w && tile == 0 && lane < hh) whist_new[j * hh + lane] = w_at(wj, hj, hh, n_w - hh + lane);
     }
-    keys[chunk * ld_keys + p] = best;
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOut; t += kFuseThreads) {
+        const int64_t p = p0 + t;
+        if (p < n_out) keys[chunk * ld_keys + p] = kred[t];
+    }
 }
 
 }  // namespace
+
+hipError_t launch_mr_interp_keys(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w, int64_t ld_w,
+                                 const int32_t *wrow, int64_t n_w, const float2 *whist, float2 *whist_new, int hh,
+                                 const float *g, int lg, int64_t n_out, int T, uint64_t *keys, int64_t ld_keys,
+                                 hipStream_t st) {
+    if (n_out <= 0) return hipSuccess;
+    const int64_t tiles = nblk(n_out, kOut);
+    hipLaunchKernelGGL(mr_interp_keys_kernel, dim3((unsigned)(tiles * mr_key_chunks(T))), dim3(kFuseThreads), 0,
+                       st, z, ld_z, zrow, w, ld_w, wrow, n_w, whist, whist_new, hh, g, lg, n_out, T, keys, ld_keys,
+                       tiles);
+    return hipGetLastError();
+}
 
 hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
                               const float *h, int lh, float *dst, hipStream_t st) {
@@ -152,14 +213,5 @@ hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *
 }
 
 int mr_key_chunks(int T) { return (T + kKeyChunk - 1) / kKeyChunk; }
-
-hipError_t launch_mr_row_keys(const float2 *zz, int64_t ld, int T, int64_t n, uint64_t *keys, int64_t ld_keys,
-                              hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int64_t tiles = nblk(n, kThreads);
-    hipLaunchKernelGGL(mr_row_keys_kernel, dim3((unsigned)(tiles * mr_key_chunks(T))), dim3(kThreads), 0, st, zz,
-                       ld, T, n, keys, ld_keys, tiles);
-    return hipGetLastError();
-}
 
 }  // namespace spiir

@@ -26,7 +26,6 @@ struct spiir_multirate {
     std::vector<float2 *> w;             // 1 <= r < top: w_r [T][B >> r]
     std::vector<float2 *> wh[2];         // 1 <= r <= top: interpolation history of w_r [T][hh]
     int cur = 0;
-    float2 *w0 = nullptr;                // [T][B]: full-rate z for the max / argmax
     uint64_t *keys = nullptr;            // [chunks][B]
     float *h = nullptr, *g = nullptr;
     // the level banks run concurrently: each on its own stream, forked from the
@@ -81,7 +80,6 @@ void mr_free(spiir_multirate *mr) {
     }
     for (auto *p : mr->z) dfree(p);
     for (auto *p : mr->w) dfree(p);
-    dfree(mr->w0);
     dfree(mr->keys);
     dfree(mr->h);
     dfree(mr->g);
@@ -124,31 +122,37 @@ int mr_piece(spiir_multirate *mr, const float *x0, int64_t np, float2 *out0, int
     }
     for (int r = 0; r <= top; ++r)
         if (mr->bank[r]) HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
-    if (!out0) {
-        out0 = mr->w0;
-        ld0 = mr->B;
-    }
-    if (top == 0) {
-        HIPCHK(launch_mr_upsample_add(mr->z[0], mr->B, mr->zrow[0], nullptr, 0, nullptr, 0, nullptr, nullptr, 0,
-                                      mr->g, mr->lg, out0, ld0, np, mr->T, st));
-    } else {
-        const float2 *src = mr->z[top];
-        int64_t ld_src = mr->B >> top;
-        const int32_t *srow = mr->zrow[top];
-        for (int r = top - 1; r >= 0; --r) {
-            float2 *dst = r == 0 ? out0 : mr->w[r];
-            const int64_t ld_dst = r == 0 ? ld0 : (mr->B >> r);
+    // interpolation from the top level down to level 1 into w_r; the last
+    // step (into level 0) writes the full-rate z, or, for the max / argmax,
+    // runs fused with the per-sample keys
+    const float2 *src = nullptr;
+    int64_t ld_src = 0;
+    const int32_t *srow = nullptr;
+    if (top > 0) {
+        src = mr->z[top];
+        ld_src = mr->B >> top;
+        srow = mr->zrow[top];
+        for (int r = top - 1; r >= 1; --r) {
             HIPCHK(launch_mr_upsample_add(mr->bank[r] ? mr->z[r] : nullptr, mr->B >> r, mr->zrow[r], src, ld_src,
                                           srow, np >> (r + 1), mr->wh[c][r + 1], mr->wh[c ^ 1][r + 1], mr->hh,
-                                          mr->g, mr->lg, dst, ld_dst, np >> r, mr->T, st));
-            src = dst;
-            ld_src = ld_dst;
+                                          mr->g, mr->lg, mr->w[r], mr->B >> r, np >> r, mr->T, st));
+            src = mr->w[r];
+            ld_src = mr->B >> r;
             srow = nullptr;
         }
     }
+    const float2 *z0 = mr->bank[0] ? mr->z[0] : nullptr;
+    const float2 *h1 = top > 0 ? mr->wh[c][1] : nullptr;
+    float2 *h1n = top > 0 ? mr->wh[c ^ 1][1] : nullptr;
+    const int hh = top > 0 ? mr->hh : 0;
     if (mx) {
-        HIPCHK(launch_mr_row_keys(mr->w0, mr->B, mr->T, np, mr->keys, mr->B, st));
+        HIPCHK(launch_mr_interp_keys(z0, mr->B, mr->zrow[0], src, ld_src, srow, np >> 1, h1, h1n, hh, mr->g, mr->lg,
+                                     np, mr->T, mr->keys, mr->B, st));
         HIPCHK(launch_finalize_keys(mr->keys, mr_key_chunks(mr->T), mr->B, np, mx, am, st));
+    } else {
+        if (!out0) return fail(SPIIR_EINVAL, "multi-rate piece without an output");
+        HIPCHK(launch_mr_upsample_add(z0, mr->B, mr->zrow[0], src, ld_src, srow, np >> 1, h1, h1n, hh, mr->g,
+                                      mr->lg, out0, ld0, np, mr->T, st));
     }
     mr->cur ^= 1;
     return SPIIR_OK;
@@ -367,8 +371,7 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         if (e != hipSuccess) return alloc_fail(e);
     }
     {
-        hipError_t e = dalloc(&mr->w0, (size_t)T * (size_t)B);
-        if (e == hipSuccess) e = dalloc(&mr->keys, (size_t)mr_key_chunks(T) * (size_t)B);
+        hipError_t e = dalloc(&mr->keys, (size_t)mr_key_chunks(T) * (size_t)B);
         if (e == hipSuccess) e = dalloc(&mr->h, (size_t)mr->lh);
         if (e == hipSuccess) e = dalloc(&mr->g, (size_t)mr->lg);
         if (e != hipSuccess) return alloc_fail(e);

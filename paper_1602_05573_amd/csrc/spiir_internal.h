@@ -108,8 +108,18 @@ int forward_occupancy(int fl, int tt, int wpg, size_t lds);
 // Adjoint over nseg time segments: segment-local lambda scan, FP64 chain,
 // per-segment backward, FP64 reduction of the per-segment gradients.
 hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
+// The next call's strain history: the last dmax samples of old_h[0..dmax) ++ x[0..n).
+struct HistCopy {
+    const float *old_h;
+    float *new_h;   // a different buffer than old_h
+    const float *x;
+    int64_t n;
+    int dmax;
+};
+// Per-sample max over the groups' keys; with hc, the same launch also writes
+// the history copy (one launch fewer per streaming call).
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
-                                float *mx, int32_t *am, hipStream_t stream);
+                                float *mx, int32_t *am, hipStream_t stream, const HistCopy *hc = nullptr);
 hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, float *mx,
                               int32_t *am, hipStream_t stream);
 hipError_t launch_hist_update(const float *old_h, float *new_h, const float *x, int64_t n,
@@ -145,9 +155,12 @@ hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *
                                   float2 *whist_new, int hh, const float *g, int lg, float2 *out,
                                   int64_t ld_out, int64_t n_out, int T, hipStream_t stream);
 int mr_key_chunks(int T);
-hipError_t launch_mr_row_keys(const float2 *z, int64_t ld, int T, int64_t n, uint64_t *keys, int64_t ld_keys,
-                              hipStream_t stream);
-
+// Interpolation into level 0 fused with the per-sample keys of the full-rate z
+// (keys[chunk][p] = max over the chunk's rows of (|z|^2 bits << 32 | ~j)).
+hipError_t launch_mr_interp_keys(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w, int64_t ld_w,
+                                 const int32_t *wrow, int64_t n_w, const float2 *whist, float2 *whist_new, int hh,
+                                 const float *g, int lg, int64_t n_out, int T, uint64_t *keys, int64_t ld_keys,
+                                 hipStream_t stream);
 // Whitening front end: frame FFTs (PSD or whitening mode), PSD average,
 // 1/sqrt(S) from a given PSD, overlap-add with history and pending half-frame.
 hipError_t launch_wh_frames(bool psd, const float *hist, int64_t hlen, const float *x, const float *wtab,
