@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kThreads) void mr_decimate_kernel(const float *__re
 }
 
 // One template row j per blockIdx.x / tiles, kOut = 1,024 output samples per
-// block of 256 threads (4 per thread, kThreads apart):
+// block of 256 threads (two adjacent pairs per thread):
 //   out[j][p] = Z(j, p) + sum_{i < lg, p - i even} g[i] W(j, (p - i) / 2)
 // Z(j, p) = z[zrow[j]][p] (0 if z is NULL or zrow[j] < 0); W(j, q) =
 // w[wrow(j)][q] for q >= 0 (wrow = identity if NULL; 0 if wrow[j] < 0) and
@@ -59,6 +59,31 @@ constexpr int kOut = 4 * kThreads;
 __device__ inline float2 w_at(const float2 *wj, const float2 *hj, int hh, int64_t q) {
     if (q >= 0) return wj ? wj[q] : make_float2(0.0f, 0.0f);
     return hj[hh + q];
+}
+
+// Outputs t = 2m and 2m + 1 of a tile (t = p - p0) read the same W samples:
+// out(2m) += sum_k g[2k] W(m' - k), out(2m + 1) += sum_k g[2k + 1] W(m' - k),
+// m' = p0 / 2 + m, with s[sb + m - k] the staged W(m' - k). Each of the NU
+// pairs of a lane accumulates its taps in ascending order, as the plain
+// per-output sum does, so both forms give the same values.
+template <int NU>
+__device__ __forceinline__ void interp_pairs(const float2 *s, int sb, const float *sg, int lg, const int (&m)[NU],
+                                             float2 (&ev)[NU], float2 (&od)[NU]) {
+    for (int k = 0; 2 * k < lg; ++k) {
+        const float ge = sg[2 * k];
+        const bool odd = 2 * k + 1 < lg;   // uniform
+        const float go = sg[2 * k + 1];    // inside the staged taps (lg <= kMaxTaps)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const float2 x = s[sb + m[u] - k];
+            ev[u].x = fmaf(ge, x.x, ev[u].x);
+            ev[u].y = fmaf(ge, x.y, ev[u].y);
+            if (odd) {
+                od[u].x = fmaf(go, x.x, od[u].x);
+                od[u].y = fmaf(go, x.y, od[u].y);
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
@@ -89,21 +114,22 @@ __global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
     __syncthreads();
     const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
     float2 *oj = out + j * ld_out;
+    constexpr int NU = kOut / 2 / kThreads;
+    int m[NU];
+    float2 ev[NU], od[NU];
 #pragma unroll
-    for (int u = 0; u < kOut / kThreads; ++u) {
-        const int t = u * kThreads + (int)threadIdx.x;   // offset inside the tile
-        const int64_t p = p0 + t;
-        if (p >= n_out) break;
-        float2 acc = zj ? zj[p] : make_float2(0.0f, 0.0f);
-        if (w) {
-            const int base = (int)(p0 / 2 - q_lo) + (t >> 1);   // sw index of q = p / 2
-            for (int i = t & 1, k = 0; i < lg; i += 2, ++k) {
-                const float2 x = sw[base - k];                     // q = (p - i) / 2 = p / 2 - k
-                acc.x = fmaf(sg[i], x.x, acc.x);
-                acc.y = fmaf(sg[i], x.y, acc.y);
-            }
-        }
-        oj[p] = acc;
+    for (int u = 0; u < NU; ++u) {
+        m[u] = u * kThreads + (int)threadIdx.x;   // pair m: tile offsets 2m, 2m + 1
+        const int64_t p = p0 + 2 * m[u];
+        ev[u] = zj && p < n_out ? zj[p] : make_float2(0.0f, 0.0f);
+        od[u] = zj && p + 1 < n_out ? zj[p + 1] : make_float2(0.0f, 0.0f);
+    }
+    if (w) interp_pairs<NU>(sw, (int)(p0 / 2 - q_lo), sg, lg, m, ev, od);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int64_t p = p0 + 2 * m[u];
+        if (p < n_out) oj[p] = ev[u];
+        if (p + 1 < n_out) oj[p + 1] = od[u];
     }
     if (w && tile == 0 && threadIdx.x < hh) whist_new[j * hh + threadIdx.x] = w_at(wj, hj, hh, n_w - hh + threadIdx.x);
 }
@@ -114,10 +140,10 @@ constexpr int kKeyChunk = 16;
 // The last interpolation (into level 0) fused with the per-sample keys:
 // block = one chunk of kKeyChunk template rows x kOut samples, one wave per
 // row. Each wave stages its row's W samples in its own LDS slice, forms the
-// full-rate z of its kOut / 64 samples per lane as in mr_upsample_add_kernel
-// and folds its keys into the block's per-sample maximum (LDS atomics); the
-// full-rate z itself is never stored. Tile 0 also writes every row's next
-// interpolation history.
+// full-rate z of its kOut / 64 samples per lane (8 adjacent pairs) as
+// mr_upsample_add_kernel does, and folds its keys into the block's
+// per-sample maximum (LDS atomics); the full-rate z itself is never stored.
+// Tile 0 also writes every row's next interpolation history.
 constexpr int kSw = kOut / 2 + kMaxTaps / 2 + 2;
 constexpr int kFuseThreads = kKeyChunk * 64;
 
@@ -152,23 +178,25 @@ __global__ __launch_bounds__(kFuseThreads) void mr_interp_keys_kernel(
     __syncthreads();
     if (live) {
         const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
-        const uint32_t jkey = 0xFFFFFFFFu - (uint32_t)j;
-        const int b0 = (int)(p0 / 2 - q_lo);
-        for (int u = 0; u < kOut / 64; ++u) {
-            const int t = u * 64 + lane;
-            const int64_t p = p0 + t;
-            if (p >= n_out) break;
-            float2 acc = zj ? zj[p] : make_float2(0.0f, 0.0f);
-            if (w) {
-                const int base = b0 + (t >> 1);
-                for (int i = t & 1, k = 0; i < lg; i += 2, ++k) {
-                    const float2 x = sw[wv][base - k];
-                    acc.x = fmaf(sg[i], x.x, acc.x);
-                    acc.y = fmaf(sg[i], x.y, acc.y);
-                }
-            }
-            const float s = acc.x * acc.x + acc.y * acc.y;
-            atomicMax(&kred[t], ((unsigned long long)__float_as_uint(s) << 32) | (unsigned long long)jkey);
+        const unsigned long long jkey = 0xFFFFFFFFu - (uint32_t)j;
+        constexpr int NU = kOut / 2 / 64;
+        int m[NU];
+        float2 ev[NU], od[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            m[u] = u * 64 + lane;   // pair m: tile offsets 2m, 2m + 1
+            const int64_t p = p0 + 2 * m[u];
+            ev[u] = zj && p < n_out ? zj[p] : make_float2(0.0f, 0.0f);
+            od[u] = zj && p + 1 < n_out ? zj[p + 1] : make_float2(0.0f, 0.0f);
+        }
+        if (w) interp_pairs<NU>(sw[wv], (int)(p0 / 2 - q_lo), sg, lg, m, ev, od);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int64_t p = p0 + 2 * m[u];
+            const float se = ev[u].x * ev[u].x + ev[u].y * ev[u].y;
+            const float so = od[u].x * od[u].x + od[u].y * od[u].y;
+            if (p < n_out) atomicMax(&kred[2 * m[u]], ((unsigned long long)__float_as_uint(se) << 32) | jkey);
+            if (p + 1 < n_out) atomicMax(&kred[2 * m[u] + 1], ((unsigned long long)__float_as_uint(so) << 32) | jkey);
         }
         if (w && tile == 0 && lane < hh) whist_new[j * hh + lane] = w_at(wj, hj, hh, n_w - hh + lane);
     }
