@@ -676,6 +676,7 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
         if (rc) return rc;
         HIPCHK(launch_window_fill(bk->xwin, hist, x, n, bk->dmax, st));
     }
+    bool hist_done = false;
     for (int64_t P = 0; P < n; P += bk->max_block) {
         const int64_t np = std::min<int64_t>(bk->max_block, n - P);
         FwdArgs a = bk->base_args();
@@ -701,6 +702,15 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
             nseg = (int)((np + a.seg_len - 1) / a.seg_len);
         }
+        // the next call's history is written by a launch that follows every
+        // strain read of this call: the last key finalisation, else the last
+        // piece's carry chain, else a launch of its own after the loop
+        const bool last = P + np >= n;
+        const HistCopy hc{hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax};
+        if (last && nseg >= 2 && mode != kModeKeys) {
+            a.hist_next = hc;
+            hist_done = true;
+        }
         KernelEvents ev;
         HIPCHK(timer_next(bk, &ev));
         if (nseg >= 2)
@@ -708,14 +718,13 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
                                         bk->slot_filter, st, ev));
         else
             HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev));
-        // the last key finalisation of a call also writes the next history
-        const bool last = P + np >= n;
-        const HistCopy hc{hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax};
-        if (mode == kModeKeys)
+        if (mode == kModeKeys) {
             HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st,
                                         last ? &hc : nullptr));
+            hist_done = hist_done || last;
+        }
     }
-    if (mode != kModeKeys || n <= 0) HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
+    if (!hist_done) HIPCHK(launch_hist_update(hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax, st));
     bk->hist_cur ^= 1;
     return SPIIR_OK;
 }

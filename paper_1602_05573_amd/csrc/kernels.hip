@@ -592,6 +592,11 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     fwd_group<FL, TT, MODE, false, true>(p, g, smem, sc);
 }
 
+__device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
+    const int64_t m = hc.n - hc.dmax + i;
+    hc.new_h[i] = m >= 0 ? hc.x[m] : hc.old_h[hc.dmax + m];
+}
+
 // Carries of one slot across the segments of a launch: c holds the true end
 // state of segment 0 on entry; for k >= 1 the true start of segment k is c,
 // then c <- a^{len_k} c + e_k (e_k = segment k's end state from rest), in
@@ -630,7 +635,12 @@ __device__ __forceinline__ void chain_segments(const float4 *seg_end, float4 *se
 // launch's final state.
 __global__ void seg_chain_kernel(const float4 *seg_end, float4 *seg_start, float4 *state, const double2 *a64,
                                  const float2 *a32, int prec, int64_t nslots, int nseg, int64_t seg_len,
-                                 int64_t n) {
+                                 int64_t n, HistCopy hc, unsigned chain_blocks) {
+    if (blockIdx.x >= chain_blocks) {   // the history copy (hc.dmax > 0), 256 samples per block
+        const int i = (int)(blockIdx.x - chain_blocks) * 256 + (int)threadIdx.x;
+        if (i < hc.dmax) hist_copy_at(hc, i);
+        return;
+    }
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= nslots) return;  // every slot, padding included (its states stay zero)
     const float4 e0 = seg_end[sl];
@@ -759,11 +769,6 @@ __global__ void __launch_bounds__(256) batch_chain_kernel(const BatchStream *str
     chain_segments(a.seg_end, a.seg_start, a.nslots, sl, av, nv, a.seg_len, n, cr, ci);
     const float hr = (float)cr, hi = (float)ci;
     a.state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
-}
-
-__device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
-    const int64_t m = hc.n - hc.dmax + i;
-    hc.new_h[i] = m >= 0 ? hc.x[m] : hc.old_h[hc.dmax + m];
 }
 
 // Max over workgroup partial keys: 16 samples x 16 group slices per block.
@@ -1243,9 +1248,10 @@ hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_car
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((a.nslots + 255) / 256);
+    const unsigned hb = a.hist_next.dmax > 0 ? (unsigned)((a.hist_next.dmax + 255) / 256) : 0u;
     (void)slot_filter;
-    hipLaunchKernelGGL(seg_chain_kernel, dim3(nb), dim3(256), 0, st, a.seg_end, a.seg_start, a.state, a.s.a64,
-                       a.s.a32, a.prec, a.nslots, nseg, a.seg_len, a.n);
+    hipLaunchKernelGGL(seg_chain_kernel, dim3(nb + hb), dim3(256), 0, st, a.seg_end, a.seg_start, a.state, a.s.a64,
+                       a.s.a32, a.prec, a.nslots, nseg, a.seg_len, a.n, a.hist_next, nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),

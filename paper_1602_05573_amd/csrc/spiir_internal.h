@@ -31,6 +31,15 @@ struct SlotArrays {
     const int32_t *flags; // bit 0: |a| > 1 - 1e-5 (FP64 carry in hybrid mode)
 };
 
+// The next call's strain history: the last dmax samples of old_h[0..dmax) ++ x[0..n).
+struct HistCopy {
+    const float *old_h;
+    float *new_h;   // a different buffer than old_h
+    const float *x;
+    int64_t n;
+    int dmax;
+};
+
 struct FwdArgs {
     SlotArrays s;
     float4 *state;        // (hi.re, hi.im, lo.re, lo.im) per slot; null: cold start, not stored
@@ -58,6 +67,7 @@ struct FwdArgs {
     float4 *seg_end;      // [nseg][nslots] state at each segment end (local from zero for segments > 0)
     float4 *seg_start;    // [nseg][nslots] true state at each segment start (segments > 0)
     float2 *zl;           // [nseg - 1][T][seg_len] local z of segments > 0
+    HistCopy hist_next;   // time split: history copy done by the chain launch (dmax 0: none)
 };
 
 struct BwdArgs {
@@ -108,14 +118,6 @@ int forward_occupancy(int fl, int tt, int wpg, size_t lds);
 // Adjoint over nseg time segments: segment-local lambda scan, FP64 chain,
 // per-segment backward, FP64 reduction of the per-segment gradients.
 hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
-// The next call's strain history: the last dmax samples of old_h[0..dmax) ++ x[0..n).
-struct HistCopy {
-    const float *old_h;
-    float *new_h;   // a different buffer than old_h
-    const float *x;
-    int64_t n;
-    int dmax;
-};
 // Per-sample max over the groups' keys; with hc, the same launch also writes
 // the history copy (one launch fewer per streaming call).
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
