@@ -7,9 +7,9 @@
 // The stream is whitened with a delay of H samples (H zeros precede it).
 // Each frame is one workgroup of 1,024 threads: a radix-2 FFT of N complex
 // points in LDS (bit-reversed load, in-place butterflies taken two stages per
-// pass; the FP64-computed twiddle table is staged in LDS once per frame, so no
-// stage waits on global memory); the inverse transform is the forward one
-// applied to the conjugate.
+// pass, a bank swizzle on the frame buffer; the FP64-computed twiddle table
+// is staged in LDS once per frame, so no stage waits on global memory); the
+// inverse transform is the forward one applied to the conjugate.
 #include "spiir_internal.h"
 
 #include <atomic>
@@ -21,6 +21,17 @@ constexpr int kThreads = 256;      // overlap-add and PSD launches
 constexpr int kFftThreads = 1024;  // one frame per workgroup
 
 __device__ inline int bitrev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
+
+// LDS position of frame element i: inside each aligned block of 16 elements,
+// bits 4-5 of i are XORed into bits 0-1 and 2-3. The first two radix-2^2
+// passes have 16 lanes touching elements 4 (s = 0) or 16 (s = 2) apart, which
+// land on 4 bank groups unswizzled (4-way conflicts) and on 16 swizzled; the
+// later passes touch 16 consecutive elements either way. A bijection on
+// [0, n), applied to every access of the frame buffer.
+__device__ inline int sw(int i) {
+    const int m = (i >> 4) & 3;
+    return i ^ (m | (m << 2));
+}
 
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -43,14 +54,15 @@ __device__ void fft_stages(float2 *buf, const float2 *tw, int n, int logn) {
             const int b = ((q >> s) << (s + 2)) + pos;
             const float2 w1 = tw[pos * st1];
             const float2 w2a = tw[pos * st2], w2b = tw[(pos + h) * st2];
-            const float2 a0 = buf[b], a1 = cmul(buf[b + h], w1), a2 = buf[b + 2 * h], a3 = cmul(buf[b + 3 * h], w1);
+            const int e0 = sw(b), e1 = sw(b + h), e2 = sw(b + 2 * h), e3 = sw(b + 3 * h);
+            const float2 a0 = buf[e0], a1 = cmul(buf[e1], w1), a2 = buf[e2], a3 = cmul(buf[e3], w1);
             const float2 b0 = make_float2(a0.x + a1.x, a0.y + a1.y), b1 = make_float2(a0.x - a1.x, a0.y - a1.y);
             const float2 c2 = cmul(make_float2(a2.x + a3.x, a2.y + a3.y), w2a);
             const float2 c3 = cmul(make_float2(a2.x - a3.x, a2.y - a3.y), w2b);
-            buf[b] = make_float2(b0.x + c2.x, b0.y + c2.y);
-            buf[b + 2 * h] = make_float2(b0.x - c2.x, b0.y - c2.y);
-            buf[b + h] = make_float2(b1.x + c3.x, b1.y + c3.y);
-            buf[b + 3 * h] = make_float2(b1.x - c3.x, b1.y - c3.y);
+            buf[e0] = make_float2(b0.x + c2.x, b0.y + c2.y);
+            buf[e2] = make_float2(b0.x - c2.x, b0.y - c2.y);
+            buf[e1] = make_float2(b1.x + c3.x, b1.y + c3.y);
+            buf[e3] = make_float2(b1.x - c3.x, b1.y - c3.y);
         }
         __syncthreads();
     }
@@ -60,9 +72,10 @@ __device__ void fft_stages(float2 *buf, const float2 *tw, int n, int logn) {
         for (int q = threadIdx.x; q < n / 2; q += kFftThreads) {
             const int pos = q & (h - 1);
             const int i0 = ((q >> s) << (s + 1)) + pos;
-            const float2 u = buf[i0], v = cmul(buf[i0 + h], tw[pos * step]);
-            buf[i0] = make_float2(u.x + v.x, u.y + v.y);
-            buf[i0 + h] = make_float2(u.x - v.x, u.y - v.y);
+            const int p0 = sw(i0), p1 = sw(i0 + h);
+            const float2 u = buf[p0], v = cmul(buf[p1], tw[pos * step]);
+            buf[p0] = make_float2(u.x + v.x, u.y + v.y);
+            buf[p1] = make_float2(u.x - v.x, u.y - v.y);
         }
         __syncthreads();
     }
@@ -86,13 +99,13 @@ __global__ __launch_bounds__(kFftThreads) void wh_frames_kernel(const float *__r
     for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const int64_t gi = base + i;
         const float v = gi < hlen ? hist[gi] : x[gi - hlen];
-        buf[bitrev(i, logn)] = make_float2(wtab[i] * v, 0.0f);
+        buf[sw(bitrev(i, logn))] = make_float2(wtab[i] * v, 0.0f);
     }
     __syncthreads();
     fft_stages(buf, tw, n, logn);
     if (PSD) {
         for (int f = threadIdx.x; f <= H; f += kFftThreads) {
-            const float2 X = buf[f];
+            const float2 X = buf[sw(f)];
             pw[(int64_t)blockIdx.x * (H + 1) + f] = X.x * X.x + X.y * X.y;
         }
         return;
@@ -100,22 +113,23 @@ __global__ __launch_bounds__(kFftThreads) void wh_frames_kernel(const float *__r
     // conj(X * inv), then bit-reversed order for the second forward transform
     for (int f = threadIdx.x; f < n; f += kFftThreads) {
         const float s = inv[min(f, n - f)];
-        const float2 X = buf[f];
-        buf[f] = make_float2(X.x * s, -X.y * s);
+        const float2 X = buf[sw(f)];
+        buf[sw(f)] = make_float2(X.x * s, -X.y * s);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kFftThreads) {
         const int r = bitrev(i, logn);
         if (i < r) {
-            const float2 t = buf[i];
-            buf[i] = buf[r];
-            buf[r] = t;
+            const int pi = sw(i), pr = sw(r);
+            const float2 t = buf[pi];
+            buf[pi] = buf[pr];
+            buf[pr] = t;
         }
     }
     __syncthreads();
     fft_stages(buf, tw, n, logn);
     const float scale = 1.0f / (float)n;
-    for (int t = threadIdx.x; t < n; t += kFftThreads) y[(int64_t)blockIdx.x * n + t] = buf[t].x * scale;
+    for (int t = threadIdx.x; t < n; t += kFftThreads) y[(int64_t)blockIdx.x * n + t] = buf[sw(t)].x * scale;
 }
 
 // S[f] = sum_j pw[j][f] / (frames * wsum2) in FP64; inv[f] = 1 / sqrt(S[f]), 0 where S <= 0.
