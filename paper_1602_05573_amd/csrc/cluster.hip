@@ -382,6 +382,24 @@ size_t carve(void *ws, int64_t n, ClusterWs *out) {
     return o;
 }
 
+// Next window of a trigger stream: dst = src[0..keep) ++ blk[0..n), the max
+// and the argmax series together (one thread per window sample).
+__global__ __launch_bounds__(256) void ts_compose_kernel(const float *__restrict__ sm,
+                                                         const int32_t *__restrict__ sj, int64_t keep,
+                                                         const float *__restrict__ bm,
+                                                         const int32_t *__restrict__ bj, int64_t n,
+                                                         float *__restrict__ dm, int32_t *__restrict__ dj) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= keep + n) return;
+    if (i < keep) {
+        dm[i] = sm[i];
+        dj[i] = sj[i];
+    } else {
+        dm[i] = bm[i - keep];
+        dj[i] = bj[i - keep];
+    }
+}
+
 }  // namespace
 
 size_t cluster_workspace_bytes(int64_t n) { return carve(nullptr, n, nullptr); }
@@ -406,6 +424,15 @@ hipError_t launch_cluster(const float *M, const int32_t *J, int64_t n, float thr
     }
     hipLaunchKernelGGL(clus_write_kernel, dim3((unsigned)nb2), dim3(kThreads), 0, st, M, J, n, w.mask, w.cnt2,
                        off2, cap, count, index_base, idx, tpl, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_compose(const float *sm, const int32_t *sj, int64_t keep, const float *bm, const int32_t *bj,
+                             int64_t n, float *dm, int32_t *dj, hipStream_t st) {
+    const int64_t total = keep + n;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ts_compose_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, sm, sj, keep, bm,
+                       bj, n, dm, dj);
     return hipGetLastError();
 }
 

@@ -22,7 +22,10 @@ constexpr int64_t kMaxClusterN = (int64_t)1 << 40;
 // holds the samples whose triggers are not final yet plus W samples before
 // them; each push appends a block, clusters the window with candidates
 // limited to the newly final samples [final_end, total - W) and keeps the
-// last W samples before the new final_end (ping-pong buffers).
+// last W samples before the new final_end. The window sits at offset off of
+// buffer cur: a step only moves off past the dropped samples, and the next
+// push with data writes the kept samples and the new block into the other
+// buffer in one launch (ping-pong buffers).
 struct spiir_trigger_stream {
     int device = 0;
     float thr = 0.0f;
@@ -30,6 +33,7 @@ struct spiir_trigger_stream {
     float *wm[2] = {nullptr, nullptr};
     int32_t *wj[2] = {nullptr, nullptr};
     int cur = 0;
+    int64_t off = 0;   // window start inside wm[cur] / wj[cur]
     int64_t base = 0, len = 0, total = 0, final_end = 0;
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -50,20 +54,13 @@ void ts_free(spiir_trigger_stream *ts) {
 int ts_step(spiir_trigger_stream *ts, int64_t new_end, int64_t *idx, int32_t *tpl, float *val, int64_t cap,
             int64_t *count, hipStream_t st) {
     const int c = ts->cur;
-    HIPCHK(launch_cluster(ts->wm[c], ts->wj[c], ts->len, ts->thr, ts->W, ts->ws, cap, idx, tpl, val, count, st,
-                          ts->final_end - ts->base, new_end - ts->base, ts->base));
+    HIPCHK(launch_cluster(ts->wm[c] + ts->off, ts->wj[c] + ts->off, ts->len, ts->thr, ts->W, ts->ws, cap, idx, tpl,
+                          val, count, st, ts->final_end - ts->base, new_end - ts->base, ts->base));
     ts->final_end = new_end;
     const int64_t keep_from = std::max(ts->base, ts->final_end - ts->W) - ts->base;
-    const int64_t keep = ts->len - keep_from;
-    if (keep > 0) {
-        HIPCHK(hipMemcpyAsync(ts->wm[c ^ 1], ts->wm[c] + keep_from, (size_t)keep * sizeof(float),
-                              hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ts->wj[c ^ 1], ts->wj[c] + keep_from, (size_t)keep * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, st));
-    }
-    ts->cur ^= 1;
+    ts->off += keep_from;
     ts->base += keep_from;
-    ts->len = keep;
+    ts->len -= keep_from;
     return SPIIR_OK;
 }
 
@@ -120,7 +117,7 @@ int spiir_trigger_stream_reset(spiir_trigger_stream *ts, void *stream) {
     if (!ts) return fail(SPIIR_EINVAL, "trigger stream is null");
     (void)stream;   // no device state to clear: the window is rebuilt from the next push
     ts->cur = 0;
-    ts->base = ts->len = ts->total = ts->final_end = 0;
+    ts->off = ts->base = ts->len = ts->total = ts->final_end = 0;
     return SPIIR_OK;
 }
 
@@ -144,10 +141,14 @@ int spiir_trigger_stream_push(spiir_trigger_stream *ts, const float *max_dev, co
     DeviceGuard guard(ts->device);
     hipStream_t st = as_stream(stream);
     const int c = ts->cur;
-    if (n > 0) {
-        HIPCHK(hipMemcpyAsync(ts->wm[c] + ts->len, max_dev, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(ts->wj[c] + ts->len, argmax_dev, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                              st));
+    if (n > 0 && ts->off > 0) {   // kept samples and the block into the other buffer
+        HIPCHK(launch_ts_compose(ts->wm[c] + ts->off, ts->wj[c] + ts->off, ts->len, max_dev, argmax_dev, n,
+                                 ts->wm[c ^ 1], ts->wj[c ^ 1], st));
+        ts->cur = c ^ 1;
+        ts->off = 0;
+    } else if (n > 0) {           // the window starts the buffer: append the block
+        HIPCHK(launch_ts_compose(nullptr, nullptr, 0, max_dev, argmax_dev, n, ts->wm[c] + ts->len,
+                                 ts->wj[c] + ts->len, st));
     }
     ts->len += n;
     ts->total += n;

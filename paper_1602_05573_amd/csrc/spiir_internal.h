@@ -183,5 +183,8 @@ hipError_t launch_cluster(const float *max, const int32_t *argmax, int64_t n, fl
                           int64_t window, void *workspace, int64_t capacity, int64_t *index,
                           int32_t *tmpl, float *snr, int64_t *count, hipStream_t stream,
                           int64_t c_lo = 0, int64_t c_hi = -1, int64_t index_base = 0);
+// Trigger stream window: dm/dj = sm/sj[0..keep) ++ bm/bj[0..n) (no overlap).
+hipError_t launch_ts_compose(const float *sm, const int32_t *sj, int64_t keep, const float *bm, const int32_t *bj,
+                             int64_t n, float *dm, int32_t *dj, hipStream_t stream);
 
 }  // namespace spiir
