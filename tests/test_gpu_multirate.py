@@ -56,6 +56,7 @@ CONFIGS = [
     (4, [30], 8, 8, 3000, 0),                     # one level: an ordinary bank
     (7, [4, 0, 0, 0, 25], 24, 24, 4096, 1024),    # 5 levels, only the top and the bottom hold filters
     (3, [0, 0, 16], 7, 9, 4000, 0),               # odd tap counts, only the top level
+    (4, [6, 10, 14], 24, 24, 36864, 32768),       # a piece above the one-launch decimation size, then a short one
 ]
 
 
