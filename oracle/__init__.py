@@ -7,7 +7,7 @@ import this package. It shares no code with the HIP library (the C source is
 Functions (all double precision; see the C source for the definitions):
   z(bank, x, templates)          complex128 [len(templates), n]
   snr(bank, x, templates)        float64    [len(templates), n]
-  trigger(bank, x)               (float64 max [n], int32 argmax [n])
+  trigger(bank, x, peaks)        (float64 max [n], int32 argmax [n][, float64 peak [T]])
   backward(bank, x, G)           (grad_a, grad_b) complex128 [F]
   overlap_loss(z, g)             per-template loss and its gradient G
   clusters(M, J, threshold, W)   (index int64, template int32, value float32) of the triggers
@@ -55,7 +55,7 @@ def _load():
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         lib.oracle_z.argtypes = [P, P, P, P, P, i32, P, i64, P, i32]
         lib.oracle_snr.argtypes = [P, P, P, P, P, i32, P, i64, P, i32]
-        lib.oracle_trigger.argtypes = [P, P, P, P, i32, P, i64, P, P, i32]
+        lib.oracle_trigger.argtypes = [P, P, P, P, i32, P, i64, P, P, P, i32]
         lib.oracle_backward.argtypes = [P, P, P, P, i32, P, i64, P, P, P, i32]
         for f in (lib.oracle_z, lib.oracle_snr, lib.oracle_trigger, lib.oracle_backward):
             f.restype = ctypes.c_int
@@ -116,18 +116,21 @@ def snr(bank, x, templates=None, nthreads=None) -> np.ndarray:
     return out
 
 
-def trigger(bank, x, nthreads=None):
-    """Per-sample max over templates of SNR and the smallest index attaining it."""
+def trigger(bank, x, nthreads=None, peaks=False):
+    """Per-sample max over templates of SNR and the smallest index attaining
+    it; with peaks=True also every template's largest SNR over the stream
+    (float64 [T])."""
     lib = _load()
     off, a, b, d = _bank_arrays(bank)
     xd = np.ascontiguousarray(x, dtype=np.float64)
     mx = np.zeros(len(xd), np.float64)
     am = np.zeros(len(xd), np.int32)
+    pk = np.zeros(len(off) - 1, np.float64)
     rc = lib.oracle_trigger(_p(off), _p(a), _p(b), _p(d), len(off) - 1, _p(xd), len(xd),
-                            _p(mx), _p(am), _threads(nthreads))
+                            _p(mx), _p(am), _p(pk) if peaks else None, _threads(nthreads))
     if rc:
         raise RuntimeError("oracle_trigger failed (%d)" % rc)
-    return mx, am
+    return (mx, am, pk) if peaks else (mx, am)
 
 
 def clusters(M, J, threshold, window):

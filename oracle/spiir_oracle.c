@@ -132,10 +132,12 @@ int oracle_snr(const int64_t *off, const double *a, const double *b, const int32
  * index attaining it. Templates are split into contiguous ranges, one per
  * thread; within a range a strictly larger value replaces the running
  * maximum, and ranges are merged in increasing order with the same rule, so
- * ties always resolve to the smallest index. */
+ * ties always resolve to the smallest index. peak_out (NULL allowed) receives
+ * every template's largest snr over the n samples, the scale of the
+ * admissible-set rule for argmax ties. */
 int oracle_trigger(const int64_t *off, const double *a, const double *b, const int32_t *d,
                    int32_t T, const double *x, int64_t n,
-                   double *max_out, int32_t *arg_out, int32_t nthreads)
+                   double *max_out, int32_t *arg_out, double *peak_out, int32_t nthreads)
 {
     if (!off || !a || !b || !d || !x || !max_out || !arg_out || T < 1 || n < 0) return -1;
     if (nthreads < 1) nthreads = 1;
@@ -156,10 +158,13 @@ int oracle_trigger(const int64_t *off, const double *a, const double *b, const i
         for (int64_t m = 0; m < n; ++m) { m_t[m] = -1.0; j_t[m] = -1; }
         for (int32_t j = j0; j < j1; ++j) {
             template_z(a, b, d, off[j], off[j + 1], x, n, z, 1);
+            double pk = 0.0;
             for (int64_t m = 0; m < n; ++m) {
                 double s = z[2 * m] * z[2 * m] + z[2 * m + 1] * z[2 * m + 1];
                 if (s > m_t[m]) { m_t[m] = s; j_t[m] = j; }
+                if (s > pk) pk = s;
             }
+            if (peak_out) peak_out[j] = pk;
         }
         free(z);
     }

@@ -136,13 +136,16 @@ class SpiirBank:
 
     # -- forward ------------------------------------------------------------
     def filter_block(self, x: torch.Tensor, snr: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Next len(x) samples -> SNR of every template, float32 [T, n]."""
+        """Next len(x) samples -> SNR of every template, float32 [T, n]. snr may
+        be a column slice of a longer row-major array (rows of stride ld >= n)."""
         _require_cuda(x, torch.float32, "x")
         n = x.numel()
         if snr is None:
             snr = torch.empty((self.n_templates, n), dtype=torch.float32, device=x.device)
-        _require_cuda(snr, torch.float32, "snr")
-        call("spiir_filter_block", self._h, _ptr(x), n, _ptr(snr), snr.shape[-1], _stream_ptr(stream))
+        if not (snr.is_cuda and snr.dtype == torch.float32 and snr.dim() == 2 and snr.stride(1) == 1
+                and snr.shape[0] == self.n_templates and snr.shape[1] == n and snr.stride(0) >= n):
+            raise ValueError("snr must be a float32 CUDA array [T, n] with unit column stride")
+        call("spiir_filter_block", self._h, _ptr(x), n, _ptr(snr), snr.stride(0), _stream_ptr(stream))
         return snr
 
     def filter_block_z(self, x: torch.Tensor, z: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -1,22 +1,30 @@
-"""Builds libspiir.so for gfx950 with hipcc, in-tree next to this file."""
+"""Builds libspiir.so for gfx950 with hipcc, in-tree next to this file.
+
+Every source is compiled to an object of its own (in parallel, under
+``_build/``), then the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspiir.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "cluster.hip", "multirate.hip", "whiten.hip", "api.hip",
-                                                   "multirate_api.hip", "whiten_api.hip", "cluster_api.hip")]
+                                                   "multirate_api.hip", "whiten_api.hip", "cluster_api.hip",
+                                                   "layout.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", "spiir_internal.h"), os.path.join(HERE, "csrc", "host_common.h"),
+           os.path.join(HERE, "csrc", "layout.h"),
            os.path.join(ROOT, "include", "spiir.h")]
 
 # Packed FP32 instructions are switched off for the device code: ordinary
 # float code is compiled to scalar VALU instructions only.
 HIP_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
 ]
@@ -29,10 +37,25 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    # .cpp sources are plain host C++ (no device code)
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, *SOURCES]
+           "-c", *lang, src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,7 +1,8 @@
-// Host side of libspiir's filter banks: argument checking, bank layout, FP64
-// precomputation, launches, streaming state, the adjoint tape, batches in a
-// HIP graph and the autotuner; also the shared error and device helpers of
-// host_common.h. The multi-rate bank, the whitener and the clustering objects
+// Host side of libspiir's filter banks: device buffers and upload of the
+// bank plan (argument checks, slot layout, LDS geometry and FP64
+// precomputation come from layout.cpp), launches, streaming state, the
+// adjoint tape, batches in a HIP graph and the autotuner; also the shared
+// error and device helpers of host_common.h. The multi-rate bank, the whitener and the clustering objects
 // have their own host sources. Declared in include/spiir.h.
 #include "host_common.h"
 
@@ -54,202 +55,31 @@ int device_facts(int dev, DeviceFacts &f) {
 
 namespace {
 
+using layout::Layout;
+using layout::Plan;
+using layout::Geometry;
+using layout::plan_rows;
+using layout::auto_wpg;
+using layout::choose_fl;
+using layout::plan_geometry;
+using layout::fwd_lds_bytes;
 
-
-
-
-std::pair<double, double> cpow(double re, double im, long e) {
-    double rr = 1.0, ri = 0.0;
-    while (e > 0) {
-        if (e & 1) {
-            const double t = rr * re - ri * im;
-            ri = rr * im + ri * re;
-            rr = t;
-        }
-        const double t = re * re - im * im;
-        im = 2.0 * re * im;
-        re = t;
-        e >>= 1;
-    }
-    return {rr, ri};
-}
-
-// Filter-to-slot layout of one bank.
-struct Layout {
-    int fl = 1, wpg = 1, groups = 0;
-    int64_t nslots = 0;
-    std::vector<RowInfo> rows;            // [groups * wpg * 4]
-    std::vector<int32_t> slot_filter;     // [nslots], -1 = padding
-    std::vector<int64_t> pad_src;         // [nslots], padding: slot whose window offset it reuses
-    std::vector<int32_t> tpl_group;       // [T]
-};
-
-struct Plan {
-    int64_t total_rows = 0;
-    int max_nr = 0;
-};
-
-inline int rows_of(int64_t k, int fl) { return (int)((k + kRowLanes * fl - 1) / (kRowLanes * fl)); }
-
-Plan plan_rows(int T, const int64_t *off, int fl) {
-    Plan p;
-    for (int j = 0; j < T; ++j) {
-        const int nr = rows_of(off[j + 1] - off[j], fl);
-        p.total_rows += nr;
-        p.max_nr = std::max(p.max_nr, nr);
-    }
-    return p;
-}
-
-int auto_wpg(int64_t total_rows, int max_nr, int n_cu) {
-    const int64_t waves = (total_rows + 3) / 4;
-    int w = (int)((waves + n_cu - 1) / n_cu);
-    return std::min(kMaxWaves, std::max(w, (max_nr + 3) / 4));
-}
-
-// First-fit decreasing packing of whole templates, in 16-lane rows, into
-// workgroups of 4 * wpg rows; then the filter-to-slot assignment inside every
-// template. A template has nr rows x fl slots = C columns of 16 lanes, and one
-// ds_read_b32 of x[m - d] serves a column's 16 lanes in one LDS pass: filters
-// sorted by d mod 32 are dealt round-robin over the C columns, so the lanes
-// of a column have distinct d mod 32 (a residue class holds about K/32 < C
-// filters) and read from distinct banks. Padding lanes take the window offset
-// of a real lane of their column (same address: a broadcast, not a conflict).
-// Places the filters [k0, k1) of one template into its rows r0 .. r0+nr-1 of
-// workgroup g. A ds_read_b32 of the strain window x[m - d] is served 32 lanes
-// per LDS cycle with bank = (dword address mod 32), i.e. by d mod 32; the 32
-// lanes are the two rows 2q, 2q+1 of a wave at one filter column f. Where both
-// rows of such a pair belong to this template, the pair is one 32-lane column
-// that takes each residue class at most once while it can; a row whose partner
-// row belongs to another template takes residues 0..15 (even row) or 16..31
-// (odd row), so the two templates of the pair stay apart. Classes are placed
-// in order of decreasing count; a filter that finds every allowed column
-// already holding its class goes where its class is rarest, preferring
-// columns that already hold a double, so that the unavoidable extra cycles
-// gather in few passes. Padding lanes read the address of their row's first
-// lane (a broadcast).
-void deal_template(int64_t k0, int64_t k1, const int32_t *d, int g, int wpg, int fl, int r0, int nr, Layout &lay) {
-    struct Col {
-        int cap, lo, hi, rows[2], nparts, f, dbl;
-        std::vector<int32_t> items;
-        uint8_t has[32];
-    };
-    std::vector<Col> cols;
-    for (int r = r0; r < r0 + nr; ++r) {
-        const int p = r ^ 1;
-        const bool internal = p >= r0 && p < r0 + nr;
-        if (internal && p < r) continue;
-        for (int f = 0; f < fl; ++f) {
-            Col c{};
-            c.f = f;
-            c.rows[0] = r;
-            if (internal) {
-                c.cap = 2 * kRowLanes;
-                c.lo = 0;
-                c.hi = 32;
-                c.rows[1] = p;
-                c.nparts = 2;
-            } else {
-                c.cap = kRowLanes;
-                c.lo = (r & 1) ? 16 : 0;
-                c.hi = c.lo + 16;
-                c.nparts = 1;
-            }
-            cols.push_back(c);
-        }
-    }
-    std::vector<std::vector<int32_t>> bycls(32);
-    for (int64_t k = k0; k < k1; ++k) bycls[d[k] & 31].push_back((int32_t)k);
-    std::vector<int> corder(32);
-    for (int c = 0; c < 32; ++c) corder[c] = c;
-    std::stable_sort(corder.begin(), corder.end(),
-                     [&](int a, int b) { return bycls[a].size() > bycls[b].size(); });
-    // rank of a candidate column for a filter of class cls (lower is better): fewest of
-    // the class already there; among columns that already hold it, one with a double;
-    // then the least filled
-    auto key = [](const Col &c, int cls) {
-        const double fill = (double)c.items.size() / c.cap;
-        const int again = c.has[cls] > 0 && c.dbl == 0 ? 1 : 0;
-        return std::make_tuple((int)c.has[cls], again, fill);
-    };
-    for (int cls : corder) {
-        for (int32_t k : bycls[cls]) {
-            Col *best = nullptr;
-            for (int pass = 0; pass < 2 && !best; ++pass)   // allowed classes first, then any room
-                for (Col &c : cols) {
-                    if ((int)c.items.size() >= c.cap) continue;
-                    if (pass == 0 && (cls < c.lo || cls >= c.hi)) continue;
-                    if (!best || key(c, cls) < key(*best, cls)) best = &c;
-                }
-            if (best->has[cls]) ++best->dbl;
-            ++best->has[cls];
-            best->items.push_back(k);
-        }
-    }
-    for (const Col &c : cols) {
-        if (c.items.empty()) continue;
-        int64_t first = -1;   // slot of the column's first filter: padding lanes read its address
-        for (int part = 0; part < c.nparts; ++part) {
-            const int row = c.rows[part];
-            const int64_t base = ((int64_t)(g * wpg + row / 4) * fl + c.f) * 64 + (row % 4) * kRowLanes;
-            if (part == 0) first = base;
-            const int n0 = part * kRowLanes;
-            const int n = std::max(0, std::min<int>(kRowLanes, (int)c.items.size() - n0));
-            for (int l = 0; l < n; ++l) lay.slot_filter[(size_t)(base + l)] = c.items[(size_t)(n0 + l)];
-            for (int l = n; l < kRowLanes; ++l) lay.pad_src[(size_t)(base + l)] = first;
-        }
-    }
-}
+static_assert(sizeof(layout::F2) == sizeof(float2) && sizeof(layout::D2) == sizeof(double2) &&
+                  sizeof(RowInfo) == 16,
+              "host slot arrays must match the device vector types");
 
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
-    const int R = 4 * wpg;
-    std::vector<int> nr(T);
-    int max_nr = 0;
-    for (int j = 0; j < T; ++j) {
-        nr[j] = rows_of(off[j + 1] - off[j], fl);
-        max_nr = std::max(max_nr, nr[j]);
-    }
-    if (max_nr > R)
-        return fail(SPIIR_EINVAL, "a template needs %d rows of %d filters but a workgroup has %d",
-                    max_nr, kRowLanes * fl, R);
-    std::vector<int> order(T);
-    for (int j = 0; j < T; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nr[x] > nr[y]; });
-    std::vector<int> room;                  // free rows per group
-    std::vector<std::vector<int>> members;  // templates per group
-    for (int j : order) {
-        size_t g = 0;
-        for (; g < room.size(); ++g)
-            if (room[g] >= nr[j]) break;
-        if (g == room.size()) {
-            room.push_back(R);
-            members.emplace_back();
-        }
-        room[g] -= nr[j];
-        members[g].push_back(j);
-    }
-    lay.fl = fl;
-    lay.wpg = wpg;
-    lay.groups = (int)members.size();
-    lay.nslots = (int64_t)lay.groups * wpg * fl * 64;
-    lay.rows.assign((size_t)lay.groups * R, RowInfo{-1, 0, 0, 0});
-    lay.slot_filter.assign((size_t)lay.nslots, -1);
-    lay.pad_src.assign((size_t)lay.nslots, -1);
-    lay.tpl_group.assign(T, -1);
-    for (int g = 0; g < lay.groups; ++g) {
-        std::vector<int> &mem = members[g];
-        std::sort(mem.begin(), mem.end());
-        int r0 = 0;
-        for (int j : mem) {
-            lay.tpl_group[j] = g;
-            for (int r = 0; r < nr[j]; ++r) lay.rows[(size_t)g * R + r0 + r] = RowInfo{j, r0, nr[j], 0};
-            deal_template(off[j], off[j + 1], d, g, wpg, fl, r0, nr[j], lay);
-            r0 += nr[j];
-        }
-    }
-    return SPIIR_OK;
+    std::string err;
+    const int rc = layout::build_layout(T, off, d, fl, wpg, lay, err);
+    return rc ? fail(rc, "%s", err.c_str()) : SPIIR_OK;
 }
 
+int check_bank_args(int32_t T, const int64_t *off, const double *a, const double *b, const int32_t *d,
+                    const spiir_bank_opts &o, int &dmax_out) {
+    std::string err;
+    const int rc = layout::check_bank_args(T, off, a, b, d, o, dmax_out, err);
+    return rc ? fail(rc, "%s", err.c_str()) : SPIIR_OK;
+}
 
 }  // namespace
 
@@ -358,78 +188,18 @@ struct spiir_batch {
 
 namespace {
 
-// Host-side checks of create arguments; no HIP call is made here.
-int check_bank_args(int32_t T, const int64_t *off, const double *a, const double *b, const int32_t *d,
-                    const spiir_bank_opts &o, int &dmax_out) {
-    if (T < 1) return fail(SPIIR_EINVAL, "n_templates must be >= 1 (got %d)", T);
-    if (!off || !a || !b || !d) return fail(SPIIR_EINVAL, "null coefficient / offset / delay array");
-    if (off[0] != 0) return fail(SPIIR_EINVAL, "filter_offsets[0] must be 0");
-    for (int j = 0; j < T; ++j)
-        if (off[j + 1] <= off[j])
-            return fail(SPIIR_EINVAL, "template %d has no filters (offsets must strictly increase)", j);
-    const int64_t F = off[T];
-    if (F > (int64_t)INT32_MAX) return fail(SPIIR_EINVAL, "too many filters (%lld)", (long long)F);
-    int dm = 0;
-    for (int64_t k = 0; k < F; ++k) {
-        const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
-        if (!std::isfinite(ar) || !std::isfinite(ai) || !std::isfinite(br) || !std::isfinite(bi))
-            return fail(SPIIR_EINVAL, "filter %lld has a non-finite coefficient", (long long)k);
-        if (std::hypot(ar, ai) >= 1.0)
-            return fail(SPIIR_EINVAL, "filter %lld is not stable: |a| = %.17g >= 1", (long long)k, std::hypot(ar, ai));
-        if (d[k] < 0) return fail(SPIIR_EINVAL, "filter %lld has a negative delay", (long long)k);
-        dm = std::max(dm, d[k]);
-    }
-    if (o.max_delay < 0) return fail(SPIIR_EINVAL, "max_delay must be >= 0");
-    if (o.max_delay > 0 && dm > o.max_delay)
-        return fail(SPIIR_EINVAL, "a delay (%d) exceeds max_delay (%d)", dm, o.max_delay);
-    const int dmax = o.max_delay > 0 ? o.max_delay : dm;
-    if (dmax > (1 << 26)) return fail(SPIIR_EINVAL, "max_delay %d too large", dmax);
-    if (o.chunk_len != 0 && (o.chunk_len < 8 || o.chunk_len > 4096 || o.chunk_len % 8))
-        return fail(SPIIR_EINVAL, "chunk_len must be a multiple of 8 in [8, 4096] (got %d)", o.chunk_len);
-    if (o.filters_per_lane < 0 || o.filters_per_lane > 4)
-        return fail(SPIIR_EINVAL, "filters_per_lane must be 0..4 (got %d)", o.filters_per_lane);
-    if (o.precision < 0 || o.precision > 2) return fail(SPIIR_EINVAL, "precision must be 0, 1 or 2");
-    if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
-    if (o.waves_per_group < 0 || o.waves_per_group > kMaxWaves)
-        return fail(SPIIR_EINVAL, "waves_per_group must be 0..%d", kMaxWaves);
-    if (o.time_split < 0 || o.time_split > 32) return fail(SPIIR_EINVAL, "time_split must be 0..32");
-    dmax_out = dmax;
-    return SPIIR_OK;
-}
-
 // Slot arrays on the host, then uploaded.
 int upload_coeffs(spiir_bank *bk) {
     const int64_t S = bk->lay.nslots;
-    std::vector<float2> a32((size_t)S, make_float2(0.f, 0.f)), b32((size_t)S, make_float2(0.f, 0.f));
-    std::vector<int32_t> xo((size_t)S, 0), fl((size_t)S, 0);
-    std::vector<double2> aL((size_t)S, make_double2(0, 0)), dL((size_t)S, make_double2(0, 0)),
-        a64((size_t)S, make_double2(0, 0));
-    for (int64_t s = 0; s < S; ++s) {
-        const int32_t k = bk->lay.slot_filter[(size_t)s];
-        if (k < 0) {
-            const int64_t src = bk->lay.pad_src[(size_t)s];
-            if (src >= 0) xo[(size_t)s] = bk->dmax - bk->d[(size_t)bk->lay.slot_filter[(size_t)src]];
-            continue;
-        }
-        const double ar = bk->a[2 * (size_t)k], ai = bk->a[2 * (size_t)k + 1];
-        const float far = (float)ar, fai = (float)ai;
-        a32[(size_t)s] = make_float2(far, fai);
-        b32[(size_t)s] = make_float2((float)bk->b[2 * (size_t)k], (float)bk->b[2 * (size_t)k + 1]);
-        xo[(size_t)s] = bk->dmax - bk->d[(size_t)k];
-        const auto p = cpow(ar, ai, bk->L);
-        const auto q = cpow((double)far, (double)fai, bk->L);
-        aL[(size_t)s] = make_double2(p.first, p.second);
-        dL[(size_t)s] = make_double2(p.first - q.first, p.second - q.second);
-        a64[(size_t)s] = make_double2(ar, ai);
-        fl[(size_t)s] = std::hypot(ar, ai) > 1.0 - 1e-5 ? 1 : 0;
-    }
-    HIPCHK(hipMemcpy(bk->a32, a32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->b32, b32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->xoff, xo.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->flags, fl.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->aL, aL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->dL, dL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(bk->a64, a64.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    layout::SlotHost h;
+    layout::slot_arrays(bk->lay, bk->a.data(), bk->b.data(), bk->d.data(), bk->dmax, bk->L, h);
+    HIPCHK(hipMemcpy(bk->a32, h.a32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->b32, h.b32.data(), S * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->xoff, h.xoff.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->flags, h.flags.data(), S * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->aL, h.aL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->dL, h.dL.data(), S * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bk->a64, h.a64.data(), S * sizeof(double2), hipMemcpyHostToDevice));
     return SPIIR_OK;
 }
 
@@ -476,47 +246,6 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
     dfree(bk->ysub); dfree(bk->blam); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
-}
-
-// Filters per lane: the largest count that still gives every SIMD about two
-// waves (more filters per lane amortise the template sums over more updates);
-// banks too small for that get one filter per lane.
-int choose_fl(int T, const int64_t *off, int n_cu) {
-    for (int fl = 4; fl >= 1; --fl) {
-        const Plan p = plan_rows(T, off, fl);
-        if (p.max_nr > 4 * kMaxWaves) return std::min(4, fl + 1);
-        if ((p.total_rows + 3) / 4 >= (int64_t)7 * n_cu) return fl;
-    }
-    return 1;
-}
-
-struct Geometry {
-    int tt = 16, nb = 0;
-    bool xlds = true;
-    size_t lds = 0;
-};
-
-// LDS plan for a workgroup of wpg waves: the strain window (max_delay + nb
-// samples) when it fits, and 16-step tiles when they fit beside it.
-Geometry plan_geometry(int wpg, int dmax, int L, int max_block, size_t lds_cap) {
-    Geometry best;
-    for (int tt : {16, 8}) {
-        Geometry g;
-        g.tt = tt;
-        const int64_t fixed = (int64_t)fwd_lds_bytes(wpg, 0, 0, false, tt);
-        int64_t nb = ((int64_t)lds_cap - fixed - 4 * (int64_t)(dmax + tt) - 64) / (4 * L) * L;
-        nb = std::min<int64_t>(nb, max_block);
-        g.xlds = nb >= L;
-        g.nb = g.xlds ? (int)nb : max_block;
-        g.lds = fwd_lds_bytes(wpg, dmax, g.nb, g.xlds, tt);
-        if (tt == 16) {
-            best = g;
-            if (!g.xlds || g.nb >= std::min(max_block, 2048)) return g;
-        } else if (g.xlds && (!best.xlds || g.nb > best.nb)) {
-            return g;
-        }
-    }
-    return best;
 }
 
 // seg_cap: most time segments the automatic time split may choose (8 for
@@ -590,6 +319,10 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
         return rc;
     }
     const Geometry gm = plan_geometry(wpg, dmax, L, max_block, df.lds_cap);
+    if (L % gm.tt) {   // chunk ends are detected at tile ends only
+        delete bk;
+        return fail(SPIIR_EINVAL, "internal: tile length %d does not divide chunk_len %d", gm.tt, L);
+    }
     bk->tt = gm.tt;
     bk->xlds = gm.xlds;
     bk->nb = gm.nb;

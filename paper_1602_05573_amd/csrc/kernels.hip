@@ -1293,11 +1293,6 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 }  // namespace
 
-size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt) {
-    const size_t win = x_in_lds ? (size_t)((dmax + nb + tt + 3) & ~3) * 4 : 0;
-    return win + (size_t)wpg * tt * 64 * 8 + ((size_t)2 * tt * (4 * wpg + 1) + 16) * 8 + (size_t)2 * tt * 8;
-}
-
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
                           size_t lds, hipStream_t st, KernelEvents ev) {
     if (groups <= 0) return hipSuccess;

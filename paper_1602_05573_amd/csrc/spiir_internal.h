@@ -4,21 +4,15 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "layout.h"
+
 namespace spiir {
 
-constexpr int kMaxWaves = 8;    // 64-lane waves per workgroup (512 threads)
-constexpr int kRowLanes = 16;   // lanes per row; a row serves exactly one template
 constexpr int kSub = 16;        // adjoint: steps kept in registers per recompute
 constexpr float kFlagRadius = 1.0f - 1e-5f;
 
 enum Mode { kModeSnr = 0, kModeKeys = 1, kModeZ = 2 };
 enum Prec { kPrecHybrid = 0, kPrecFp32 = 1, kPrecFp64 = 2 };
-
-// Per 16-lane row of a workgroup: the template it serves (-1: none), the
-// first row of that template inside the workgroup and its number of rows.
-struct RowInfo {
-    int32_t tpl, r0, nr, pad;
-};
 
 // Per filter slot (lane-major inside each wave and slot column).
 struct SlotArrays {
@@ -106,7 +100,6 @@ struct KernelEvents {
     hipEvent_t stop = nullptr;
 };
 
-size_t fwd_lds_bytes(int wpg, int dmax, int nb, bool x_in_lds, int tt);
 hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int groups,
                           size_t lds, hipStream_t stream, KernelEvents ev = KernelEvents());
 // Time-split launch (modes kModeSnr / kModeKeys / kModeZ): local pass over every

@@ -10,7 +10,11 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-GRAD_TOL = 1e-3   # relative, per template in norm and per large entry
+# Gradient gate (FP32 adjoint against the FP64 oracle's gradient), per
+# template: the error vector's norm relative to the oracle gradient's norm,
+# and every entry of at least 1e-3 of the template's largest entry relative
+# to itself, both at most GRAD_TOL.
+GRAD_TOL = 1e-3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,17 +32,21 @@ def banner(msg):
     print("[case] " + msg, flush=True)
 
 
-def grad_close(g_gpu, g_ref, off, tol=GRAD_TOL):
-    worst = 0.0
+def grad_close(g_gpu, g_ref, off, tol=GRAD_TOL, what="grad"):
+    """Per-template norm error and large-entry error of g_gpu against g_ref,
+    both asserted at tol; returns the worst norm error."""
+    worst, worst_ent = 0.0, 0.0
     for j in range(len(off) - 1):
         sl = slice(int(off[j]), int(off[j + 1]))
-        a, b = g_gpu[sl], g_ref[sl]
+        a, b = np.asarray(g_gpu[sl], np.complex128), g_ref[sl]
         nrm = np.linalg.norm(b)
         worst = max(worst, np.linalg.norm(a - b) / max(nrm, 1e-300))
         big = np.abs(b) >= 1e-3 * np.abs(b).max()
-        ent = np.abs(a[big] - b[big]) / np.abs(b[big])
-        assert ent.max() <= 10 * tol, "template %d: entry error %.3g" % (j, ent.max())
-    assert worst <= tol, "gradient error %.3g" % worst
+        worst_ent = max(worst_ent, float(np.max(np.abs(a[big] - b[big]) / np.abs(b[big]))))
+    print("%s: worst per-template norm error %.3g, worst large-entry error %.3g" % (what, worst, worst_ent),
+          flush=True)
+    assert worst <= tol, "%s: norm error %.3g" % (what, worst)
+    assert worst_ent <= tol, "%s: entry error %.3g" % (what, worst_ent)
     return worst
 
 
@@ -58,7 +66,7 @@ def test_forward_z_parity(tsplit, max_block):
     assert np.max(np.abs(s - sref).max(axis=1) / sref.max(axis=1)) <= 1e-4
 
 
-@pytest.mark.parametrize("L,fl", [(64, 1), (256, 2), (512, 4)])
+@pytest.mark.parametrize("L,fl", [(64, 1), (256, 2), (512, 4), (24, 2), (40, 3)])
 def test_backward_matches_oracle_random_upstream(L, fl):
     banner("backward L=%d fl=%d" % (L, fl))
     bank = random_bank(61, 0, 5, 20, 300, 0.99, 0.9999, 500)
@@ -73,8 +81,8 @@ def test_backward_matches_oracle_random_upstream(L, fl):
         ga, gb = bk.backward(tape, torch.from_numpy(G.astype(np.complex64)).cuda())
         ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
         tape.close()
-    ea = grad_close(ga, ga_ref, bank.offsets)
-    eb = grad_close(gb, gb_ref, bank.offsets)
+    ea = grad_close(ga, ga_ref, bank.offsets, what="L=%d grad_a" % L)
+    eb = grad_close(gb, gb_ref, bank.offsets, what="L=%d grad_b" % L)
     print("grad err a %.3g b %.3g" % (ea, eb))
 
 
@@ -100,8 +108,8 @@ def test_backward_time_segments(tsplit, prec):
             tape.close()
     tol = GRAD_TOL if prec != 1 else 2e-2
     ga, gb = out[tsplit]
-    ea = grad_close(ga, ga_ref, bank.offsets, tol)
-    eb = grad_close(gb, gb_ref, bank.offsets, tol)
+    ea = grad_close(ga, ga_ref, bank.offsets, tol, what="split %d prec %d grad_a" % (tsplit, prec))
+    eb = grad_close(gb, gb_ref, bank.offsets, tol, what="split %d prec %d grad_b" % (tsplit, prec))
     # split and unsplit runs differ only by FP32 rounding order
     ga1, gb1 = out[1]
     da = np.linalg.norm(ga - ga1) / np.linalg.norm(ga1)
@@ -138,8 +146,8 @@ def test_backward_of_overlap_loss_on_chirps():
         ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
         tape.close()
     assert np.max(np.abs(loss - loss_ref)) < 1e-4
-    grad_close(ga, ga_ref, bank.offsets)
-    grad_close(gb, gb_ref, bank.offsets)
+    grad_close(ga, ga_ref, bank.offsets, what="chirps grad_a")
+    grad_close(gb, gb_ref, bank.offsets, what="chirps grad_b")
 
 
 def test_spiirfn_autograd_and_fit_step():
@@ -170,8 +178,8 @@ def test_spiirfn_autograd_and_fit_step():
         lref, Gref = oracle.overlap_loss(zr, g[None, :])
         ga_ref, gb_ref = oracle.backward(bank, x, Gref)
         assert abs(float(loss) - lref[0]) < 1e-4
-        grad_close(a.grad.numpy(), ga_ref, bank.offsets, tol=2e-3)
-        grad_close(b.grad.numpy(), gb_ref, bank.offsets, tol=2e-3)
+        grad_close(a.grad.numpy(), ga_ref, bank.offsets, what="SpiirFn grad_a")
+        grad_close(b.grad.numpy(), gb_ref, bank.offsets, what="SpiirFn grad_b")
         # a few optimiser steps reduce the loss (fit quality itself is not pinned)
         opt = torch.optim.Adam([a, b], lr=1e-4)
         first = float(loss)
@@ -201,9 +209,10 @@ def test_stale_tape_is_rejected():
         tape.close()
 
 
-def test_chirp_fit_full_size_sampled_templates():
-    """256 templates x 400 filters, 65,536 samples: GPU forward + adjoint over the
-    whole bank, compared with the oracle on sampled templates."""
+def test_chirp_fit_full_size_every_template():
+    """256 templates x 400 filters, 65,536 samples (the bench.py adjoint
+    workload): GPU forward + adjoint over the whole bank, compared with the
+    oracle for every template: z, the overlap loss, and both gradients."""
     banner("chirp_fit full size")
     bank, x, gs, _ = chirp_fit()
     T = bank.n_templates
@@ -222,14 +231,15 @@ def test_chirp_fit_full_size_sampled_templates():
         ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
         zs = z.cpu().numpy()
         tape.close()
-    pick = [0, 97, 255]
-    sub = bank.subset(pick)
-    zr = oracle.z(sub, x)
-    for i, j in enumerate(pick):
-        zj = zs[j].astype(np.complex128)
-        assert np.abs(zj - zr[i]).max() <= 1e-4 * np.abs(zr[i]).max()
-    lref, Gref = oracle.overlap_loss(zr, gs[pick])
-    ga_ref, gb_ref = oracle.backward(sub, x, Gref)
-    idx = np.concatenate([np.arange(bank.offsets[j], bank.offsets[j + 1]) for j in pick])
-    grad_close(ga[idx], ga_ref, sub.offsets)
-    grad_close(gb[idx], gb_ref, sub.offsets)
+    zr = oracle.z(bank, x)
+    zerr = np.abs(zs.astype(np.complex128) - zr).max(axis=1) / np.abs(zr).max(axis=1)
+    print("chirp_fit: z error %.3g of the peak (worst template %d)" % (zerr.max(), int(np.argmax(zerr))))
+    assert zerr.max() <= 1e-4
+    lref, Gref = oracle.overlap_loss(zr, gs)
+    lgpu, _ = oracle.overlap_loss(zs.astype(np.complex128), gs)
+    assert np.abs(lgpu - lref).max() <= 1e-4
+    ga_ref, gb_ref = oracle.backward(bank, x, Gref)
+    # the GPU gradient used the upstream gradient at its own z (FP32); the
+    # oracle's at the exact z
+    grad_close(ga, ga_ref, bank.offsets, what="chirp_fit grad_a")
+    grad_close(gb, gb_ref, bank.offsets, what="chirp_fit grad_b")

@@ -207,6 +207,30 @@ def test_layouts_and_precisions(mid, fl, L, wpg, prec):
     assert err <= SNR_TOL
 
 
+@pytest.mark.parametrize("L", [24, 40, 8])
+def test_chunk_len_not_multiple_of_16(L):
+    """Chunk lengths that are a multiple of 8 but not of 16 take 8-step tiles,
+    so every chunk end still falls on a tile end and gets its FP64 carry
+    correction. Poles within 2e-5 of the unit circle over 16,384-sample
+    launches: the corrected recursion must beat the plain FP32 one (the
+    precision mode without corrections) by a wide margin, as it does at L = 48,
+    and stay within the gate."""
+    banner("chunk_len %d" % L)
+    bank = random_bank(55, 0, 6, 50, 300, 1 - 2e-5, 1 - 1e-6, 1000)
+    x = strain(32768, 55)
+    ref = oracle.snr(bank, x)
+    err = {}
+    for prec, chunk in ((0, L), (1, L), (0, 48)):
+        with mk(bank, chunk_len=chunk, max_block=16384, precision=prec, time_split=1) as bk:
+            assert bk.info["sub_block"] % chunk == 0
+            s = torch.cat([bk.filter_block(dev(x[:16384])).clone(), bk.filter_block(dev(x[16384:]))], dim=1)
+        err[(prec, chunk)], _ = snr_err(s.cpu().numpy(), ref)
+    print("chunk_len %d: hybrid %.3g, all-FP32 %.3g, hybrid at L=48 %.3g"
+          % (L, err[(0, L)], err[(1, L)], err[(0, 48)]))
+    assert err[(0, L)] <= SNR_TOL
+    assert err[(0, L)] <= 0.1 * err[(1, L)]
+
+
 def test_template_too_large_for_one_workgroup(mid):
     from paper_1602_05573_amd import SpiirError
     bank, _, _ = mid
@@ -288,7 +312,7 @@ def test_single_filter_templates_and_zero_delay():
 
 
 @pytest.mark.parametrize("nseg,max_block,L", [(2, 4096, 256), (4, 2048, 128), (8, 16384, 64), (3, 5000, 8),
-                                             (16, 8192, 64), (32, 16384, 64), (32, 4096, 256)])
+                                             (16, 8192, 64), (32, 16384, 64), (32, 4096, 256), (4, 4096, 24)])
 def test_time_split_parity(mid, nseg, max_block, L):
     """Launches cut into segments filtered in parallel, joined by the FP64 carry
     chain: SNR rows and the fused max against the oracle, over several calls."""

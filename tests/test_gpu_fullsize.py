@@ -1,13 +1,22 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
-configuration bench.py times. The oracle computes what it can one by one
-(sampled templates over the whole stream, every template over a prefix); the
-rest is checked through properties that hold at any size (the fused max is
-the max of the per-template rows, the batch equals per-bank streaming)."""
+configuration bench.py times.
+
+The 1,024-template bank (1,024 templates x U{100..800} filters, 4,194,304
+samples in 4,096-sample blocks) is compared with the FP64 oracle in full:
+every template's SNR row over the whole stream, element by element, and the
+fused max/argmax over every sample with the admissible-set rule for ties.
+The oracle's work is split into eight parts of 128 templates (each part is
+one test, so progress shows); the per-sample maximum over templates is the
+merge of the parts' maxima (max, lowest index among equal values), which the
+oracle pins check against the oracle's own trigger.
+"""
+import time
+
 import numpy as np
 import pytest
 
 import oracle
-from helpers import SNR_TOL, check_argmax, snr_err
+from helpers import ARG_EPS, SNR_TOL, check_argmax
 from workloads import bank_1024, batch_streams
 
 pytestmark = pytest.mark.gpu
@@ -15,8 +24,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 B = 4096
-PICK1 = [0, 517, 1023]            # sampled templates of the 1,024-template bank
-SAMPLE_BLOCKS = (0, 1, 300, 1023)  # blocks where fused and plain outputs are compared whole
+PARTS = 8                 # oracle parts of the 1,024-template bank
+PREFIX_BLOCKS = 16        # blocks whose documented ties are counted exactly
+_parts = {}               # part -> (M, J, P, ref at the GPU argmax, row errors), filled in order
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -29,59 +39,141 @@ def banner(msg):
     print("[case] " + msg, flush=True)
 
 
-def test_bank1024_full_size():
-    """1,024 templates x U{100..800} filters over 4,194,304 samples in
-    4,096-sample blocks (the bench.py configuration)."""
+@pytest.fixture(scope="module")
+def c1():
+    """The bench.py run of the bank (chunk_len 256, 4,096-sample blocks,
+    library-chosen layout and time split): the fused max/argmax of every
+    block, then, after a reset, every template's SNR row of every block (kept
+    on the device, 17 GB). On every block the fused output must equal the max
+    of the rows and the lowest row attaining it."""
     from paper_1602_05573_amd import SpiirBank
-    banner("bank_1024 full size")
+    banner("bank_1024 full size: GPU passes")
     bank, x = bank_1024()
     N, T = len(x), bank.n_templates
     xd = torch.from_numpy(x).cuda()
-    with SpiirBank.from_bank(bank, chunk_len=256, max_block=B) as bk:
+    with SpiirBank.from_bank(bank, chunk_len=256, filters_per_lane=0, time_split=0, waves_per_group=0,
+                             max_block=B) as bk:
+        info = bk.info
         mx = torch.empty(N, dtype=torch.float32, device="cuda")
         am = torch.empty(N, dtype=torch.int32, device="cuda")
         for i in range(N // B):
             sl = slice(i * B, (i + 1) * B)
             bk.trigger_max(xd[sl], out=(mx[sl], am[sl]))
         bk.reset()
-        rows = torch.empty((len(PICK1), N), dtype=torch.float32, device="cuda")
-        snr = torch.empty((T, B), dtype=torch.float32, device="cuda")
-        pick = torch.tensor(PICK1, device="cuda")
-        ar = torch.arange(B, device="cuda")
+        rows = torch.empty((T, N), dtype=torch.float32, device="cuda")
+        bad_max, bad_arg = [], []
         for i in range(N // B):
             sl = slice(i * B, (i + 1) * B)
-            s = bk.filter_block(xd[sl], snr=snr)
-            rows[:, sl] = s.index_select(0, pick)
-            if i in SAMPLE_BLOCKS:
-                # fused epilogue = max over the plain rows, lowest index among equal values
-                m = s.max(dim=0).values
-                assert torch.equal(m, mx[sl]), "block %d: fused max differs from the rows" % i
-                first = torch.argmax((s == m[None, :]).to(torch.int8), dim=0).to(torch.int32)
-                assert torch.equal(first, am[sl]), "block %d: argmax is not the lowest maximal row" % i
+            s = bk.filter_block(xd[sl], snr=rows[:, sl])
+            m = s.max(dim=0).values
+            first = torch.argmax((s == m[None, :]).to(torch.int8), dim=0).to(torch.int32)
+            if not torch.equal(m, mx[sl]):
+                bad_max.append(i)
+            if not torch.equal(first, am[sl]):
+                bad_arg.append(i)
         torch.cuda.synchronize()
-    banner("bank_1024 oracle on templates %s" % PICK1)
-    ref = oracle.snr(bank.subset(PICK1), x)
-    got = rows.cpu().numpy()
-    err, per = snr_err(got, ref)
-    print("bank_1024 sampled-template SNR error %.3g (per template %s)" % (err, per))
-    assert err <= SNR_TOL
-    # wherever the fused argmax is a sampled template, the fused max is its oracle SNR
-    m, a = mx.cpu().numpy(), am.cpu().numpy()
+    print("bank_1024 layout %s" % info, flush=True)
+    return {"bank": bank, "x": x, "rows": rows, "mx": mx.cpu().numpy(), "am": am.cpu().numpy(),
+            "bad_max": bad_max, "bad_arg": bad_arg}
+
+
+def test_bank1024_fused_is_max_of_rows(c1):
+    """Fused epilogue = max over the per-template SNR rows, lowest index among
+    equal values, bitwise, on all 1,024 blocks."""
+    assert not c1["bad_max"], "fused max differs from the rows in blocks %s" % c1["bad_max"][:10]
+    assert not c1["bad_arg"], "argmax is not the lowest maximal row in blocks %s" % c1["bad_arg"][:10]
+
+
+def _part(c1, p):
+    """Oracle SNR of templates [128 p, 128 (p + 1)) over the whole stream
+    against the GPU rows, element by element; the part's per-sample max,
+    lowest attaining index, per-template peaks, and the oracle SNR of the
+    GPU's argmax template wherever that template is in the part."""
+    if p in _parts:
+        return _parts[p]
+    bank, x = c1["bank"], c1["x"]
+    T = bank.n_templates
+    j0, j1 = T * p // PARTS, T * (p + 1) // PARTS
+    t0 = time.time()
+    ref = oracle.snr(bank, x, templates=np.arange(j0, j1))
+    t_or = time.time() - t0
+    got = c1["rows"][j0:j1].cpu().numpy()
     P = ref.max(axis=1)
-    for r, j in enumerate(PICK1):
-        at = np.nonzero(a == j)[0]
-        if at.size:
-            assert np.max(np.abs(m[at] - ref[r, at])) <= SNR_TOL * P[r]
-        # and the max over all templates is never below a sampled template's SNR
-        assert np.all(m >= ref[r] - SNR_TOL * P[r])
-    # trigger clustering of the fused output, as bench.py runs it
+    err = np.array([np.max(np.abs(got[r].astype(np.float64) - ref[r])) / P[r] for r in range(j1 - j0)])
+    J = np.argmax(ref, axis=0)               # first (lowest) index attaining the part's max
+    M = ref[J, np.arange(ref.shape[1])]
+    g = c1["am"].astype(np.int64)
+    at = np.nonzero((g >= j0) & (g < j1))[0]
+    ref_g = ref[g[at] - j0, at]
+    _parts[p] = (M, J + j0, P, at, ref_g, err)
+    print("part %d (templates %d..%d): oracle %.1f s, max SNR error %.3g of the peak"
+          % (p, j0, j1 - 1, t_or, err.max()), flush=True)
+    del ref, got
+    return _parts[p]
+
+
+@pytest.mark.parametrize("p", range(PARTS))
+def test_bank1024_every_template_full_stream(c1, p):
+    banner("bank_1024 oracle part %d of %d" % (p, PARTS))
+    err = _part(c1, p)[5]
+    assert err.max() <= SNR_TOL, "template %d: SNR error %.3g" % (int(np.argmax(err)) + 1024 * p // PARTS,
+                                                                 err.max())
+
+
+def test_bank1024_fused_argmax_full_stream(c1):
+    """The fused max/argmax of all 4,194,304 samples against the oracle: the
+    GPU's template must be the oracle's (lowest maximal) one, or lie in the
+    admissible set A[n] = {j : ref_j >= ref_J - eps (P_j + P_J)} (a documented
+    tie); the fused max within eps of the GPU template's peak."""
+    banner("bank_1024 fused argmax over the whole stream")
+    N = len(c1["x"])
+    M = np.full(N, -1.0)
+    J = np.full(N, -1, np.int64)
+    P = []
+    ref_g = np.full(N, np.nan)
+    for p in range(PARTS):
+        m, j, pk, at, rg, _ = _part(c1, p)
+        take = (m > M) | ((m == M) & (j < J))     # merge: max, lowest index among equal values
+        M = np.where(take, m, M)
+        J = np.where(take, j, J)
+        P.append(pk)
+        ref_g[at] = rg
+    P = np.concatenate(P)
+    g = c1["am"].astype(np.int64)
+    gm = c1["mx"].astype(np.float64)
+    assert not np.isnan(ref_g).any()
+    diff = np.nonzero(g != J)[0]
+    adm = ref_g[diff] >= M[diff] - ARG_EPS * (P[g[diff]] + P[J[diff]])
+    merr = np.abs(gm - M) / P[g]
+    print("bank_1024 full stream: %d of %d samples take another template than the oracle, all inside "
+          "the admissible set: %s; max fused-max error %.3g of the template peak"
+          % (diff.size, N, bool(adm.all()), merr.max()), flush=True)
+    assert adm.all(), "argmax outside the admissible set at samples %s" % diff[~adm][:10]
+    assert merr.max() <= ARG_EPS, "fused max error %.3g" % merr.max()
+
+
+def test_bank1024_prefix_ties_counted(c1):
+    """On the first 16 blocks every template's oracle row is at hand: the
+    helper's exact rule (unique samples must match, the rest stay admissible)
+    and the number of documented ties (samples with more than one admissible
+    template)."""
+    banner("bank_1024 prefix ties")
+    n = PREFIX_BLOCKS * B
+    ref = oracle.snr(c1["bank"], c1["x"][:n])
+    ties = check_argmax(c1["mx"][:n], c1["am"][:n], ref)
+    print("bank_1024 first %d samples: %d documented ties" % (n, ties), flush=True)
+
+
+def test_bank1024_clustering_full_stream(c1):
+    """Trigger clustering of the fused output, as bench.py runs it: identical to
+    the oracle's clustering of the same series."""
     from paper_1602_05573_amd import cluster_triggers
+    m, a = c1["mx"], c1["am"]
     thr, W = float(np.quantile(m, 0.9999)), 4096
     banner("bank_1024 clustering threshold %.6g window %d" % (thr, W))
-    gi, gt, gv, total = cluster_triggers(mx, am, thr, W)
+    gi, gt, gv, total = cluster_triggers(torch.from_numpy(m).cuda(), torch.from_numpy(a).cuda(), thr, W)
     ri, rt, rv = oracle.clusters(m, a, thr, W)
-    rtotal = len(ri)
-    assert total == rtotal and total > 0
+    assert total == len(ri) and total > 0
     assert np.array_equal(gi.cpu().numpy(), ri) and np.array_equal(gt.cpu().numpy(), rt)
     assert np.array_equal(gv.cpu().numpy(), rv)
 

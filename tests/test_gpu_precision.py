@@ -1,18 +1,27 @@
 """Precision plan of the recursion at full size (64 templates x 1,000 filters,
 r ~ U[1-1e-6, 1-1e-4], 16,777,216 samples): FP32 recursion with FP64 chunk
-carries against all-FP32 and against the FP64 oracle, on sampled templates."""
+carries (for |a| > 1 - 1e-5, and for every filter) against all-FP32 and
+against the FP64 oracle, for every template over the whole stream, element
+by element; the oracle's work is split into eight parts of 8 templates (one
+test each). The fused max/argmax of the bench.py run (1,048,576-sample calls)
+is checked over every sample with the admissible-set rule."""
+import time
+
 import numpy as np
 import pytest
 
 import oracle
-from helpers import SNR_TOL, snr_err
+from helpers import ARG_EPS, SNR_TOL
 from workloads import precision_bank
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-PICK = [5, 42]
+C = 1 << 20          # samples per call, as bench.py runs the workload
+PARTS = 8
+MODES = (0, 2, 1)    # hybrid, FP64 carries for all, all-FP32
+_parts = {}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -23,34 +32,97 @@ def need_gpu():
 
 @pytest.fixture(scope="module")
 def c4():
-    bank, x = precision_bank()
-    print("[case] precision_bank oracle on templates %s" % PICK, flush=True)
-    ref = oracle.snr(bank.subset(PICK), x)
-    return bank, x, ref
-
-
-def run(bank, x, precision):
+    """Every template's SNR row over the whole stream in each precision mode
+    (kept on the device, 4.3 GB per mode), and the hybrid mode's fused
+    max/argmax."""
     from paper_1602_05573_amd import SpiirBank
-    with SpiirBank.from_bank(bank, precision=precision) as bk:
-        xd = torch.from_numpy(x).cuda()
-        out = torch.empty((len(PICK), len(x)), dtype=torch.float32)
-        # stream the whole input in 1,048,576-sample calls; keep only the sampled rows
-        snr = torch.empty((bank.n_templates, 1 << 20), dtype=torch.float32, device="cuda")
-        for c0 in range(0, len(x), 1 << 20):
-            c1 = min(len(x), c0 + (1 << 20))
-            s = bk.filter_block(xd[c0:c1], snr=snr[:, : c1 - c0] if c1 - c0 == snr.shape[1] else None)
-            out[:, c0:c1] = s[PICK].cpu()
-    return out.numpy()
+    bank, x = precision_bank()
+    N, T = len(x), bank.n_templates
+    xd = torch.from_numpy(x).cuda()
+    rows = {}
+    for prec in MODES:
+        print("[case] precision_bank GPU pass, precision=%d" % prec, flush=True)
+        with SpiirBank.from_bank(bank, precision=prec) as bk:
+            r = torch.empty((T, N), dtype=torch.float32, device="cuda")
+            for c0 in range(0, N, C):
+                c1 = min(N, c0 + C)
+                bk.filter_block(xd[c0:c1], snr=r[:, c0:c1])
+            rows[prec] = r
+            if prec == 0:
+                bk.reset()
+                mx = torch.empty(N, dtype=torch.float32, device="cuda")
+                am = torch.empty(N, dtype=torch.int32, device="cuda")
+                for c0 in range(0, N, C):
+                    c1 = min(N, c0 + C)
+                    bk.trigger_max(xd[c0:c1], out=(mx[c0:c1], am[c0:c1]))
+        torch.cuda.synchronize()
+    return {"bank": bank, "x": x, "rows": rows, "mx": mx.cpu().numpy(), "am": am.cpu().numpy()}
 
 
-@pytest.mark.parametrize("precision,must_pass", [(0, True), (2, True), (1, False)])
-def test_precision_bank_modes(c4, precision, must_pass):
-    bank, x, ref = c4
-    print("[case] precision_bank precision=%d" % precision, flush=True)
-    got = run(bank, x, precision)
-    err, per = snr_err(got, ref)
-    print("precision %d: max relative SNR error %.3g (per template %s)" % (precision, err, per))
-    if must_pass:
-        assert err <= SNR_TOL
-    else:
-        assert np.isfinite(err)
+def _part(c4, p):
+    if p in _parts:
+        return _parts[p]
+    bank, x = c4["bank"], c4["x"]
+    T = bank.n_templates
+    j0, j1 = T * p // PARTS, T * (p + 1) // PARTS
+    t0 = time.time()
+    ref = oracle.snr(bank, x, templates=np.arange(j0, j1))
+    t_or = time.time() - t0
+    P = ref.max(axis=1)
+    err = {}
+    for prec in MODES:
+        got = c4["rows"][prec][j0:j1].cpu().numpy()
+        err[prec] = np.array([np.max(np.abs(got[r].astype(np.float64) - ref[r])) / P[r] for r in range(j1 - j0)])
+    J = np.argmax(ref, axis=0)
+    M = ref[J, np.arange(ref.shape[1])]
+    g = c4["am"].astype(np.int64)
+    at = np.nonzero((g >= j0) & (g < j1))[0]
+    _parts[p] = (M, J + j0, P, at, ref[g[at] - j0, at], err)
+    print("part %d (templates %d..%d): oracle %.1f s; max relative SNR error hybrid %.3g, FP64 carries %.3g, "
+          "all-FP32 %.3g" % (p, j0, j1 - 1, t_or, err[0].max(), err[2].max(), err[1].max()), flush=True)
+    return _parts[p]
+
+
+@pytest.mark.parametrize("p", range(PARTS))
+def test_precision_bank_every_template(c4, p):
+    print("[case] precision_bank oracle part %d of %d" % (p, PARTS), flush=True)
+    err = _part(c4, p)[5]
+    assert err[0].max() <= SNR_TOL and err[2].max() <= SNR_TOL
+    assert np.isfinite(err[1]).all()
+
+
+def test_precision_bank_modes_summary(c4):
+    """The hybrid and FP64-carry modes pass the gate for all 64 templates; the
+    all-FP32 recursion is reported (it drifts by ~5e-3 near the unit circle)."""
+    e = {prec: np.concatenate([_part(c4, p)[5][prec] for p in range(PARTS)]) for prec in MODES}
+    print("precision_bank, 64 templates x 16,777,216 samples, max relative SNR error: hybrid %.3g, "
+          "FP64 carries %.3g, all-FP32 %.3g" % (e[0].max(), e[2].max(), e[1].max()), flush=True)
+    assert e[0].max() <= SNR_TOL and e[2].max() <= SNR_TOL
+    assert e[1].max() > e[0].max()
+
+
+def test_precision_bank_fused_argmax_full_stream(c4):
+    """Fused max/argmax of the hybrid mode over every sample against the
+    oracle: equal to the oracle's template or a documented tie."""
+    N = len(c4["x"])
+    M = np.full(N, -1.0)
+    J = np.full(N, -1, np.int64)
+    P = []
+    ref_g = np.full(N, np.nan)
+    for p in range(PARTS):
+        m, j, pk, at, rg, _ = _part(c4, p)
+        take = (m > M) | ((m == M) & (j < J))
+        M = np.where(take, m, M)
+        J = np.where(take, j, J)
+        P.append(pk)
+        ref_g[at] = rg
+    P = np.concatenate(P)
+    g = c4["am"].astype(np.int64)
+    assert not np.isnan(ref_g).any()
+    diff = np.nonzero(g != J)[0]
+    adm = ref_g[diff] >= M[diff] - ARG_EPS * (P[g[diff]] + P[J[diff]])
+    merr = np.abs(c4["mx"].astype(np.float64) - M) / P[g]
+    print("precision_bank full stream: %d of %d samples take another template than the oracle (all admissible: "
+          "%s); max fused-max error %.3g" % (diff.size, N, bool(adm.all()), merr.max()), flush=True)
+    assert adm.all(), "argmax outside the admissible set at samples %s" % diff[~adm][:10]
+    assert merr.max() <= ARG_EPS

@@ -207,6 +207,31 @@ def test_trigger_tie_rule_lowest_index():
         assert np.array_equal(am, first)
 
 
+def test_trigger_peaks_and_merge_of_template_subsets():
+    """Per-template peaks equal the maxima of the SNR rows; the trigger of a
+    bank equals the merge (max, lowest index among equal values) of the
+    triggers of a partition of its templates, which is how the full-size GPU
+    parity tests split the oracle's work. Duplicated templates put exact ties
+    across the parts."""
+    rng = np.random.default_rng(12)
+    base = small_bank(12, T=5, klo=2, khi=6)
+    bank = base.subset([0, 1, 2, 3, 4, 1, 0, 3])
+    x = rng.standard_normal(500)
+    s = oracle.snr(bank, x)
+    mx, am, pk = oracle.trigger(bank, x, nthreads=3, peaks=True)
+    assert np.array_equal(pk, s.max(axis=1))
+    for parts in ([[0, 1, 2], [3, 4, 5, 6, 7]], [[0, 1], [2, 3], [4, 5], [6, 7]]):
+        M = np.full(len(x), -1.0)
+        J = np.full(len(x), -1, np.int64)
+        for p in parts:
+            m, j = oracle.trigger(bank.subset(p), x, nthreads=2)
+            j = np.asarray(p)[j]
+            take = (m > M) | ((m == M) & (j < J))
+            M = np.where(take, m, M)
+            J = np.where(take, j, J)
+        assert np.array_equal(M, mx) and np.array_equal(J, am)
+
+
 def test_trigger_threads_agree():
     rng = np.random.default_rng(10)
     bank = small_bank(10, T=7, klo=2, khi=5)
