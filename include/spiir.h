@@ -166,18 +166,29 @@ int spiir_bank_set_state(spiir_bank *bank, const void *host_buf, size_t nbytes);
 
 /*
  * Filters the next n samples of the stream and writes every template's SNR.
+ * Defined by Sect. "GPU accelerated SPIIR method": subsection "SPIIR method"
+ * (a template's SNR approximated by a parallel bank of single-pole IIR
+ * filters) and subsection "Optimized GPU implementation of SPIIR" (the SNR of
+ * a template at a time point needs its parameter array and the data window,
+ * and sums the outputs of all its filters). The paper prints no formula; the
+ * recursion with an input delay and the SNR as the raw |z|^2 (no
+ * normalisation, no square root) are this library's readings, stated at the
+ * top of this file.
  *   x_dev    float32 [n], the next n samples
  *   snr_dev  float32, row-major [T][ld_snr], ld_snr >= n; row j receives snr_j
- * n = 0 is a no-op. One launch covers all templates.
+ * n = 0 is a no-op. One launch covers all templates. EINVAL for a null bank or
+ * pointer, n < 0 or ld_snr < n.
  */
 int spiir_filter_block(spiir_bank *bank, const float *x_dev, int64_t n,
                        float *snr_dev, int64_t ld_snr, void *stream);
 
 /*
  * Filters the next n samples of the stream and writes every template's
- * complex sum z_j (the quantity whose squared modulus is the SNR).
+ * complex sum z_j (the quantity whose squared modulus is the SNR; the summed
+ * filter outputs of subsection "Optimized GPU implementation of SPIIR").
  *   z_dev  complex64, row-major [T][ld_z] (interleaved), ld_z >= n
- * n = 0 is a no-op. Continues the same stream as spiir_filter_block.
+ * n = 0 is a no-op. Continues the same stream as spiir_filter_block. EINVAL as
+ * for spiir_filter_block.
  */
 int spiir_filter_block_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_dev,
                          int64_t ld_z, void *stream);
@@ -185,20 +196,24 @@ int spiir_filter_block_z(spiir_bank *bank, const float *x_dev, int64_t n, float 
 /*
  * Filters the next n samples and writes only the per-sample maximum of the
  * SNR over templates and its smallest attaining template index; the [T][n]
- * SNR is never stored (fused epilogue).
+ * SNR is never stored (fused epilogue). The paper has no trigger step: its
+ * subsection "SPIIR method" states the purpose (identifying the presence of a
+ * signal in noisy data with zero latency); the per-sample maximum over the
+ * bank, ties to the lowest template index, is this library's reading of it.
  *   x_dev       float32 [n]
  *   max_dev     float32 [n]
  *   argmax_dev  int32 [n]
+ * n = 0 is a no-op; EINVAL for a null bank or pointer or n < 0.
  */
 int spiir_trigger_max(spiir_bank *bank, const float *x_dev, int64_t n,
                       float *max_dev, int32_t *argmax_dev, void *stream);
 
 /*
  * Reference design for comparison: the same outputs as spiir_trigger_max, but
- * computed with one kernel launch per template (as in the paper's
- * template-to-block mapping), each writing that template's SNR row to
- * snr_scratch_dev (float32 [T][n], caller-owned), followed by a separate
- * max/argmax pass over the stored rows.
+ * computed template by template (the template-to-block mapping of subsection
+ * "Optimized GPU implementation of SPIIR"), each template's launches writing
+ * its SNR row to snr_scratch_dev (float32 [T][n], caller-owned), followed by
+ * a separate max/argmax pass over the stored rows.
  */
 int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t n,
                                    float *max_dev, int32_t *argmax_dev,
@@ -206,7 +221,11 @@ int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t
 
 /*
  * One-shot forward from a cold start over x[0..n), independent of the
- * bank's streaming state (which is left untouched). Writes z_j[m] as complex64
+ * bank's streaming state (which is left untouched). The forward half of the
+ * coefficient fit: the paper reports that a SPIIR bank reaches more than 99%
+ * overlap with the matched filter (subsection "SPIIR method") but gives no
+ * procedure; fitting (a_k, b_k) by gradient descent on an overlap loss is this
+ * library's extension, and this call records what its adjoint needs. Writes z_j[m] as complex64
  * into z_dev [T][n] (interleaved). If tape_out is not NULL, *tape_out receives
  * a tape holding the FP32 pair (hi, lo) carried at every chunk start of every
  * filter (n / chunk_len rounded up per filter), which spiir_backward uses to
@@ -217,7 +236,9 @@ int spiir_forward_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_de
                     spiir_tape **tape_out, void *stream);
 
 /*
- * Reverse-time adjoint of spiir_forward_z for a real loss L of z.
+ * Reverse-time adjoint of spiir_forward_z for a real loss L of z (the
+ * gradient half of the coefficient fit described at spiir_forward_z; not in
+ * the paper, derived here from the recursion by the chain rule).
  *   grad_z_dev  complex64 [T][n]: dL/dRe(z) + i dL/dIm(z)
  *   grad_a_dev, grad_b_dev  complex64 [F], caller's filter order, same convention
  * lambda_k[m] = G_j[m] + conj(a_k) lambda_k[m+1] runs backwards chunk by
@@ -236,6 +257,10 @@ int spiir_tape_destroy(spiir_tape *tape);
  * Batched streams: n_streams banks, each filtering its own stream, advanced
  * together one block per step by one persistent kernel launch recorded in a
  * HIP graph (created on stream). All banks must share filters_per_lane.
+ * Subsection "Optimized GPU implementation of SPIIR" maps templates of uneven
+ * size onto the thread hierarchy and sizes blocks for full occupancy; here the
+ * uneven unit is a (stream, workgroup) item taken from a device work list, so
+ * banks of uneven size and streams of uneven length share one launch.
  *   banks       [n_streams] banks (not used elsewhere while the batch lives)
  *   x_dev       [n_streams] float32 streams, whole, resident on the device
  *   lengths     [n_streams] samples of each stream (>= 1)
