@@ -209,6 +209,28 @@ int spiir_trigger_max(spiir_bank *bank, const float *x_dev, int64_t n,
                       float *max_dev, int32_t *argmax_dev, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as spiir_trigger_max, with the same arguments, results and stream
+ * semantics (it continues the same stream; the two may be mixed call by
+ * call), but its working memory (per-workgroup partial keys, the time split's
+ * segment states and local sums, the strain window when it is not staged in
+ * LDS) lives in a fixed 32 MiB array per device that the library holds until
+ * the process ends. It calls no hipMalloc/hipFree. Needed bytes:
+ *   groups * min(n, max_block) * 8
+ *   + (time split) 2 * segments * slots * 16 + (segments - 1) * T * segment_len * 8
+ *   + (window not in LDS) (n + max_delay + 16) * 4,
+ * each rounded up to 256; the 1,024-template bank at 4,096 samples per call
+ * needs 7.9 MB. EINVAL (nothing launched) when a call needs more than 32 MiB;
+ * otherwise as spiir_trigger_max. Every call on one device shares that
+ * device's array, which keeps the last call's contents: calls that overlap in
+ * time on one device (several streams or host threads) race and must not be
+ * issued; calls on one stream are ordered and safe.
+ */
+int spiir_trigger_max_noalloc(spiir_bank *bank, const float *x_dev, int64_t n,
+                              float *max_dev, int32_t *argmax_dev, void *stream);
+
+/*
  * Reference design for comparison: the same outputs as spiir_trigger_max, but
  * computed template by template (the template-to-block mapping of subsection
  * "Optimized GPU implementation of SPIIR"), each template's launches writing

@@ -31,6 +31,7 @@ EXPORTS = (
     "spiir_whitener_get_psd", "spiir_whitener_process", "spiir_whitener_reset",
     "spiir_trigger_stream_create", "spiir_trigger_stream_push", "spiir_trigger_stream_flush",
     "spiir_trigger_stream_reset", "spiir_trigger_stream_destroy",
+    "spiir_trigger_max_noalloc",
     "spiir_last_error", "spiir_version",
 )
 
@@ -88,6 +89,7 @@ def load():
         "spiir_bank_set_state": (ctypes.c_int, [P, P, SZ]),
         "spiir_filter_block": (ctypes.c_int, [P, P, I64, P, I64, P]),
         "spiir_trigger_max": (ctypes.c_int, [P, P, I64, P, P, P]),
+        "spiir_trigger_max_noalloc": (ctypes.c_int, [P, P, I64, P, P, P]),
         "spiir_trigger_max_per_template": (ctypes.c_int, [P, P, I64, P, P, P, P]),
         "spiir_forward_z": (ctypes.c_int, [P, P, I64, P, PP, P]),
         "spiir_backward": (ctypes.c_int, [P, P, P, P, P, P]),

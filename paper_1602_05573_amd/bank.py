@@ -169,6 +169,20 @@ class SpiirBank:
         call("spiir_trigger_max", self._h, _ptr(x), n, _ptr(mx), _ptr(am), _stream_ptr(stream))
         return mx, am
 
+    def trigger_max_noalloc(self, x: torch.Tensor, out, stream=None):
+        """trigger_max whose working memory is the library's fixed per-device
+        array (no device allocation in the call); out = (max float32 [n],
+        argmax int32 [n]) is required."""
+        _require_cuda(x, torch.float32, "x")
+        n = x.numel()
+        mx, am = out
+        _require_cuda(mx, torch.float32, "max")
+        _require_cuda(am, torch.int32, "argmax")
+        if mx.numel() < n or am.numel() < n:
+            raise ValueError("outputs hold fewer than len(x) samples")
+        call("spiir_trigger_max_noalloc", self._h, _ptr(x), n, _ptr(mx), _ptr(am), _stream_ptr(stream))
+        return mx, am
+
     def trigger_max_per_template(self, x: torch.Tensor, out=None, snr_scratch=None, stream=None):
         """Same outputs as trigger_max via one launch per template plus a max pass."""
         _require_cuda(x, torch.float32, "x")

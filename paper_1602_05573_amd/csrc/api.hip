@@ -248,6 +248,35 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->ysub); dfree(bk->blam); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
 }
 
+// Working memory of the allocation-free trigger call (spiir_trigger_max_noalloc):
+// one array per device, held until the process ends. Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in): its device
+// address is looked up once per device with that device current and kept.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's scratch array; the device must be current.
+int scratch_setup(int dev, unsigned char **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(SPIIR_ENODEV, "device %d: no allocation-free scratch slot (ordinals below %d)", dev,
+                    kScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SPIIR_EHIP, "scratch symbol address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return SPIIR_OK;
+}
+
 // seg_cap: most time segments the automatic time split may choose (8 for
 // banks created through the ABI; the multi-rate object allows more for its
 // small levels, whose calls are short serial recursions).
@@ -267,6 +296,9 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     rc = device_facts(dev, df);
     if (rc) return rc;
     DeviceGuard guard(dev);
+    unsigned char *scr = nullptr;
+    rc = scratch_setup(dev, &scr);
+    if (rc) return rc;
 
     const int L = o.chunk_len ? o.chunk_len : 256;
     int max_block = o.max_block ? o.max_block : 16384;
@@ -399,24 +431,49 @@ int ensure_xwin(spiir_bank *bk, int64_t need) {
     return SPIIR_OK;
 }
 
-// Shared driver of the streaming calls (snr rows or fused keys).
+// Working buffers of one streaming call besides the bank's state and history:
+// per-workgroup partial keys [groups][keys_ld], the time split's segment
+// states and local z, and the strain window when it is not staged in LDS.
+struct CallScratch {
+    uint64_t *keys = nullptr;
+    int64_t keys_ld = 0;
+    float4 *seg_end = nullptr, *seg_start = nullptr;
+    float2 *zl = nullptr;
+    float *xwin = nullptr;
+};
+
+// Shared driver of the streaming calls (snr rows or fused keys). cs = null:
+// the bank's own buffers (the global strain window grown on demand).
 int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr, int64_t ld,
-                float *mx, int32_t *am, hipStream_t st) {
+                float *mx, int32_t *am, hipStream_t st, const CallScratch *cs = nullptr) {
     DeviceGuard guard(bk->device);
     const float *hist = bk->hist[bk->hist_cur];
+    float *xwin = bk->xwin;
     if (!bk->xlds) {
-        int rc = ensure_xwin(bk, n + bk->dmax);
-        if (rc) return rc;
-        HIPCHK(launch_window_fill(bk->xwin, hist, x, n, bk->dmax, st));
+        if (cs) {
+            xwin = cs->xwin;
+        } else {
+            int rc = ensure_xwin(bk, n + bk->dmax);
+            if (rc) return rc;
+            xwin = bk->xwin;
+        }
+        HIPCHK(launch_window_fill(xwin, hist, x, n, bk->dmax, st));
     }
+    uint64_t *keys = cs ? cs->keys : bk->keys;
+    const int64_t keys_ld = cs ? cs->keys_ld : bk->max_block;
     bool hist_done = false;
     for (int64_t P = 0; P < n; P += bk->max_block) {
         const int64_t np = std::min<int64_t>(bk->max_block, n - P);
         FwdArgs a = bk->base_args();
+        if (cs) {
+            a.seg_end = cs->seg_end;
+            a.seg_start = cs->seg_start;
+            a.zl = cs->zl;
+        }
         a.state = bk->state;
         a.x = x;
         a.hist = hist;
-        a.xwin = bk->xwin;
+        a.xwin = xwin;
         a.xbase = P;
         a.n = np;
         a.obase = P;
@@ -427,8 +484,8 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.z = reinterpret_cast<float2 *>(snr);
             a.ld = ld;
         } else {
-            a.keys = bk->keys;
-            a.ld = bk->max_block;
+            a.keys = keys;
+            a.ld = keys_ld;
         }
         int nseg = 1;
         if (bk->nseg > 1) {
@@ -452,7 +509,7 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
         else
             HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev));
         if (mode == kModeKeys) {
-            HIPCHK(launch_finalize_keys(bk->keys, bk->lay.groups, bk->max_block, np, mx + P, am + P, st,
+            HIPCHK(launch_finalize_keys(keys, bk->lay.groups, keys_ld, np, mx + P, am + P, st,
                                         last ? &hc : nullptr));
             hist_done = hist_done || last;
         }
@@ -724,6 +781,62 @@ int spiir_trigger_max(spiir_bank *bk, const float *x, int64_t n, float *mx, int3
     if (n == 0) return SPIIR_OK;
     if (!x || !mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
     return stream_call(bk, x, n, kModeKeys, nullptr, 0, mx, am, as_stream(stream));
+}
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The allocation-free call's buffers carved from the device's scratch array
+// (scr = null: only the size). Bytes needed, or 0 with an error set.
+size_t plan_scratch(const spiir_bank *bk, int64_t n, unsigned char *scr, CallScratch &cs) {
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = scr ? scr + at : nullptr;
+        at += align256(bytes);
+        return p;
+    };
+    const int64_t keys_ld = std::min<int64_t>(n, bk->max_block);
+    cs.keys_ld = keys_ld;
+    cs.keys = reinterpret_cast<uint64_t *>(take((size_t)bk->lay.groups * keys_ld * sizeof(uint64_t)));
+    const size_t seg_bytes = (size_t)bk->nseg * bk->lay.nslots * sizeof(float4);
+    if (bk->nseg > 1) {
+        cs.seg_end = reinterpret_cast<float4 *>(take(seg_bytes));
+        cs.seg_start = reinterpret_cast<float4 *>(take(seg_bytes));
+        cs.zl = reinterpret_cast<float2 *>(
+            take((size_t)(bk->nseg - 1) * bk->T * bk->seg_len_max * sizeof(float2)));
+    }
+    if (!bk->xlds) cs.xwin = reinterpret_cast<float *>(take((size_t)(n + bk->dmax + 16) * sizeof(float)));
+    return at;
+}
+
+}  // namespace
+
+int spiir_trigger_max_noalloc(spiir_bank *bk, const float *x, int64_t n, float *mx, int32_t *am, void *stream) {
+    if (!bk) return fail(SPIIR_EINVAL, "bank is null");
+    if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
+    if (n == 0) return SPIIR_OK;
+    if (!x || !mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
+    CallScratch cs;
+    const size_t need = plan_scratch(bk, n, nullptr, cs);
+    if (need > kScratchBytes)
+        return fail(SPIIR_EINVAL,
+                    "this call needs %zu bytes of working memory, more than the %zu bytes the allocation-free "
+                    "call holds per device (fewer samples per call, or spiir_trigger_max)",
+                    need, kScratchBytes);
+    DeviceGuard guard(bk->device);
+    unsigned char *scr = nullptr;
+    const int rc = scratch_setup(bk->device, &scr);   // the address looked up when the bank was created
+    if (rc) return rc;
+    plan_scratch(bk, n, scr, cs);
+    hipStream_t st = as_stream(stream);
+    if (bk->nseg > 1) {
+        // slots outside every template are chained from these buffers; start them at zero as the bank's own
+        const size_t seg_bytes = (size_t)bk->nseg * bk->lay.nslots * sizeof(float4);
+        HIPCHK(launch_fill_zero(cs.seg_end, seg_bytes, st));
+        HIPCHK(launch_fill_zero(cs.seg_start, seg_bytes, st));
+    }
+    return stream_call(bk, x, n, kModeKeys, nullptr, 0, mx, am, st, &cs);
 }
 
 int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, float *mx, int32_t *am,
