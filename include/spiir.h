@@ -231,11 +231,20 @@ int spiir_trigger_max_noalloc(spiir_bank *bank, const float *x_dev, int64_t n,
                               float *max_dev, int32_t *argmax_dev, void *stream);
 
 /*
- * Reference design for comparison: the same outputs as spiir_trigger_max, but
- * computed template by template (the template-to-block mapping of subsection
+ * Reference design for comparison: the same outputs as spiir_trigger_max
+ * (within the same error against the FP64 oracle; not bitwise), but computed
+ * template by template (the template-to-block mapping of subsection
  * "Optimized GPU implementation of SPIIR"), each template's launches writing
  * its SNR row to snr_scratch_dev (float32 [T][n], caller-owned), followed by
- * a separate max/argmax pass over the stored rows.
+ * a separate max/argmax pass over the stored rows. Each template's launches
+ * fill the device on their own: every piece of at most max_block samples is
+ * cut into segments of chunk_len samples, one workgroup each, whose carries
+ * are chained in FP64 (three launches per template and piece; one launch
+ * when the piece is a single chunk); their strain is read from a window of
+ * the call's samples in global memory. The segment scratch (two states per
+ * slot of one workgroup and segment, one complex sum per template-sample)
+ * and the window are allocated on first use. Continues the same stream as spiir_trigger_max.
+ * n = 0 is a no-op; EINVAL for a null bank or pointer or n < 0.
  */
 int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t n,
                                    float *max_dev, int32_t *argmax_dev,

@@ -115,6 +115,10 @@ struct spiir_bank {
     size_t lds_carry = 0;
     float4 *seg_end = nullptr, *seg_start = nullptr;
     float2 *zl = nullptr;
+    // per-template comparator: segment states [pl_cap][one workgroup's slots], local z [pl_cap - 1][T][L]
+    float4 *pl_seg_end = nullptr, *pl_seg_start = nullptr;
+    float2 *pl_zl = nullptr;
+    int pl_cap = 0;
     int tsplit_opt = 0;           // opts.time_split as given (the adjoint honours it too)
     // adjoint scratch, grown on demand: ysub [cap][ceil(L/kSub)][S], lam [2][cap][S], gpart [cap][2][S]
     int bwd_cap = 0;
@@ -146,6 +150,8 @@ struct spiir_bank {
         p.n_templates = T;
         p.seg_end = seg_end;
         p.seg_start = seg_start;
+        p.seg_slot0 = 0;
+        p.seg_stride = lay.nslots;
         p.zl = zl;
         return p;
     }
@@ -246,6 +252,8 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
     dfree(bk->ysub); dfree(bk->blam); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
+    dfree(bk->pl_seg_end); dfree(bk->pl_seg_start); dfree(bk->pl_zl);
+    bk->pl_cap = 0;
 }
 
 // Working memory of the allocation-free trigger call (spiir_trigger_max_noalloc):
@@ -848,13 +856,42 @@ int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, fl
     DeviceGuard guard(bk->device);
     hipStream_t st = as_stream(stream);
     const float *hist = bk->hist[bk->hist_cur];
-    if (!bk->xlds) {
+    // The strain window stays in global memory: a segment workgroup reads only
+    // its template's delayed samples for one chunk instead of staging the
+    // whole max_delay + chunk window in LDS.
+    {
         int rc = ensure_xwin(bk, n + bk->dmax);
         if (rc) return rc;
         HIPCHK(launch_window_fill(bk->xwin, hist, x, n, bk->dmax, st));
     }
+    // Each template's launch fills the device by itself: its block is cut into
+    // segments of one chunk (L samples), one workgroup per segment, chained in
+    // FP64 as in the bank's own time split, over that template's workgroup only.
+    const int L = bk->L;
+    const int64_t gslots = (int64_t)bk->lay.wpg * bk->lay.fl * 64;   // slots of one workgroup
+    const int nseg_max = (int)((std::min<int64_t>(n, bk->max_block) + L - 1) / L);
+    if (nseg_max >= 2 && bk->pl_cap < nseg_max) {
+        HIPCHK(hipDeviceSynchronize());
+        dfree(bk->pl_seg_end);
+        dfree(bk->pl_seg_start);
+        dfree(bk->pl_zl);
+        bk->pl_cap = 0;
+        hipError_t e = dalloc(&bk->pl_seg_end, (size_t)nseg_max * gslots);
+        if (e == hipSuccess) e = dalloc(&bk->pl_seg_start, (size_t)nseg_max * gslots);
+        if (e == hipSuccess) e = dalloc(&bk->pl_zl, (size_t)(nseg_max - 1) * bk->T * L);
+        if (e == hipSuccess) e = launch_fill_zero(bk->pl_seg_end, (size_t)nseg_max * gslots * sizeof(float4), st);
+        if (e == hipSuccess) e = launch_fill_zero(bk->pl_seg_start, (size_t)nseg_max * gslots * sizeof(float4), st);
+        if (e != hipSuccess) {
+            dfree(bk->pl_seg_end);
+            dfree(bk->pl_seg_start);
+            dfree(bk->pl_zl);
+            return fail(SPIIR_ENOMEM, "per-template scratch allocation failed: %s", hipGetErrorString(e));
+        }
+        bk->pl_cap = nseg_max;
+    }
     for (int64_t P = 0; P < n; P += bk->max_block) {
         const int64_t np = std::min<int64_t>(bk->max_block, n - P);
+        const int nseg = (int)((np + L - 1) / L);
         for (int j = 0; j < bk->T; ++j) {
             FwdArgs a = bk->base_args();
             a.state = bk->state;
@@ -868,7 +905,19 @@ int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, fl
             a.ld = n;
             a.only_tpl = j;
             a.gbase = bk->lay.tpl_group[j];
-            HIPCHK(launch_forward(a, kModeSnr, bk->lay.fl, bk->tt, bk->xlds, 1, bk->lds, st));
+            a.groups = 1;
+            if (nseg >= 2) {
+                a.seg_len = L;
+                a.seg_end = bk->pl_seg_end;
+                a.seg_start = bk->pl_seg_start;
+                a.zl = bk->pl_zl;
+                a.seg_slot0 = (int64_t)a.gbase * gslots;
+                a.seg_stride = gslots;
+                HIPCHK(launch_forward_split(a, kModeSnr, bk->lay.fl, bk->tt, false, nseg, bk->lds_carry, bk->lds_carry,
+                                            bk->slot_filter, st, KernelEvents()));
+            } else {
+                HIPCHK(launch_forward(a, kModeSnr, bk->lay.fl, bk->tt, false, 1, bk->lds_carry, st));
+            }
         }
     }
     HIPCHK(launch_rows_argmax(snr, bk->T, n, n, mx, am, st));

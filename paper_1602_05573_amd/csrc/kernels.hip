@@ -334,8 +334,9 @@ __device__ __forceinline__ void carry_correct(Lane<FL> &s, const SlotArrays &sa,
 // Time range and data routing of one workgroup item.
 struct SegCtx {
     int64_t tb, tn;          // launch samples [tb, tb + tn)
-    const float4 *st_in;     // initial state per slot (null: cold start)
-    float4 *st_out;          // final state per slot (null: not stored)
+    const float4 *st_in;     // initial state per slot (null: cold start), entry slot - in_off
+    float4 *st_out;          // final state per slot (null: not stored), entry slot - out_off
+    int64_t in_off, out_off;
     float2 *zl_out;          // local z goes here ([T][ld_zl]) instead of the mode's output
     const float2 *zl_in;     // added to z before the mode's output (carry pass)
     int64_t ld_zl;
@@ -389,7 +390,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
             s.xo[f] = p.s.xoff[s.slot(f)];
             s.flags |= (unsigned)(p.s.flags[s.slot(f)] & 1) << f;
             float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (sc.st_in) st = sc.st_in[s.slot(f)];
+            if (sc.st_in) st = sc.st_in[s.slot(f) - sc.in_off];
             s.yr[f] = st.x; s.yi[f] = st.y; s.l0r[f] = st.z; s.l0i[f] = st.w;
         } else {
             s.ar[f] = s.ai[f] = s.br[f] = s.bi[f] = 0.f;
@@ -524,7 +525,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
     if (ract && sc.st_out) {
 #pragma unroll
         for (int f = 0; f < FL; ++f)
-            sc.st_out[s.slot(f)] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
+            sc.st_out[s.slot(f) - sc.out_off] = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
     }
 }
 
@@ -534,6 +535,8 @@ __device__ __forceinline__ SegCtx whole_launch(const FwdArgs &p) {
     sc.tn = p.n;
     sc.st_in = p.state;
     sc.st_out = p.state;
+    sc.in_off = 0;
+    sc.out_off = 0;
     sc.zl_out = nullptr;
     sc.zl_in = nullptr;
     sc.ld_zl = 0;
@@ -553,12 +556,14 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
 template <int FL, int TT, int MODE, bool XLDS>
 __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int g = blockIdx.x % p.groups, seg = blockIdx.x / p.groups;
+    const int g = p.gbase + blockIdx.x % p.groups, seg = blockIdx.x / p.groups;
     SegCtx sc;
     sc.tb = (int64_t)seg * p.seg_len;
     sc.tn = min(p.seg_len, p.n - sc.tb);
     sc.st_in = seg == 0 ? p.state : nullptr;
-    sc.st_out = p.seg_end + (int64_t)seg * p.nslots;
+    sc.st_out = p.seg_end + (int64_t)seg * p.seg_stride;
+    sc.in_off = 0;
+    sc.out_off = p.seg_slot0;
     if (MODE == kModeZ) {  // the local z goes straight to the output rows; the carry pass adds to it
         sc.zl_out = seg == 0 ? nullptr : p.z + p.obase + sc.tb;
         sc.ld_zl = p.ld;
@@ -575,12 +580,14 @@ __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
 template <int FL, int TT, int MODE>
 __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int g = blockIdx.x % p.groups, seg = 1 + blockIdx.x / p.groups;
+    const int g = p.gbase + blockIdx.x % p.groups, seg = 1 + blockIdx.x / p.groups;
     SegCtx sc;
     sc.tb = (int64_t)seg * p.seg_len;
     sc.tn = min(p.seg_len, p.n - sc.tb);
-    sc.st_in = p.seg_start + (int64_t)seg * p.nslots;
+    sc.st_in = p.seg_start + (int64_t)seg * p.seg_stride;
     sc.st_out = nullptr;
+    sc.in_off = p.seg_slot0;
+    sc.out_off = 0;
     sc.zl_out = nullptr;
     if (MODE == kModeZ) {
         sc.zl_in = p.z + p.obase + sc.tb;
@@ -632,27 +639,33 @@ __device__ __forceinline__ void chain_segments(const float4 *seg_end, float4 *se
 
 // Time split, carry chain: c_{s+1} = a^len_s c_s + e_s in FP64 per slot, from
 // the true end of segment 0; writes every segment's true start state and the
-// launch's final state.
-__global__ void seg_chain_kernel(const float4 *seg_end, float4 *seg_start, float4 *state, const double2 *a64,
-                                 const float2 *a32, int prec, int64_t nslots, int nseg, int64_t seg_len,
-                                 int64_t n, HistCopy hc, unsigned chain_blocks) {
-    if (blockIdx.x >= chain_blocks) {   // the history copy (hc.dmax > 0), 256 samples per block
+// launch's final state. Covers slots [seg_slot0, seg_slot0 + seg_stride) of
+// the segment buffers; with only_tpl >= 0 only that template's slots (the
+// other slots' entries were not written by the segment pass).
+__global__ void seg_chain_kernel(FwdArgs p, int fl, int nseg, unsigned chain_blocks) {
+    if (blockIdx.x >= chain_blocks) {   // the history copy (hist_next.dmax > 0), 256 samples per block
         const int i = (int)(blockIdx.x - chain_blocks) * 256 + (int)threadIdx.x;
-        if (i < hc.dmax) hist_copy_at(hc, i);
+        if (i < p.hist_next.dmax) hist_copy_at(p.hist_next, i);
         return;
     }
-    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (sl >= nslots) return;  // every slot, padding included (its states stay zero)
-    const float4 e0 = seg_end[sl];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.seg_stride) return;  // every slot, padding included (its states stay zero)
+    const int64_t sl = p.seg_slot0 + i;
+    if (p.only_tpl >= 0) {
+        // slot = ((group * wpg + wave) * fl + f) * 64 + lane; row = 4 (group * wpg + wave) + lane / 16
+        const RowInfo ri = p.rows[((sl >> 6) / fl) * 4 + ((sl & 63) >> 4)];
+        if (ri.tpl != p.only_tpl) return;
+    }
+    const float4 e0 = p.seg_end[i];
     double cr = (double)e0.x + (double)e0.z, ci = (double)e0.y + (double)e0.w;
-    double2 a = a64[sl];
-    if (prec == kPrecFp32) {  // the all-FP32 mode propagates with the rounded coefficient
-        const float2 r = a32[sl];
+    double2 a = p.s.a64[sl];
+    if (p.prec == kPrecFp32) {  // the all-FP32 mode propagates with the rounded coefficient
+        const float2 r = p.s.a32[sl];
         a = make_double2((double)r.x, (double)r.y);
     }
-    chain_segments(seg_end, seg_start, nslots, sl, a, nseg, seg_len, n, cr, ci);
+    chain_segments(p.seg_end, p.seg_start, p.seg_stride, i, a, nseg, p.seg_len, p.n, cr, ci);
     const float hr = (float)cr, hi = (float)ci;
-    state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+    p.state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
 }
 
 // Persistent batch kernel: workgroups pop (stream, group) items until the list
@@ -719,6 +732,8 @@ __global__ void __launch_bounds__(512) batch_seg_kernel(const BatchStream *strea
     sc.tn = min(a.seg_len, n - sc.tb);
     sc.st_in = seg == 0 ? a.state : nullptr;
     sc.st_out = a.seg_end + (int64_t)seg * a.nslots;
+    sc.in_off = 0;
+    sc.out_off = 0;
     sc.zl_out = seg == 0 ? nullptr : a.zl + (int64_t)(seg - 1) * a.n_templates * a.seg_len;
     sc.zl_in = nullptr;
     sc.ld_zl = a.seg_len;
@@ -741,6 +756,8 @@ __global__ void __launch_bounds__(512) batch_carry_kernel(const BatchStream *str
     sc.tn = min(a.seg_len, n - sc.tb);
     sc.st_in = a.seg_start + (int64_t)seg * a.nslots;
     sc.st_out = nullptr;
+    sc.in_off = 0;
+    sc.out_off = 0;
     sc.zl_out = nullptr;
     sc.zl_in = a.zl + (int64_t)(seg - 1) * a.n_templates * a.seg_len;
     sc.ld_zl = a.seg_len;
@@ -1247,11 +1264,10 @@ hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_car
                           (uint32_t)lds, st, ev.start, (hipEvent_t) nullptr, 0u, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned nb = (unsigned)((a.nslots + 255) / 256);
+    const unsigned nb = (unsigned)((a.seg_stride + 255) / 256);
     const unsigned hb = a.hist_next.dmax > 0 ? (unsigned)((a.hist_next.dmax + 255) / 256) : 0u;
     (void)slot_filter;
-    hipLaunchKernelGGL(seg_chain_kernel, dim3(nb + hb), dim3(256), 0, st, a.seg_end, a.seg_start, a.state, a.s.a64,
-                       a.s.a32, a.prec, a.nslots, nseg, a.seg_len, a.n, a.hist_next, nb);
+    hipLaunchKernelGGL(seg_chain_kernel, dim3(nb + hb), dim3(256), 0, st, a, FL, nseg, nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),

@@ -62,6 +62,9 @@ struct FwdArgs {
     float4 *seg_start;    // [nseg][nslots] true state at each segment start (segments > 0)
     float2 *zl;           // [nseg - 1][T][seg_len] local z of segments > 0
     HistCopy hist_next;   // time split: history copy done by the chain launch (dmax 0: none)
+    // seg_end / seg_start hold slots [seg_slot0, seg_slot0 + seg_stride) of every segment
+    // (entry [seg][slot - seg_slot0]); the whole bank: 0 and nslots
+    int64_t seg_slot0, seg_stride;
 };
 
 struct BwdArgs {

@@ -80,16 +80,46 @@ def test_fused_equals_max_of_plain_rows(c0):
     assert np.array_equal(am.cpu().numpy(), first)
 
 
-def test_per_template_launches_match_fused(c0):
-    bank, x, _ = c0
-    banner("per-template vs fused")
+@pytest.mark.parametrize("L,cuts", [(256, (0, 16384)), (16, (0, 5000, 16384)), (64, (0, 3001, 9000, 16384))])
+def test_per_template_launches_parity(c0, L, cuts):
+    """The per-template comparator (each template's launches split into
+    chunk-length segments over that template's workgroup only; here all four
+    templates share one workgroup) over several calls of one stream, pieces
+    of 4,096 samples and ragged tails: every template's SNR row of every call
+    within the gate, and the max/argmax by the argmax rule."""
+    bank, x, ref = c0
+    banner("per-template L=%d cuts %s" % (L, cuts))
     xd = dev(x)
-    # the per-template comparator never splits a launch in time; compare like with like
-    with mk(bank, time_split=1) as b1, mk(bank, time_split=1) as b2:
-        m1, a1 = b1.trigger_max(xd)
-        m2, a2 = b2.trigger_max_per_template(xd)
+    n = len(x)
+    mx = torch.empty(n, dtype=torch.float32, device="cuda")
+    am = torch.empty(n, dtype=torch.int32, device="cuda")
+    with mk(bank, chunk_len=L, max_block=4096, filters_per_lane=1, waves_per_group=8) as bk:
+        assert bk.info["n_groups"] == 1
+        for c0_, c1_ in zip(cuts[:-1], cuts[1:]):
+            rows = torch.empty((bank.n_templates, c1_ - c0_), dtype=torch.float32, device="cuda")
+            bk.trigger_max_per_template(xd[c0_:c1_], out=(mx[c0_:c1_], am[c0_:c1_]), snr_scratch=rows)
+            err, _ = snr_err(rows.cpu().numpy(), ref[:, c0_:c1_])
+            assert err <= SNR_TOL, "samples %d..%d: SNR error %.3g" % (c0_, c1_, err)
         torch.cuda.synchronize()
-    assert torch.equal(m1, m2) and torch.equal(a1, a2)
+    check_argmax(mx.cpu().numpy(), am.cpu().numpy(), ref)
+
+
+def test_per_template_launches_many_groups(mid):
+    """Several workgroups of several templates each: the per-template launches
+    leave every other template's state alone (two calls of one stream)."""
+    bank, x, ref = mid
+    banner("per-template, many groups")
+    xd = dev(x)
+    n = len(x)
+    mx = torch.empty(n, dtype=torch.float32, device="cuda")
+    am = torch.empty(n, dtype=torch.int32, device="cuda")
+    h = n // 2 + 37
+    with mk(bank, chunk_len=64, max_block=4096, filters_per_lane=2, waves_per_group=8) as bk:
+        assert bk.info["n_groups"] >= 2
+        bk.trigger_max_per_template(xd[:h], out=(mx[:h], am[:h]))
+        bk.trigger_max_per_template(xd[h:], out=(mx[h:], am[h:]))
+        torch.cuda.synchronize()
+    check_argmax(mx.cpu().numpy(), am.cpu().numpy(), ref)
 
 
 def test_determinism(c0):
