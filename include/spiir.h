@@ -258,10 +258,10 @@ int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t
  * procedure; fitting (a_k, b_k) by gradient descent on an overlap loss is this
  * library's extension, and this call records what its adjoint needs. Writes z_j[m] as complex64
  * into z_dev [T][n] (interleaved). If tape_out is not NULL, *tape_out receives
- * a tape holding the FP32 pair (hi, lo) carried at every chunk start of every
- * filter (n / chunk_len rounded up per filter), which spiir_backward uses to
- * recompute y chunk by chunk instead of storing every y_k. The tape keeps a
- * reference to x_dev: keep x_dev alive and unchanged until spiir_backward.
+ * a tape for spiir_backward: a device copy of the call's strain (with
+ * max_delay leading zeros) and the coefficient version it ran with; no filter
+ * output or state is stored (the adjoint does not need y, see
+ * spiir_backward). x_dev may be reused once the call's work has completed.
  */
 int spiir_forward_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_dev,
                     spiir_tape **tape_out, void *stream);
@@ -272,11 +272,17 @@ int spiir_forward_z(spiir_bank *bank, const float *x_dev, int64_t n, float *z_de
  * the paper, derived here from the recursion by the chain rule).
  *   grad_z_dev  complex64 [T][n]: dL/dRe(z) + i dL/dIm(z)
  *   grad_a_dev, grad_b_dev  complex64 [F], caller's filter order, same convention
- * lambda_k[m] = G_j[m] + conj(a_k) lambda_k[m+1] runs backwards chunk by
- * chunk; y is recomputed from the tape; grad_b_k = sum_m lambda_k[m] x[m-d_k],
- * grad_a_k = sum_m lambda_k[m] conj(y_k[m-1]). Per-chunk sums are FP32 and
- * are accumulated across chunks in FP64. Returns SPIIR_ESTATE if the tape
- * belongs to another bank or the coefficients changed since it was made.
+ * lambda_k[m] = G_j[m] + conj(a_k) lambda_k[m+1] runs backwards from
+ * lambda_k[n] = 0; grad_b_k = sum_m lambda_k[m] x[m-d_k] and
+ * grad_a_k = sum_m lambda_k[m] conj(y_k[m-1]). The library forms the second
+ * sum without y: from a cold start it equals conj(b_k) sum_m nu_k[m] x[m-d_k]
+ * with nu_k[m] = lambda_k[m+1] + conj(a_k) nu_k[m+1] (nu_k[n-1] = 0), a second
+ * reverse recursion run beside lambda. The pair is carried in FP32 with an
+ * FP32 correction for fl32(a_k) every chunk_len samples; time segments (see
+ * spiir_bank_opts.time_split) are composed in FP64. Per-chunk sums are FP32
+ * and are accumulated across chunks in FP64. Returns SPIIR_ESTATE if the tape
+ * belongs to another bank or the coefficients changed since it was made;
+ * EINVAL for null pointers.
  */
 int spiir_backward(spiir_bank *bank, const spiir_tape *tape, const float *grad_z_dev,
                    float *grad_a_dev, float *grad_b_dev, void *stream);

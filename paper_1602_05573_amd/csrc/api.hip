@@ -99,7 +99,9 @@ struct spiir_bank {
     uint64_t coeff_version = 1;
     // device buffers
     float2 *a32 = nullptr, *b32 = nullptr;
-    int32_t *xoff = nullptr, *flags = nullptr, *slot_filter = nullptr;
+    int32_t *xoff = nullptr, *flags = nullptr, *slot_filter = nullptr, *filter_slot = nullptr;
+    int4 *bwaves = nullptr;       // backward waves: (template, first filter, end filter, 0)
+    int n_bwaves = 0;
     double2 *aL = nullptr, *dL = nullptr, *a64 = nullptr;
     float4 *state = nullptr, *zstate = nullptr;
     RowInfo *rows = nullptr;
@@ -109,7 +111,6 @@ struct spiir_bank {
     uint64_t *keys = nullptr;
     float *xwin = nullptr;
     int64_t xwin_cap = 0;
-    float2 *ysub = nullptr;
     int nseg = 1;                 // time segments per streaming launch
     int64_t seg_len_max = 0;
     size_t lds_carry = 0;
@@ -120,9 +121,9 @@ struct spiir_bank {
     float2 *pl_zl = nullptr;
     int pl_cap = 0;
     int tsplit_opt = 0;           // opts.time_split as given (the adjoint honours it too)
-    // adjoint scratch, grown on demand: ysub [cap][ceil(L/kSub)][S], lam [2][cap][S], gpart [cap][2][S]
+    // adjoint scratch, grown on demand: (lambda, nu) pairs [2][cap][S], gpart [cap][2][S]
     int bwd_cap = 0;
-    float2 *blam = nullptr;
+    float4 *bpair = nullptr;
     double2 *bgpart = nullptr;
     // optional kernel timing ring (spiir_bank_time_kernels)
     std::vector<hipEvent_t> tev0, tev1;
@@ -157,11 +158,14 @@ struct spiir_bank {
     }
 };
 
+// What the adjoint needs from a forward_z call: the strain window of the call
+// (the backward reads x[m - d] for every filter) and the coefficient version
+// the forward ran with. No filter state is kept: the a-gradient is formed from
+// a second reverse recursion instead of the forward outputs.
 struct spiir_tape {
     spiir_bank *bank = nullptr;
     uint64_t coeff_version = 0;
-    int64_t n = 0, nchunks = 0;
-    float4 *tape = nullptr;
+    int64_t n = 0;
     float *xwin = nullptr;
 };
 
@@ -249,9 +253,10 @@ void timer_free(spiir_bank *bk) {
 void free_bank_buffers(spiir_bank *bk) {
     timer_free(bk);
     dfree(bk->a32); dfree(bk->b32); dfree(bk->xoff); dfree(bk->flags); dfree(bk->slot_filter);
+    dfree(bk->filter_slot); dfree(bk->bwaves);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
-    dfree(bk->ysub); dfree(bk->blam); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
+    dfree(bk->bpair); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
     dfree(bk->pl_seg_end); dfree(bk->pl_seg_start); dfree(bk->pl_zl);
     bk->pl_cap = 0;
 }
@@ -391,7 +396,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     A(dalloc(&bk->a32, S)); A(dalloc(&bk->b32, S)); A(dalloc(&bk->xoff, S)); A(dalloc(&bk->flags, S));
-    A(dalloc(&bk->slot_filter, S)); A(dalloc(&bk->aL, S)); A(dalloc(&bk->dL, S)); A(dalloc(&bk->a64, S));
+    A(dalloc(&bk->slot_filter, S)); A(dalloc(&bk->filter_slot, (size_t)bk->F)); A(dalloc(&bk->aL, S)); A(dalloc(&bk->dL, S)); A(dalloc(&bk->a64, S));
     A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->rows, (size_t)G * wpg * 4));
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
     A(dalloc(&bk->keys, (size_t)G * max_block));
@@ -408,6 +413,23 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     rc = upload_coeffs(bk);
     if (!rc) {
         e = hipMemcpy(bk->slot_filter, bk->lay.slot_filter.data(), S * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            std::vector<int32_t> fs((size_t)bk->F, -1);
+            for (int64_t sl = 0; sl < S; ++sl)
+                if (bk->lay.slot_filter[(size_t)sl] >= 0) fs[(size_t)bk->lay.slot_filter[(size_t)sl]] = (int32_t)sl;
+            e = hipMemcpy(bk->filter_slot, fs.data(), fs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) {
+            // backward waves: each template's filters in runs of at most 64
+            std::vector<int4> bw;
+            for (int j = 0; j < T; ++j)
+                for (int64_t k0 = off[j]; k0 < off[j + 1]; k0 += 64)
+                    bw.push_back(make_int4(j, (int)k0, (int)std::min<int64_t>(off[j + 1], k0 + 64), 0));
+            bk->n_bwaves = (int)bw.size();
+            e = dalloc(&bk->bwaves, bw.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(bk->bwaves, bw.data(), bw.size() * sizeof(int4), hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess)
             e = hipMemcpy(bk->rows, bk->lay.rows.data(), bk->lay.rows.size() * sizeof(RowInfo),
                           hipMemcpyHostToDevice);
@@ -941,12 +963,9 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
         tp->bank = bk;
         tp->coeff_version = bk->coeff_version;
         tp->n = n;
-        tp->nchunks = (n + bk->L - 1) / bk->L;
         hipError_t e = dalloc(&tp->xwin, (size_t)(n + bk->dmax) + 16);  // read-ahead padding
-        if (e == hipSuccess && tape_out) e = dalloc(&tp->tape, (size_t)(tp->nchunks * bk->lay.nslots));
         if (e != hipSuccess) {
             dfree(tp->xwin);
-            dfree(tp->tape);
             delete tp;
             return fail(SPIIR_ENOMEM, "tape allocation failed: %s", hipGetErrorString(e));
         }
@@ -970,8 +989,6 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
         a.obase = P;
         a.z = reinterpret_cast<float2 *>(z);
         a.ld = n;
-        a.tape = tp ? tp->tape : nullptr;
-        a.chunk0 = P / bk->L;
         int nseg = 1;
         if (bk->nseg > 1) {
             a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
@@ -1008,26 +1025,27 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     if (tp->bank != bk) return fail(SPIIR_ESTATE, "tape was made by another bank");
     if (tp->coeff_version != bk->coeff_version)
         return fail(SPIIR_ESTATE, "bank coefficients changed since the tape was made");
-    if (!tp->tape) return fail(SPIIR_ESTATE, "tape holds no carries");
+    if (!tp->xwin) return fail(SPIIR_ESTATE, "tape holds no strain window");
     DeviceGuard guard(bk->device);
     BwdArgs a;
     std::memset(&a, 0, sizeof a);
     a.s = bk->slots();
     a.rows = bk->rows;
     a.slot_filter = bk->slot_filter;
-    a.tape = tp->tape;
+    a.filter_slot = bk->filter_slot;
+    a.bwaves = bk->bwaves;
+    a.n_bwaves = bk->n_bwaves;
     a.xwin = tp->xwin;
     a.gz = reinterpret_cast<const float2 *>(gz);
-    // time segments: enough waves for about 8 per SIMD, at most 16 segments
+    // time segments only when the per-segment kernel (one filter per lane)
+    // would leave SIMDs idle: segments add a G-only scan over all but the first
     const int64_t nch = (tp->n + bk->L - 1) / bk->L;
     int want = 1;
     if (bk->tsplit_opt >= 2) {
         want = bk->tsplit_opt;
     } else if (bk->tsplit_opt == 0) {
-        // counted in layout waves (the per-segment kernel runs FL times as many): on the
-        // chirp-fit bank 16 segments of 4-filter lanes ran faster than 4
-        const int64_t waves = std::max<int64_t>(1, (int64_t)bk->lay.groups * bk->lay.wpg);
-        const int64_t target = (int64_t)32 * bk->dev.n_cu;
+        const int64_t waves = std::max<int64_t>(1, bk->n_bwaves);
+        const int64_t target = (int64_t)4 * bk->dev.n_cu;   // one wave per SIMD
         want = (int)std::min<int64_t>(16, (target + waves - 1) / waves);
     }
     want = (int)std::max<int64_t>(1, std::min<int64_t>(want, nch));
@@ -1035,24 +1053,20 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     const int nseg = (int)((nch + seg_chunks - 1) / seg_chunks);
     const int64_t S = bk->lay.nslots;
     if (bk->bwd_cap < nseg) {
-        dfree(bk->ysub);
-        dfree(bk->blam);
+        dfree(bk->bpair);
         dfree(bk->bgpart);
         bk->bwd_cap = 0;
-        hipError_t e = dalloc(&bk->ysub, (size_t)nseg * ((bk->L + kSub - 1) / kSub) * S);
-        if (e == hipSuccess) e = dalloc(&bk->blam, (size_t)2 * nseg * S);
+        hipError_t e = dalloc(&bk->bpair, (size_t)2 * nseg * S);
         if (e == hipSuccess) e = dalloc(&bk->bgpart, (size_t)2 * nseg * S);
         if (e != hipSuccess) {
-            dfree(bk->ysub);
-            dfree(bk->blam);
+            dfree(bk->bpair);
             dfree(bk->bgpart);
             return fail(SPIIR_ENOMEM, "adjoint scratch allocation failed: %s", hipGetErrorString(e));
         }
         bk->bwd_cap = nseg;
     }
-    a.ysub = bk->ysub;
-    a.lam_loc = bk->blam;
-    a.lam_in = bk->blam + (size_t)nseg * S;
+    a.pair_loc = bk->bpair;
+    a.pair_in = bk->bpair + (size_t)nseg * S;
     a.gpart = bk->bgpart;
     a.nseg = nseg;
     a.seg_chunks = (int32_t)seg_chunks;
@@ -1064,13 +1078,12 @@ int spiir_backward(spiir_bank *bk, const spiir_tape *tp, const float *gz, float 
     a.L = bk->L;
     a.prec = bk->prec;
     a.wpg = bk->lay.wpg;
-    HIPCHK(launch_backward(a, bk->lay.fl, bk->lay.groups, as_stream(stream)));
+    HIPCHK(launch_backward(a, as_stream(stream)));
     return SPIIR_OK;
 }
 
 int spiir_tape_destroy(spiir_tape *tp) {
     if (!tp) return SPIIR_OK;
-    dfree(tp->tape);
     dfree(tp->xwin);
     delete tp;
     return SPIIR_OK;

@@ -342,21 +342,6 @@ struct SegCtx {
     int64_t ld_zl;
 };
 
-// Tape entry (chunk-start state as float-float hi/lo) of filter f. The carry
-// pass adds its state to the local entry already there, in FP64.
-template <int FL, bool ADD>
-__device__ __forceinline__ void tape_put(float4 *tp, const Lane<FL> &s, int f) {
-    if (ADD) {
-        const float4 o = *tp;
-        const double cr = ((double)o.x + (double)o.z) + ((double)s.yr[f] + (double)s.l0r[f]);
-        const double ci = ((double)o.y + (double)o.w) + ((double)s.yi[f] + (double)s.l0i[f]);
-        const float hr = (float)cr, hi = (float)ci;
-        *tp = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
-    } else {
-        *tp = make_float4(s.yr[f], s.yi[f], s.l0r[f], s.l0i[f]);
-    }
-}
-
 // The whole forward pass of workgroup g over launch samples [sc.tb, sc.tb + sc.tn).
 // CARRY: free response of the given state only (no input), z_local added.
 template <int FL, int TT, int MODE, bool XLDS, bool CARRY>
@@ -404,15 +389,8 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
     const int64_t n = sc.tn;
     const int64_t xbase = p.xbase + sc.tb;
     if (keys_out && tid < 2 * TT) kmax[tid] = 0ull;
-    // tape chunk index of the item's first sample (items start on chunk bounds)
-    const int64_t tchunk0 = p.chunk0 + sc.tb / p.L;
-    if (MODE == kModeZ && ract && p.tape) {
-#pragma unroll
-        for (int f = 0; f < FL; ++f) tape_put<FL, CARRY>(p.tape + tchunk0 * p.nslots + s.slot(f), s, f);
-    }
 
     int64_t chunk_start = 0;
-    int64_t chunk_idx = 0;
     int buf = 0;
     bool pending = false;
     int64_t pend_t = 0;
@@ -500,16 +478,8 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
             }
             const int64_t tend = s0 + t0 + steps;
             if (tend - chunk_start == p.L || tend == n) {
-                if (wact) {
-                    carry_correct<FL>(s, p.s, p.prec, (int)(tend - chunk_start), p.L);
-                    if (MODE == kModeZ && ract && p.tape && tend < n) {
-#pragma unroll
-                        for (int f = 0; f < FL; ++f)
-                            tape_put<FL, CARRY>(p.tape + (tchunk0 + chunk_idx + 1) * p.nslots + s.slot(f), s, f);
-                    }
-                }
+                if (wact) carry_correct<FL>(s, p.s, p.prec, (int)(tend - chunk_start), p.L);
                 chunk_start = tend;
-                ++chunk_idx;
             }
             buf ^= 1;
         }
@@ -863,18 +833,29 @@ __global__ void noise_fill_kernel(float *x, int64_t n, uint32_t seed) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint. The reverse recursion lambda[m] = G[m] + conj(a) lambda[m+1] is
-// linear, so the stream is cut into nseg segments of whole chunks and, inside
-// a segment [s0, e),
-//     lambda[m] = lambda_loc[m] + conj(a)^(e - m) lambda[e],
-// with lambda_loc started from zero at e. bwd_scan_kernel runs lambda_loc over
-// every segment but the first (reading only G), bwd_chain_kernel composes the
-// segments from the end in FP64, which gives the true lambda entering each
-// segment, and bwd_seg_kernel runs the full backward of every segment from
-// that value: chunks in reverse order, y recomputed from the tape (chunk-start
-// state), first over the whole chunk keeping every kSub-th state in scratch
-// memory, then per sub-chunk in registers. bwd_reduce_kernel adds the
-// per-segment gradients in FP64 in segment order.
+// Adjoint. With lambda[m] = G[m] + conj(a) lambda[m+1] (lambda[n] = 0) the
+// gradients of a real loss of z are
+//     grad_b = sum_m lambda[m] x[m - d],
+//     grad_a = sum_m lambda[m] conj(y[m - 1]).
+// From a cold start y[m - 1] = sum_{k < m} a^(m-1-k) b x[k - d], so the second
+// sum regroups exactly as
+//     grad_a = conj(b) sum_k nu[k] x[k - d],
+//     nu[k] = sum_{m > k} conj(a)^(m-1-k) lambda[m] = lambda[k+1] + conj(a) nu[k+1],
+// a second reverse recursion driven by lambda. The backward therefore runs the
+// pair (lambda, nu) from the end of the stream and never forms y: no forward
+// recomputation and no stored filter states. Over s steps without input the
+// pair moves by the Jordan block
+//     lambda <- conj(a)^s lambda,   nu <- conj(a)^s nu + s conj(a)^(s-1) lambda.
+// The pair recursion is linear, so the stream is cut into nseg segments of
+// whole chunks: bwd_scan_kernel runs every segment but the first from a zero
+// pair at its end (reading only G), bwd_chain_kernel composes the segments from
+// the end in FP64 with the Jordan block, which gives the true pair entering
+// each segment, and bwd_seg_kernel runs every segment from that pair with the
+// gradient sums (FP32 within a chunk, FP64 across chunks). bwd_reduce_kernel
+// adds the per-segment sums in FP64 in segment order and applies conj(b).
+// Every L samples (a chunk) the pair carried into the chunk is corrected for
+// the FP32 coefficient: lambda += conj(a^l - fl(a)^l) lambda_in,
+// nu += conj(a^l - fl(a)^l) nu_in + l conj(a^(l-1) - fl(a)^(l-1)) lambda_in.
 // ---------------------------------------------------------------------------
 
 
@@ -916,162 +897,205 @@ __device__ __forceinline__ void fetch_g(const float2 *p, int ql, float (&gr)[kSu
     }
 }
 
-// conj(a^l - fl32(a)^l): the part of an l-step lambda carry that a recursion
-// with fl32(a) misses (added as times lambda entering the chunk).
-__device__ __forceinline__ float2 lam_drift(const SlotArrays &s, int64_t slot, int l, int L, float ar, float ai) {
-    double2 dl;
-    if (l == L) {
-        dl = s.dL[slot];
+// G of one template for one sub-chunk when the address is the same for the
+// whole wave: read through the constant address space, so the loads are
+// scalar (one per wave, values in SGPRs) and never reach the texture path.
+typedef const __attribute__((address_space(4))) float cfloat;
+
+__device__ __forceinline__ void fetch_g_uniform(const float2 *p, int ql, float (&gr)[kSub], float (&gi)[kSub]) {
+    cfloat *c = (cfloat *)p;
+    if (ql == kSub) {
+#pragma unroll
+        for (int t = 0; t < kSub; ++t) {
+            gr[t] = c[2 * t];
+            gi[t] = c[2 * t + 1];
+        }
     } else {
-        const double2 al = cpow64(s.a64[slot], l);
-        const double2 ah = cpow64(make_double2((double)ar, (double)ai), l);
-        dl = make_double2(al.x - ah.x, al.y - ah.y);
+#pragma unroll
+        for (int t = 0; t < kSub; ++t) {
+            gr[t] = t < ql ? c[2 * t] : 0.f;
+            gi[t] = t < ql ? c[2 * t + 1] : 0.f;
+        }
     }
-    return make_float2((float)dl.x, (float)dl.y);
 }
 
-struct BwdWave {
-    int g, wave, lane;
-    RowInfo ri;
+// A backward wave: the filters [k0, k1) of template tpl (at most 64, lane i
+// takes filter k0 + i), so that G is the same for the whole wave.
+struct BwdLane {
+    int tpl;
+    int64_t k0, k1, k;
 };
 
-__device__ __forceinline__ BwdWave bwd_wave(const BwdArgs &p) {
-    BwdWave w;
-    w.lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    w.g = gw / p.wpg;
-    w.wave = gw % p.wpg;
-    w.ri = p.rows[(int64_t)w.g * 4 * p.wpg + w.wave * 4 + (w.lane >> 4)];
-    return w;
+__device__ __forceinline__ bool bwd_lane(const BwdArgs &p, BwdLane &bl) {
+    const int w = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (w >= p.n_bwaves) return false;
+    const int4 e = p.bwaves[w];
+    bl.tpl = __builtin_amdgcn_readfirstlane(e.x);
+    bl.k0 = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane(e.y);
+    bl.k1 = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane(e.z);
+    bl.k = bl.k0 + (threadIdx.x & 63);
+    return bl.k < bl.k1;
 }
 
-// One wave per slot column f of a wave of the layout (FL of them per layout
-// wave), so that the per-filter backward has FL times the waves of the layout.
-__device__ __forceinline__ BwdWave bwd_slot_wave(const BwdArgs &p, int fl, int &f) {
-    BwdWave w;
-    w.lane = threadIdx.x & 63;
-    const int gs = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    f = gs % fl;
-    const int gw = gs / fl;
-    w.g = gw / p.wpg;
-    w.wave = gw % p.wpg;
-    w.ri = p.rows[(int64_t)w.g * 4 * p.wpg + w.wave * 4 + (w.lane >> 4)];
-    return w;
+// The carried-pair corrections of an l-step chunk (see above), FP32:
+// d1 = conj(a^l - fl(a)^l), d2 = l conj(a^(l-1) - fl(a)^(l-1)).
+struct PairDrift {
+    float d1r, d1i, d2r, d2i;
+};
+
+__device__ __forceinline__ PairDrift pair_drift(const SlotArrays &s, int64_t slot, int l, float ar, float ai) {
+    const double2 a = s.a64[slot];
+    const double2 af = make_double2((double)ar, (double)ai);
+    const double2 p1 = cpow64(a, l - 1), q1 = cpow64(af, l - 1);
+    const double2 p = cmul64(p1, a), q = cmul64(q1, af);
+    PairDrift d;
+    d.d1r = (float)(p.x - q.x);
+    d.d1i = (float)-(p.y - q.y);
+    d.d2r = (float)((double)l * (p1.x - q1.x));
+    d.d2i = (float)-((double)l * (p1.y - q1.y));
+    return d;
 }
 
-// lambda[m] = G[m] + conj(a) lambda[m+1] over one sub-chunk, last step first
-// (FULL: all kSub steps, no per-step guard).
+// lambda += d1 lambda_in; nu += d1 nu_in + d2 lambda_in (complex products).
+__device__ __forceinline__ void pair_correct(float &lr, float &li, float &vr, float &vi, const PairDrift &d,
+                                             float l0r, float l0i, float v0r, float v0i) {
+    lr = fmaf(d.d1r, l0r, fmaf(-d.d1i, l0i, lr));
+    li = fmaf(d.d1r, l0i, fmaf(d.d1i, l0r, li));
+    vr = fmaf(d.d1r, v0r, fmaf(-d.d1i, v0i, fmaf(d.d2r, l0r, fmaf(-d.d2i, l0i, vr))));
+    vi = fmaf(d.d1r, v0i, fmaf(d.d1i, v0r, fmaf(d.d2r, l0i, fmaf(d.d2i, l0r, vi))));
+}
+
+// One sub-chunk of the pair recursion, last step first: on entry (l, v) =
+// (lambda[m+1], nu[m+1]); each step forms nu[m] = lambda[m+1] + conj(a) nu[m+1]
+// and lambda[m] = G[m] + conj(a) lambda[m+1] (FULL: all kSub steps).
 template <int FL, bool FULL>
-__device__ __forceinline__ void lam_steps(float (&lr)[FL], float (&li)[FL], const float (&ar)[FL],
-                                          const float (&ai)[FL], const float (&gr)[kSub], const float (&gi)[kSub],
-                                          int ql) {
+__device__ __forceinline__ void pair_steps(float (&lr)[FL], float (&li)[FL], float (&vr)[FL], float (&vi)[FL],
+                                           const float (&ar)[FL], const float (&ai)[FL], const float (&gr)[kSub],
+                                           const float (&gi)[kSub], int ql) {
 #pragma unroll
     for (int t = kSub - 1; t >= 0; --t) {
         if (FULL || t < ql) {
 #pragma unroll
             for (int f = 0; f < FL; ++f) {
-                const float nr = fmaf(ar[f], lr[f], fmaf(ai[f], li[f], gr[t]));
-                const float ni = fmaf(ar[f], li[f], fmaf(-ai[f], lr[f], gi[t]));
-                lr[f] = nr;
-                li[f] = ni;
+                const float nvr = fmaf(ar[f], vr[f], fmaf(ai[f], vi[f], lr[f]));
+                const float nvi = fmaf(ar[f], vi[f], fmaf(-ai[f], vr[f], li[f]));
+                const float nlr = fmaf(ar[f], lr[f], fmaf(ai[f], li[f], gr[t]));
+                const float nli = fmaf(ar[f], li[f], fmaf(-ai[f], lr[f], gi[t]));
+                vr[f] = nvr;
+                vi[f] = nvi;
+                lr[f] = nlr;
+                li[f] = nli;
             }
         }
     }
 }
 
-// Forward recursion over one sub-chunk from (yr, yi).
+// The same steps with the gradient sums sb += lambda[m] x[m - d],
+// sa += nu[m] x[m - d] for one filter.
 template <bool FULL>
-__device__ __forceinline__ void y_steps(float &yr, float &yi, float ar, float ai, float br, float bi,
-                                        const float (&xv)[kSub], int ql) {
-#pragma unroll
-    for (int t = 0; t < kSub; ++t) {
-        if (FULL || t < ql) {
-            const float nr = fmaf(-ai, yi, fmaf(ar, yr, br * xv[t]));
-            const float ni = fmaf(ai, yr, fmaf(ar, yi, bi * xv[t]));
-            yr = nr;
-            yi = ni;
-        }
-    }
-}
-
-// Reverse sweep of one sub-chunk: lambda, and the gradient sums
-// sb += lambda x[m - d], sa += lambda conj(y[m - 1]); hr/hi hold y[m - 1].
-template <bool FULL>
-__device__ __forceinline__ void adj_steps(float &lr, float &li, float ar, float ai, const float (&xv)[kSub],
-                                          const float (&gr)[kSub], const float (&gi)[kSub],
-                                          const float (&hr)[kSub + 1], const float (&hi)[kSub + 1], float &sar,
-                                          float &sai, float &sbr, float &sbi, int ql) {
+__device__ __forceinline__ void grad_steps(float &lr, float &li, float &vr, float &vi, float ar, float ai,
+                                           const float (&xv)[kSub], const float (&gr)[kSub], const float (&gi)[kSub],
+                                           float &sar, float &sai, float &sbr, float &sbi, int ql) {
 #pragma unroll
     for (int t = kSub - 1; t >= 0; --t) {
         if (FULL || t < ql) {
-            const float nr = fmaf(ar, lr, fmaf(ai, li, gr[t]));
-            const float ni = fmaf(ar, li, fmaf(-ai, lr, gi[t]));
-            lr = nr;
-            li = ni;
+            const float nvr = fmaf(ar, vr, fmaf(ai, vi, lr));
+            const float nvi = fmaf(ar, vi, fmaf(-ai, vr, li));
+            const float nlr = fmaf(ar, lr, fmaf(ai, li, gr[t]));
+            const float nli = fmaf(ar, li, fmaf(-ai, lr, gi[t]));
+            vr = nvr;
+            vi = nvi;
+            lr = nlr;
+            li = nli;
             sbr = fmaf(lr, xv[t], sbr);
             sbi = fmaf(li, xv[t], sbi);
-            sar = fmaf(lr, hr[t], fmaf(li, hi[t], sar));
-            sai = fmaf(li, hr[t], fmaf(-lr, hi[t], sai));
+            sar = fmaf(vr, xv[t], sar);
+            sai = fmaf(vi, xv[t], sai);
         }
     }
 }
 
-// Segment-local lambda at the start of segment blockIdx.y + 1. The FL filters
-// of a lane share their template's G and run side by side.
-template <int FL>
+// Segment-local pair at the start of segment blockIdx.y + 1, from a zero pair
+// at its end (reads only G, by scalar loads). One filter per lane, one
+// template per wave; the G of the next sub-chunk is loaded while the current
+// one is computed.
 __global__ void __launch_bounds__(256) bwd_scan_kernel(BwdArgs p) {
-    const BwdWave w = bwd_wave(p);
-    if (w.ri.tpl < 0) return;
+    BwdLane bl;
+    if (!bwd_lane(p, bl)) return;
+    const int64_t slot = p.filter_slot[bl.k];
+    const int tpl = bl.tpl;
     const int seg = blockIdx.y + 1;
     const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
     const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
-    const float2 *gz = p.gz + (int64_t)w.ri.tpl * n;
-    float ar[FL], ai[FL], lr[FL], li[FL];
-    int64_t slot[FL];
-#pragma unroll
-    for (int f = 0; f < FL; ++f) {
-        slot[f] = slot_index(w.g, p.wpg, w.wave, f, FL, w.lane);
-        const float2 a = p.s.a32[slot[f]];
-        ar[f] = a.x;
-        ai[f] = a.y;
-        lr[f] = 0.f;
-        li[f] = 0.f;
+    const float2 *gz = p.gz + (int64_t)tpl * n;
+    const float2 a = p.s.a32[slot];
+    float ar[1] = {a.x}, ai[1] = {a.y};
+    PairDrift dfull;
+    if (p.prec != kPrecFp32) dfull = pair_drift(p.s, slot, p.L, ar[0], ai[0]);
+    float lr[1] = {0.f}, li[1] = {0.f}, vr[1] = {0.f}, vi[1] = {0.f};
+    float l0r = 0.f, l0i = 0.f, v0r = 0.f, v0i = 0.f;
+    auto nq_of = [&](int64_t c) { return (int)((min((int64_t)p.L, n - c * p.L) + kSub - 1) / kSub); };
+    auto fetch = [&](float (&gr)[kSub], float (&gi)[kSub], int64_t c, int q) {
+        const int64_t m0 = c * p.L + (int64_t)q * kSub;
+        const int ql = (int)min((int64_t)kSub, min((int64_t)p.L, n - c * p.L) - (int64_t)q * kSub);
+        fetch_g_uniform(gz + m0, ql, gr, gi);
+    };
+    auto run = [&](const float (&gr)[kSub], const float (&gi)[kSub], int64_t c, int q) {
+        const int l = (int)min((int64_t)p.L, n - c * p.L);
+        const int ql = min(kSub, l - q * kSub);
+        if (q == nq_of(c) - 1) {
+            l0r = lr[0];
+            l0i = li[0];
+            v0r = vr[0];
+            v0i = vi[0];
+        }
+        if (ql == kSub)
+            pair_steps<1, true>(lr, li, vr, vi, ar, ai, gr, gi, ql);
+        else
+            pair_steps<1, false>(lr, li, vr, vi, ar, ai, gr, gi, ql);
+        if (q == 0 && p.prec != kPrecFp32) {
+            const PairDrift d = l == p.L ? dfull : pair_drift(p.s, slot, l, ar[0], ai[0]);
+            pair_correct(lr[0], li[0], vr[0], vi[0], d, l0r, l0i, v0r, v0i);
+        }
+    };
+    auto step_back = [&](int64_t &c, int &q) {
+        if (q > 0) {
+            --q;
+        } else {
+            --c;
+            q = c >= cs ? nq_of(c) - 1 : 0;
+        }
+    };
+    if (ce > cs) {
+        float agr[kSub], agi[kSub], bgr[kSub], bgi[kSub];
+        int64_t c = ce - 1;
+        int q = nq_of(c) - 1;
+        fetch(agr, agi, c, q);
+        while (true) {
+            int64_t cb = c;
+            int qb = q;
+            step_back(cb, qb);
+            if (cb >= cs) fetch(bgr, bgi, cb, qb);
+            run(agr, agi, c, q);
+            if (cb < cs) break;
+            c = cb;
+            q = qb;
+            int64_t ca = c;
+            int qa = q;
+            step_back(ca, qa);
+            if (ca >= cs) fetch(agr, agi, ca, qa);
+            run(bgr, bgi, c, q);
+            if (ca < cs) break;
+            c = ca;
+            q = qa;
+        }
     }
-    for (int64_t c = ce - 1; c >= cs; --c) {
-        const int64_t c0 = c * p.L;
-        const int l = (int)min((int64_t)p.L, n - c0);
-        const int nq = (l + kSub - 1) / kSub;
-        float lin_r[FL], lin_i[FL];
-#pragma unroll
-        for (int f = 0; f < FL; ++f) {
-            lin_r[f] = lr[f];
-            lin_i[f] = li[f];
-        }
-        for (int q = nq - 1; q >= 0; --q) {
-            const int qs = q * kSub, ql = min(kSub, l - qs);
-            float gr[kSub], gi[kSub];
-            fetch_g(gz + c0 + qs, ql, gr, gi);
-            if (ql == kSub)
-                lam_steps<FL, true>(lr, li, ar, ai, gr, gi, ql);
-            else
-                lam_steps<FL, false>(lr, li, ar, ai, gr, gi, ql);
-        }
-        if (p.prec != kPrecFp32) {
-#pragma unroll
-            for (int f = 0; f < FL; ++f) {
-                const float2 d = lam_drift(p.s, slot[f], l, p.L, ar[f], ai[f]);
-                lr[f] = fmaf(d.x, lin_r[f], fmaf(d.y, lin_i[f], lr[f]));
-                li[f] = fmaf(d.x, lin_i[f], fmaf(-d.y, lin_r[f], li[f]));
-            }
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < FL; ++f) p.lam_loc[(int64_t)seg * p.nslots + slot[f]] = make_float2(lr[f], li[f]);
+    p.pair_loc[(int64_t)seg * p.nslots + slot] = make_float4(lr[0], li[0], vr[0], vi[0]);
 }
 
-// True lambda entering every segment from the right (zero for the last one):
-// lambda[s0] = lambda_loc[s0] + conj(a)^(e - s0) lambda[e], in FP64 (with
-// fl32(a) in the all-FP32 mode).
+// True pair entering every segment from the right (zero for the last one):
+// pair[s0] = pair_loc[s0] + J^(e - s0) pair[e], J the Jordan block of conj(a),
+// in FP64 (with fl32(a) in the all-FP32 mode).
 __global__ void __launch_bounds__(256) bwd_chain_kernel(BwdArgs p) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= p.nslots) return;
@@ -1081,97 +1105,126 @@ __global__ void __launch_bounds__(256) bwd_chain_kernel(BwdArgs p) {
         const float2 a32 = p.s.a32[slot];
         a = make_double2((double)a32.x, (double)a32.y);
     }
-    double lr = 0.0, li = 0.0;
+    double lr = 0.0, li = 0.0, vr = 0.0, vi = 0.0;
     for (int seg = p.nseg - 1; seg >= 0; --seg) {
-        p.lam_in[(int64_t)seg * p.nslots + slot] = make_float2((float)lr, (float)li);
+        p.pair_in[(int64_t)seg * p.nslots + slot] = make_float4((float)lr, (float)li, (float)vr, (float)vi);
         if (seg == 0) break;
         const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
         const int64_t len = min(n, ce * p.L) - cs * p.L;
-        const double2 al = cpow64(a, len);            // conj(a)^len = conj(a^len)
-        const float2 loc = p.lam_loc[(int64_t)seg * p.nslots + slot];
-        const double nr = (double)loc.x + al.x * lr + al.y * li;
-        const double ni = (double)loc.y + al.x * li - al.y * lr;
-        lr = nr;
-        li = ni;
+        const double2 a1 = cpow64(a, (int)(len - 1));   // conj(a)^k = conj(a^k)
+        const double2 al = cmul64(a1, a);
+        const double sr = (double)len * a1.x, si = (double)len * a1.y;
+        const float4 loc = p.pair_loc[(int64_t)seg * p.nslots + slot];
+        const double nvr = (double)loc.z + (al.x * vr + al.y * vi) + (sr * lr + si * li);
+        const double nvi = (double)loc.w + (al.x * vi - al.y * vr) + (sr * li - si * lr);
+        const double nlr = (double)loc.x + al.x * lr + al.y * li;
+        const double nli = (double)loc.y + al.x * li - al.y * lr;
+        lr = nlr;
+        li = nli;
+        vr = nvr;
+        vi = nvi;
     }
 }
 
-// Full backward of segment blockIdx.y from its true incoming lambda; one
-// filter slot per lane (grid: one wave per slot column).
-template <int FL>
+// Strain and G of one sub-chunk of the backward.
+struct SubBuf {
+    float x[kSub], gr[kSub], gi[kSub];
+};
+
+// Full backward of segment blockIdx.y from its true incoming pair. One filter
+// per lane; every wave holds filters of one template (G read by scalar loads).
+// Sub-chunks are taken in reverse order through two register buffers: the
+// next one is loaded while the current one is computed.
 __global__ void __launch_bounds__(256) bwd_seg_kernel(BwdArgs p) {
-    int fcol = 0;
-    const BwdWave w = bwd_slot_wave(p, FL, fcol);
-    if (w.ri.tpl < 0) return;
+    BwdLane bl;
+    if (!bwd_lane(p, bl)) return;
+    const int64_t slot = p.filter_slot[bl.k];
+    const int tpl = bl.tpl;
     const int seg = blockIdx.y;
     const int64_t n = p.n, nch = (n + p.L - 1) / p.L;
     const int64_t cs = (int64_t)seg * p.seg_chunks, ce = min(nch, cs + p.seg_chunks);
-    const int nqmax = (p.L + kSub - 1) / kSub;
-    float2 *ysub = p.ysub + (int64_t)seg * nqmax * p.nslots;
-    const float2 *gz = p.gz + (int64_t)w.ri.tpl * n;
-    {
-        const int64_t slot = slot_index(w.g, p.wpg, w.wave, fcol, FL, w.lane);
-        if (p.slot_filter[slot] < 0) return;
-        const float2 a = p.s.a32[slot], b = p.s.b32[slot];
-        const float ar = a.x, ai = a.y, br = b.x, bi = b.y;
-        const float *xw = p.xwin + p.s.xoff[slot];  // xw[m] = x[m - d]
-        double gar = 0.0, gai = 0.0, gbr = 0.0, gbi = 0.0;
-        const float2 lam = p.lam_in[(int64_t)seg * p.nslots + slot];
-        float lr = lam.x, li = lam.y;  // lambda at the sample after the current chunk
-        for (int64_t c = ce - 1; c >= cs; --c) {
-            const int64_t c0 = c * p.L;
-            const int l = (int)min((int64_t)p.L, n - c0);
-            const int nq = (l + kSub - 1) / kSub;
-            // pass 1: forward over the chunk, keep the state before every sub-chunk
-            const float4 tp = p.tape[c * p.nslots + slot];
-            float yr = tp.x, yi = tp.y;
-            for (int q = 0; q < nq; ++q) {
-                ysub[(int64_t)q * p.nslots + slot] = make_float2(yr, yi);
-                const int qs = q * kSub, ql = min(kSub, l - qs);
-                float xv[kSub];
-                fetch_x(xw + c0 + qs, ql, xv);
-                if (ql == kSub)
-                    y_steps<true>(yr, yi, ar, ai, br, bi, xv, ql);
-                else
-                    y_steps<false>(yr, yi, ar, ai, br, bi, xv, ql);
-            }
-            // pass 2: sub-chunks in reverse
-            const float lin_r = lr, lin_i = li;
-            float sar = 0.f, sai = 0.f, sbr = 0.f, sbi = 0.f;
-            for (int q = nq - 1; q >= 0; --q) {
-                const int qs = q * kSub, ql = min(kSub, l - qs);
-                float xv[kSub], gr[kSub], gi[kSub];
-                fetch_x(xw + c0 + qs, ql, xv);
-                fetch_g(gz + c0 + qs, ql, gr, gi);
-                float hr[kSub + 1], hi[kSub + 1];  // hr[t] = y[m - 1] for m = c0 + qs + t
-                const float2 y0 = ysub[(int64_t)q * p.nslots + slot];
-                hr[0] = y0.x;
-                hi[0] = y0.y;
-#pragma unroll
-                for (int t = 0; t < kSub; ++t) {
-                    hr[t + 1] = fmaf(-ai, hi[t], fmaf(ar, hr[t], br * xv[t]));
-                    hi[t + 1] = fmaf(ai, hr[t], fmaf(ar, hi[t], bi * xv[t]));
-                }
-                if (ql == kSub)
-                    adj_steps<true>(lr, li, ar, ai, xv, gr, gi, hr, hi, sar, sai, sbr, sbi, ql);
-                else
-                    adj_steps<false>(lr, li, ar, ai, xv, gr, gi, hr, hi, sar, sai, sbr, sbi, ql);
-            }
+    const float2 *gz = p.gz + (int64_t)tpl * n;
+    const float2 a = p.s.a32[slot];
+    const float ar = a.x, ai = a.y;
+    const float *xw = p.xwin + p.s.xoff[slot];  // xw[m] = x[m - d]
+    PairDrift dfull;
+    if (p.prec != kPrecFp32) dfull = pair_drift(p.s, slot, p.L, ar, ai);
+    double gar = 0.0, gai = 0.0, gbr = 0.0, gbi = 0.0;
+    const float4 pin = p.pair_in[(int64_t)seg * p.nslots + slot];
+    float lr = pin.x, li = pin.y, vr = pin.z, vi = pin.w;   // the pair after the current chunk
+    float l0r = 0.f, l0i = 0.f, v0r = 0.f, v0i = 0.f;       // the pair entering the current chunk
+    float sar = 0.f, sai = 0.f, sbr = 0.f, sbi = 0.f;
+    auto nq_of = [&](int64_t c) { return (int)((min((int64_t)p.L, n - c * p.L) + kSub - 1) / kSub); };
+    auto fetch = [&](SubBuf &b, int64_t c, int q) {
+        const int64_t m0 = c * p.L + (int64_t)q * kSub;
+        const int ql = (int)min((int64_t)kSub, min((int64_t)p.L, n - c * p.L) - (int64_t)q * kSub);
+        fetch_x(xw + m0, ql, b.x);
+        fetch_g_uniform(gz + m0, ql, b.gr, b.gi);
+    };
+    // one sub-chunk: chunk bookkeeping at its first (q = last) and last (q = 0) sub-chunk
+    auto run = [&](const SubBuf &b, int64_t c, int q) {
+        const int l = (int)min((int64_t)p.L, n - c * p.L);
+        const int ql = min(kSub, l - q * kSub);
+        if (q == nq_of(c) - 1) {
+            l0r = lr;
+            l0i = li;
+            v0r = vr;
+            v0i = vi;
+            sar = sai = sbr = sbi = 0.f;
+        }
+        if (ql == kSub)
+            grad_steps<true>(lr, li, vr, vi, ar, ai, b.x, b.gr, b.gi, sar, sai, sbr, sbi, ql);
+        else
+            grad_steps<false>(lr, li, vr, vi, ar, ai, b.x, b.gr, b.gi, sar, sai, sbr, sbi, ql);
+        if (q == 0) {
             if (p.prec != kPrecFp32) {
-                const float2 d = lam_drift(p.s, slot, l, p.L, ar, ai);
-                lr = fmaf(d.x, lin_r, fmaf(d.y, lin_i, lr));
-                li = fmaf(d.x, lin_i, fmaf(-d.y, lin_r, li));
+                const PairDrift d = l == p.L ? dfull : pair_drift(p.s, slot, l, ar, ai);
+                pair_correct(lr, li, vr, vi, d, l0r, l0i, v0r, v0i);
             }
             gar += (double)sar;
             gai += (double)sai;
             gbr += (double)sbr;
             gbi += (double)sbi;
         }
-        p.gpart[((int64_t)seg * 2 + 0) * p.nslots + slot] = make_double2(gar, gai);
-        p.gpart[((int64_t)seg * 2 + 1) * p.nslots + slot] = make_double2(gbr, gbi);
+    };
+    // reverse enumeration of the segment's sub-chunks
+    auto step_back = [&](int64_t &c, int &q) {
+        if (q > 0) {
+            --q;
+        } else {
+            --c;
+            q = c >= cs ? nq_of(c) - 1 : 0;
+        }
+    };
+    if (ce > cs) {
+        SubBuf A, B;
+        int64_t c = ce - 1;
+        int q = nq_of(c) - 1;
+        fetch(A, c, q);
+        while (true) {
+            int64_t cb = c;
+            int qb = q;
+            step_back(cb, qb);
+            if (cb >= cs) fetch(B, cb, qb);
+            run(A, c, q);
+            if (cb < cs) break;
+            c = cb;
+            q = qb;
+            int64_t ca = c;
+            int qa = q;
+            step_back(ca, qa);
+            if (ca >= cs) fetch(A, ca, qa);
+            run(B, c, q);
+            if (ca < cs) break;
+            c = ca;
+            q = qa;
+        }
     }
+    p.gpart[((int64_t)seg * 2 + 0) * p.nslots + slot] = make_double2(gar, gai);
+    p.gpart[((int64_t)seg * 2 + 1) * p.nslots + slot] = make_double2(gbr, gbi);
 }
 
+// Sum over segments in FP64, then grad_a = conj(fl32(b)) * sum nu x.
 __global__ void __launch_bounds__(256) bwd_reduce_kernel(BwdArgs p) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= p.nslots) return;
@@ -1186,7 +1239,9 @@ __global__ void __launch_bounds__(256) bwd_reduce_kernel(BwdArgs p) {
         gbr += gb.x;
         gbi += gb.y;
     }
-    p.grad_a[k] = make_float2((float)gar, (float)gai);
+    const float2 b = p.s.b32[slot];
+    const double br = (double)b.x, bi = (double)b.y;
+    p.grad_a[k] = make_float2((float)(br * gar + bi * gai), (float)(br * gai - bi * gar));
     p.grad_b[k] = make_float2((float)gbr, (float)gbi);
 }
 
@@ -1425,37 +1480,26 @@ hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int FL>
-hipError_t launch_backward_t(const BwdArgs &a, dim3 wgrid, dim3 block, hipStream_t st) {
+hipError_t launch_backward_t(const BwdArgs &a, hipStream_t st) {
     if (a.nseg > 1) {
-        hipLaunchKernelGGL(bwd_scan_kernel<FL>, dim3(wgrid.x, a.nseg - 1), block, 0, st, a);
+        hipLaunchKernelGGL(bwd_scan_kernel, dim3(nblocks(a.n_bwaves, 4), a.nseg - 1), dim3(256), 0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(bwd_chain_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bwd_seg_kernel<FL>, dim3(wgrid.x * FL, a.nseg), block, 0, st, a);
+    hipLaunchKernelGGL(bwd_seg_kernel, dim3(nblocks(a.n_bwaves, 4), a.nseg), dim3(256), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bwd_reduce_kernel, dim3(nblocks(a.nslots, 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t st) {
-    const int total_waves = groups * a.wpg;
-    if (total_waves <= 0) return hipSuccess;
+hipError_t launch_backward(const BwdArgs &a, hipStream_t st) {
+    if (a.n_bwaves <= 0) return hipSuccess;
     if (a.nseg < 1 || a.nseg > 65535 || a.seg_chunks < 1) return hipErrorInvalidValue;
-    // 4 waves per block; the wave count of a bank is a multiple of wpg, pad to 4
-    const int wpb = (total_waves % 4 == 0) ? 4 : (total_waves % 2 == 0 ? 2 : 1);
-    const dim3 grid(total_waves / wpb), block(64 * wpb);
-    switch (fl) {
-        case 1: return launch_backward_t<1>(a, grid, block, st);
-        case 2: return launch_backward_t<2>(a, grid, block, st);
-        case 3: return launch_backward_t<3>(a, grid, block, st);
-        case 4: return launch_backward_t<4>(a, grid, block, st);
-        default: return hipErrorInvalidValue;
-    }
+    return launch_backward_t(a, st);
 }
 
 template <int FL, int TT>

@@ -8,7 +8,7 @@
 
 namespace spiir {
 
-constexpr int kSub = 16;        // adjoint: steps kept in registers per recompute
+constexpr int kSub = 16;        // adjoint: steps of strain and G loaded together
 constexpr float kFlagRadius = 1.0f - 1e-5f;
 
 enum Mode { kModeSnr = 0, kModeKeys = 1, kModeZ = 2 };
@@ -51,8 +51,6 @@ struct FwdArgs {
     float *snr;           // kModeSnr: snr[tpl * ld + obase + t]
     uint64_t *keys;       // kModeKeys: keys[group * ld + t]
     float2 *z;            // kModeZ: z[tpl * ld + obase + t]
-    float4 *tape;         // kModeZ: tape[(chunk0 + c) * nslots + slot] = state at chunk start
-    int64_t chunk0;
     int64_t nslots;
     // time split of one launch into nseg segments of seg_len samples
     int32_t groups;       // workgroups of the bank (item = segment * groups + group)
@@ -71,13 +69,14 @@ struct BwdArgs {
     SlotArrays s;
     const RowInfo *rows;
     const int32_t *slot_filter;  // slot -> caller filter index (-1 padding)
-    const float4 *tape;          // [nchunks][nslots]
+    const int32_t *filter_slot;  // caller filter index -> slot
+    const int4 *bwaves;          // [n_bwaves] (template, first filter, end filter, 0): the backward's waves
+    int32_t n_bwaves, pad0;
     const float *xwin;           // xwin[dmax + m] = x[m] for m in [-dmax, n)
     const float2 *gz;            // [T][n]
-    float2 *ysub;                // scratch [nseg][ceil(L / kSub)][nslots]
-    float2 *lam_loc;             // scratch [nseg][nslots]: segment-local lambda at the segment start
-    float2 *lam_in;              // scratch [nseg][nslots]: true lambda entering each segment from the right
-    double2 *gpart;              // scratch [nseg][2][nslots]: per-segment grad_a, grad_b
+    float4 *pair_loc;            // scratch [nseg][nslots]: segment-local (lambda, nu) at the segment start
+    float4 *pair_in;             // scratch [nseg][nslots]: true (lambda, nu) entering each segment from the right
+    double2 *gpart;              // scratch [nseg][2][nslots]: per-segment sum nu x, sum lambda x
     float2 *grad_a, *grad_b;     // [F] caller order
     int64_t n, nslots;
     int32_t dmax, L, prec, wpg;
@@ -111,9 +110,9 @@ hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool
                                 size_t lds, size_t lds_carry, const int32_t *slot_filter,
                                 hipStream_t stream, KernelEvents ev = KernelEvents());
 int forward_occupancy(int fl, int tt, int wpg, size_t lds);
-// Adjoint over nseg time segments: segment-local lambda scan, FP64 chain,
+// Adjoint over nseg time segments: segment-local (lambda, nu) scan, FP64 chain,
 // per-segment backward, FP64 reduction of the per-segment gradients.
-hipError_t launch_backward(const BwdArgs &a, int fl, int groups, hipStream_t stream);
+hipError_t launch_backward(const BwdArgs &a, hipStream_t stream);
 // Per-sample max over the groups' keys; with hc, the same launch also writes
 // the history copy (one launch fewer per streaming call).
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
