@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "complex IIR filter-updates/s + % FP32 vector peak; fused vs plain at 1e-4 err"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed FP32 issue), FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E bandwidth, bytes/s
+# FP32 issue ceiling of the recursion loop without packed FP32 instructions:
+# 256 CU x 2.4 GHz x 64 lanes x 12 FLOP per 8 VALU issues = 59.0 TFLOP/s
+ISSUE_CEILING = 256 * 2.4e9 * 64 * 12 / 8
 FLOP_UPDATE = 12              # a*y 6 + b*x 2 + add 2 + template accumulation 2
 FLOP_SAMPLE = 4               # |z|^2 3 + compare 1, per template and sample
 FLOP_ADJ = 30                 # adjoint per update, the scope table's figure: y 10, lambda 8, grad_b 4, grad_a 8
@@ -48,19 +51,24 @@ def cpu_model():
 
 
 def measured_traffic():
-    """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by a device copy of known size), or None when the
-    kernel source changed since those counters were taken."""
+    """HBM bytes per forward launch and where the figure comes from: the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a device copy
+    of known size) of this kernel source, not a measurement of this run; None
+    when the kernel source changed since those counters were taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
             t = json.load(f)
         src = open(os.path.join(ROOT, "paper_1602_05573_amd", "csrc", "kernels.hip"), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != t["kernel_sha256_prefix"]:
-            return None
-        return int(t["fetch_bytes"] + t["write_bytes"])
+        sha = hashlib.sha256(src).hexdigest()[:16]
+        if sha != t["kernel_sha256_prefix"]:
+            return None, ("null: kernels.hip (sha256 %s) changed since the committed counters (%s)"
+                          % (sha, t["kernel_sha256_prefix"]))
+        return (int(t["fetch_bytes"] + t["write_bytes"]),
+                "committed rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source (sha256 %s), %s"
+                % (sha, t.get("source", "profiles/traffic.json")))
     except (OSError, KeyError, ValueError):
-        return None
+        return None, "null: no committed traffic counters"
 
 
 def main():
@@ -269,6 +277,7 @@ def run_bank(args, torch):
     kern_s = k_ms * 1e-3 / k_launches if (k_launches and N % B == 0) else blk_s
     flops_launch = FLOP_UPDATE * float(F) * B + FLOP_SAMPLE * float(T) * B
     achieved = flops_launch / kern_s
+    traffic, traffic_source = measured_traffic()
     log("step %.1f ms, %.3e updates/s, forward kernel %.1f us (%d launches), block call %.1f us "
         "(p50 %.1f, p99 %.1f)" % (ms_step, value, kern_s * 1e6, k_launches, blk_s * 1e6,
                                  np.percentile(blk_ms, 50) * 1e3, np.percentile(blk_ms, 99) * 1e3))
@@ -285,7 +294,9 @@ def run_bank(args, torch):
                    "waves_per_group": info["waves_per_group"], "workgroups": info["n_groups"]},
         "pct_fp32_peak": 100.0 * FLOP_UPDATE * value / PEAK_FP32,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
+                     "traffic_source": traffic_source,
+                     "issue_ceiling": ISSUE_CEILING / 1e12, "frac_of_issue_ceiling": achieved / ISSUE_CEILING,
                      "kernel": "fwd_kernel<FL=%d, keys, LDS window>" % info["filters_per_lane"],
                      "launch_us": kern_s * 1e6, "launches_timed": k_launches,
                      "block_call_us": blk_s * 1e6, "flop_per_launch": flops_launch},
