@@ -577,8 +577,9 @@ def run_adjoint(args, torch):
 
     # a short fit through the autograd Function: loss before and after (fit quality is not a gate)
     from paper_1602_05573_amd import SpiirFn
-    a = torch.tensor(bank.a, dtype=torch.complex128, requires_grad=True)
-    b = torch.tensor(bank.b, dtype=torch.complex128, requires_grad=True)
+    # coefficients, gradients and the optimiser state stay on the device
+    a = torch.tensor(bank.a, dtype=torch.complex128, device="cuda", requires_grad=True)
+    b = torch.tensor(bank.b, dtype=torch.complex128, device="cuda", requires_grad=True)
     Gn = torch.linalg.norm(gt, dim=1)
 
     def overlap_loss(z):
@@ -587,11 +588,14 @@ def run_adjoint(args, torch):
 
     opt = torch.optim.Adam([a, b], lr=args.fit_lr)
     losses = []
-    tf = time.perf_counter()
-    for _ in range(args.fit_steps + 1):
+    tf = 0.0
+    for it in range(args.fit_steps + 1):
+        if it == 1:     # the first step carries the optimiser's and torch's first-use costs
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
         opt.zero_grad()
         lval = overlap_loss(SpiirFn.apply(a, b, bk, xd))
-        losses.append(float(lval))
+        losses.append(lval.detach())   # read after the loop: no host sync inside a step
         if len(losses) > args.fit_steps:
             break
         lval.backward()
@@ -599,12 +603,16 @@ def run_adjoint(args, torch):
         with torch.no_grad():   # keep every pole inside the unit circle
             r = torch.abs(a)
             a.mul_(torch.where(r > 1 - 1e-6, (1 - 1e-6) / r, torch.ones_like(r)))
+    torch.cuda.synchronize()
     tf = time.perf_counter() - tf
+    losses = [float(v) for v in losses]
     res["fit"] = {"steps": args.fit_steps, "optimizer": "Adam lr %g" % args.fit_lr,
                   "mean_loss_before": losses[0], "mean_loss_after": losses[-1],
-                  "s_per_step": tf / max(1, args.fit_steps)}
-    log("fit: mean overlap loss %.4f -> %.4f over %d steps (%.3f s/step incl. coefficient upload)"
-        % (losses[0], losses[-1], args.fit_steps, tf / max(1, args.fit_steps)))
+                  "s_per_step": tf / max(1, args.fit_steps - 1) if args.fit_steps > 1 else None,
+                  "timed_steps": max(0, args.fit_steps - 1),
+                  "note": "coefficients, gradients and optimiser state on the device (spiir_bank_set_coeffs_dev)"}
+    log("fit: mean overlap loss %.4f -> %.4f over %d steps (%.4f s per step after the first, coefficients set "
+        "from the device)" % (losses[0], losses[-1], args.fit_steps, tf / max(1, args.fit_steps - 1)))
     bk.close()
     print(json.dumps(res), flush=True)
 

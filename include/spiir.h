@@ -153,6 +153,22 @@ int spiir_bank_reset(spiir_bank *bank, void *stream);
  */
 int spiir_bank_set_coeffs(spiir_bank *bank, const double *a, const double *b);
 
+/*
+ * The same replacement from device arrays, enqueued on stream (no host copy,
+ * no synchronisation): the gradient step of a coefficient fit can stay on the
+ * device between spiir_backward and the next spiir_forward_z (the fit is this
+ * library's extension; see spiir_forward_z).
+ *   a_dev, b_dev  complex128 [F] (interleaved), caller's filter order, device
+ * The slot values are formed by a kernel exactly as the host call forms them
+ * (fl32 roundings, a^chunk_len and its FP32 drift in FP64, the FP64-carry
+ * flag). The values are not checked: the caller keeps every |a_k| < 1 and
+ * every value finite (the host call rejects others with EINVAL). Work already
+ * enqueued on other streams that uses this bank must complete first (a bank
+ * is used from one stream at a time). Tapes made before the call become stale
+ * (spiir_backward returns SPIIR_ESTATE for them). EINVAL for null pointers.
+ */
+int spiir_bank_set_coeffs_dev(spiir_bank *bank, const double *a_dev, const double *b_dev, void *stream);
+
 /* Size in bytes of a state checkpoint of this bank. */
 int spiir_bank_state_size(const spiir_bank *bank, size_t *nbytes);
 

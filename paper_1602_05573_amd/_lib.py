@@ -31,7 +31,7 @@ EXPORTS = (
     "spiir_whitener_get_psd", "spiir_whitener_process", "spiir_whitener_reset",
     "spiir_trigger_stream_create", "spiir_trigger_stream_push", "spiir_trigger_stream_flush",
     "spiir_trigger_stream_reset", "spiir_trigger_stream_destroy",
-    "spiir_trigger_max_noalloc",
+    "spiir_trigger_max_noalloc", "spiir_bank_set_coeffs_dev",
     "spiir_last_error", "spiir_version",
 )
 
@@ -84,6 +84,7 @@ def load():
         "spiir_bank_get_info": (ctypes.c_int, [P, ctypes.POINTER(BankInfo)]),
         "spiir_bank_reset": (ctypes.c_int, [P, P]),
         "spiir_bank_set_coeffs": (ctypes.c_int, [P, P, P]),
+        "spiir_bank_set_coeffs_dev": (ctypes.c_int, [P, P, P, P]),
         "spiir_bank_state_size": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
         "spiir_bank_get_state": (ctypes.c_int, [P, P, SZ]),
         "spiir_bank_set_state": (ctypes.c_int, [P, P, SZ]),

@@ -113,6 +113,15 @@ class SpiirBank:
         call("spiir_bank_set_coeffs", self._h, self._a.ctypes.data_as(ctypes.c_void_p),
              self._b.ctypes.data_as(ctypes.c_void_p))
 
+    def set_coeffs_dev(self, a: torch.Tensor, b: torch.Tensor, stream=None):
+        """Replaces a, b from complex128 CUDA tensors [F] (caller order), on the
+        stream; the values are not checked (keep |a| < 1)."""
+        for t, name in ((a, "a"), (b, "b")):
+            _require_cuda(t, torch.complex128, name)
+            if t.numel() != self.n_filters:
+                raise ValueError("%s must hold %d coefficients" % (name, self.n_filters))
+        call("spiir_bank_set_coeffs_dev", self._h, _ptr(a), _ptr(b), _stream_ptr(stream))
+
     def get_state(self) -> bytes:
         n = ctypes.c_size_t()
         call("spiir_bank_state_size", self._h, ctypes.byref(n))
@@ -328,15 +337,19 @@ def batch_banks(banks, chunk_len: int, filters_per_lane: int, device: int = 0, *
 class SpiirFn(torch.autograd.Function):
     """z = bank(x) from a cold start, differentiable in the coefficients.
 
-    forward(ctx, a, b, bank, x): a, b complex128 CPU tensors [F] (set into the
-    bank), x float32 CUDA [n]; returns z complex64 CUDA [T, n]. backward runs
-    the library's reverse-time adjoint and returns complex128 CPU gradients in
-    PyTorch's convention (dL/dRe + i dL/dIm).
+    forward(ctx, a, b, bank, x): a, b complex128 tensors [F] (set into the
+    bank: from the device when they live on the bank's GPU, else through the
+    host), x float32 CUDA [n]; returns z complex64 CUDA [T, n]. backward runs
+    the library's reverse-time adjoint and returns complex128 gradients on
+    a's device in PyTorch's convention (dL/dRe + i dL/dIm).
     """
 
     @staticmethod
     def forward(ctx, a, b, bank: SpiirBank, x: torch.Tensor):
-        bank.set_coeffs(a.detach().cpu().numpy(), b.detach().cpu().numpy())
+        if a.is_cuda and b.is_cuda:
+            bank.set_coeffs_dev(a.detach().contiguous(), b.detach().contiguous())
+        else:
+            bank.set_coeffs(a.detach().cpu().numpy(), b.detach().cpu().numpy())
         z, tape = bank.forward_z(x, want_tape=True)
         ctx.bank = bank
         ctx.tape = tape

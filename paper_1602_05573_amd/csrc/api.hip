@@ -731,6 +731,15 @@ int spiir_bank_set_coeffs(spiir_bank *bk, const double *a, const double *b) {
     return SPIIR_OK;
 }
 
+int spiir_bank_set_coeffs_dev(spiir_bank *bk, const double *a, const double *b, void *stream) {
+    if (!bk || !a || !b) return fail(SPIIR_EINVAL, "null argument");
+    DeviceGuard guard(bk->device);
+    HIPCHK(launch_set_coeffs(a, b, bk->slot_filter, bk->lay.nslots, bk->L, bk->a32, bk->b32, bk->aL, bk->dL,
+                             bk->a64, bk->flags, as_stream(stream)));
+    ++bk->coeff_version;
+    return SPIIR_OK;
+}
+
 int spiir_bank_state_size(const spiir_bank *bk, size_t *nbytes) {
     if (!bk || !nbytes) return fail(SPIIR_EINVAL, "null argument");
     *nbytes = 32 + (size_t)bk->F * sizeof(float4) + (size_t)bk->dmax * sizeof(float);

@@ -787,6 +787,28 @@ __global__ void __launch_bounds__(256) finalize_keys_kernel(const uint64_t *keys
     }
 }
 
+// Slot arrays from caller-order FP64 coefficients on the device (the same
+// values the host plan computes: fl32 roundings, a^L and a^L - fl32(a)^L in
+// FP64, the FP64-carry flag). Padding slots keep their zeros.
+__global__ void __launch_bounds__(256) set_coeffs_kernel(const double2 *a, const double2 *b,
+                                                         const int32_t *slot_filter, int64_t nslots, int L,
+                                                         float2 *a32, float2 *b32, double2 *aL, double2 *dL,
+                                                         double2 *a64, int32_t *flags) {
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslots) return;
+    const int k = slot_filter[sl];
+    if (k < 0) return;
+    const double2 av = a[k], bv = b[k];
+    const float2 af = make_float2((float)av.x, (float)av.y);
+    a32[sl] = af;
+    b32[sl] = make_float2((float)bv.x, (float)bv.y);
+    const double2 p = cpow64(av, L), q = cpow64(make_double2((double)af.x, (double)af.y), L);
+    aL[sl] = p;
+    dL[sl] = make_double2(p.x - q.x, p.y - q.y);
+    a64[sl] = av;
+    flags[sl] = hypot(av.x, av.y) > 1.0 - 1e-5 ? 1 : 0;
+}
+
 __global__ void rows_argmax_kernel(const float *snr, int T, int64_t ld, int64_t n, float *mx,
                                    int32_t *am) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1417,6 +1439,16 @@ hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, in
     if (kb + hb == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_keys_kernel, dim3(kb + hb), dim3(256), 0, st, keys, groups, ld, n, mx, am, h,
                        kb);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_coeffs(const double *a, const double *b, const int32_t *slot_filter, int64_t nslots, int L,
+                             float2 *a32, float2 *b32, double2 *aL, double2 *dL, double2 *a64, int32_t *flags,
+                             hipStream_t st) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_coeffs_kernel, dim3(nblocks(nslots, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const double2 *>(a), reinterpret_cast<const double2 *>(b), slot_filter,
+                       nslots, L, a32, b32, aL, dL, a64, flags);
     return hipGetLastError();
 }
 

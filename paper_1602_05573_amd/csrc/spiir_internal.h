@@ -117,6 +117,10 @@ hipError_t launch_backward(const BwdArgs &a, hipStream_t stream);
 // the history copy (one launch fewer per streaming call).
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t stream, const HistCopy *hc = nullptr);
+// Slot arrays of a bank from caller-order complex128 a, b on the device.
+hipError_t launch_set_coeffs(const double *a, const double *b, const int32_t *slot_filter, int64_t nslots, int L,
+                             float2 *a32, float2 *b32, double2 *aL, double2 *dL, double2 *a64, int32_t *flags,
+                             hipStream_t stream);
 hipError_t launch_rows_argmax(const float *snr, int T, int64_t ld, int64_t n, float *mx,
                               int32_t *am, hipStream_t stream);
 hipError_t launch_hist_update(const float *old_h, float *new_h, const float *x, int64_t n,

@@ -209,6 +209,84 @@ def test_stale_tape_is_rejected():
         tape.close()
 
 
+def test_set_coeffs_from_device():
+    """spiir_bank_set_coeffs_dev: new coefficients from device arrays give the
+    oracle's z for those coefficients, agree with the host call to rounding,
+    and make older tapes stale; padding slots and the FP64-carry flags are
+    formed as the host forms them (a filter with |a| > 1 - 1e-5 included)."""
+    banner("set coeffs from the device")
+    from paper_1602_05573_amd import SpiirError
+    bank = random_bank(63, 0, 5, 30, 300, 0.99, 1 - 1e-6, 1000)
+    rng = np.random.default_rng(6301)
+    F = bank.n_filters
+    r = rng.uniform(0.99, 1 - 2e-6, F)
+    r[3] = 1 - 3e-6                                   # FP64-carry filter
+    a2 = r * np.exp(1j * rng.uniform(0.01, 1.5, F))
+    b2 = bank.b * np.exp(1j * rng.uniform(0, 6.28, F))
+    bank2 = Bank(bank.offsets, a2, b2, bank.d, bank.dmax)
+    x = strain(6000, 63)
+    xd = torch.from_numpy(x).cuda()
+    with mk(bank, chunk_len=128) as hb, mk(bank, chunk_len=128) as db:
+        z0, tape = db.forward_z(xd, want_tape=True)
+        hb.set_coeffs(a2, b2)
+        db.set_coeffs_dev(torch.from_numpy(a2).cuda(), torch.from_numpy(b2).cuda())
+        with pytest.raises(SpiirError, match="changed"):
+            db.backward(tape, torch.zeros_like(z0))
+        tape.close()
+        zh = hb.forward_z(xd).cpu().numpy()
+        zd = db.forward_z(xd).cpu().numpy()
+    ref = oracle.z(bank2, x)
+    peak = np.abs(ref).max(axis=1)
+    err_d = float(np.max(np.abs(zd - ref).max(axis=1) / peak))
+    err_hd = float(np.max(np.abs(zd - zh).max(axis=1) / peak))
+    print("device-set z error %.3g of the peak, device vs host %.3g" % (err_d, err_hd), flush=True)
+    assert err_d <= 1e-4 and err_hd <= 1e-6
+
+
+def test_spiirfn_on_device():
+    """SpiirFn with a, b on the GPU: the coefficients go in by the device call
+    and the gradients come back on the device, equal to the oracle's; a few
+    device-resident Adam steps lower the loss."""
+    banner("SpiirFn on the device")
+    from paper_1602_05573_amd import SpiirFn
+    bank = random_bank(64, 0, 3, 40, 120, 0.95, 0.999, 300)
+    x = strain(3000, 64)
+    rng = np.random.default_rng(6401)
+    g = (rng.standard_normal((3, 3000)) + 1j * rng.standard_normal((3, 3000)))
+    gt = torch.from_numpy(g.astype(np.complex64)).cuda()
+    xd = torch.from_numpy(x).cuda()
+
+    def loss_fn(z):
+        c = torch.sum(z * torch.conj(gt), dim=1)
+        return torch.sum(1 - torch.abs(c) / (torch.linalg.norm(z, dim=1) * torch.linalg.norm(gt, dim=1)))
+
+    with mk(bank) as bk:
+        a = torch.tensor(bank.a, dtype=torch.complex128, device="cuda", requires_grad=True)
+        b = torch.tensor(bank.b, dtype=torch.complex128, device="cuda", requires_grad=True)
+        loss = loss_fn(SpiirFn.apply(a, b, bk, xd))
+        loss.backward()
+        assert a.grad.is_cuda and b.grad.is_cuda
+        zr = oracle.z(bank, x)
+        lref, Gref = oracle.overlap_loss(zr, g)
+        ga_ref, gb_ref = oracle.backward(bank, x, Gref)
+        assert abs(float(loss.detach()) - float(np.sum(lref))) < 1e-4
+        grad_close(a.grad.cpu().numpy(), ga_ref, bank.offsets, what="device SpiirFn grad_a")
+        grad_close(b.grad.cpu().numpy(), gb_ref, bank.offsets, what="device SpiirFn grad_b")
+        opt = torch.optim.Adam([a, b], lr=1e-4)
+        first = float(loss.detach())
+        for _ in range(10):
+            opt.zero_grad()
+            l = loss_fn(SpiirFn.apply(a, b, bk, xd))
+            l.backward()
+            opt.step()
+            with torch.no_grad():
+                r = torch.abs(a)
+                a.mul_(torch.where(r > 1 - 1e-6, (1 - 1e-6) / r, torch.ones_like(r)))
+        last = float(loss_fn(SpiirFn.apply(a, b, bk, xd)).detach())
+        print("device fit loss %.4f -> %.4f" % (first, last), flush=True)
+        assert last < first
+
+
 def test_chirp_fit_full_size_every_template():
     """256 templates x 400 filters, 65,536 samples (the bench.py adjoint
     workload): GPU forward + adjoint over the whole bank, compared with the
