@@ -113,6 +113,7 @@ typedef struct {
     int32_t device;
     int32_t n_cu;             /* compute units of the device */
     int32_t time_split;       /* segments per streaming launch (1 = no split) */
+    int32_t n_parts;          /* parts of the templates split over workgroups (0: none) */
 } spiir_bank_info;
 
 /* Fills *opts with the defaults listed above. */
@@ -129,7 +130,13 @@ void spiir_bank_opts_default(spiir_bank_opts *opts);
  *   d               int32 [F], 0 <= d_k <= max_delay
  *   opts            NULL = defaults
  * Filters are reordered into device slots internally; every per-filter output
- * (gradients, state) is reported in the caller's order. The bank starts cold
+ * (gradients, state) is reported in the caller's order. A template with more
+ * filters than one workgroup holds (4 x waves_per_group rows of 16 lanes x
+ * filters_per_lane; 2,048 at 8 waves and 4 filters per lane) is split into
+ * parts in separate workgroups; each part's partial sum is written to a bank
+ * buffer and a combine launch adds the parts, in part order, before the SNR,
+ * z or key of that template. Banks with split templates are not accepted by
+ * spiir_trigger_max_per_template and spiir_batch_create. The bank starts cold
  * (zero states, zero history). *out receives the bank, or NULL on failure.
  */
 int spiir_bank_create(spiir_bank **out, int32_t n_templates, const int64_t *filter_offsets,
@@ -260,7 +267,8 @@ int spiir_trigger_max_noalloc(spiir_bank *bank, const float *x_dev, int64_t n,
  * the call's samples in global memory. The segment scratch (two states per
  * slot of one workgroup and segment, one complex sum per template-sample)
  * and the window are allocated on first use. Continues the same stream as spiir_trigger_max.
- * n = 0 is a no-op; EINVAL for a null bank or pointer or n < 0.
+ * n = 0 is a no-op; EINVAL for a null bank or pointer, n < 0, or a bank with
+ * templates split over workgroups.
  */
 int spiir_trigger_max_per_template(spiir_bank *bank, const float *x_dev, int64_t n,
                                    float *max_dev, int32_t *argmax_dev,
@@ -322,7 +330,9 @@ int spiir_tape_destroy(spiir_tape *tape);
  *   block_len   samples per step and stream, multiple of 8 (e.g. 4096)
  * The stream positions live on the device, so each replay of the same graph
  * advances every live stream by one block; ended streams are skipped and the
- * last block of a stream may be partial. Banks start cold.
+ * last block of a stream may be partial. Banks start cold. EINVAL for banks
+ * that differ in layout, keep their strain window outside LDS, or hold
+ * templates split over workgroups.
  */
 int spiir_batch_create(spiir_batch **out, int32_t n_streams, spiir_bank *const *banks,
                        const float *const *x_dev, const int64_t *lengths,

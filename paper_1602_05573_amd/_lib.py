@@ -57,7 +57,8 @@ class BankInfo(ctypes.Structure):
                 ("n_groups", ctypes.c_int32), ("n_slots", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int32), ("x_in_lds", ctypes.c_int32),
                 ("sub_block", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("n_cu", ctypes.c_int32), ("time_split", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("n_cu", ctypes.c_int32), ("time_split", ctypes.c_int32),
+                ("n_parts", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -108,9 +108,14 @@ struct spiir_bank {
     int tt = 16;
     float *hist[2] = {nullptr, nullptr};
     int hist_cur = 0;
-    uint64_t *keys = nullptr;
+    uint64_t *keys = nullptr;     // [groups + (split templates ? 1 : 0)][max_block]
     float *xwin = nullptr;
     int64_t xwin_cap = 0;
+    // templates split over workgroups (layout parts): partial sums [n_parts][max_block],
+    // the split templates and their part ranges on the device
+    float2 *zpart = nullptr;
+    int32_t *split_tpl = nullptr, *split_off = nullptr;
+    int n_split = 0;
     int nseg = 1;                 // time segments per streaming launch
     int64_t seg_len_max = 0;
     size_t lds_carry = 0;
@@ -153,6 +158,8 @@ struct spiir_bank {
         p.seg_start = seg_start;
         p.seg_slot0 = 0;
         p.seg_stride = lay.nslots;
+        p.zpart = zpart;
+        p.ld_part = max_block;
         p.zl = zl;
         return p;
     }
@@ -256,6 +263,7 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->filter_slot); dfree(bk->bwaves);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
+    dfree(bk->zpart); dfree(bk->split_tpl); dfree(bk->split_off);
     dfree(bk->bpair); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
     dfree(bk->pl_seg_end); dfree(bk->pl_seg_start); dfree(bk->pl_zl);
     bk->pl_cap = 0;
@@ -326,13 +334,11 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
         if (global_window && plan_rows(T, off, 4).max_nr <= 4 * kMaxWaves) fl = 4;
     }
     const Plan plan = plan_rows(T, off, fl);
-    if (plan.max_nr > 4 * kMaxWaves)
-        return fail(SPIIR_EINVAL, "a template has more than %d filters; use more filters per lane",
-                    4 * kMaxWaves * kRowLanes * fl);
     int wpg = o.waves_per_group;
     if (wpg == 0) {
-        // smallest workgroup that packs the bank into one round of resident workgroups
-        const int w0 = auto_wpg(plan.total_rows, plan.max_nr, df.n_cu);
+        // smallest workgroup that packs the bank into one round of resident workgroups (a
+        // template longer than the largest workgroup is split into parts)
+        const int w0 = auto_wpg(plan.total_rows, std::min(plan.max_nr, 4 * kMaxWaves), df.n_cu);
         wpg = w0;
         for (int w = w0; w <= kMaxWaves; ++w) {
             const Geometry gm = plan_geometry(w, dmax, L, max_block, df.lds_cap);
@@ -399,7 +405,13 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     A(dalloc(&bk->slot_filter, S)); A(dalloc(&bk->filter_slot, (size_t)bk->F)); A(dalloc(&bk->aL, S)); A(dalloc(&bk->dL, S)); A(dalloc(&bk->a64, S));
     A(dalloc(&bk->state, S)); A(dalloc(&bk->zstate, S)); A(dalloc(&bk->rows, (size_t)G * wpg * 4));
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
-    A(dalloc(&bk->keys, (size_t)G * max_block));
+    bk->n_split = (int)bk->lay.split_tpl.size();
+    A(dalloc(&bk->keys, (size_t)(G + (bk->n_split ? 1 : 0)) * max_block));
+    if (bk->n_split) {
+        A(dalloc(&bk->zpart, (size_t)bk->lay.n_parts * max_block));
+        A(dalloc(&bk->split_tpl, bk->lay.split_tpl.size()));
+        A(dalloc(&bk->split_off, bk->lay.split_off.size()));
+    }
     if (bk->nseg > 1) {
         A(dalloc(&bk->seg_end, (size_t)bk->nseg * S));
         A(dalloc(&bk->seg_start, (size_t)bk->nseg * S));
@@ -434,6 +446,12 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
             e = hipMemcpy(bk->rows, bk->lay.rows.data(), bk->lay.rows.size() * sizeof(RowInfo),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(bk->state, 0, S * sizeof(float4));
+        if (e == hipSuccess && bk->n_split)
+            e = hipMemcpy(bk->split_tpl, bk->lay.split_tpl.data(), bk->lay.split_tpl.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess && bk->n_split)
+            e = hipMemcpy(bk->split_off, bk->lay.split_off.data(), bk->lay.split_off.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
         if (e == hipSuccess && bk->nseg > 1) e = hipMemset(bk->seg_end, 0, (size_t)bk->nseg * S * sizeof(float4));
         if (e == hipSuccess && bk->nseg > 1) e = hipMemset(bk->seg_start, 0, (size_t)bk->nseg * S * sizeof(float4));
         if (e == hipSuccess && dmax > 0) e = hipMemset(bk->hist[0], 0, (size_t)dmax * sizeof(float));
@@ -538,9 +556,13 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
                                         bk->slot_filter, st, ev));
         else
             HIPCHK(launch_forward(a, mode, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev));
+        if (bk->n_split)   // split templates: their parts' sums, then their SNR / z / keys
+            HIPCHK(launch_combine_parts(bk->zpart, bk->max_block, bk->split_tpl, bk->split_off, bk->n_split, np,
+                                        mode, a.snr, a.z, a.ld, a.obase, keys + (int64_t)bk->lay.groups * keys_ld,
+                                        st));
         if (mode == kModeKeys) {
-            HIPCHK(launch_finalize_keys(keys, bk->lay.groups, keys_ld, np, mx + P, am + P, st,
-                                        last ? &hc : nullptr));
+            HIPCHK(launch_finalize_keys(keys, bk->lay.groups + (bk->n_split ? 1 : 0), keys_ld, np, mx + P, am + P,
+                                        st, last ? &hc : nullptr));
             hist_done = hist_done || last;
         }
     }
@@ -699,6 +721,7 @@ int spiir_bank_get_info(const spiir_bank *bk, spiir_bank_info *info) {
     info->device = bk->device;
     info->n_cu = bk->dev.n_cu;
     info->time_split = bk->nseg;
+    info->n_parts = bk->lay.n_parts;
     return SPIIR_OK;
 }
 
@@ -837,7 +860,8 @@ size_t plan_scratch(const spiir_bank *bk, int64_t n, unsigned char *scr, CallScr
     };
     const int64_t keys_ld = std::min<int64_t>(n, bk->max_block);
     cs.keys_ld = keys_ld;
-    cs.keys = reinterpret_cast<uint64_t *>(take((size_t)bk->lay.groups * keys_ld * sizeof(uint64_t)));
+    cs.keys = reinterpret_cast<uint64_t *>(
+        take((size_t)(bk->lay.groups + (bk->n_split ? 1 : 0)) * keys_ld * sizeof(uint64_t)));
     const size_t seg_bytes = (size_t)bk->nseg * bk->lay.nslots * sizeof(float4);
     if (bk->nseg > 1) {
         cs.seg_end = reinterpret_cast<float4 *>(take(seg_bytes));
@@ -884,6 +908,8 @@ int spiir_trigger_max_per_template(spiir_bank *bk, const float *x, int64_t n, fl
     if (n < 0) return fail(SPIIR_EINVAL, "n must be >= 0");
     if (n == 0) return SPIIR_OK;
     if (!x || !mx || !am || !snr) return fail(SPIIR_EINVAL, "null device pointer");
+    if (bk->n_split)
+        return fail(SPIIR_EINVAL, "the per-template comparator needs every template inside one workgroup");
     DeviceGuard guard(bk->device);
     hipStream_t st = as_stream(stream);
     const float *hist = bk->hist[bk->hist_cur];
@@ -1011,6 +1037,9 @@ int spiir_forward_z(spiir_bank *bk, const float *x, int64_t n, float *z, spiir_t
                                      bk->slot_filter, st, ev);
         else
             e = launch_forward(a, kModeZ, bk->lay.fl, bk->tt, bk->xlds, bk->lay.groups, bk->lds, st, ev);
+        if (e == hipSuccess && bk->n_split)
+            e = launch_combine_parts(bk->zpart, bk->max_block, bk->split_tpl, bk->split_off, bk->n_split, np, kModeZ,
+                                     nullptr, a.z, a.ld, a.obase, nullptr, st);
     }
     if (e != hipSuccess) {
         if (tp) {
@@ -1117,6 +1146,8 @@ int spiir_batch_create(spiir_batch **out, int32_t ns, spiir_bank *const *banks, 
             banks[s]->tt != banks[0]->tt)
             return fail(SPIIR_EINVAL, "banks must share filters_per_lane, waves_per_group and tile length");
         if (!banks[s]->xlds) return fail(SPIIR_EINVAL, "bank %d keeps its strain window outside LDS", s);
+        if (banks[s]->n_split)
+            return fail(SPIIR_EINVAL, "bank %d has templates split over workgroups; a batch takes none", s);
         for (int t = 0; t < s; ++t)
             if (banks[t] == banks[s]) return fail(SPIIR_EINVAL, "a bank appears twice in the batch");
     }

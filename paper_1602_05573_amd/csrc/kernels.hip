@@ -344,7 +344,9 @@ struct SegCtx {
 
 // The whole forward pass of workgroup g over launch samples [sc.tb, sc.tb + sc.tn).
 // CARRY: free response of the given state only (no input), z_local added.
-template <int FL, int TT, int MODE, bool XLDS, bool CARRY>
+// PARTS: the bank has templates split over workgroups (rows with part >= 0);
+// banks without them run the variant that has no part branch.
+template <int FL, int TT, int MODE, bool XLDS, bool CARRY, bool PARTS = false>
 __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const SegCtx &sc) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = p.wpg, R = 4 * W, Rp = R + 1;  // odd row stride of wsum: no bank aliasing over t
@@ -452,23 +454,36 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
                 else
                     sum_rows_loop(ws, ri.nr, zr, zi);
                 const int64_t tl = s0 + t0 + tl16;
-                if (sc.zl_in) {
-                    const float2 zl = sc.zl_in[(int64_t)ri.tpl * sc.ld_zl + tl];
-                    zr += zl.x;
-                    zi += zl.y;
-                }
-                if (sc.zl_out) {
-                    sc.zl_out[(int64_t)ri.tpl * sc.ld_zl + tl] = make_float2(zr, zi);
-                } else if (MODE == kModeSnr) {
-                    p.snr[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = zr * zr + zi * zi;
-                } else if (MODE == kModeZ) {
-                    p.z[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = make_float2(zr, zi);
+                if (PARTS && ri.part >= 0) {
+                    // one part of a template split over workgroups: its partial sum (the
+                    // segment's local sum, completed in place by the carry pass) goes to the
+                    // part's row; the parts are added before the mode's output
+                    float2 *zp = p.zpart + (int64_t)ri.part * p.ld_part + sc.tb + tl;
+                    if (sc.zl_in) {
+                        const float2 zl = *zp;
+                        zr += zl.x;
+                        zi += zl.y;
+                    }
+                    *zp = make_float2(zr, zi);
                 } else {
-                    const float sn = zr * zr + zi * zi;
-                    const unsigned long long key =
-                        ((unsigned long long)__float_as_uint(sn) << 32) |
-                        (unsigned long long)(0xFFFFFFFFu - (uint32_t)ri.tpl);
-                    atomicMax(&kmax[buf * TT + tl16], key);
+                    if (sc.zl_in) {
+                        const float2 zl = sc.zl_in[(int64_t)ri.tpl * sc.ld_zl + tl];
+                        zr += zl.x;
+                        zi += zl.y;
+                    }
+                    if (sc.zl_out) {
+                        sc.zl_out[(int64_t)ri.tpl * sc.ld_zl + tl] = make_float2(zr, zi);
+                    } else if (MODE == kModeSnr) {
+                        p.snr[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = zr * zr + zi * zi;
+                    } else if (MODE == kModeZ) {
+                        p.z[(int64_t)ri.tpl * p.ld + p.obase + sc.tb + tl] = make_float2(zr, zi);
+                    } else {
+                        const float sn = zr * zr + zi * zi;
+                        const unsigned long long key =
+                            ((unsigned long long)__float_as_uint(sn) << 32) |
+                            (unsigned long long)(0xFFFFFFFFu - (uint32_t)ri.tpl);
+                        atomicMax(&kmax[buf * TT + tl16], key);
+                    }
                 }
             }
             if (keys_out) {
@@ -513,17 +528,17 @@ __device__ __forceinline__ SegCtx whole_launch(const FwdArgs &p) {
     return sc;
 }
 
-template <int FL, int TT, int MODE, bool XLDS>
+template <int FL, int TT, int MODE, bool XLDS, bool PARTS>
 __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SegCtx sc = whole_launch(p);
-    fwd_group<FL, TT, MODE, XLDS, false>(p, p.gbase + blockIdx.x, smem, sc);
+    fwd_group<FL, TT, MODE, XLDS, false, PARTS>(p, p.gbase + blockIdx.x, smem, sc);
 }
 
 // Time split, local pass: item (segment, group). Segment 0 starts from the
 // carried state and writes the mode's output; later segments start cold and
 // keep their local z. Every item stores its end state.
-template <int FL, int TT, int MODE, bool XLDS>
+template <int FL, int TT, int MODE, bool XLDS, bool PARTS>
 __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int g = p.gbase + blockIdx.x % p.groups, seg = blockIdx.x / p.groups;
@@ -542,12 +557,12 @@ __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
         sc.ld_zl = p.seg_len;
     }
     sc.zl_in = nullptr;
-    fwd_group<FL, TT, MODE, XLDS, false>(p, g, smem, sc);
+    fwd_group<FL, TT, MODE, XLDS, false, PARTS>(p, g, smem, sc);
 }
 
 // Time split, carry pass over segments 1..: free response of the true
 // segment-start state plus the local z, then the mode's output.
-template <int FL, int TT, int MODE>
+template <int FL, int TT, int MODE, bool PARTS>
 __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int g = p.gbase + blockIdx.x % p.groups, seg = 1 + blockIdx.x / p.groups;
@@ -566,7 +581,7 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
         sc.zl_in = p.zl + (int64_t)(seg - 1) * p.n_templates * p.seg_len;
         sc.ld_zl = p.seg_len;
     }
-    fwd_group<FL, TT, MODE, false, true>(p, g, smem, sc);
+    fwd_group<FL, TT, MODE, false, true, PARTS>(p, g, smem, sc);
 }
 
 __device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
@@ -785,6 +800,40 @@ __global__ void __launch_bounds__(256) finalize_keys_kernel(const uint64_t *keys
         mx[i] = __uint_as_float((uint32_t)(k >> 32));
         am[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
     }
+}
+
+// Templates split over workgroups: z_j = the sum of its parts' partial sums
+// (in part order) for samples [0, n) of a piece, then the mode's output for
+// those templates: SNR rows, z rows, or (keys) the per-sample maximum key over
+// the split templates into key_row, which the key finalisation takes as one
+// more workgroup.
+__global__ void __launch_bounds__(256) combine_parts_kernel(const float2 *zpart, int64_t ld_part,
+                                                            const int32_t *split_tpl, const int32_t *split_off,
+                                                            int n_split, int64_t n, int mode, float *snr, float2 *z,
+                                                            int64_t ld, int64_t obase, uint64_t *key_row) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    unsigned long long kbest = 0ull;
+    for (int i = 0; i < n_split; ++i) {
+        float zr = 0.f, zi = 0.f;
+        for (int q = split_off[i]; q < split_off[i + 1]; ++q) {
+            const float2 v = zpart[(int64_t)q * ld_part + t];
+            zr += v.x;
+            zi += v.y;
+        }
+        const int j = split_tpl[i];
+        if (mode == kModeSnr) {
+            snr[(int64_t)j * ld + obase + t] = zr * zr + zi * zi;
+        } else if (mode == kModeZ) {
+            z[(int64_t)j * ld + obase + t] = make_float2(zr, zi);
+        } else {
+            const float sn = zr * zr + zi * zi;
+            const unsigned long long key = ((unsigned long long)__float_as_uint(sn) << 32) |
+                                           (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
+            kbest = key > kbest ? key : kbest;
+        }
+    }
+    if (mode == kModeKeys) key_row[t] = kbest;
 }
 
 // Slot arrays from caller-order FP64 coefficients on the device (the same
@@ -1307,8 +1356,12 @@ __global__ void batch_advance_kernel(int64_t *pos, const BatchStream *streams, i
 
 template <int FL, int TT, int MODE, bool XLDS>
 hipError_t launch_fwd_t(const FwdArgs &a, int groups, size_t lds, hipStream_t st, KernelEvents ev) {
-    hipExtLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS>), dim3(groups), dim3(a.wpg * 64), (uint32_t)lds, st,
-                          ev.start, ev.stop, 0u, a);
+    if (a.zpart)
+        hipExtLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS, true>), dim3(groups), dim3(a.wpg * 64), (uint32_t)lds,
+                              st, ev.start, ev.stop, 0u, a);
+    else
+        hipExtLaunchKernelGGL((fwd_kernel<FL, TT, MODE, XLDS, false>), dim3(groups), dim3(a.wpg * 64), (uint32_t)lds,
+                              st, ev.start, ev.stop, 0u, a);
     return hipGetLastError();
 }
 
@@ -1337,8 +1390,12 @@ hipError_t launch_fwd_x(const FwdArgs &a, int mode, int fl, int groups, size_t l
 template <int FL, int TT, int MODE, bool XLDS>
 hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_carry, const int32_t *slot_filter,
                           hipStream_t st, KernelEvents ev) {
-    hipExtLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS>), dim3(a.groups * nseg), dim3(a.wpg * 64),
-                          (uint32_t)lds, st, ev.start, (hipEvent_t) nullptr, 0u, a);
+    if (a.zpart)
+        hipExtLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS, true>), dim3(a.groups * nseg), dim3(a.wpg * 64),
+                              (uint32_t)lds, st, ev.start, (hipEvent_t) nullptr, 0u, a);
+    else
+        hipExtLaunchKernelGGL((fwd_seg_kernel<FL, TT, MODE, XLDS, false>), dim3(a.groups * nseg), dim3(a.wpg * 64),
+                              (uint32_t)lds, st, ev.start, (hipEvent_t) nullptr, 0u, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((a.seg_stride + 255) / 256);
@@ -1347,8 +1404,12 @@ hipError_t launch_split_t(const FwdArgs &a, int nseg, size_t lds, size_t lds_car
     hipLaunchKernelGGL(seg_chain_kernel, dim3(nb + hb), dim3(256), 0, st, a, FL, nseg, nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),
-                          (uint32_t)lds_carry, st, (hipEvent_t) nullptr, ev.stop, 0u, a);
+    if (a.zpart)
+        hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE, true>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),
+                              (uint32_t)lds_carry, st, (hipEvent_t) nullptr, ev.stop, 0u, a);
+    else
+        hipExtLaunchKernelGGL((fwd_carry_kernel<FL, TT, MODE, false>), dim3(a.groups * (nseg - 1)), dim3(a.wpg * 64),
+                              (uint32_t)lds_carry, st, (hipEvent_t) nullptr, ev.stop, 0u, a);
     return hipGetLastError();
 }
 
@@ -1376,7 +1437,7 @@ hipError_t launch_split_x(const FwdArgs &a, int mode, int fl, int nseg, size_t l
 template <int FL, int TT>
 int occ_t(int wpg, size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<FL, TT, kModeKeys, true>, wpg * 64, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<FL, TT, kModeKeys, true, false>, wpg * 64, lds) !=
         hipSuccess)
         return 0;
     return nb;
@@ -1439,6 +1500,15 @@ hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, in
     if (kb + hb == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_keys_kernel, dim3(kb + hb), dim3(256), 0, st, keys, groups, ld, n, mx, am, h,
                        kb);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine_parts(const float2 *zpart, int64_t ld_part, const int32_t *split_tpl,
+                                const int32_t *split_off, int n_split, int64_t n, int mode, float *snr, float2 *z,
+                                int64_t ld, int64_t obase, uint64_t *key_row, hipStream_t st) {
+    if (n <= 0 || n_split <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_parts_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, zpart, ld_part, split_tpl,
+                       split_off, n_split, n, mode, snr, z, ld, obase, key_row);
     return hipGetLastError();
 }
 

@@ -227,48 +227,77 @@ int check_bank_args(int32_t T, const int64_t *off, const double *a, const double
 }
 
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay, std::string &err) {
+    (void)err;
     const int R = 4 * wpg;
-    std::vector<int> nr(T);
-    int max_nr = 0;
+    const int64_t row_cap = (int64_t)kRowLanes * fl;   // filters per row
+    // packing items: a whole template, or one part of a split template
+    struct Item {
+        int tpl, part, nr;
+        int64_t k0, k1;
+    };
+    std::vector<Item> items;
+    std::vector<int> first_part((size_t)T, -1);
+    lay.n_parts = 0;
+    lay.part_tpl.clear();
+    lay.split_tpl.clear();
+    lay.split_off.assign(1, 0);
     for (int j = 0; j < T; ++j) {
-        nr[j] = rows_of(off[j + 1] - off[j], fl);
-        max_nr = std::max(max_nr, nr[j]);
+        const int nr = rows_of(off[j + 1] - off[j], fl);
+        if (nr <= R) {
+            items.push_back(Item{j, -1, nr, off[j], off[j + 1]});
+            continue;
+        }
+        const int np = (nr + R - 1) / R;
+        lay.split_tpl.push_back(j);
+        first_part[(size_t)j] = lay.n_parts;
+        int64_t k0 = off[j];
+        int done = 0;
+        for (int q = 0; q < np; ++q) {
+            const int rq = (nr - done + (np - q) - 1) / (np - q);   // balanced row counts
+            const int64_t k1 = std::min<int64_t>(off[j + 1], k0 + rq * row_cap);
+            items.push_back(Item{j, lay.n_parts, rows_of(k1 - k0, fl), k0, k1});
+            lay.part_tpl.push_back(j);
+            ++lay.n_parts;
+            done += rq;
+            k0 = k1;
+        }
+        lay.split_off.push_back(lay.n_parts);
     }
-    if (max_nr > R)
-        return bad(err, "a template needs %d rows of %d filters but a workgroup has %d", max_nr, kRowLanes * fl, R);
-    std::vector<int> order(T);
-    for (int j = 0; j < T; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nr[x] > nr[y]; });
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return items[x].nr > items[y].nr; });
     std::vector<int> room;                  // free rows per group
-    std::vector<std::vector<int>> members;  // templates per group
-    for (int j : order) {
+    std::vector<std::vector<int>> members;  // items per group
+    for (int i : order) {
         size_t g = 0;
         for (; g < room.size(); ++g)
-            if (room[g] >= nr[j]) break;
+            if (room[g] >= items[i].nr) break;
         if (g == room.size()) {
             room.push_back(R);
             members.emplace_back();
         }
-        room[g] -= nr[j];
-        members[g].push_back(j);
+        room[g] -= items[i].nr;
+        members[g].push_back(i);
     }
     lay.fl = fl;
     lay.wpg = wpg;
     lay.groups = (int)members.size();
     lay.nslots = (int64_t)lay.groups * wpg * fl * 64;
-    lay.rows.assign((size_t)lay.groups * R, RowInfo{-1, 0, 0, 0});
+    lay.rows.assign((size_t)lay.groups * R, RowInfo{-1, 0, 0, -1});
     lay.slot_filter.assign((size_t)lay.nslots, -1);
     lay.pad_src.assign((size_t)lay.nslots, -1);
     lay.tpl_group.assign(T, -1);
     for (int g = 0; g < lay.groups; ++g) {
         std::vector<int> &mem = members[g];
-        std::sort(mem.begin(), mem.end());
+        std::sort(mem.begin(), mem.end());   // items are in template order, parts in part order
         int r0 = 0;
-        for (int j : mem) {
-            lay.tpl_group[j] = g;
-            for (int r = 0; r < nr[j]; ++r) lay.rows[(size_t)g * R + r0 + r] = RowInfo{j, r0, nr[j], 0};
-            deal_template(off[j], off[j + 1], d, g, wpg, fl, r0, nr[j], lay);
-            r0 += nr[j];
+        for (int i : mem) {
+            const Item &it = items[i];
+            if (it.part < 0 || it.part == first_part[(size_t)it.tpl]) lay.tpl_group[it.tpl] = g;
+            for (int r = 0; r < it.nr; ++r)
+                lay.rows[(size_t)g * R + r0 + r] = RowInfo{it.tpl, r0, it.nr, it.part};
+            deal_template(it.k0, it.k1, d, g, wpg, fl, r0, it.nr, lay);
+            r0 += it.nr;
         }
     }
     return SPIIR_OK;

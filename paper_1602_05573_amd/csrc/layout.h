@@ -19,9 +19,11 @@ constexpr int kMaxWaves = 8;    // 64-lane waves per workgroup (512 threads)
 constexpr int kRowLanes = 16;   // lanes per row; a row serves exactly one template
 
 // Per 16-lane row of a workgroup: the template it serves (-1: none), the
-// first row of that template inside the workgroup and its number of rows.
+// first row of that template (or of its part) inside the workgroup, its number
+// of rows there, and the part index when the template is split over several
+// workgroups (-1: the whole template is in this workgroup).
 struct RowInfo {
-    int32_t tpl, r0, nr, pad;
+    int32_t tpl, r0, nr, part;
 };
 
 namespace layout {
@@ -35,7 +37,14 @@ struct Layout {
     std::vector<RowInfo> rows;            // [groups * wpg * 4]
     std::vector<int32_t> slot_filter;     // [nslots], -1 = padding
     std::vector<int64_t> pad_src;         // [nslots], padding: slot whose window offset it reuses (-1: none)
-    std::vector<int32_t> tpl_group;       // [T]
+    std::vector<int32_t> tpl_group;       // [T] (a split template: the group of its first part)
+    // Templates with more rows than a workgroup has are split into parts of at
+    // most 4 wpg rows, each packed like a template; parts of one template have
+    // consecutive indices.
+    int n_parts = 0;
+    std::vector<int32_t> part_tpl;        // [n_parts] template of each part
+    std::vector<int32_t> split_tpl;       // [n_split] split templates, increasing
+    std::vector<int32_t> split_off;       // [n_split + 1] parts of split_tpl[i]: split_off[i] .. split_off[i+1]-1
 };
 
 struct Plan {
@@ -86,10 +95,10 @@ Geometry plan_geometry(int wpg, int dmax, int L, int max_block, size_t lds_cap);
 // effective max_delay, or SPIIR_EINVAL with a message in err.
 int check_bank_args(int32_t T, const int64_t *off, const double *a, const double *b, const int32_t *d,
                     const spiir_bank_opts &o, int &dmax_out, std::string &err);
-// First-fit decreasing packing of whole templates into workgroups of 4 wpg
-// rows, then the delay-aware dealing of every template's filters over its
-// slot columns. Returns SPIIR_OK, or SPIIR_EINVAL (message in err) when a
-// template needs more rows than a workgroup has.
+// First-fit decreasing packing of templates into workgroups of 4 wpg rows (a
+// template with more rows than that is first split into parts of balanced row
+// counts, each packed as one item), then the delay-aware dealing of every
+// template's (or part's) filters over its slot columns. Returns SPIIR_OK.
 int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay, std::string &err);
 // FP64 powers and FP32 roundings of every slot's coefficients (a, b complex128
 // interleaved [F], caller order).

@@ -51,6 +51,8 @@ struct FwdArgs {
     float *snr;           // kModeSnr: snr[tpl * ld + obase + t]
     uint64_t *keys;       // kModeKeys: keys[group * ld + t]
     float2 *z;            // kModeZ: z[tpl * ld + obase + t]
+    float2 *zpart;        // rows of split templates' parts: zpart[part * ld_part + t] (piece-local t)
+    int64_t ld_part;
     int64_t nslots;
     // time split of one launch into nseg segments of seg_len samples
     int32_t groups;       // workgroups of the bank (item = segment * groups + group)
@@ -117,6 +119,11 @@ hipError_t launch_backward(const BwdArgs &a, hipStream_t stream);
 // the history copy (one launch fewer per streaming call).
 hipError_t launch_finalize_keys(const uint64_t *keys, int groups, int64_t ld, int64_t n,
                                 float *mx, int32_t *am, hipStream_t stream, const HistCopy *hc = nullptr);
+// Sums the parts of split templates and writes the mode's output for them
+// (key_row: the per-sample maximum key over the split templates).
+hipError_t launch_combine_parts(const float2 *zpart, int64_t ld_part, const int32_t *split_tpl,
+                                const int32_t *split_off, int n_split, int64_t n, int mode, float *snr, float2 *z,
+                                int64_t ld, int64_t obase, uint64_t *key_row, hipStream_t stream);
 // Slot arrays of a bank from caller-order complex128 a, b on the device.
 hipError_t launch_set_coeffs(const double *a, const double *b, const int32_t *slot_filter, int64_t nslots, int L,
                              float2 *a32, float2 *b32, double2 *aL, double2 *dL, double2 *a64, int32_t *flags,

@@ -76,14 +76,22 @@ void check_layout(const TestBank &tb, int fl, int wpg, int L) {
     std::string err;
     const int T = tb.T;
     const int rc = build_layout(T, tb.off.data(), tb.d.data(), fl, wpg, lay, err);
-    int max_nr = 0;
-    for (int j = 0; j < T; ++j) max_nr = std::max(max_nr, rows_of(tb.off[j + 1] - tb.off[j], fl));
-    if (max_nr > 4 * wpg) {
-        CHECK(rc == SPIIR_EINVAL && !err.empty(), "oversized template accepted (fl %d wpg %d)", fl, wpg);
-        return;
-    }
     CHECK(rc == SPIIR_OK, "build_layout failed: %s", err.c_str());
     const int R = 4 * wpg;
+    // split templates: exactly those with more rows than a workgroup, parts consecutive
+    std::vector<int> nparts(T, 0);
+    CHECK(lay.split_off.size() == lay.split_tpl.size() + 1 && lay.split_off[0] == 0 &&
+              lay.split_off.back() == lay.n_parts && (int)lay.part_tpl.size() == lay.n_parts,
+          "part tables");
+    for (size_t i = 0; i < lay.split_tpl.size(); ++i) {
+        const int j = lay.split_tpl[i];
+        CHECK(j >= 0 && j < T && (i == 0 || lay.split_tpl[i - 1] < j), "split template list");
+        CHECK(lay.split_off[i + 1] - lay.split_off[i] >= 2, "a split template with fewer than two parts");
+        for (int q = lay.split_off[i]; q < lay.split_off[i + 1]; ++q) CHECK(lay.part_tpl[q] == j, "part owner");
+        nparts[j] = lay.split_off[i + 1] - lay.split_off[i];
+    }
+    for (int j = 0; j < T; ++j)
+        CHECK((rows_of(tb.off[j + 1] - tb.off[j], fl) > R) == (nparts[j] > 0), "template %d split wrongly", j);
     CHECK(lay.groups >= 1 && lay.nslots == (int64_t)lay.groups * wpg * fl * 64, "slot count");
     CHECK(lay.rows.size() == (size_t)lay.groups * R && lay.slot_filter.size() == (size_t)lay.nslots &&
               lay.pad_src.size() == (size_t)lay.nslots && lay.tpl_group.size() == (size_t)T,
@@ -92,19 +100,40 @@ void check_layout(const TestBank &tb, int fl, int wpg, int L) {
     std::vector<int32_t> owner(F);
     for (int j = 0; j < T; ++j)
         for (int64_t k = tb.off[j]; k < tb.off[j + 1]; ++k) owner[k] = j;
-    // rows: each template is one contiguous run of rows_of(K, fl) rows in its group
+    // rows: each whole template (each part) is one contiguous run of rows in one group; the
+    // rows of a split template's parts add up to its row count
+    std::vector<int> part_rows(lay.n_parts, 0), part_group(lay.n_parts, -1);
     for (int g = 0; g < lay.groups; ++g) {
         for (int row = 0; row < R; ++row) {
             const RowInfo ri = lay.rows[(size_t)g * R + row];
             if (ri.tpl < 0) continue;
             CHECK(ri.tpl < T, "row template out of range");
-            CHECK(lay.tpl_group[ri.tpl] == g, "template %d in group %d but rows in %d", ri.tpl,
-                  lay.tpl_group[ri.tpl], g);
-            CHECK(ri.nr == rows_of(tb.off[ri.tpl + 1] - tb.off[ri.tpl], fl), "row count of template %d", ri.tpl);
             CHECK(ri.r0 <= row && row < ri.r0 + ri.nr && ri.r0 + ri.nr <= R, "row range of template %d", ri.tpl);
             for (int q = ri.r0; q < ri.r0 + ri.nr; ++q)
-                CHECK(lay.rows[(size_t)g * R + q].tpl == ri.tpl, "template %d rows not contiguous", ri.tpl);
+                CHECK(lay.rows[(size_t)g * R + q].tpl == ri.tpl && lay.rows[(size_t)g * R + q].part == ri.part,
+                      "template %d rows not contiguous", ri.tpl);
+            if (ri.part < 0) {
+                CHECK(nparts[ri.tpl] == 0, "whole rows of a split template");
+                CHECK(lay.tpl_group[ri.tpl] == g, "template %d in group %d but rows in %d", ri.tpl,
+                      lay.tpl_group[ri.tpl], g);
+                CHECK(ri.nr == rows_of(tb.off[ri.tpl + 1] - tb.off[ri.tpl], fl), "row count of template %d", ri.tpl);
+            } else {
+                CHECK(ri.part < lay.n_parts && lay.part_tpl[ri.part] == ri.tpl, "part of another template");
+                CHECK(part_group[ri.part] < 0 || part_group[ri.part] == g, "a part in two groups");
+                part_group[ri.part] = g;
+                if (row == ri.r0) part_rows[ri.part] += ri.nr;
+            }
         }
+    }
+    for (size_t i = 0; i < lay.split_tpl.size(); ++i) {
+        const int j = lay.split_tpl[i];
+        int rows = 0;
+        for (int q = lay.split_off[i]; q < lay.split_off[i + 1]; ++q) {
+            CHECK(part_group[q] >= 0 && part_rows[q] >= 1 && part_rows[q] <= R, "part %d unplaced", q);
+            rows += part_rows[q];
+        }
+        CHECK(rows <= rows_of(tb.off[j + 1] - tb.off[j], fl) + nparts[j], "rows of split template %d", j);
+        CHECK(lay.tpl_group[j] == part_group[lay.split_off[i]], "group of a split template's first part");
     }
     for (int j = 0; j < T; ++j) CHECK(lay.tpl_group[j] >= 0 && lay.tpl_group[j] < lay.groups, "template unplaced");
     // every filter in exactly one slot, of a row serving its template
@@ -240,10 +269,11 @@ int main(int argc, char **argv) {
     for (int sd = 0; sd < seeds && !g_fail; ++sd) {
         Rng rb(1000 + sd);
         TestBank tb;
-        switch (sd % 5) {
+        switch (sd % 6) {
             case 0: tb = random_bank(rb, rb.uni(1, 40), 1, 600, 2047); break;
             case 1: tb = random_bank(rb, rb.uni(1, 12), 100, 800, 16384); break;
-            case 2: tb = random_bank(rb, 3, 2048, 2048, 100); break;     // largest template at fl = 4
+            case 2: tb = random_bank(rb, 3, 2048, 2048, 100); break;     // one full workgroup at fl = 4
+            case 5: tb = random_bank(rb, rb.uni(2, 6), 1, 9000, 3000); break;  // templates split into parts
             case 3: tb = random_bank(rb, rb.uni(1, 64), 1, 40, 31); break;    // many tiny templates
             default: tb = random_bank(rb, rb.uni(2, 20), 16, 16 * rb.uni(1, 8), 4096); break;  // exact rows
         }

@@ -262,11 +262,17 @@ def test_chunk_len_not_multiple_of_16(L):
 
 
 def test_template_too_large_for_one_workgroup(mid):
-    from paper_1602_05573_amd import SpiirError
-    bank, _, _ = mid
+    """At one filter per lane a workgroup holds 512 filters: the larger
+    templates of the bank are split into parts (time split on and off)."""
+    bank, x, ref = mid
     assert bank.counts().max() > 512
-    with pytest.raises(SpiirError, match="more than 512 filters"):
-        mk(bank, filters_per_lane=1)
+    for ts in (1, 0):
+        banner("templates over 512 filters at fl=1, time_split=%d" % ts)
+        with mk(bank, filters_per_lane=1, time_split=ts) as bk:
+            assert bk.info["n_parts"] >= 2
+            snr = bk.filter_block(dev(x)).cpu().numpy()
+        err, _ = snr_err(snr, ref)
+        assert err <= SNR_TOL, "time_split %d: %.3g" % (ts, err)
 
 
 def test_all_fp32_mode_runs(mid):
@@ -473,3 +479,84 @@ def test_degenerate_coefficients_and_largest_template():
     tap[dmax:] = np.abs(b[K0]) ** 2 * x[:-dmax].astype(np.float64) ** 2
     assert np.allclose(ref[1], tap, rtol=1e-12, atol=1e-300)
 
+
+
+# ---------------------------------------------------------------------------
+# Templates longer than one workgroup: split into parts, summed by a combine
+# launch before the SNR / z / keys
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def big():
+    # templates of 5,000 and 2,500 filters (3 and 2 parts at 8 waves x 4 filters
+    # per lane) among small ones
+    b0 = random_bank(81, 0, 6, 20, 400, 0.99, 1 - 1e-5, 3000)
+    b1 = random_bank(81, 1, 1, 5000, 5000, 0.99, 1 - 1e-5, 3000)
+    b2 = random_bank(81, 2, 1, 2500, 2500, 0.99, 0.9999, 3000)
+    parts = [b0.subset([0, 1]), b1, b0.subset([2, 3, 4]), b2, b0.subset([5])]
+    off = [0]
+    for p in parts:
+        off += list(off[-1] + p.offsets[1:])
+    bank = Bank(np.array(off, np.int64), np.concatenate([p.a for p in parts]),
+                np.concatenate([p.b for p in parts]), np.concatenate([p.d for p in parts]).astype(np.int32), 3000)
+    x = strain(9000, 81)
+    return bank, x, oracle.snr(bank, x)
+
+
+@pytest.mark.parametrize("tsplit", [1, 4])
+def test_split_templates_snr_and_trigger(big, tsplit):
+    bank, x, ref = big
+    banner("split templates time_split=%d" % tsplit)
+    xd = dev(x)
+    with mk(bank, filters_per_lane=4, waves_per_group=8, chunk_len=128, max_block=4096,
+            time_split=tsplit) as bk:
+        info = bk.info
+        assert info["n_parts"] == 5, info
+        s1 = bk.filter_block(xd[:5000]).clone()
+        s2 = bk.filter_block(xd[5000:])
+        snr = torch.cat([s1, s2], dim=1).cpu().numpy()
+        bk.reset()
+        mx, am = bk.trigger_max(xd)
+        mx, am = mx.cpu().numpy(), am.cpu().numpy()
+    err, _ = snr_err(snr, ref)
+    print("split templates: SNR error %.3g" % err)
+    assert err <= SNR_TOL
+    check_argmax(mx, am, ref)
+
+
+def test_split_templates_forward_z_and_adjoint(big):
+    bank, x, _ = big
+    banner("split templates forward_z + backward")
+    n = 3000
+    xs = x[:n]
+    zr = oracle.z(bank, xs)
+    rng = np.random.default_rng(8101)
+    G = (rng.standard_normal(zr.shape) + 1j * rng.standard_normal(zr.shape)) / 50
+    ga_ref, gb_ref = oracle.backward(bank, xs, G)
+    with mk(bank, filters_per_lane=4, waves_per_group=8, chunk_len=128, max_block=2048) as bk:
+        assert bk.info["n_parts"] == 5
+        z, tape = bk.forward_z(dev(xs), want_tape=True)
+        ga, gb = bk.backward(tape, torch.from_numpy(G.astype(np.complex64)).cuda())
+        tape.close()
+        z, ga, gb = z.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy()
+    peak = np.abs(zr).max(axis=1)
+    zerr = float(np.max(np.abs(z - zr).max(axis=1) / peak))
+    print("split templates: z error %.3g" % zerr)
+    assert zerr <= SNR_TOL
+    for g, gref, what in ((ga, ga_ref, "grad_a"), (gb, gb_ref, "grad_b")):
+        for j in range(bank.n_templates):
+            sl = slice(int(bank.offsets[j]), int(bank.offsets[j + 1]))
+            e = np.linalg.norm(g[sl] - gref[sl]) / np.linalg.norm(gref[sl])
+            assert e <= 1e-3, "%s template %d: %.3g" % (what, j, e)
+
+
+def test_split_templates_refused_by_comparator_and_batch(big):
+    from paper_1602_05573_amd import SpiirBatch, SpiirError
+    bank, x, _ = big
+    banner("split templates refused")
+    xd = dev(x[:4096])
+    with mk(bank, filters_per_lane=4, waves_per_group=8) as bk:
+        with pytest.raises(SpiirError, match="one workgroup"):
+            bk.trigger_max_per_template(xd)
+        with pytest.raises(SpiirError, match="split"):
+            SpiirBatch([bk], [xd], block_len=4096)

@@ -1,7 +1,8 @@
 """The bank plan (argument checks, filter-to-slot layout, per-slot FP64
 coefficients, LDS geometry) is plain C++ with no HIP dependency: build it with
 g++ under AddressSanitizer and UBSan and drive it with random banks, including
-the largest template (2,048 filters at 4 filters per lane), templates that
+a template filling a whole workgroup (2,048 filters at 4 filters per lane),
+templates split over several workgroups (up to 9,000 filters), templates that
 fill their rows exactly, many one-filter templates and chunk lengths that are
 not multiples of 16."""
 import os

@@ -5,7 +5,8 @@ second shorter), must give identical max/argmax, which must also pass the
 argmax rule against the FP64 oracle. Covered: a bank whose strain window sits
 in LDS, a time-split bank (segment states and local sums in the scratch
 array), a bank whose window stays in global memory (window in the scratch
-array), two banks sharing the array call by call, and the size limit."""
+array), a bank with a template split over workgroups, two banks sharing the
+array call by call, and the size limit."""
 import numpy as np
 import pytest
 
@@ -93,6 +94,22 @@ def test_window_in_global_memory():
     x = strain(7000, 73)
     outs, info = run_pair(bank, x, [0, 4500, 7000])
     assert info["x_in_lds"] == 0
+    check_same(bank, x, outs)
+
+
+def test_templates_split_over_workgroups():
+    """A template of 5,000 filters (three parts) beside small ones: the key
+    row of the split templates is carved from the array too."""
+    banner("noalloc: split templates")
+    b0 = random_bank(76, 0, 5, 20, 300, 0.99, 0.99999, 1000)
+    b1 = random_bank(76, 1, 1, 5000, 5000, 0.99, 0.99999, 1000)
+    from workloads import Bank
+    off = np.concatenate([b0.offsets, b0.offsets[-1] + b1.offsets[1:]]).astype(np.int64)
+    bank = Bank(off, np.concatenate([b0.a, b1.a]), np.concatenate([b0.b, b1.b]),
+                np.concatenate([b0.d, b1.d]).astype(np.int32), 1000)
+    x = strain(6000, 76)
+    outs, info = run_pair(bank, x, [0, 4100, 6000], filters_per_lane=4, waves_per_group=8, max_block=4096)
+    assert info["n_parts"] == 3
     check_same(bank, x, outs)
 
 
