@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--fl", type=int, default=0, help="filters per lane (0 = library choice)")
     ap.add_argument("--wpg", type=int, default=0)
     ap.add_argument("--time-split", type=int, default=0, help="time segments (0 = library choice, 1 = off)")
+    ap.add_argument("--delay-band", type=int, default=0,
+                    help="adjoint: delay band width (0 = none: the strain window stays in global memory)")
     ap.add_argument("--fit-steps", type=int, default=5, help="adjoint: optimiser steps of the chirp fit")
     ap.add_argument("--fit-lr", type=float, default=1e-4, help="adjoint: Adam learning rate of the fit")
     ap.add_argument("--plain-blocks", type=int, default=16)
@@ -506,7 +508,7 @@ def run_adjoint(args, torch):
     bank, x, gs, _ = chirp_fit()
     F, T, N = bank.n_filters, bank.n_templates, len(x)
     bk = SpiirBank.from_bank(bank, filters_per_lane=args.fl, waves_per_group=args.wpg,
-                             time_split=args.time_split)
+                             time_split=args.time_split, delay_band=args.delay_band)
     info = bk.info
     log("bank:", info)
     xd = torch.from_numpy(x).cuda()
@@ -555,7 +557,8 @@ def run_adjoint(args, torch):
         "config": {"workload": "adjoint fit: %d templates x 400 filters, %d samples, unit impulse input" % (T, N),
                    "chunk_len": info["chunk_len"], "filters_per_lane": info["filters_per_lane"],
                    "waves_per_group": info["waves_per_group"], "workgroups": info["n_groups"],
-                   "time_split": info["time_split"]},
+                   "time_split": info["time_split"], "delay_band": info["delay_band"],
+                   "template_parts": info["n_parts"]},
         "forward_ms": fwd, "loss_ms": loss, "backward_ms": bwd,
         "forward_updates_per_s": updates / (fwd * 1e-3), "backward_updates_per_s": updates / (bwd * 1e-3),
         # backward call = (lambda, nu) scan + FP64 chain + per-segment backward + reduction

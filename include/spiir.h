@@ -94,6 +94,14 @@ typedef struct {
                                  reverse scan into segments (automatic count up to 16
                                  for 0, the given count for 2..32). 0 = automatic, 1 = off,
                                  2..32 = forced. Not used by the per-template comparator. */
+    int32_t delay_band;       /* 0 = no delay bands (default: the strain window is staged in
+                                 LDS when it fits, else read from global memory); w >= 1 =
+                                 delay bands of width w: every workgroup holds filters with
+                                 delays in one band [k*w, (k+1)*w) and stages only that
+                                 band's window (w - 1 + sub-block samples, the sub-block at
+                                 most w rounded up to chunk_len) in LDS; a template with
+                                 filters in several bands is split into parts. EINVAL if a
+                                 band's window does not fit LDS */
 } spiir_bank_opts;
 
 /* Layout facts of a created bank (for tests, tuning reports and benchmarks). */
@@ -114,6 +122,7 @@ typedef struct {
     int32_t n_cu;             /* compute units of the device */
     int32_t time_split;       /* segments per streaming launch (1 = no split) */
     int32_t n_parts;          /* parts of the templates split over workgroups (0: none) */
+    int32_t delay_band;       /* delay band width (0: no bands) */
 } spiir_bank_info;
 
 /* Fills *opts with the defaults listed above. */

@@ -47,7 +47,7 @@ class BankOpts(ctypes.Structure):
                 ("max_delay", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("max_block", ctypes.c_int32),
                 ("waves_per_group", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("time_split", ctypes.c_int32)]
+                ("time_split", ctypes.c_int32), ("delay_band", ctypes.c_int32)]
 
 
 class BankInfo(ctypes.Structure):
@@ -58,7 +58,7 @@ class BankInfo(ctypes.Structure):
                 ("lds_bytes", ctypes.c_int32), ("x_in_lds", ctypes.c_int32),
                 ("sub_block", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("n_cu", ctypes.c_int32), ("time_split", ctypes.c_int32),
-                ("n_parts", ctypes.c_int32)]
+                ("n_parts", ctypes.c_int32), ("delay_band", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

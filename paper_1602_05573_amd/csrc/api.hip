@@ -68,9 +68,9 @@ static_assert(sizeof(layout::F2) == sizeof(float2) && sizeof(layout::D2) == size
                   sizeof(RowInfo) == 16,
               "host slot arrays must match the device vector types");
 
-int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay) {
+int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, int band, Layout &lay) {
     std::string err;
-    const int rc = layout::build_layout(T, off, d, fl, wpg, lay, err);
+    const int rc = layout::build_layout(T, off, d, fl, wpg, band, lay, err);
     return rc ? fail(rc, "%s", err.c_str()) : SPIIR_OK;
 }
 
@@ -116,6 +116,8 @@ struct spiir_bank {
     float2 *zpart = nullptr;
     int32_t *split_tpl = nullptr, *split_off = nullptr;
     int n_split = 0;
+    int band = 0;                  // delay band width (0: none); group_lo [groups] on the device
+    int32_t *group_lo = nullptr;
     int nseg = 1;                 // time segments per streaming launch
     int64_t seg_len_max = 0;
     size_t lds_carry = 0;
@@ -160,6 +162,8 @@ struct spiir_bank {
         p.seg_stride = lay.nslots;
         p.zpart = zpart;
         p.ld_part = max_block;
+        p.band_w = band ? band - 1 : dmax;
+        p.group_lo = band ? group_lo : nullptr;
         p.zl = zl;
         return p;
     }
@@ -263,7 +267,7 @@ void free_bank_buffers(spiir_bank *bk) {
     dfree(bk->filter_slot); dfree(bk->bwaves);
     dfree(bk->aL); dfree(bk->dL); dfree(bk->a64); dfree(bk->state); dfree(bk->zstate);
     dfree(bk->rows); dfree(bk->hist[0]); dfree(bk->hist[1]); dfree(bk->keys); dfree(bk->xwin);
-    dfree(bk->zpart); dfree(bk->split_tpl); dfree(bk->split_off);
+    dfree(bk->zpart); dfree(bk->split_tpl); dfree(bk->split_off); dfree(bk->group_lo);
     dfree(bk->bpair); dfree(bk->bgpart); dfree(bk->seg_end); dfree(bk->seg_start); dfree(bk->zl);
     dfree(bk->pl_seg_end); dfree(bk->pl_seg_start); dfree(bk->pl_zl);
     bk->pl_cap = 0;
@@ -324,14 +328,27 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     const int L = o.chunk_len ? o.chunk_len : 256;
     int max_block = o.max_block ? o.max_block : 16384;
     max_block = std::max(L, (max_block / L) * L);
+    // Delay bands (an option): every workgroup takes filters of one band of delays and stages
+    // only that band's window in LDS. Not chosen automatically: on the chirp-fit bank (delays
+    // up to 65,535) the best banded layout only matched the strain window in global memory.
+    const bool global_window = !plan_geometry(1, dmax, L, max_block, df.lds_cap).xlds;
+    int band = 0;
+    if (o.delay_band > 0) {
+        band = o.delay_band;
+        if (!plan_geometry(1, band - 1, L, max_block, df.lds_cap).xlds)
+            return fail(SPIIR_EINVAL, "delay_band %d: its strain window does not fit LDS", band);
+    }
+    const int win_delay = band ? band - 1 : dmax;   // delays one workgroup's window covers
+    // a banded window is refilled every band samples (at most), so that several workgroups
+    // share a compute unit
+    const int nb_cap = band ? std::max(L, std::min(max_block, (band + L - 1) / L * L)) : max_block;
     int fl = o.filters_per_lane;
     if (fl == 0) {
-        // A delay window too long for LDS (even beside a single wave's tiles) leaves the strain
-        // in global memory; there four filters per lane give each wave more independent loads
-        // in flight, and the time split supplies the parallelism a small bank lacks.
-        const bool global_window = !plan_geometry(1, dmax, L, max_block, df.lds_cap).xlds;
+        // With the strain in global memory four filters per lane give each wave more
+        // independent loads in flight, and the time split supplies the parallelism a small
+        // bank lacks.
         fl = choose_fl(T, off, df.n_cu);
-        if (global_window && plan_rows(T, off, 4).max_nr <= 4 * kMaxWaves) fl = 4;
+        if (global_window && !band && plan_rows(T, off, 4).max_nr <= 4 * kMaxWaves) fl = 4;
     }
     const Plan plan = plan_rows(T, off, fl);
     int wpg = o.waves_per_group;
@@ -341,10 +358,10 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
         const int w0 = auto_wpg(plan.total_rows, std::min(plan.max_nr, 4 * kMaxWaves), df.n_cu);
         wpg = w0;
         for (int w = w0; w <= kMaxWaves; ++w) {
-            const Geometry gm = plan_geometry(w, dmax, L, max_block, df.lds_cap);
+            const Geometry gm = plan_geometry(w, win_delay, L, nb_cap, df.lds_cap);
             const int occ = std::max(1, forward_occupancy(fl, gm.tt, w, gm.lds));
             Layout trial;
-            if (build_layout(T, off, d, fl, w, trial)) continue;
+            if (build_layout(T, off, d, fl, w, band, trial)) continue;
             wpg = w;
             if (trial.groups <= (int64_t)df.n_cu * occ) break;
         }
@@ -364,12 +381,13 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     bk->a.assign(a, a + 2 * bk->F);
     bk->b.assign(b, b + 2 * bk->F);
     bk->d.assign(d, d + bk->F);
-    rc = build_layout(T, off, d, fl, wpg, bk->lay);
+    rc = build_layout(T, off, d, fl, wpg, band, bk->lay);
     if (rc) {
         delete bk;
         return rc;
     }
-    const Geometry gm = plan_geometry(wpg, dmax, L, max_block, df.lds_cap);
+    bk->band = band;
+    const Geometry gm = plan_geometry(wpg, win_delay, L, nb_cap, df.lds_cap);
     if (L % gm.tt) {   // chunk ends are detected at tile ends only
         delete bk;
         return fail(SPIIR_EINVAL, "internal: tile length %d does not divide chunk_len %d", gm.tt, L);
@@ -407,6 +425,7 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     A(dalloc(&bk->hist[0], (size_t)dmax)); A(dalloc(&bk->hist[1], (size_t)dmax));
     bk->n_split = (int)bk->lay.split_tpl.size();
     A(dalloc(&bk->keys, (size_t)(G + (bk->n_split ? 1 : 0)) * max_block));
+    if (bk->band) A(dalloc(&bk->group_lo, (size_t)G));
     if (bk->n_split) {
         A(dalloc(&bk->zpart, (size_t)bk->lay.n_parts * max_block));
         A(dalloc(&bk->split_tpl, bk->lay.split_tpl.size()));
@@ -446,6 +465,8 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
             e = hipMemcpy(bk->rows, bk->lay.rows.data(), bk->lay.rows.size() * sizeof(RowInfo),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(bk->state, 0, S * sizeof(float4));
+        if (e == hipSuccess && bk->band)
+            e = hipMemcpy(bk->group_lo, bk->lay.group_lo.data(), (size_t)G * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess && bk->n_split)
             e = hipMemcpy(bk->split_tpl, bk->lay.split_tpl.data(), bk->lay.split_tpl.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice);
@@ -627,6 +648,7 @@ void spiir_bank_opts_default(spiir_bank_opts *o) {
     o->waves_per_group = 0;
     o->autotune = 0;
     o->time_split = 0;
+    o->delay_band = 0;
 }
 
 int spiir_bank_create(spiir_bank **out, int32_t n_templates, const int64_t *filter_offsets,
@@ -722,6 +744,7 @@ int spiir_bank_get_info(const spiir_bank *bk, spiir_bank_info *info) {
     info->n_cu = bk->dev.n_cu;
     info->time_split = bk->nseg;
     info->n_parts = bk->lay.n_parts;
+    info->delay_band = bk->band;
     return SPIIR_OK;
 }
 

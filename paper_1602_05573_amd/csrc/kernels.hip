@@ -350,7 +350,12 @@ template <int FL, int TT, int MODE, bool XLDS, bool CARRY, bool PARTS = false>
 __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const SegCtx &sc) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = p.wpg, R = 4 * W, Rp = R + 1;  // odd row stride of wsum: no bank aliasing over t
-    const size_t win_bytes = XLDS ? (size_t)((p.dmax + p.nb + TT + 3) & ~3) * 4 : 0;
+    // LDS window: x[m - d] for the group's delays d in [glo, glo + gw]; slot offsets are
+    // max_delay - d, so a lane's window offset is that minus (max_delay - glo - gw)
+    const int glo = XLDS && p.group_lo ? p.group_lo[g] : 0;
+    const int gw = XLDS ? p.band_w : p.dmax;
+    const int xshift = p.dmax - glo - gw;
+    const size_t win_bytes = XLDS ? (size_t)((gw + p.nb + TT + 3) & ~3) * 4 : 0;
     float *xs = reinterpret_cast<float *>(smem);
     float2 *wt = reinterpret_cast<float2 *>(smem + win_bytes) + wave * TT * 64;
     float2 *wsum = reinterpret_cast<float2 *>(smem + win_bytes) + W * TT * 64;  // [2][TT][Rp]
@@ -374,7 +379,7 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
         if (ract) {
             const float2 a = p.s.a32[s.slot(f)], b = p.s.b32[s.slot(f)];
             s.ar[f] = a.x; s.ai[f] = a.y; s.br[f] = b.x; s.bi[f] = b.y;
-            s.xo[f] = p.s.xoff[s.slot(f)];
+            s.xo[f] = p.s.xoff[s.slot(f)] - xshift;
             s.flags |= (unsigned)(p.s.flags[s.slot(f)] & 1) << f;
             float4 st = make_float4(0.f, 0.f, 0.f, 0.f);
             if (sc.st_in) st = sc.st_in[s.slot(f) - sc.in_off];
@@ -406,8 +411,8 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
             xw = nullptr;
         } else if (XLDS) {
             __syncthreads();
-            const int cnt = p.dmax + nbs;
-            const int64_t m0 = xbase + s0 - p.dmax;   // xs[i] = x[m0 + i]; m < 0 from the history
+            const int cnt = gw + nbs;
+            const int64_t m0 = xbase + s0 - glo - gw;   // xs[i] = x[m0 + i]; m < 0 from the history
             const int nneg = (int)min((int64_t)cnt, max((int64_t)0, -m0));
             if (p.hist)
                 stage_range<false>(xs, p.hist, p.dmax + m0, 0, nneg);

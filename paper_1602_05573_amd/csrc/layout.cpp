@@ -25,7 +25,7 @@ int bad(std::string &err, const char *fmt, ...) {
     return SPIIR_EINVAL;
 }
 
-// Places the filters [k0, k1) of one template into its rows r0 .. r0+nr-1 of
+// Places the filters ks of one template (or part) into its rows r0 .. r0+nr-1 of
 // workgroup g. A ds_read_b32 of the strain window x[m - d] is served 32 lanes
 // per LDS cycle with bank = (dword address mod 32), i.e. by d mod 32; the 32
 // lanes are the two rows 2q, 2q+1 of a wave at one filter column f. Where both
@@ -38,7 +38,8 @@ int bad(std::string &err, const char *fmt, ...) {
 // columns that already hold a double, so that the unavoidable extra cycles
 // gather in few passes. Padding lanes read the address of their column's first
 // lane (a broadcast).
-void deal_template(int64_t k0, int64_t k1, const int32_t *d, int g, int wpg, int fl, int r0, int nr, Layout &lay) {
+void deal_template(const std::vector<int32_t> &ks, const int32_t *d, int g, int wpg, int fl, int r0, int nr,
+                   Layout &lay) {
     struct Col {
         int cap, lo, hi, rows[2], nparts, f, dbl;
         std::vector<int32_t> items;
@@ -69,7 +70,7 @@ void deal_template(int64_t k0, int64_t k1, const int32_t *d, int g, int wpg, int
         }
     }
     std::vector<std::vector<int32_t>> bycls(32);
-    for (int64_t k = k0; k < k1; ++k) bycls[d[k] & 31].push_back((int32_t)k);
+    for (int32_t k : ks) bycls[d[k] & 31].push_back(k);
     std::vector<int> corder(32);
     for (int c = 0; c < 32; ++c) corder[c] = c;
     std::stable_sort(corder.begin(), corder.end(),
@@ -222,18 +223,21 @@ int check_bank_args(int32_t T, const int64_t *off, const double *a, const double
     if (o.waves_per_group < 0 || o.waves_per_group > kMaxWaves)
         return bad(err, "waves_per_group must be 0..%d", kMaxWaves);
     if (o.time_split < 0 || o.time_split > 32) return bad(err, "time_split must be 0..32");
+    if (o.delay_band < 0) return bad(err, "delay_band must be 0 (no bands) or a band width >= 1");
     dmax_out = dmax;
     return SPIIR_OK;
 }
 
-int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay, std::string &err) {
+int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, int band, Layout &lay,
+                 std::string &err) {
     (void)err;
     const int R = 4 * wpg;
     const int64_t row_cap = (int64_t)kRowLanes * fl;   // filters per row
-    // packing items: a whole template, or one part of a split template
+    // packing items: a whole template, or one part of a split template; with
+    // delay bands every item holds filters of one band only
     struct Item {
-        int tpl, part, nr;
-        int64_t k0, k1;
+        int tpl, part, nr, band;
+        std::vector<int32_t> ks;
     };
     std::vector<Item> items;
     std::vector<int> first_part((size_t)T, -1);
@@ -241,39 +245,81 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
     lay.part_tpl.clear();
     lay.split_tpl.clear();
     lay.split_off.assign(1, 0);
+    lay.band = band;
     for (int j = 0; j < T; ++j) {
-        const int nr = rows_of(off[j + 1] - off[j], fl);
-        if (nr <= R) {
-            items.push_back(Item{j, -1, nr, off[j], off[j + 1]});
-            continue;
+        // the template's filters by band (one piece without bands), in filter order
+        std::vector<std::vector<int32_t>> pieces;
+        std::vector<int> piece_band;
+        if (band <= 0) {
+            pieces.emplace_back();
+            piece_band.push_back(0);
+            for (int64_t k = off[j]; k < off[j + 1]; ++k) pieces.back().push_back((int32_t)k);
+        } else {
+            std::vector<std::pair<int, int32_t>> bk;
+            for (int64_t k = off[j]; k < off[j + 1]; ++k) bk.emplace_back(d[k] / band, (int32_t)k);
+            std::stable_sort(bk.begin(), bk.end(),
+                             [](const std::pair<int, int32_t> &x, const std::pair<int, int32_t> &y) {
+                                 return x.first < y.first;
+                             });
+            for (size_t i = 0; i < bk.size(); ++i) {
+                if (i == 0 || bk[i].first != bk[i - 1].first) {
+                    pieces.emplace_back();
+                    piece_band.push_back(bk[i].first);
+                }
+                pieces.back().push_back(bk[i].second);
+            }
         }
-        const int np = (nr + R - 1) / R;
-        lay.split_tpl.push_back(j);
-        first_part[(size_t)j] = lay.n_parts;
-        int64_t k0 = off[j];
-        int done = 0;
-        for (int q = 0; q < np; ++q) {
-            const int rq = (nr - done + (np - q) - 1) / (np - q);   // balanced row counts
-            const int64_t k1 = std::min<int64_t>(off[j + 1], k0 + rq * row_cap);
-            items.push_back(Item{j, lay.n_parts, rows_of(k1 - k0, fl), k0, k1});
-            lay.part_tpl.push_back(j);
-            ++lay.n_parts;
-            done += rq;
-            k0 = k1;
+        // pieces longer than a workgroup are cut into balanced row counts
+        std::vector<Item> mine;
+        for (size_t q = 0; q < pieces.size(); ++q) {
+            const std::vector<int32_t> &pk = pieces[q];
+            const int nr = rows_of((int64_t)pk.size(), fl);
+            const int np = (nr + R - 1) / R;
+            size_t at = 0;
+            int done = 0;
+            for (int c = 0; c < np; ++c) {
+                const int rq = (nr - done + (np - c) - 1) / (np - c);
+                const size_t to = std::min(pk.size(), at + (size_t)(rq * row_cap));
+                Item it;
+                it.tpl = j;
+                it.part = -1;
+                it.band = piece_band[q];
+                it.ks.assign(pk.begin() + (long)at, pk.begin() + (long)to);
+                it.nr = rows_of((int64_t)it.ks.size(), fl);
+                mine.push_back(std::move(it));
+                done += rq;
+                at = to;
+            }
         }
-        lay.split_off.push_back(lay.n_parts);
+        if (mine.size() > 1) {
+            lay.split_tpl.push_back(j);
+            first_part[(size_t)j] = lay.n_parts;
+            for (Item &it : mine) {
+                it.part = lay.n_parts++;
+                lay.part_tpl.push_back(j);
+            }
+            lay.split_off.push_back(lay.n_parts);
+        }
+        for (Item &it : mine) items.push_back(std::move(it));
     }
+    // first-fit decreasing per band: a workgroup holds filters of one band
     std::vector<int> order(items.size());
     for (size_t i = 0; i < items.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return items[x].nr > items[y].nr; });
-    std::vector<int> room;                  // free rows per group
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return items[x].band != items[y].band ? items[x].band < items[y].band : items[x].nr > items[y].nr;
+    });
+    std::vector<int> room, gband;           // free rows and band per group
     std::vector<std::vector<int>> members;  // items per group
-    for (int i : order) {
-        size_t g = 0;
+    size_t band_first = 0;                  // first group of the current band
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const int i = order[oi];
+        if (oi > 0 && items[i].band != items[order[oi - 1]].band) band_first = room.size();
+        size_t g = band_first;
         for (; g < room.size(); ++g)
             if (room[g] >= items[i].nr) break;
         if (g == room.size()) {
             room.push_back(R);
+            gband.push_back(items[i].band);
             members.emplace_back();
         }
         room[g] -= items[i].nr;
@@ -287,7 +333,9 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
     lay.slot_filter.assign((size_t)lay.nslots, -1);
     lay.pad_src.assign((size_t)lay.nslots, -1);
     lay.tpl_group.assign(T, -1);
+    lay.group_lo.assign((size_t)lay.groups, 0);
     for (int g = 0; g < lay.groups; ++g) {
+        lay.group_lo[(size_t)g] = band > 0 ? gband[(size_t)g] * band : 0;
         std::vector<int> &mem = members[g];
         std::sort(mem.begin(), mem.end());   // items are in template order, parts in part order
         int r0 = 0;
@@ -296,7 +344,7 @@ int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, L
             if (it.part < 0 || it.part == first_part[(size_t)it.tpl]) lay.tpl_group[it.tpl] = g;
             for (int r = 0; r < it.nr; ++r)
                 lay.rows[(size_t)g * R + r0 + r] = RowInfo{it.tpl, r0, it.nr, it.part};
-            deal_template(it.k0, it.k1, d, g, wpg, fl, r0, it.nr, lay);
+            deal_template(it.ks, d, g, wpg, fl, r0, it.nr, lay);
             r0 += it.nr;
         }
     }

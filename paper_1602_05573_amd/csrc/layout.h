@@ -45,6 +45,12 @@ struct Layout {
     std::vector<int32_t> part_tpl;        // [n_parts] template of each part
     std::vector<int32_t> split_tpl;       // [n_split] split templates, increasing
     std::vector<int32_t> split_off;       // [n_split + 1] parts of split_tpl[i]: split_off[i] .. split_off[i+1]-1
+    // Delay bands (band > 0): every workgroup holds filters with delays in
+    // [group_lo[g], group_lo[g] + band) only, so that its strain window is band
+    // + block samples long; a template with filters in several bands is split
+    // into parts by band.
+    int band = 0;
+    std::vector<int32_t> group_lo;        // [groups] lowest delay of the group's band (0 without bands)
 };
 
 struct Plan {
@@ -97,9 +103,12 @@ int check_bank_args(int32_t T, const int64_t *off, const double *a, const double
                     const spiir_bank_opts &o, int &dmax_out, std::string &err);
 // First-fit decreasing packing of templates into workgroups of 4 wpg rows (a
 // template with more rows than that is first split into parts of balanced row
-// counts, each packed as one item), then the delay-aware dealing of every
-// template's (or part's) filters over its slot columns. Returns SPIIR_OK.
-int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, Layout &lay, std::string &err);
+// counts, each packed as one item; with band > 0 a template is first cut by
+// delay band d / band and workgroups hold one band each), then the
+// delay-aware dealing of every template's (or part's) filters over its slot
+// columns. Returns SPIIR_OK.
+int build_layout(int T, const int64_t *off, const int32_t *d, int fl, int wpg, int band, Layout &lay,
+                 std::string &err);
 // FP64 powers and FP32 roundings of every slot's coefficients (a, b complex128
 // interleaved [F], caller order).
 void slot_arrays(const Layout &lay, const double *a, const double *b, const int32_t *d, int dmax, int L,

@@ -44,7 +44,8 @@ struct FwdArgs {
     int64_t n;            // samples in this launch
     int32_t dmax, L, nb, prec, wpg, only_tpl;
     int32_t gbase;        // group of blockIdx.x == 0
-    int32_t pad0;
+    int32_t band_w;       // LDS window: delays of a group lie in [lo, lo + band_w]; max_delay without bands
+    const int32_t *group_lo;  // [groups] lowest delay of each group's band (null: no bands, lo = 0)
     const RowInfo *rows;  // [groups * wpg * 4]
     int64_t obase;        // output column of launch sample 0
     int64_t ld;           // row length of snr / z / keys

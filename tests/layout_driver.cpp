@@ -71,11 +71,11 @@ TestBank random_bank(Rng &r, int T, int klo, int khi, int dmax) {
     return tb;
 }
 
-void check_layout(const TestBank &tb, int fl, int wpg, int L) {
+void check_layout(const TestBank &tb, int fl, int wpg, int L, int band) {
     Layout lay;
     std::string err;
     const int T = tb.T;
-    const int rc = build_layout(T, tb.off.data(), tb.d.data(), fl, wpg, lay, err);
+    const int rc = build_layout(T, tb.off.data(), tb.d.data(), fl, wpg, band, lay, err);
     CHECK(rc == SPIIR_OK, "build_layout failed: %s", err.c_str());
     const int R = 4 * wpg;
     // split templates: exactly those with more rows than a workgroup, parts consecutive
@@ -90,8 +90,14 @@ void check_layout(const TestBank &tb, int fl, int wpg, int L) {
         for (int q = lay.split_off[i]; q < lay.split_off[i + 1]; ++q) CHECK(lay.part_tpl[q] == j, "part owner");
         nparts[j] = lay.split_off[i + 1] - lay.split_off[i];
     }
-    for (int j = 0; j < T; ++j)
-        CHECK((rows_of(tb.off[j + 1] - tb.off[j], fl) > R) == (nparts[j] > 0), "template %d split wrongly", j);
+    for (int j = 0; j < T; ++j) {
+        bool one_band = true;
+        for (int64_t k = tb.off[j]; band > 0 && k < tb.off[j + 1]; ++k)
+            one_band = one_band && tb.d[k] / band == tb.d[tb.off[j]] / band;
+        CHECK((rows_of(tb.off[j + 1] - tb.off[j], fl) > R || !one_band) == (nparts[j] > 0),
+              "template %d split wrongly", j);
+    }
+    CHECK(lay.band == band && lay.group_lo.size() == (size_t)lay.groups, "band tables");
     CHECK(lay.groups >= 1 && lay.nslots == (int64_t)lay.groups * wpg * fl * 64, "slot count");
     CHECK(lay.rows.size() == (size_t)lay.groups * R && lay.slot_filter.size() == (size_t)lay.nslots &&
               lay.pad_src.size() == (size_t)lay.nslots && lay.tpl_group.size() == (size_t)T,
@@ -149,6 +155,9 @@ void check_layout(const TestBank &tb, int fl, int wpg, int L) {
         if (k >= 0) {
             CHECK(k < F, "slot filter out of range");
             ++seen[k];
+            CHECK(band == 0 ? lay.group_lo[(size_t)g] == 0
+                            : tb.d[k] >= lay.group_lo[(size_t)g] && tb.d[k] < lay.group_lo[(size_t)g] + band,
+                  "filter %d (delay %d) outside its group's band [%d, +%d)", k, tb.d[k], lay.group_lo[(size_t)g], band);
             CHECK(ri.tpl == owner[k], "filter %d of template %d sits in a row of template %d", k, owner[k], ri.tpl);
             CHECK(lay.pad_src[(size_t)s] == -1, "real slot with a padding source");
         } else {
@@ -222,6 +231,7 @@ void check_args() {
     o.waves_per_group = 0;
     o.autotune = 0;
     o.time_split = 0;
+    o.delay_band = 0;
     std::string err;
     int dm = -1;
     CHECK(check_bank_args(2, off, a, b, d, o, dm, err) == SPIIR_OK && dm == 7, "valid bank rejected: %s", err.c_str());
@@ -242,6 +252,7 @@ void check_args() {
         {"max_delay", [](int64_t *, double *, double *, int32_t *, spiir_bank_opts &oo) { oo.max_delay = 6; }},
         {"wpg 9", [](int64_t *, double *, double *, int32_t *, spiir_bank_opts &oo) { oo.waves_per_group = 9; }},
         {"split 33", [](int64_t *, double *, double *, int32_t *, spiir_bank_opts &oo) { oo.time_split = 33; }},
+        {"band -1", [](int64_t *, double *, double *, int32_t *, spiir_bank_opts &oo) { oo.delay_band = -1; }},
     };
     for (const Case &c : cases) {
         int64_t o2[3] = {off[0], off[1], off[2]};
@@ -281,8 +292,10 @@ int main(int argc, char **argv) {
         for (int fl = 1; fl <= 4 && !g_fail; ++fl)
             for (int wpg = 1; wpg <= kMaxWaves && !g_fail; wpg += (sd % 2 ? 3 : 1)) {
                 const int L = 8 * rb.uni(1, 64);
-                check_layout(tb, fl, wpg, L);
-                ++layouts;
+                check_layout(tb, fl, wpg, L, 0);
+                const int band = tb.dmax > 0 ? rb.uni(1, tb.dmax + 1) : 1;   // delay bands of random width
+                check_layout(tb, fl, wpg, L, band);
+                layouts += 2;
             }
     }
     if (g_fail) return 1;

@@ -313,13 +313,19 @@ def test_small_lds_sub_blocks(mid):
     check_argmax(mx, am, ref)
 
 
-def test_strain_window_in_global_memory():
-    banner("global window")
-    bank = random_bank(52, 0, 5, 20, 200, 0.99, 0.9999, 60000)   # 240 KB of history: not in LDS
+@pytest.mark.parametrize("band", [0, 4096, 16384])
+def test_strain_window_in_global_memory(band):
+    """240 KB of history does not fit LDS: without delay bands the window stays
+    in global memory; with bands each workgroup stages its band's window in
+    LDS (templates spanning bands are split into parts)."""
+    banner("long delay window, delay_band=%d" % band)
+    bank = random_bank(52, 0, 5, 20, 200, 0.99, 0.9999, 60000)
     x = strain(7000, 52)
     ref = oracle.snr(bank, x)
-    with mk(bank) as bk:
-        assert bk.info["x_in_lds"] == 0
+    with mk(bank, delay_band=band) as bk:
+        info = bk.info
+        assert info["x_in_lds"] == (0 if band == 0 else 1)
+        assert info["delay_band"] == band
         snr = bk.filter_block(dev(x[:3000])).clone()
         snr2 = bk.filter_block(dev(x[3000:]))
         s = torch.cat([snr, snr2], dim=1).cpu().numpy()
@@ -560,3 +566,41 @@ def test_split_templates_refused_by_comparator_and_batch(big):
             bk.trigger_max_per_template(xd)
         with pytest.raises(SpiirError, match="split"):
             SpiirBatch([bk], [xd], block_len=4096)
+
+
+@pytest.mark.parametrize("band,tsplit,L", [(512, 1, 256), (700, 4, 128), (64, 0, 64)])
+def test_forced_delay_bands(mid, band, tsplit, L):
+    """Delay bands forced on a bank whose window fits LDS anyway: every
+    template is split by band; SNR over two calls, the fused trigger, and
+    z / gradients of the adjoint against the oracle."""
+    bank, x, ref = mid
+    banner("forced delay bands %d, time_split %d, L %d" % (band, tsplit, L))
+    xd = dev(x)
+    with mk(bank, delay_band=band, time_split=tsplit, chunk_len=L, max_block=4096) as bk:
+        info = bk.info
+        assert info["delay_band"] == band and info["x_in_lds"] == 1 and info["n_parts"] > 0
+        s1 = bk.filter_block(xd[:2500]).clone()
+        s2 = bk.filter_block(xd[2500:])
+        snr = torch.cat([s1, s2], dim=1).cpu().numpy()
+        bk.reset()
+        mx, am = bk.trigger_max(xd)
+        mx, am = mx.cpu().numpy(), am.cpu().numpy()
+        n = 2000
+        zr = oracle.z(bank, x[:n])
+        rng = np.random.default_rng(9101)
+        G = (rng.standard_normal(zr.shape) + 1j * rng.standard_normal(zr.shape)) / 40
+        ga_ref, gb_ref = oracle.backward(bank, x[:n], G)
+        z, tape = bk.forward_z(dev(x[:n]), want_tape=True)
+        ga, gb = bk.backward(tape, torch.from_numpy(G.astype(np.complex64)).cuda())
+        tape.close()
+        z, ga, gb = z.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy()
+    err, _ = snr_err(snr, ref)
+    print("delay bands %d: SNR error %.3g, %d parts" % (band, err, info["n_parts"]))
+    assert err <= SNR_TOL
+    check_argmax(mx, am, ref)
+    peak = np.abs(zr).max(axis=1)
+    assert float(np.max(np.abs(z - zr).max(axis=1) / peak)) <= SNR_TOL
+    for g, gref in ((ga, ga_ref), (gb, gb_ref)):
+        for j in range(bank.n_templates):
+            sl = slice(int(bank.offsets[j]), int(bank.offsets[j + 1]))
+            assert np.linalg.norm(g[sl] - gref[sl]) <= 1e-3 * np.linalg.norm(gref[sl])
