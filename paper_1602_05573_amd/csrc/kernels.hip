@@ -414,10 +414,16 @@ __device__ void fwd_group(const FwdArgs &p, int g, unsigned char *smem, const Se
             const int cnt = gw + nbs;
             const int64_t m0 = xbase + s0 - glo - gw;   // xs[i] = x[m0 + i]; m < 0 from the history
             const int nneg = (int)min((int64_t)cnt, max((int64_t)0, -m0));
-            if (p.hist)
-                stage_range<false>(xs, p.hist, p.dmax + m0, 0, nneg);
-            else
+            // a band's window may reach past the largest delay (glo + gw > max_delay):
+            // samples before the history (m < -max_delay) are read by no filter and
+            // staged as zeros, so the history is only read at indices >= 0
+            const int nz = (int)min((int64_t)nneg, max((int64_t)0, -(int64_t)p.dmax - m0));
+            if (p.hist) {
+                stage_range<true>(xs, nullptr, 0, 0, nz);
+                stage_range<false>(xs, p.hist, p.dmax + m0, nz, nneg);
+            } else {
                 stage_range<true>(xs, nullptr, 0, 0, nneg);
+            }
             stage_range<false>(xs, p.x, m0, nneg, cnt);
             __syncthreads();
             xw = xs;
