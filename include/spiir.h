@@ -449,10 +449,13 @@ int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches
  *                    per call) uses 64-sample chunks and up to 32 time
  *                    segments instead of chunk_len and 8.
  * Calls take n a multiple of 2^R and continue one stream. Device memory held:
- * the level banks, the decimated streams, the level sums, the interpolated
- * sums of levels 1..top-1 (T x max_block / 2^r complex64 each) and
- * ceil(T / 16) x max_block uint64 keys; the full-rate z is only ever written
- * to the caller's buffer (spiir_multirate_filter_block_z).
+ * the level banks, the decimated streams, the level sums and ceil(T / 16) x
+ * max_block uint64 keys. The interpolation runs in one launch per piece, each
+ * workgroup forming the interpolated sums its full-rate samples need in LDS,
+ * so neither those sums nor the full-rate z are stored (z is only written to
+ * the caller's buffer by spiir_multirate_filter_block_z). The decimation of
+ * every level also runs in one launch when max_block / 2 + max_block / 4
+ * samples fit in 64 KB of LDS, else one launch per level.
  */
 int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_templates,
                            const int64_t *const *filter_offsets, const double *const *a,

@@ -562,11 +562,12 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             nseg = (int)((np + a.seg_len - 1) / a.seg_len);
         }
         // the next call's history is written by a launch that follows every
-        // strain read of this call: the last key finalisation, else the last
-        // piece's carry chain, else a launch of its own after the loop
+        // strain read of this call or by the last reading launch itself (it
+        // goes to the other history buffer): the last key finalisation, else
+        // the last piece's carry chain or its one forward launch
         const bool last = P + np >= n;
         const HistCopy hc{hist, bk->hist[bk->hist_cur ^ 1], x, n, bk->dmax};
-        if (last && nseg >= 2 && mode != kModeKeys) {
+        if (last && mode != kModeKeys) {
             a.hist_next = hc;
             hist_done = true;
         }
@@ -604,6 +605,64 @@ int bank_stream_z(spiir_bank *bk, const float *x, int64_t n, float *z, int64_t l
 int bank_create_capped(spiir_bank **out, int32_t T, const int64_t *off, const double *a, const double *b,
                        const int32_t *d, const spiir_bank_opts &o, int seg_cap) {
     return create_bank(out, T, off, a, b, d, o, seg_cap);
+}
+
+int bank_wpg(const spiir_bank *bk) { return bk->lay.wpg; }
+
+bool banks_multi_ok(spiir_bank *const *bks, int nb, const int64_t *n) {
+    if (nb < 1 || nb > kMultiMax) return false;
+    const spiir_bank *b0 = bks[0];
+    for (int b = 0; b < nb; ++b) {
+        const spiir_bank *bk = bks[b];
+        if (!bk || !bk->xlds || bk->n_split || bk->nseg < 2 || !bk->tev0.empty()) return false;
+        if (bk->device != b0->device || bk->lay.fl != b0->lay.fl || bk->tt != b0->tt || bk->lay.wpg != b0->lay.wpg)
+            return false;
+        if (n[b] <= 0 || n[b] > bk->max_block) return false;
+        const int64_t seg_len = ((n[b] + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
+        if (n[b] <= seg_len) return false;   // one segment: the call would not be time-split
+    }
+    return true;
+}
+
+int banks_stream_z_multi(spiir_bank *const *bks, int nb, const float *const *x, const int64_t *n, float *const *z,
+                         const int64_t *ld, hipStream_t st) {
+    if (!banks_multi_ok(bks, nb, n)) return fail(SPIIR_EINVAL, "internal: the banks cannot share time-split launches");
+    DeviceGuard guard(bks[0]->device);
+    MultiFwd m;
+    std::memset(&m, 0, sizeof m);
+    m.count = nb;
+    size_t lds = 0, lds_carry = 0;
+    for (int b = 0; b < nb; ++b) {
+        spiir_bank *bk = bks[b];
+        const float *hist = bk->hist[bk->hist_cur];
+        // the arguments of this bank's streaming z call as one time-split piece
+        FwdArgs a = bk->base_args();
+        a.state = bk->state;
+        a.x = x[b];
+        a.hist = hist;
+        a.xwin = bk->xwin;
+        a.xbase = 0;
+        a.n = n[b];
+        a.obase = 0;
+        a.z = reinterpret_cast<float2 *>(z[b]);
+        a.ld = ld[b];
+        a.seg_len = ((n[b] + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
+        a.hist_next = HistCopy{hist, bk->hist[bk->hist_cur ^ 1], x[b], n[b], bk->dmax};
+        const int nseg = (int)((n[b] + a.seg_len - 1) / a.seg_len);
+        const int cb = (int)((a.seg_stride + 255) / 256);
+        const int hb = bk->dmax > 0 ? (bk->dmax + 255) / 256 : 0;
+        m.a[b] = a;
+        m.nseg[b] = nseg;
+        m.chain_blocks[b] = cb;
+        m.seg_first[b + 1] = m.seg_first[b] + bk->lay.groups * nseg;
+        m.chain_first[b + 1] = m.chain_first[b] + cb + hb;
+        m.carry_first[b + 1] = m.carry_first[b] + bk->lay.groups * (nseg - 1);
+        lds = std::max(lds, bk->lds);
+        lds_carry = std::max(lds_carry, bk->lds_carry);
+    }
+    HIPCHK(launch_forward_split_multi(m, bks[0]->lay.fl, bks[0]->tt, bks[0]->lay.wpg, lds, lds_carry, st));
+    for (int b = 0; b < nb; ++b) bks[b]->hist_cur ^= 1;
+    return SPIIR_OK;
 }
 
 int bank_hist_cur(const spiir_bank *bk) { return bk->hist_cur; }

@@ -61,6 +61,18 @@ int bank_create_capped(spiir_bank **out, int32_t T, const int64_t *off, const do
 int bank_hist_cur(const spiir_bank *bk);
 void bank_set_hist_cur(spiir_bank *bk, int v);
 bool bank_timing_on(const spiir_bank *bk);
+int bank_wpg(const spiir_bank *bk);
+// Whether banks bks[0..nb) can take streaming z calls of n[b] samples through
+// banks_stream_z_multi: each call one time-split piece (at most max_block
+// samples, two segments or more) with the strain window in LDS, no split
+// templates, no kernel timing, one device, and the same filters per lane,
+// tile length and workgroup size.
+bool banks_multi_ok(spiir_bank *const *bks, int nb, const int64_t *n);
+// Streaming z calls of several banks, bank b on x[b][0..n[b]) into z[b] (row
+// stride ld[b]), as one launch per time-split pass for all of them; the same
+// results and state as one bank_stream_z call per bank.
+int banks_stream_z_multi(spiir_bank *const *bks, int nb, const float *const *x, const int64_t *n, float *const *z,
+                         const int64_t *ld, hipStream_t st);
 
 }  // namespace host
 }  // namespace spiir

@@ -539,9 +539,21 @@ __device__ __forceinline__ SegCtx whole_launch(const FwdArgs &p) {
     return sc;
 }
 
+__device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
+    const int64_t m = hc.n - hc.dmax + i;
+    hc.new_h[i] = m >= 0 ? hc.x[m] : hc.old_h[hc.dmax + m];
+}
+
 template <int FL, int TT, int MODE, bool XLDS, bool PARTS>
 __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if constexpr (MODE != kModeKeys) {
+        // a streaming call's last launch also writes the next call's history
+        // (hist_next.dmax > 0); it reads old_h and x only, which this launch
+        // does not write
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.hist_next.dmax; i += gridDim.x * blockDim.x)
+            hist_copy_at(p.hist_next, i);
+    }
     const SegCtx sc = whole_launch(p);
     fwd_group<FL, TT, MODE, XLDS, false, PARTS>(p, p.gbase + blockIdx.x, smem, sc);
 }
@@ -550,9 +562,8 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs p) {
 // carried state and writes the mode's output; later segments start cold and
 // keep their local z. Every item stores its end state.
 template <int FL, int TT, int MODE, bool XLDS, bool PARTS>
-__global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int g = p.gbase + blockIdx.x % p.groups, seg = blockIdx.x / p.groups;
+__device__ __forceinline__ void seg_item(const FwdArgs &p, unsigned bid, unsigned char *smem) {
+    const int g = p.gbase + bid % p.groups, seg = bid / p.groups;
     SegCtx sc;
     sc.tb = (int64_t)seg * p.seg_len;
     sc.tn = min(p.seg_len, p.n - sc.tb);
@@ -571,12 +582,17 @@ __global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
     fwd_group<FL, TT, MODE, XLDS, false, PARTS>(p, g, smem, sc);
 }
 
+template <int FL, int TT, int MODE, bool XLDS, bool PARTS>
+__global__ void __launch_bounds__(512) fwd_seg_kernel(FwdArgs p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    seg_item<FL, TT, MODE, XLDS, PARTS>(p, blockIdx.x, smem);
+}
+
 // Time split, carry pass over segments 1..: free response of the true
 // segment-start state plus the local z, then the mode's output.
 template <int FL, int TT, int MODE, bool PARTS>
-__global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int g = p.gbase + blockIdx.x % p.groups, seg = 1 + blockIdx.x / p.groups;
+__device__ __forceinline__ void carry_item(const FwdArgs &p, unsigned bid, unsigned char *smem) {
+    const int g = p.gbase + bid % p.groups, seg = 1 + bid / p.groups;
     SegCtx sc;
     sc.tb = (int64_t)seg * p.seg_len;
     sc.tn = min(p.seg_len, p.n - sc.tb);
@@ -595,9 +611,10 @@ __global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
     fwd_group<FL, TT, MODE, false, true, PARTS>(p, g, smem, sc);
 }
 
-__device__ __forceinline__ void hist_copy_at(const HistCopy &hc, int i) {
-    const int64_t m = hc.n - hc.dmax + i;
-    hc.new_h[i] = m >= 0 ? hc.x[m] : hc.old_h[hc.dmax + m];
+template <int FL, int TT, int MODE, bool PARTS>
+__global__ void __launch_bounds__(512) fwd_carry_kernel(FwdArgs p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    carry_item<FL, TT, MODE, PARTS>(p, blockIdx.x, smem);
 }
 
 // Carries of one slot across the segments of a launch: c holds the true end
@@ -638,13 +655,13 @@ __device__ __forceinline__ void chain_segments(const float4 *seg_end, float4 *se
 // launch's final state. Covers slots [seg_slot0, seg_slot0 + seg_stride) of
 // the segment buffers; with only_tpl >= 0 only that template's slots (the
 // other slots' entries were not written by the segment pass).
-__global__ void seg_chain_kernel(FwdArgs p, int fl, int nseg, unsigned chain_blocks) {
-    if (blockIdx.x >= chain_blocks) {   // the history copy (hist_next.dmax > 0), 256 samples per block
-        const int i = (int)(blockIdx.x - chain_blocks) * 256 + (int)threadIdx.x;
+__device__ __forceinline__ void chain_item(const FwdArgs &p, int fl, int nseg, unsigned chain_blocks, unsigned bid) {
+    if (bid >= chain_blocks) {   // the history copy (hist_next.dmax > 0), 256 samples per block
+        const int i = (int)(bid - chain_blocks) * 256 + (int)threadIdx.x;
         if (i < p.hist_next.dmax) hist_copy_at(p.hist_next, i);
         return;
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
     if (i >= p.seg_stride) return;  // every slot, padding included (its states stay zero)
     const int64_t sl = p.seg_slot0 + i;
     if (p.only_tpl >= 0) {
@@ -662,6 +679,38 @@ __global__ void seg_chain_kernel(FwdArgs p, int fl, int nseg, unsigned chain_blo
     chain_segments(p.seg_end, p.seg_start, p.seg_stride, i, a, nseg, p.seg_len, p.n, cr, ci);
     const float hr = (float)cr, hi = (float)ci;
     p.state[sl] = make_float4(hr, hi, (float)(cr - (double)hr), (float)(ci - (double)hi));
+}
+
+__global__ void seg_chain_kernel(FwdArgs p, int fl, int nseg, unsigned chain_blocks) {
+    chain_item(p, fl, nseg, chain_blocks, blockIdx.x);
+}
+
+// Several banks' time-split passes, one launch per pass for all of them: the
+// workgroups [first[b], first[b + 1]) of a pass run bank b's items (its own
+// strain, segments, state and output rows) exactly as the one-bank kernels do.
+__device__ __forceinline__ int multi_bank(const int32_t *first, int count) {
+    int b = 0;
+    while (b + 1 < count && (int)blockIdx.x >= first[b + 1]) ++b;
+    return b;
+}
+
+template <int FL, int TT, int MODE>
+__global__ void __launch_bounds__(512) fwd_seg_multi_kernel(MultiFwd m) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = multi_bank(m.seg_first, m.count);
+    seg_item<FL, TT, MODE, true, false>(m.a[b], blockIdx.x - (unsigned)m.seg_first[b], smem);
+}
+
+template <int FL, int TT, int MODE>
+__global__ void __launch_bounds__(512) fwd_carry_multi_kernel(MultiFwd m) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = multi_bank(m.carry_first, m.count);
+    carry_item<FL, TT, MODE, false>(m.a[b], blockIdx.x - (unsigned)m.carry_first[b], smem);
+}
+
+__global__ void __launch_bounds__(256) seg_chain_multi_kernel(MultiFwd m, int fl) {
+    const int b = multi_bank(m.chain_first, m.count);
+    chain_item(m.a[b], fl, m.nseg[b], (unsigned)m.chain_blocks[b], blockIdx.x - (unsigned)m.chain_first[b]);
 }
 
 // Persistent batch kernel: workgroups pop (stream, group) items until the list
@@ -1480,6 +1529,44 @@ hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool
     if (tt == 8)
         return x_in_lds ? launch_split_x<8, true>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev)
                         : launch_split_x<8, false>(a, mode, fl, nseg, lds, lds_carry, slot_filter, st, ev);
+    return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <int FL, int TT>
+hipError_t launch_multi_t(const MultiFwd &m, int wpg, size_t lds, size_t lds_carry, hipStream_t st) {
+    const int n = m.count;
+    hipLaunchKernelGGL((fwd_seg_multi_kernel<FL, TT, kModeZ>), dim3((unsigned)m.seg_first[n]), dim3(wpg * 64), lds,
+                       st, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(seg_chain_multi_kernel, dim3((unsigned)m.chain_first[n]), dim3(256), 0, st, m, FL);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_carry_multi_kernel<FL, TT, kModeZ>), dim3((unsigned)m.carry_first[n]), dim3(wpg * 64),
+                       lds_carry, st, m);
+    return hipGetLastError();
+}
+
+template <int TT>
+hipError_t launch_multi_f(const MultiFwd &m, int fl, int wpg, size_t lds, size_t lds_carry, hipStream_t st) {
+    switch (fl) {
+        case 1: return launch_multi_t<1, TT>(m, wpg, lds, lds_carry, st);
+        case 2: return launch_multi_t<2, TT>(m, wpg, lds, lds_carry, st);
+        case 3: return launch_multi_t<3, TT>(m, wpg, lds, lds_carry, st);
+        case 4: return launch_multi_t<4, TT>(m, wpg, lds, lds_carry, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_forward_split_multi(const MultiFwd &m, int fl, int tt, int wpg, size_t lds, size_t lds_carry,
+                                      hipStream_t st) {
+    if (m.count < 1 || m.count > kMultiMax) return hipErrorInvalidValue;
+    if (tt == 16) return launch_multi_f<16>(m, fl, wpg, lds, lds_carry, st);
+    if (tt == 8) return launch_multi_f<8>(m, fl, wpg, lds, lds_carry, st);
     return hipErrorInvalidValue;
 }
 

@@ -10,6 +10,9 @@
 // resampling input as history, so consecutive calls continue one stream.
 #include "spiir_internal.h"
 
+#include <algorithm>
+#include <atomic>
+
 namespace spiir {
 namespace {
 
@@ -43,29 +46,13 @@ __global__ __launch_bounds__(kThreads) void mr_decimate_kernel(const float *__re
     }
 }
 
-// One template row j per blockIdx.x / tiles, kOut = 1,024 output samples per
-// block of 256 threads (two adjacent pairs per thread):
-//   out[j][p] = Z(j, p) + sum_{i < lg, p - i even} g[i] W(j, (p - i) / 2)
-// Z(j, p) = z[zrow[j]][p] (0 if z is NULL or zrow[j] < 0); W(j, q) =
-// w[wrow(j)][q] for q >= 0 (wrow = identity if NULL; 0 if wrow[j] < 0) and
-// whist[j][hh + q] for -hh <= q < 0, hh = lg / 2. w == NULL: no interpolation
-// term. The block first stages the W samples its outputs need (at most
-// kOut / 2 + hh + 1) and the taps in LDS, so the tap loop reads LDS only. The
-// first block of a row writes the row's next history (the last hh samples of
-// W) to whist_new.
 constexpr int kMaxTaps = 64;
-constexpr int kOut = 4 * kThreads;
 
-__device__ inline float2 w_at(const float2 *wj, const float2 *hj, int hh, int64_t q) {
-    if (q >= 0) return wj ? wj[q] : make_float2(0.0f, 0.0f);
-    return hj[hh + q];
-}
-
-// Outputs t = 2m and 2m + 1 of a tile (t = p - p0) read the same W samples:
-// out(2m) += sum_k g[2k] W(m' - k), out(2m + 1) += sum_k g[2k + 1] W(m' - k),
-// m' = p0 / 2 + m, with s[sb + m - k] the staged W(m' - k). Each of the NU
-// pairs of a lane accumulates its taps in ascending order, as the plain
-// per-output sum does, so both forms give the same values.
+// Output pairs (2m, 2m + 1) read the same W samples:
+// out(2m) += sum_k g[2k] W(m - k), out(2m + 1) += sum_k g[2k + 1] W(m - k),
+// with s[sb + m[u] - k] the staged W(m - k). Each of the NU pairs of a lane
+// accumulates its taps in ascending order, as the plain per-output sum does,
+// so both forms give the same values.
 template <int NU>
 __device__ __forceinline__ void interp_pairs(const float2 *s, int sb, const float *sg, int lg, const int (&m)[NU],
                                              float2 (&ev)[NU], float2 (&od)[NU]) {
@@ -86,140 +73,243 @@ __device__ __forceinline__ void interp_pairs(const float2 *s, int sb, const floa
     }
 }
 
-__global__ __launch_bounds__(kThreads) void mr_upsample_add_kernel(
-    const float2 *__restrict__ z, int64_t ld_z, const int32_t *__restrict__ zrow, const float2 *__restrict__ w,
-    int64_t ld_w, const int32_t *__restrict__ wrow, int64_t n_w, const float2 *__restrict__ whist,
-    float2 *__restrict__ whist_new, int hh, const float *__restrict__ g, int lg, float2 *__restrict__ out,
-    int64_t ld_out, int64_t n_out, int64_t tiles) {
-    __shared__ float2 sw[kOut / 2 + kMaxTaps / 2 + 2];
-    __shared__ float sg[kMaxTaps];
-    const int64_t j = blockIdx.x / tiles;
-    const int64_t tile = blockIdx.x % tiles;
-    const int64_t p0 = tile * kOut;
-    const int zr = (z && zrow) ? zrow[j] : -1;
-    const int wr = w ? (wrow ? wrow[j] : (int)j) : -1;
-    const float2 *wj = wr >= 0 ? w + (int64_t)wr * ld_w : nullptr;
-    const float2 *hj = whist ? whist + j * hh : nullptr;
-    // staged W(j, q) for q in [q_lo, q_lo + cnt): q_lo = floor((p0 - lg + 1) / 2) >= -hh
-    const int64_t v = p0 - lg + 1;
-    const int64_t q_lo = v >= 0 ? v / 2 : -((-v + 1) / 2);
-    const int cnt = (int)((p0 + kOut - 1) / 2 - q_lo + 1);
-    if (w) {
-        for (int k = threadIdx.x; k < cnt; k += kThreads) {
-            const int64_t q = q_lo + k;
-            sw[k] = q < n_w ? w_at(wj, hj, hh, q) : make_float2(0.0f, 0.0f);
-        }
-        if (threadIdx.x < lg) sg[threadIdx.x] = g[threadIdx.x];
-    }
-    __syncthreads();
-    const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
-    float2 *oj = out + j * ld_out;
-    constexpr int NU = kOut / 2 / kThreads;
-    int m[NU];
-    float2 ev[NU], od[NU];
+// Every decimation level of a piece in one launch: one workgroup, each level's
+// samples kept in LDS (after the lh - 1 history samples of that level) as the
+// input of the next; the full-rate input is staged in chunks. Level r
+// (1 <= r <= top) is formed from level r - 1 with the taps in the same order
+// as mr_decimate_kernel, so the values are those of the per-level launches;
+// so are the histories written to hist_new.
+constexpr int kPyrThreads = 1024;
+constexpr int kPyrChunk = 1024;   // level-1 outputs per staged chunk of the input
+
+// acc = sum_{i < lh} h[i] v(m0 - i), v(m0 - i) = s[-i], taps ascending.
+__device__ __forceinline__ float fir_down(const float *sh, const float *s, int lh) {
+    float acc = 0.0f;
+    int i = 0;
+    for (; i + 8 <= lh; i += 8) {
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        m[u] = u * kThreads + (int)threadIdx.x;   // pair m: tile offsets 2m, 2m + 1
-        const int64_t p = p0 + 2 * m[u];
-        ev[u] = zj && p < n_out ? zj[p] : make_float2(0.0f, 0.0f);
-        od[u] = zj && p + 1 < n_out ? zj[p + 1] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < 8; ++u) acc = fmaf(sh[i + u], s[-(i + u)], acc);
     }
-    if (w) interp_pairs<NU>(sw, (int)(p0 / 2 - q_lo), sg, lg, m, ev, od);
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int64_t p = p0 + 2 * m[u];
-        if (p < n_out) oj[p] = ev[u];
-        if (p + 1 < n_out) oj[p + 1] = od[u];
-    }
-    if (w && tile == 0 && threadIdx.x < hh) whist_new[j * hh + threadIdx.x] = w_at(wj, hj, hh, n_w - hh + threadIdx.x);
+    for (; i < lh; ++i) acc = fmaf(sh[i], s[-i], acc);
+    return acc;
 }
 
-// Templates per key chunk (rows folded into one per-sample key).
+__global__ __launch_bounds__(kPyrThreads) void mr_pyramid_kernel(const float *__restrict__ x, int64_t n, int top,
+                                                                 MrPyramid pm, const float *__restrict__ h, int lh,
+                                                                 int cap0, int cap1) {
+    // dynamic LDS: [cap0] level r < top with r odd, [cap1] r even (history, then
+    // samples), [2 kPyrChunk + lh - 1] the staged chunk of the full-rate input
+    extern __shared__ float pbuf[];
+    __shared__ float sh[kMaxTaps];
+    const int hl = lh - 1;
+    float *xs = pbuf + cap0 + cap1;
+    if (threadIdx.x < lh) sh[threadIdx.x] = h[threadIdx.x];
+    for (int r = 1; r <= top; ++r) {
+        const int64_t ns = n >> (r - 1);
+        const int64_t nq = ns / 2;
+        const float *hist = pm.hist[r];
+        float *ldst = r < top ? pbuf + ((r - 1) & 1) * cap0 : nullptr;
+        if (ldst)
+            for (int i = threadIdx.x; i < hl; i += kPyrThreads) ldst[i] = pm.hist[r + 1][i];
+        if (r == 1) {
+            // chunks of kPyrChunk outputs: inputs 2 q0 + 1 - hl .. 2 q0 + 2 kPyrChunk - 1
+            for (int64_t q0 = 0; q0 < nq; q0 += kPyrChunk) {
+                const int64_t m0 = 2 * q0 + 1 - hl;
+                const int cnt = (int)min((int64_t)(2 * kPyrChunk + hl), ns - m0);
+                __syncthreads();   // the previous chunk's reads are done
+                for (int k = threadIdx.x; k < cnt; k += kPyrThreads) {
+                    const int64_t m = m0 + k;
+                    xs[k] = m >= 0 ? x[m] : hist[hl + m];
+                }
+                __syncthreads();
+                const int64_t q = q0 + threadIdx.x;
+                if (threadIdx.x < kPyrChunk && q < nq) {
+                    const float acc = fir_down(sh, xs + (2 * q + 1 - m0), lh);
+                    pm.dst[1][q] = acc;
+                    if (ldst) ldst[hl + q] = acc;
+                }
+            }
+            for (int i = threadIdx.x; i < hl; i += kPyrThreads) {
+                const int64_t m = ns - hl + i;
+                pm.hist_new[1][i] = m >= 0 ? x[m] : hist[hl + m];
+            }
+        } else {
+            const float *lsrc = pbuf + ((r - 2) & 1) * cap0;   // level r - 1: lsrc[hl + m] = sample m
+            for (int64_t q = threadIdx.x; q < nq; q += kPyrThreads) {
+                const float acc = fir_down(sh, lsrc + hl + 2 * q + 1, lh);
+                pm.dst[r][q] = acc;
+                if (ldst) ldst[hl + q] = acc;
+            }
+            for (int i = threadIdx.x; i < hl; i += kPyrThreads) pm.hist_new[r][i] = lsrc[hl + ns - hl + i];
+        }
+        __syncthreads();
+    }
+}
+
+// Interpolation of every level back to the full rate, fused with the output:
+//   W_top = z_top,  W_r(q) = Z_r(q) + sum_{i < lg, q - i even} g[i] W_{r+1}((q - i) / 2)  (r = top - 1 .. 0)
+// with Z_r(q) = z[r][zrow[r][j]][q] (0 where the level or the row has no
+// filters) and W_r(q) for -hh <= q < 0 taken from the previous call's history
+// whist[r][j][hh + q]. Block = one chunk of kKeyChunk template rows x one
+// tile of kTile full-rate samples, one wave per row. For the tile each wave
+// forms, from the top level down, the window of every level that the tile's
+// outputs depend on (level r + 1's window covers the taps of level r's,
+// recomputed where tiles overlap) in two LDS buffers used in turn, then
+// writes the full-rate z of the tile (Z mode) or its |z|^2 to LDS, from which
+// every sample's largest key (|z|^2 bits << 32 | ~j) over the chunk's rows is
+// formed (keys mode; plain LDS reads, no atomics). Outputs pair
+// up (2m, 2m + 1), which read the same W samples with the even and the odd
+// taps; each output adds its taps in ascending order onto Z_r, as the plain
+// per-output sum does. The last tile writes every level's next history (the
+// last hh samples of W_r) to whist_new.
 constexpr int kKeyChunk = 16;
+constexpr int kChainThreads = kKeyChunk * 64;
+constexpr int kTile = 512;
+constexpr int kChainLdsMax = 80 * 1024;
 
-// The last interpolation (into level 0) fused with the per-sample keys:
-// block = one chunk of kKeyChunk template rows x kOut samples, one wave per
-// row. Each wave stages its row's W samples in its own LDS slice, forms the
-// full-rate z of its kOut / 64 samples per lane (8 adjacent pairs) as
-// mr_upsample_add_kernel does, and folds its keys into the block's
-// per-sample maximum (LDS atomics); the full-rate z itself is never stored.
-// Tile 0 also writes every row's next interpolation history.
-constexpr int kSw = kOut / 2 + kMaxTaps / 2 + 2;
-constexpr int kFuseThreads = kKeyChunk * 64;
+__device__ __forceinline__ int64_t floor_half(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 
-__global__ __launch_bounds__(kFuseThreads) void mr_interp_keys_kernel(
-    const float2 *__restrict__ z, int64_t ld_z, const int32_t *__restrict__ zrow, const float2 *__restrict__ w,
-    int64_t ld_w, const int32_t *__restrict__ wrow, int64_t n_w, const float2 *__restrict__ whist,
-    float2 *__restrict__ whist_new, int hh, const float *__restrict__ g, int lg, int64_t n_out, int T,
-    uint64_t *__restrict__ keys, int64_t ld_keys, int64_t tiles) {
-    __shared__ float2 sw[kKeyChunk][kSw];
+__device__ __forceinline__ float2 z_at(const float2 *zj, int64_t q, int64_t n) {
+    return zj && q < n ? zj[q] : make_float2(0.0f, 0.0f);
+}
+
+template <bool KEYS>
+__global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int top, int hh,
+                                                                 const float *__restrict__ g, int lg, int64_t n_out,
+                                                                 int T, int capA, int capB, uint64_t *__restrict__ keys,
+                                                                 int64_t ld_keys, float2 *__restrict__ out,
+                                                                 int64_t ld_out, int64_t tiles) {
+    extern __shared__ __align__(16) float2 wbuf[];   // per wave: capA then capB samples
     __shared__ float sg[kMaxTaps];
-    __shared__ unsigned long long kred[kOut];
+    __shared__ int64_t slo[kMaxLevels], shi[kMaxLevels];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t chunk = blockIdx.x / tiles;
     const int64_t tile = blockIdx.x % tiles;
-    const int64_t p0 = tile * kOut;
+    const bool last = tile == tiles - 1;
+    const int64_t p0 = tile * kTile;
     const int64_t j = chunk * kKeyChunk + wv;
     const bool live = j < T;
-    const int zr = (live && z && zrow) ? zrow[j] : -1;
-    const int wr = (live && w) ? (wrow ? wrow[j] : (int)j) : -1;
-    const float2 *wj = wr >= 0 ? w + (int64_t)wr * ld_w : nullptr;
-    const float2 *hj = (live && whist) ? whist + j * hh : nullptr;
-    const int64_t v = p0 - lg + 1;
-    const int64_t q_lo = v >= 0 ? v / 2 : -((-v + 1) / 2);
-    const int cnt = (int)((p0 + kOut - 1) / 2 - q_lo + 1);
-    for (int t = threadIdx.x; t < kOut; t += kFuseThreads) kred[t] = 0ull;
-    if (threadIdx.x < lg) sg[threadIdx.x] = g[threadIdx.x];
-    if (live && w)
-        for (int k = lane; k < cnt; k += 64) {
-            const int64_t q = q_lo + k;
-            sw[wv][k] = q < n_w ? w_at(wj, hj, hh, q) : make_float2(0.0f, 0.0f);
+    float2 *bufA = wbuf + (int64_t)wv * (capA + capB);
+    float2 *bufB = bufA + capA;
+    if (threadIdx.x == 0) {
+        // windows: level 0 = the tile; level r covers the taps of level r - 1's
+        // computed part (its non-negative indices; the rest is history)
+        slo[0] = p0;
+        shi[0] = min(p0 + kTile, n_out) - 1;
+        for (int r = 1; r <= top; ++r) {
+            const int64_t a = r == 1 ? slo[0] : max(slo[r - 1], (int64_t)0);
+            slo[r] = floor_half(a - lg + 1);
+            shi[r] = shi[r - 1] / 2;
         }
+    }
+    if (threadIdx.x < lg) sg[threadIdx.x] = g[threadIdx.x];
     __syncthreads();
+    auto zrow_of = [&](int r) -> const float2 * {
+        if (!live || !c.z[r]) return nullptr;
+        const int zr = c.zrow[r][j];
+        return zr >= 0 ? c.z[r] + (int64_t)zr * c.ld_z[r] : nullptr;
+    };
+    auto write_hist = [&](int r, const float2 *win) {
+        // the last hh samples of W_r lie inside the last tile's window of level r
+        if (live && last && lane < hh) c.whist_new[r][j * hh + lane] = win[(n_out >> r) - hh + lane - slo[r]];
+    };
+    if (top > 0) {
+        // top level: W_top = z_top, history below index 0
+        float2 *win = (top & 1) ? bufA : bufB;
+        const int64_t lo = slo[top], hi = shi[top], nr = n_out >> top;
+        const float2 *zj = zrow_of(top);
+        if (live)
+            for (int64_t q = lo + lane; q <= hi; q += 64)
+                win[q - lo] = q >= 0 ? z_at(zj, q, nr) : c.whist[top][j * hh + hh + q];
+        __syncthreads();
+        write_hist(top, win);
+    }
+    for (int r = top - 1; r >= 1; --r) {
+        float2 *win = (r & 1) ? bufA : bufB;
+        const float2 *src = (r & 1) ? bufB : bufA;   // W_{r+1}
+        const int64_t lo = slo[r], hi = shi[r], nr = n_out >> r, lo_src = slo[r + 1];
+        const int64_t qa = max(lo, (int64_t)0);
+        if (live) {
+            for (int64_t q = lo + lane; q < qa; q += 64) win[q - lo] = c.whist[r][j * hh + hh + q];
+            const float2 *zj = zrow_of(r);
+            const int64_t mlo = qa / 2, mhi = hi / 2;
+            for (int64_t m0 = mlo; m0 <= mhi; m0 += 128) {
+                int m[2];
+                float2 ev[2], od[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int64_t mm = min(m0 + u * 64 + lane, mhi);   // past mhi: a repeat, not written
+                    m[u] = (int)(mm - mlo);
+                    ev[u] = z_at(zj, 2 * mm, nr);
+                    od[u] = z_at(zj, 2 * mm + 1, nr);
+                }
+                interp_pairs<2>(src, (int)(mlo - lo_src), sg, lg, m, ev, od);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int64_t mm = m0 + u * 64 + lane;
+                    if (mm > mhi) continue;
+                    if (2 * mm >= qa) win[2 * mm - lo] = ev[u];
+                    if (2 * mm + 1 <= hi) win[2 * mm + 1 - lo] = od[u];
+                }
+            }
+        }
+        __syncthreads();
+        write_hist(r, win);
+    }
+    constexpr int NU = kTile / 2 / 64;
+    float2 ev[NU], od[NU];
     if (live) {
-        const float2 *zj = zr >= 0 ? z + (int64_t)zr * ld_z : nullptr;
-        const unsigned long long jkey = 0xFFFFFFFFu - (uint32_t)j;
-        constexpr int NU = kOut / 2 / 64;
+        const float2 *zj = zrow_of(0);
         int m[NU];
-        float2 ev[NU], od[NU];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             m[u] = u * 64 + lane;   // pair m: tile offsets 2m, 2m + 1
             const int64_t p = p0 + 2 * m[u];
-            ev[u] = zj && p < n_out ? zj[p] : make_float2(0.0f, 0.0f);
-            od[u] = zj && p + 1 < n_out ? zj[p + 1] : make_float2(0.0f, 0.0f);
+            ev[u] = z_at(zj, p, n_out);
+            od[u] = z_at(zj, p + 1, n_out);
         }
-        if (w) interp_pairs<NU>(sw[wv], (int)(p0 / 2 - q_lo), sg, lg, m, ev, od);
+        if (top > 0) interp_pairs<NU>(bufA, (int)(p0 / 2 - slo[1]), sg, lg, m, ev, od);
+        if (!KEYS) {
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int64_t p = p0 + 2 * m[u];
-            const float se = ev[u].x * ev[u].x + ev[u].y * ev[u].y;
-            const float so = od[u].x * od[u].x + od[u].y * od[u].y;
-            if (p < n_out) atomicMax(&kred[2 * m[u]], ((unsigned long long)__float_as_uint(se) << 32) | jkey);
-            if (p + 1 < n_out) atomicMax(&kred[2 * m[u] + 1], ((unsigned long long)__float_as_uint(so) << 32) | jkey);
+            for (int u = 0; u < NU; ++u) {
+                const int64_t p = p0 + 2 * m[u];
+                if (p < n_out) out[j * ld_out + p] = ev[u];
+                if (p + 1 < n_out) out[j * ld_out + p + 1] = od[u];
+            }
         }
-        if (w && tile == 0 && lane < hh) whist_new[j * hh + lane] = w_at(wj, hj, hh, n_w - hh + lane);
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kOut; t += kFuseThreads) {
-        const int64_t p = p0 + t;
-        if (p < n_out) keys[chunk * ld_keys + p] = kred[t];
+    if (KEYS) {
+        // |z|^2 of each row into its wave's first buffer (free once every wave
+        // has read W_1), then per sample the largest key over the chunk's rows
+        __syncthreads();
+        float *sq = reinterpret_cast<float *>(bufA);
+        if (live) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int t = 2 * (u * 64 + lane);
+                sq[t] = ev[u].x * ev[u].x + ev[u].y * ev[u].y;
+                sq[t + 1] = od[u].x * od[u].x + od[u].y * od[u].y;
+            }
+        }
+        __syncthreads();
+        const int nlive = (int)min((int64_t)kKeyChunk, (int64_t)T - chunk * kKeyChunk);
+        const size_t wstride = (size_t)(capA + capB) * 2;   // floats between the waves' buffers
+        const float *sq0 = reinterpret_cast<const float *>(wbuf);
+        for (int t = threadIdx.x; t < kTile; t += kChainThreads) {
+            const int64_t p = p0 + t;
+            if (p >= n_out) continue;
+            unsigned long long best = 0ull;
+            for (int w = 0; w < nlive; ++w) {
+                const unsigned long long key = ((unsigned long long)__float_as_uint(sq0[w * wstride + t]) << 32) |
+                                               (unsigned long long)(0xFFFFFFFFu - (uint32_t)(chunk * kKeyChunk + w));
+                best = key > best ? key : best;
+            }
+            keys[chunk * ld_keys + p] = best;
+        }
     }
 }
 
 }  // namespace
-
-hipError_t launch_mr_interp_keys(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w, int64_t ld_w,
-                                 const int32_t *wrow, int64_t n_w, const float2 *whist, float2 *whist_new, int hh,
-                                 const float *g, int lg, int64_t n_out, int T, uint64_t *keys, int64_t ld_keys,
-                                 hipStream_t st) {
-    if (n_out <= 0) return hipSuccess;
-    const int64_t tiles = nblk(n_out, kOut);
-    hipLaunchKernelGGL(mr_interp_keys_kernel, dim3((unsigned)(tiles * mr_key_chunks(T))), dim3(kFuseThreads), 0,
-                       st, z, ld_z, zrow, w, ld_w, wrow, n_w, whist, whist_new, hh, g, lg, n_out, T, keys, ld_keys,
-                       tiles);
-    return hipGetLastError();
-}
 
 hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
                               const float *h, int lh, float *dst, hipStream_t st) {
@@ -230,13 +320,72 @@ hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist
     return hipGetLastError();
 }
 
-hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w,
-                                  int64_t ld_w, const int32_t *wrow, int64_t n_w, const float2 *whist,
-                                  float2 *whist_new, int hh, const float *g, int lg, float2 *out,
-                                  int64_t ld_out, int64_t n_out, int T, hipStream_t st) {
-    const int64_t tiles = std::max<int64_t>(1, nblk(n_out, kOut));
-    hipLaunchKernelGGL(mr_upsample_add_kernel, dim3((unsigned)(tiles * T)), dim3(kThreads), 0, st, z, ld_z, zrow,
-                       w, ld_w, wrow, n_w, whist, whist_new, hh, g, lg, out, ld_out, n_out, tiles);
+void mr_chain_caps(int top, int lg, int *capA, int *capB) {
+    // window lengths: level 1 at most (kTile + lg + 1) / 2, level r at most
+    // (len_{r-1} + lg + 1) / 2 + 1; odd levels share buffer A, even ones B
+    int cap = kTile;
+    *capA = kTile / 2;   // at least the tile's |z|^2 (kTile floats) for the keys
+    *capB = 0;
+    for (int r = 1; r <= top; ++r) {
+        cap = (cap + lg + 1) / 2 + 1;
+        int &slot = (r & 1) ? *capA : *capB;
+        slot = std::max(slot, cap);
+    }
+}
+
+size_t mr_chain_lds(int top, int lg) {
+    int capA = 0, capB = 0;
+    mr_chain_caps(top, lg, &capA, &capB);
+    return (size_t)kKeyChunk * (size_t)(capA + capB) * sizeof(float2);
+}
+
+hipError_t launch_mr_chain(const MrChain &c, int top, int hh, const float *g, int lg, int64_t n_out, int T,
+                           uint64_t *keys, int64_t ld_keys, float2 *out, int64_t ld_out, hipStream_t st) {
+    if (n_out <= 0) return hipSuccess;
+    int capA = 0, capB = 0;
+    mr_chain_caps(top, lg, &capA, &capB);
+    const size_t lds = mr_chain_lds(top, lg);
+    // with the longest taps the windows need a little more than the default
+    // 64 KB of dynamic LDS: raise the limit once per device
+    static std::atomic<uint64_t> attr_done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_done.load() & bit)) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mr_chain_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kChainLdsMax);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mr_chain_kernel<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kChainLdsMax);
+        if (e != hipSuccess) return e;
+        attr_done.fetch_or(bit);
+    }
+    if (lds > (size_t)kChainLdsMax) return hipErrorInvalidValue;
+    const int64_t tiles = nblk(n_out, kTile);
+    const unsigned grid = (unsigned)(tiles * mr_key_chunks(T));
+    if (keys)
+        hipLaunchKernelGGL(mr_chain_kernel<true>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg, n_out,
+                           T, capA, capB, keys, ld_keys, out, ld_out, tiles);
+    else
+        hipLaunchKernelGGL(mr_chain_kernel<false>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg,
+                           n_out, T, capA, capB, keys, ld_keys, out, ld_out, tiles);
+    return hipGetLastError();
+}
+
+size_t mr_pyramid_lds(int64_t B, int top, int lh) {
+    // level buffers (levels 1..top-1) and the staged input chunk
+    const int64_t hl = lh - 1;
+    const int64_t cap0 = top >= 2 ? hl + (B >> 1) : 0, cap1 = top >= 3 ? hl + (B >> 2) : 0;
+    return (size_t)(cap0 + cap1 + 2 * kPyrChunk + hl) * sizeof(float);
+}
+
+hipError_t launch_mr_pyramid(const float *x, int64_t n, int top, const MrPyramid &pm, const float *h, int lh,
+                             int64_t B, hipStream_t st) {
+    const int hl = lh - 1;
+    const int cap0 = top >= 2 ? (int)(hl + (B >> 1)) : 0, cap1 = top >= 3 ? (int)(hl + (B >> 2)) : 0;
+    hipLaunchKernelGGL(mr_pyramid_kernel, dim3(1), dim3(kPyrThreads), mr_pyramid_lds(B, top, lh), st, x, n, top, pm,
+                       h, lh, cap0, cap1);
     return hipGetLastError();
 }
 

@@ -23,8 +23,9 @@ struct spiir_multirate {
     std::vector<float *> xbuf;           // per level >= 1: the decimated stream [B >> r]
     std::vector<float *> dh[2];          // per level >= 1: decimation history [lh - 1] (double-buffered)
     std::vector<float2 *> z;             // per level with filters: template sums [T_r][B >> r]
-    std::vector<float2 *> w;             // 1 <= r < top: w_r [T][B >> r]
-    std::vector<float2 *> wh[2];         // 1 <= r <= top: interpolation history of w_r [T][hh]
+    std::vector<float2 *> wh[2];         // 1 <= r <= top: interpolation history of W_r [T][hh]
+    bool pyramid = false;                // every decimation level in one launch (fits in LDS)
+    std::vector<int> multi;              // levels whose banks share one launch per time-split pass
     int cur = 0;
     uint64_t *keys = nullptr;            // [chunks][B]
     float *h = nullptr, *g = nullptr;
@@ -79,7 +80,6 @@ void mr_free(spiir_multirate *mr) {
         for (auto *p : mr->wh[c]) dfree(p);
     }
     for (auto *p : mr->z) dfree(p);
-    for (auto *p : mr->w) dfree(p);
     dfree(mr->keys);
     dfree(mr->h);
     dfree(mr->g);
@@ -96,63 +96,95 @@ int mr_clear_history(spiir_multirate *mr, hipStream_t st) {
 }
 
 // One piece (np <= B samples) of the multi-rate bank: decimation, the level
-// banks forked onto their streams, interpolation and sums, and the full-rate
-// z (out0, row stride ld0) or the max / argmax (mx, am).
+// banks forked onto their streams, then one launch that interpolates every
+// level back to the full rate and writes the full-rate z (out0, row stride
+// ld0) or the per-sample keys for the max / argmax (mx, am).
 int mr_piece(spiir_multirate *mr, const float *x0, int64_t np, float2 *out0, int64_t ld0, float *mx, int32_t *am,
              hipStream_t st) {
     const int top = mr->top;
     const int c = mr->cur;
-    // each level's bank is forked onto its stream as soon as its input exists
-    // (level 0 at once, level r after r decimations); the joins come after
-    // the whole decimation chain has been enqueued
-    const float *xr = x0;
-    for (int r = 0; r <= top; ++r) {
-        if (r > 0) {
-            HIPCHK(launch_mr_decimate(xr, np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r], mr->h, mr->lh, mr->xbuf[r],
-                                      st));
-            xr = mr->xbuf[r];
+    // the small levels' banks as one group of time-split launches, on the
+    // stream of the group's first level once the group's last input exists
+    bool grouped[kMaxLevels] = {};
+    int g0 = -1, g1 = -1;
+    std::vector<spiir_bank *> gb;
+    std::vector<const float *> gx;
+    std::vector<int64_t> gn, gld;
+    std::vector<float *> gz;
+    if (!mr->multi.empty()) {
+        for (int r : mr->multi) {
+            gb.push_back(mr->bank[r]);
+            gx.push_back(r == 0 ? x0 : mr->xbuf[r]);
+            gn.push_back(np >> r);
+            gz.push_back(reinterpret_cast<float *>(mr->z[r]));
+            gld.push_back(mr->B >> r);
         }
-        if (!mr->bank[r]) continue;
+        if (banks_multi_ok(gb.data(), (int)gb.size(), gn.data())) {
+            for (int r : mr->multi) grouped[r] = true;
+            g0 = mr->multi.front();
+            g1 = mr->multi.back();
+        }
+    }
+    // each level's bank is forked onto its stream as soon as its input exists
+    auto fork = [&](int r, const float *xr) -> int {
+        if (!mr->bank[r]) return SPIIR_OK;
+        if (grouped[r]) {
+            if (r != g1) return SPIIR_OK;
+            HIPCHK(hipEventRecord(mr->lfork[g0], st));
+            HIPCHK(hipStreamWaitEvent(mr->lstream[g0], mr->lfork[g0], 0));
+            const int rc = banks_stream_z_multi(gb.data(), (int)gb.size(), gx.data(), gn.data(), gz.data(),
+                                                gld.data(), mr->lstream[g0]);
+            if (rc) return rc;
+            HIPCHK(hipEventRecord(mr->ldone[g0], mr->lstream[g0]));
+            return SPIIR_OK;
+        }
         HIPCHK(hipEventRecord(mr->lfork[r], st));
         HIPCHK(hipStreamWaitEvent(mr->lstream[r], mr->lfork[r], 0));
         const int rc = bank_stream_z(mr->bank[r], xr, np >> r, reinterpret_cast<float *>(mr->z[r]), mr->B >> r,
                                      mr->lstream[r]);
         if (rc) return rc;
         HIPCHK(hipEventRecord(mr->ldone[r], mr->lstream[r]));
-    }
-    for (int r = 0; r <= top; ++r)
-        if (mr->bank[r]) HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
-    // interpolation from the top level down to level 1 into w_r; the last
-    // step (into level 0) writes the full-rate z, or, for the max / argmax,
-    // runs fused with the per-sample keys
-    const float2 *src = nullptr;
-    int64_t ld_src = 0;
-    const int32_t *srow = nullptr;
-    if (top > 0) {
-        src = mr->z[top];
-        ld_src = mr->B >> top;
-        srow = mr->zrow[top];
-        for (int r = top - 1; r >= 1; --r) {
-            HIPCHK(launch_mr_upsample_add(mr->bank[r] ? mr->z[r] : nullptr, mr->B >> r, mr->zrow[r], src, ld_src,
-                                          srow, np >> (r + 1), mr->wh[c][r + 1], mr->wh[c ^ 1][r + 1], mr->hh,
-                                          mr->g, mr->lg, mr->w[r], mr->B >> r, np >> r, mr->T, st));
-            src = mr->w[r];
-            ld_src = mr->B >> r;
-            srow = nullptr;
+        return SPIIR_OK;
+    };
+    int rc = fork(0, x0);
+    if (rc) return rc;
+    if (top > 0 && mr->pyramid) {
+        MrPyramid pm;
+        std::memset(&pm, 0, sizeof pm);
+        for (int r = 1; r <= top; ++r) {
+            pm.hist[r] = mr->dh[c][r];
+            pm.hist_new[r] = mr->dh[c ^ 1][r];
+            pm.dst[r] = mr->xbuf[r];
+        }
+        HIPCHK(launch_mr_pyramid(x0, np, top, pm, mr->h, mr->lh, mr->B, st));
+        for (int r = 1; r <= top; ++r)
+            if ((rc = fork(r, mr->xbuf[r]))) return rc;
+    } else {
+        for (int r = 1; r <= top; ++r) {
+            HIPCHK(launch_mr_decimate(r == 1 ? x0 : mr->xbuf[r - 1], np >> (r - 1), mr->dh[c][r], mr->dh[c ^ 1][r],
+                                      mr->h, mr->lh, mr->xbuf[r], st));
+            if ((rc = fork(r, mr->xbuf[r]))) return rc;
         }
     }
-    const float2 *z0 = mr->bank[0] ? mr->z[0] : nullptr;
-    const float2 *h1 = top > 0 ? mr->wh[c][1] : nullptr;
-    float2 *h1n = top > 0 ? mr->wh[c ^ 1][1] : nullptr;
-    const int hh = top > 0 ? mr->hh : 0;
+    for (int r = 0; r <= top; ++r)
+        if (mr->bank[r] && (!grouped[r] || r == g0)) HIPCHK(hipStreamWaitEvent(st, mr->ldone[r], 0));
+    MrChain ch;
+    std::memset(&ch, 0, sizeof ch);
+    for (int r = 0; r <= top; ++r) {
+        ch.z[r] = mr->bank[r] ? mr->z[r] : nullptr;
+        ch.ld_z[r] = mr->B >> r;
+        ch.zrow[r] = mr->zrow[r];
+        if (r >= 1) {
+            ch.whist[r] = mr->wh[c][r];
+            ch.whist_new[r] = mr->wh[c ^ 1][r];
+        }
+    }
     if (mx) {
-        HIPCHK(launch_mr_interp_keys(z0, mr->B, mr->zrow[0], src, ld_src, srow, np >> 1, h1, h1n, hh, mr->g, mr->lg,
-                                     np, mr->T, mr->keys, mr->B, st));
+        HIPCHK(launch_mr_chain(ch, top, mr->hh, mr->g, mr->lg, np, mr->T, mr->keys, mr->B, nullptr, 0, st));
         HIPCHK(launch_finalize_keys(mr->keys, mr_key_chunks(mr->T), mr->B, np, mx, am, st));
     } else {
         if (!out0) return fail(SPIIR_EINVAL, "multi-rate piece without an output");
-        HIPCHK(launch_mr_upsample_add(z0, mr->B, mr->zrow[0], src, ld_src, srow, np >> 1, h1, h1n, hh, mr->g,
-                                      mr->lg, out0, ld0, np, mr->T, st));
+        HIPCHK(launch_mr_chain(ch, top, mr->hh, mr->g, mr->lg, np, mr->T, nullptr, 0, out0, ld0, st));
     }
     mr->cur ^= 1;
     return SPIIR_OK;
@@ -280,8 +312,8 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
     if (o.max_block < 0) return fail(SPIIR_EINVAL, "max_block must be >= 0");
     int64_t B = o.max_block ? o.max_block : 16384;
     B = std::max<int64_t>((B >> R) << R, (int64_t)1 << R);
-    // interpolation launches one workgroup per (template, 1,024 outputs)
-    if (((B + 1023) / 1024) * (int64_t)T > INT32_MAX)
+    // the interpolation launch: ceil(B / 512) x ceil(T / 16) workgroups of 1,024 threads
+    if (((B + 511) / 512) * (((int64_t)T + 15) / 16) * 1024 > (int64_t)UINT32_MAX)
         return fail(SPIIR_EINVAL, "n_templates x max_block too large (%d x %lld)", T, (long long)B);
     int dev = o.device;
     if (dev < 0) {
@@ -304,11 +336,11 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
     mr->lg = n_interp_taps;
     mr->hh = n_interp_taps / 2;
     mr->B = B;
+    mr->pyramid = mr_pyramid_lds(B, top, n_decim_taps) <= 64 * 1024;
     mr->bank.assign(R + 1, nullptr);
     mr->zrow.assign(R + 1, nullptr);
     mr->xbuf.assign(R + 1, nullptr);
     mr->z.assign(R + 1, nullptr);
-    mr->w.assign(R + 1, nullptr);
     for (int c = 0; c < 2; ++c) {
         mr->dh[c].assign(R + 1, nullptr);
         mr->wh[c].assign(R + 1, nullptr);
@@ -327,39 +359,65 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         const int code = fail(SPIIR_EHIP, "%s: %s", what, hipGetErrorString(e));
         return bail(code);
     };
+    std::vector<std::vector<int64_t>> offc(R + 1);
+    std::vector<bool> small(R + 1, false);
+    // a level whose filters leave most of the device idle is a short serial
+    // recursion per call: let the automatic time split cut it into up to 32
+    // segments, with 64-sample chunks so that segments can be that short
+    auto make_bank = [&](int r, int wpg) -> int {
+        spiir_bank_opts orr = o;
+        orr.device = dev;
+        orr.max_block = (int32_t)std::max<int64_t>(8, B >> r);
+        if (wpg > 0) orr.waves_per_group = wpg;
+        if (small[r]) orr.chunk_len = 64;
+        spiir_bank *bk = nullptr;
+        const int n_rows = (int32_t)(offc[r].size() - 1);
+        const int code = orr.autotune
+                             ? spiir_bank_create(&bk, n_rows, offc[r].data(), a[r], b[r], d[r], &orr)
+                             : bank_create_capped(&bk, n_rows, offc[r].data(), a[r], b[r], d[r], orr, small[r] ? 32 : 8);
+        if (code) {
+            g_err = "level " + std::to_string(r) + ": " + g_err;
+            return code;
+        }
+        mr->bank[r] = bk;
+        return SPIIR_OK;
+    };
     for (int r = 0; r <= R; ++r) {
         const int64_t *off = filter_offsets[r];
         std::vector<int32_t> row(T, -1);
-        std::vector<int64_t> offc(1, 0);
+        offc[r].assign(1, 0);
         for (int j = 0; j < T; ++j)
             if (off[j + 1] > off[j]) {
-                row[j] = (int32_t)(offc.size() - 1);
-                offc.push_back(off[j + 1]);
+                row[j] = (int32_t)(offc[r].size() - 1);
+                offc[r].push_back(off[j + 1]);
             }
         hipError_t e = dalloc(&mr->zrow[r], (size_t)T);
         if (e != hipSuccess) return alloc_fail(e);
         e = hipMemcpy(mr->zrow[r], row.data(), T * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "row map upload");
         if (off[T] == 0) continue;
-        spiir_bank_opts orr = o;
-        orr.device = dev;
-        orr.max_block = (int32_t)std::max<int64_t>(8, B >> r);
-        // a level whose filters leave most of the device idle is a short serial
-        // recursion per call: let the automatic time split cut it into up to 32
-        // segments, with 64-sample chunks so that segments can be that short
-        const bool small = o.time_split == 0 && off[T] <= 128 * (int64_t)df.n_cu;
-        if (small) orr.chunk_len = 64;
-        spiir_bank *bk = nullptr;
-        rc = orr.autotune ? spiir_bank_create(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], &orr)
-                          : bank_create_capped(&bk, (int32_t)(offc.size() - 1), offc.data(), a[r], b[r], d[r], orr,
-                                        small ? 32 : 8);
-        if (rc) {
-            g_err = "level " + std::to_string(r) + ": " + g_err;
-            return bail(rc);
-        }
-        mr->bank[r] = bk;
-        e = dalloc(&mr->z[r], (size_t)(offc.size() - 1) * (size_t)(B >> r));
+        small[r] = o.time_split == 0 && off[T] <= 128 * (int64_t)df.n_cu;
+        if ((rc = make_bank(r, 0))) return bail(rc);
+        e = dalloc(&mr->z[r], (size_t)(offc[r].size() - 1) * (size_t)(B >> r));
         if (e != hipSuccess) return alloc_fail(e);
+    }
+    // the small levels share one launch per time-split pass (one stream, three
+    // launches in place of three per level) when their banks agree in
+    // workgroup size: with the automatic choice, rebuild the ones below the
+    // largest with that size
+    for (int r = 0; r <= R; ++r)
+        if (mr->bank[r] && small[r]) mr->multi.push_back(r);
+    if (mr->multi.size() < 2 || mr->multi.size() > (size_t)kMultiMax) {
+        mr->multi.clear();
+    } else if (o.waves_per_group == 0) {
+        int wmax = 0;
+        for (int r : mr->multi) wmax = std::max(wmax, bank_wpg(mr->bank[r]));
+        for (int r : mr->multi)
+            if (bank_wpg(mr->bank[r]) != wmax) {
+                spiir_bank_destroy(mr->bank[r]);
+                mr->bank[r] = nullptr;
+                if ((rc = make_bank(r, wmax))) return bail(rc);
+            }
     }
     for (int r = 1; r <= top; ++r) {
         hipError_t e = dalloc(&mr->xbuf[r], (size_t)(B >> r));
@@ -367,7 +425,6 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
             e = dalloc(&mr->dh[c][r], (size_t)std::max(1, mr->lh - 1));
             if (e == hipSuccess) e = dalloc(&mr->wh[c][r], (size_t)T * std::max(1, mr->hh));
         }
-        if (e == hipSuccess && r < top) e = dalloc(&mr->w[r], (size_t)T * (size_t)(B >> r));
         if (e != hipSuccess) return alloc_fail(e);
     }
     {

@@ -86,6 +86,21 @@ struct BwdArgs {
     int32_t nseg, seg_chunks;    // time segments of seg_chunks chunks each (the last may be shorter)
 };
 
+// Time-split streaming z calls of several banks (each on its own strain) in
+// one launch per pass: pass workgroups [first[b], first[b + 1]) belong to
+// bank b (segment pass: groups x nseg; chain: chain_blocks plus the history
+// copy's blocks; carry pass: groups x (nseg - 1)).
+constexpr int kMultiMax = 8;
+struct MultiFwd {
+    FwdArgs a[kMultiMax];
+    int32_t seg_first[kMultiMax + 1];
+    int32_t chain_first[kMultiMax + 1];
+    int32_t carry_first[kMultiMax + 1];
+    int32_t nseg[kMultiMax];
+    int32_t chain_blocks[kMultiMax];
+    int32_t count;
+};
+
 // One stream of a batch, as the persistent kernel sees it.
 struct BatchStream {
     FwdArgs args;       // bank part filled at creation; x = whole stream, xbase/n per step
@@ -112,6 +127,10 @@ hipError_t launch_forward(const FwdArgs &a, int mode, int fl, int tt, bool x_in_
 hipError_t launch_forward_split(const FwdArgs &a, int mode, int fl, int tt, bool x_in_lds, int nseg,
                                 size_t lds, size_t lds_carry, const int32_t *slot_filter,
                                 hipStream_t stream, KernelEvents ev = KernelEvents());
+// The three passes of a MultiFwd (z mode, strain windows in LDS); every bank
+// shares fl, tt and the workgroup size wpg * 64.
+hipError_t launch_forward_split_multi(const MultiFwd &m, int fl, int tt, int wpg, size_t lds, size_t lds_carry,
+                                      hipStream_t stream);
 int forward_occupancy(int fl, int tt, int wpg, size_t lds);
 // Adjoint over nseg time segments: segment-local (lambda, nu) scan, FP64 chain,
 // per-segment backward, FP64 reduction of the per-segment gradients.
@@ -154,22 +173,36 @@ hipError_t launch_batch_advance(int64_t *pos, const BatchStream *streams, int ns
 hipError_t launch_noise_fill(float *x, int64_t n, uint32_t seed, hipStream_t stream);
 int forward_max_threads();
 
-// Multi-rate bank: decimation by two with history, interpolation by two added
-// to the level below (template rows through row maps, with history), and
-// per-sample keys over chunks of template rows for finalize_keys.
+// Multi-rate bank: decimation by two with history (one launch per level, or
+// every level in one launch when the levels fit in LDS), then the
+// interpolation of every level back to the full rate in one launch, fused
+// with the full-rate z or with the per-sample keys over chunks of template
+// rows for finalize_keys.
+constexpr int kMaxLevels = 8;
+struct MrPyramid {
+    const float *hist[kMaxLevels];   // [r >= 1]: the previous lh - 1 samples of level r - 1
+    float *hist_new[kMaxLevels];     // [r >= 1]: the next call's (a different buffer)
+    float *dst[kMaxLevels];          // [r >= 1]: level r's samples, n >> r
+};
+struct MrChain {
+    const float2 *z[kMaxLevels];       // level sums [rows][ld_z] (null: the level has no filters)
+    int64_t ld_z[kMaxLevels];
+    const int32_t *zrow[kMaxLevels];   // template j -> row of z[r] (-1: none)
+    const float2 *whist[kMaxLevels];   // [r >= 1]: the previous hh samples of W_r, [T][hh]
+    float2 *whist_new[kMaxLevels];     // [r >= 1]: the next call's (a different buffer)
+};
 hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
                               const float *h, int lh, float *dst, hipStream_t stream);
-hipError_t launch_mr_upsample_add(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w,
-                                  int64_t ld_w, const int32_t *wrow, int64_t n_w, const float2 *whist,
-                                  float2 *whist_new, int hh, const float *g, int lg, float2 *out,
-                                  int64_t ld_out, int64_t n_out, int T, hipStream_t stream);
+size_t mr_pyramid_lds(int64_t B, int top, int lh);
+hipError_t launch_mr_pyramid(const float *x, int64_t n, int top, const MrPyramid &pm, const float *h, int lh,
+                             int64_t B, hipStream_t stream);
+size_t mr_chain_lds(int top, int lg);
+// keys != null: keys[chunk][p] = max over the chunk's rows of (|z|^2 bits << 32 | ~j);
+// else the full-rate z to out[j * ld_out + p].
+hipError_t launch_mr_chain(const MrChain &c, int top, int hh, const float *g, int lg, int64_t n_out, int T,
+                           uint64_t *keys, int64_t ld_keys, float2 *out, int64_t ld_out, hipStream_t stream);
 int mr_key_chunks(int T);
-// Interpolation into level 0 fused with the per-sample keys of the full-rate z
-// (keys[chunk][p] = max over the chunk's rows of (|z|^2 bits << 32 | ~j)).
-hipError_t launch_mr_interp_keys(const float2 *z, int64_t ld_z, const int32_t *zrow, const float2 *w, int64_t ld_w,
-                                 const int32_t *wrow, int64_t n_w, const float2 *whist, float2 *whist_new, int hh,
-                                 const float *g, int lg, int64_t n_out, int T, uint64_t *keys, int64_t ld_keys,
-                                 hipStream_t stream);
+
 // Whitening front end: frame FFTs (PSD or whitening mode), PSD average,
 // 1/sqrt(S) from a given PSD, overlap-add with history and pending half-frame.
 hipError_t launch_wh_frames(bool psd, const float *hist, int64_t hlen, const float *x, const float *wtab,

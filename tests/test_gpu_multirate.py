@@ -171,6 +171,48 @@ def test_multirate_graph_replay_equals_eager():
     assert np.max(np.abs(g2[0].cpu().numpy() - s.max(axis=0))) <= SNR_TOL * s.max()
 
 
+def test_multirate_grouped_small_levels_equal_per_level_calls():
+    """Small levels (few filters per compute unit) run as one group of
+    time-split launches; with kernel timing on, every level is its own bank
+    call. Both give the same full-rate z and max / argmax bitwise over
+    several calls, and the grouped banks share one workgroup size."""
+    from paper_1602_05573_amd import SpiirMultiRate
+    T, per = 12, [6, 10, 0, 16, 30]
+    levels = rand_levels(T, per, 41)
+    h, g = resample_taps(24)
+    B = 2048
+    n = 5 * B
+    x = strain(n, 6, 41)
+    banner("multirate grouped small levels")
+    xd = torch.from_numpy(x).cuda()
+
+    def run(timing):
+        z = torch.empty((T, n), dtype=torch.complex64, device="cuda")
+        mx = torch.empty(n, dtype=torch.float32, device="cuda")
+        am = torch.empty(n, dtype=torch.int32, device="cuda")
+        with SpiirMultiRate(levels, h, g, max_block=B) as mr:
+            wpg = {mr.level_info(r)["waves_per_group"] for r in (0, 1, 3, 4)}
+            mr.set_graph(False)
+            mr.time_kernels(timing)
+            for k in range(0, n, B):
+                z[:, k:k + B] = mr.filter_block_z(xd[k:k + B])
+            mr.reset()
+            for k in range(0, n, B):
+                mr.trigger_max(xd[k:k + B], out=(mx[k:k + B], am[k:k + B]))
+            torch.cuda.synchronize()
+            if timing:
+                mr.kernel_time()
+        return wpg, z.cpu(), mx.cpu(), am.cpu()
+
+    wg, zg, mg, ag = run(False)
+    wt, zt, mt, at = run(True)
+    assert len(wg) == 1 and wg == wt
+    assert torch.equal(zg, zt)
+    assert torch.equal(mg, mt) and torch.equal(ag, at)
+    zz = oracle.multirate_z(levels, h, g, x)
+    assert z_err(zg.numpy(), zz) <= SNR_TOL
+
+
 def test_multirate_graph_after_odd_reset():
     """Reset after an odd number of pieces, then graph replays mixed with eager
     pieces: equal to the same calls with graphs off (the graphs bake in which
