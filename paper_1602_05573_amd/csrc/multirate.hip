@@ -11,7 +11,6 @@
 #include "spiir_internal.h"
 
 #include <algorithm>
-#include <atomic>
 
 namespace spiir {
 namespace {
@@ -165,7 +164,7 @@ __global__ __launch_bounds__(kPyrThreads) void mr_pyramid_kernel(const float *__
 constexpr int kKeyChunk = 16;
 constexpr int kChainThreads = kKeyChunk * 64;
 constexpr int kTile = 512;
-constexpr int kChainLdsMax = 80 * 1024;
+constexpr int kChainLdsMax = 60 * 1024;   // dynamic LDS of mr_chain_kernel (static part: 384 bytes)
 
 __device__ __forceinline__ int64_t floor_half(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 
@@ -345,22 +344,7 @@ hipError_t launch_mr_chain(const MrChain &c, int top, int hh, const float *g, in
     int capA = 0, capB = 0;
     mr_chain_caps(top, lg, &capA, &capB);
     const size_t lds = mr_chain_lds(top, lg);
-    // with the longest taps the windows need a little more than the default
-    // 64 KB of dynamic LDS: raise the limit once per device
-    static std::atomic<uint64_t> attr_done{0};
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    const uint64_t bit = 1ull << (dev & 63);
-    if (!(attr_done.load() & bit)) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mr_chain_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kChainLdsMax);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mr_chain_kernel<false>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, kChainLdsMax);
-        if (e != hipSuccess) return e;
-        attr_done.fetch_or(bit);
-    }
+    // at most 59,776 bytes (64 taps), within the default 64 KB with the static part
     if (lds > (size_t)kChainLdsMax) return hipErrorInvalidValue;
     const int64_t tiles = nblk(n_out, kTile);
     const unsigned grid = (unsigned)(tiles * mr_key_chunks(T));

@@ -57,6 +57,7 @@ CONFIGS = [
     (7, [4, 0, 0, 0, 25], 24, 24, 4096, 1024),    # 5 levels, only the top and the bottom hold filters
     (3, [0, 0, 16], 7, 9, 4000, 0),               # odd tap counts, only the top level
     (4, [6, 10, 14], 24, 24, 36864, 32768),       # a piece above the one-launch decimation size, then a short one
+    (5, [4, 8, 12], 64, 64, 6144, 2048),          # longest taps: the largest interpolation windows
 ]
 
 
@@ -80,7 +81,7 @@ def test_multirate_z_parity(cfg):
     assert e <= SNR_TOL
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 3, 6])
 def test_multirate_trigger_parity(cfg):
     from paper_1602_05573_amd import SpiirMultiRate
     T, per, lh, lg, n, mb = CONFIGS[cfg]
