@@ -55,19 +55,27 @@ constexpr int kMaxTaps = 64;
 template <int NU>
 __device__ __forceinline__ void interp_pairs(const float2 *s, int sb, const float *sg, int lg, const int (&m)[NU],
                                              float2 (&ev)[NU], float2 (&od)[NU]) {
-    for (int k = 0; 2 * k < lg; ++k) {
-        const float ge = sg[2 * k];
-        const bool odd = 2 * k + 1 < lg;   // uniform
-        const float go = sg[2 * k + 1];    // inside the staged taps (lg <= kMaxTaps)
+    // whole (even, odd) tap pairs, then an odd tap count's last even tap: the
+    // loop body has no per-tap condition
+    const int kp = lg >> 1;
+    for (int k = 0; k < kp; ++k) {
+        const float ge = sg[2 * k], go = sg[2 * k + 1];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             const float2 x = s[sb + m[u] - k];
             ev[u].x = fmaf(ge, x.x, ev[u].x);
             ev[u].y = fmaf(ge, x.y, ev[u].y);
-            if (odd) {
-                od[u].x = fmaf(go, x.x, od[u].x);
-                od[u].y = fmaf(go, x.y, od[u].y);
-            }
+            od[u].x = fmaf(go, x.x, od[u].x);
+            od[u].y = fmaf(go, x.y, od[u].y);
+        }
+    }
+    if (lg & 1) {
+        const float ge = sg[2 * kp];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const float2 x = s[sb + m[u] - kp];
+            ev[u].x = fmaf(ge, x.x, ev[u].x);
+            ev[u].y = fmaf(ge, x.y, ev[u].y);
         }
     }
 }
@@ -166,29 +174,30 @@ constexpr int kChainThreads = kKeyChunk * 64;
 constexpr int kTile = 512;
 constexpr int kChainLdsMax = 60 * 1024;   // dynamic LDS of mr_chain_kernel (static part: 384 bytes)
 
-__device__ __forceinline__ int64_t floor_half(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+__device__ __forceinline__ int floor_half(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 
-__device__ __forceinline__ float2 z_at(const float2 *zj, int64_t q, int64_t n) {
+__device__ __forceinline__ float2 z_at(const float2 *zj, int q, int n) {
     return zj && q < n ? zj[q] : make_float2(0.0f, 0.0f);
 }
 
+// Indices inside a piece fit int32 (a piece has at most max_block samples).
 template <bool KEYS>
 __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int top, int hh,
-                                                                 const float *__restrict__ g, int lg, int64_t n_out,
+                                                                 const float *__restrict__ g, int lg, int n_out,
                                                                  int T, int capA, int capB, uint64_t *__restrict__ keys,
                                                                  int64_t ld_keys, float2 *__restrict__ out,
-                                                                 int64_t ld_out, int64_t tiles) {
+                                                                 int64_t ld_out, int tiles) {
     extern __shared__ __align__(16) float2 wbuf[];   // per wave: capA then capB samples
     __shared__ float sg[kMaxTaps];
-    __shared__ int64_t slo[kMaxLevels], shi[kMaxLevels];
+    __shared__ int slo[kMaxLevels], shi[kMaxLevels];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t chunk = blockIdx.x / tiles;
-    const int64_t tile = blockIdx.x % tiles;
+    const int chunk = (int)blockIdx.x / tiles;
+    const int tile = (int)blockIdx.x % tiles;
     const bool last = tile == tiles - 1;
-    const int64_t p0 = tile * kTile;
-    const int64_t j = chunk * kKeyChunk + wv;
+    const int p0 = tile * kTile;
+    const int j = chunk * kKeyChunk + wv;
     const bool live = j < T;
-    float2 *bufA = wbuf + (int64_t)wv * (capA + capB);
+    float2 *bufA = wbuf + wv * (capA + capB);
     float2 *bufB = bufA + capA;
     if (threadIdx.x == 0) {
         // windows: level 0 = the tile; level r covers the taps of level r - 1's
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
         slo[0] = p0;
         shi[0] = min(p0 + kTile, n_out) - 1;
         for (int r = 1; r <= top; ++r) {
-            const int64_t a = r == 1 ? slo[0] : max(slo[r - 1], (int64_t)0);
+            const int a = r == 1 ? slo[0] : max(slo[r - 1], 0);
             slo[r] = floor_half(a - lg + 1);
             shi[r] = shi[r - 1] / 2;
         }
@@ -215,10 +224,10 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
     if (top > 0) {
         // top level: W_top = z_top, history below index 0
         float2 *win = (top & 1) ? bufA : bufB;
-        const int64_t lo = slo[top], hi = shi[top], nr = n_out >> top;
+        const int lo = slo[top], hi = shi[top], nr = n_out >> top;
         const float2 *zj = zrow_of(top);
         if (live)
-            for (int64_t q = lo + lane; q <= hi; q += 64)
+            for (int q = lo + lane; q <= hi; q += 64)
                 win[q - lo] = q >= 0 ? z_at(zj, q, nr) : c.whist[top][j * hh + hh + q];
         __syncthreads();
         write_hist(top, win);
@@ -226,26 +235,26 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
     for (int r = top - 1; r >= 1; --r) {
         float2 *win = (r & 1) ? bufA : bufB;
         const float2 *src = (r & 1) ? bufB : bufA;   // W_{r+1}
-        const int64_t lo = slo[r], hi = shi[r], nr = n_out >> r, lo_src = slo[r + 1];
-        const int64_t qa = max(lo, (int64_t)0);
+        const int lo = slo[r], hi = shi[r], nr = n_out >> r, lo_src = slo[r + 1];
+        const int qa = max(lo, 0);
         if (live) {
-            for (int64_t q = lo + lane; q < qa; q += 64) win[q - lo] = c.whist[r][j * hh + hh + q];
+            for (int q = lo + lane; q < qa; q += 64) win[q - lo] = c.whist[r][j * hh + hh + q];
             const float2 *zj = zrow_of(r);
-            const int64_t mlo = qa / 2, mhi = hi / 2;
-            for (int64_t m0 = mlo; m0 <= mhi; m0 += 128) {
+            const int mlo = qa / 2, mhi = hi / 2;
+            for (int m0 = mlo; m0 <= mhi; m0 += 128) {
                 int m[2];
                 float2 ev[2], od[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const int64_t mm = min(m0 + u * 64 + lane, mhi);   // past mhi: a repeat, not written
-                    m[u] = (int)(mm - mlo);
+                    const int mm = min(m0 + u * 64 + lane, mhi);   // past mhi: a repeat, not written
+                    m[u] = mm - mlo;
                     ev[u] = z_at(zj, 2 * mm, nr);
                     od[u] = z_at(zj, 2 * mm + 1, nr);
                 }
-                interp_pairs<2>(src, (int)(mlo - lo_src), sg, lg, m, ev, od);
+                interp_pairs<2>(src, mlo - lo_src, sg, lg, m, ev, od);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const int64_t mm = m0 + u * 64 + lane;
+                    const int mm = m0 + u * 64 + lane;
                     if (mm > mhi) continue;
                     if (2 * mm >= qa) win[2 * mm - lo] = ev[u];
                     if (2 * mm + 1 <= hi) win[2 * mm + 1 - lo] = od[u];
@@ -263,15 +272,15 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             m[u] = u * 64 + lane;   // pair m: tile offsets 2m, 2m + 1
-            const int64_t p = p0 + 2 * m[u];
+            const int p = p0 + 2 * m[u];
             ev[u] = z_at(zj, p, n_out);
             od[u] = z_at(zj, p + 1, n_out);
         }
-        if (top > 0) interp_pairs<NU>(bufA, (int)(p0 / 2 - slo[1]), sg, lg, m, ev, od);
+        if (top > 0) interp_pairs<NU>(bufA, p0 / 2 - slo[1], sg, lg, m, ev, od);
         if (!KEYS) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                const int64_t p = p0 + 2 * m[u];
+                const int p = p0 + 2 * m[u];
                 if (p < n_out) out[j * ld_out + p] = ev[u];
                 if (p + 1 < n_out) out[j * ld_out + p + 1] = od[u];
             }
@@ -291,11 +300,11 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
             }
         }
         __syncthreads();
-        const int nlive = (int)min((int64_t)kKeyChunk, (int64_t)T - chunk * kKeyChunk);
-        const size_t wstride = (size_t)(capA + capB) * 2;   // floats between the waves' buffers
+        const int nlive = min(kKeyChunk, T - chunk * kKeyChunk);
+        const int wstride = (capA + capB) * 2;   // floats between the waves' buffers
         const float *sq0 = reinterpret_cast<const float *>(wbuf);
         for (int t = threadIdx.x; t < kTile; t += kChainThreads) {
-            const int64_t p = p0 + t;
+            const int p = p0 + t;
             if (p >= n_out) continue;
             unsigned long long best = 0ull;
             for (int w = 0; w < nlive; ++w) {
@@ -346,14 +355,16 @@ hipError_t launch_mr_chain(const MrChain &c, int top, int hh, const float *g, in
     const size_t lds = mr_chain_lds(top, lg);
     // at most 59,776 bytes (64 taps), within the default 64 KB with the static part
     if (lds > (size_t)kChainLdsMax) return hipErrorInvalidValue;
-    const int64_t tiles = nblk(n_out, kTile);
+    if (n_out > INT32_MAX - kTile) return hipErrorInvalidValue;   // tile-local indices are int32
+    const int tiles = (int)nblk(n_out, kTile);
     const unsigned grid = (unsigned)(tiles * mr_key_chunks(T));
+    const int n = (int)n_out;
     if (keys)
-        hipLaunchKernelGGL(mr_chain_kernel<true>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg, n_out,
-                           T, capA, capB, keys, ld_keys, out, ld_out, tiles);
+        hipLaunchKernelGGL(mr_chain_kernel<true>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg, n, T,
+                           capA, capB, keys, ld_keys, out, ld_out, tiles);
     else
-        hipLaunchKernelGGL(mr_chain_kernel<false>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg,
-                           n_out, T, capA, capB, keys, ld_keys, out, ld_out, tiles);
+        hipLaunchKernelGGL(mr_chain_kernel<false>, dim3(grid), dim3(kChainThreads), lds, st, c, top, hh, g, lg, n, T,
+                           capA, capB, keys, ld_keys, out, ld_out, tiles);
     return hipGetLastError();
 }
 
