@@ -317,7 +317,27 @@ __global__ __launch_bounds__(kChainThreads) void mr_chain_kernel(MrChain c, int 
     }
 }
 
+// The replayed piece's max / argmax out of the graph's buffers, one launch
+// for both arrays.
+__global__ __launch_bounds__(kThreads) void mr_copy_out_kernel(float *__restrict__ mx, const float *__restrict__ mxo,
+                                                               int32_t *__restrict__ am,
+                                                               const int32_t *__restrict__ amo, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) {
+        mx[i] = mxo[i];
+        am[i] = amo[i];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mr_copy_out(float *mx, const float *mxo, int32_t *am, const int32_t *amo, int64_t n,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mr_copy_out_kernel, dim3((unsigned)nblk(n, kThreads)), dim3(kThreads), 0, st, mx, mxo, am, amo,
+                       n);
+    return hipGetLastError();
+}
 
 hipError_t launch_mr_decimate(const float *src, int64_t n_src, const float *hist, float *hist_new,
                               const float *h, int lh, float *dst, hipStream_t st) {

@@ -256,8 +256,7 @@ int mr_run(spiir_multirate *mr, const float *x, int64_t n, float2 *zout, int64_t
         if (graph) {
             HIPCHK(hipMemcpyAsync(mr->xin, x + P, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGraphLaunch(mr->gexec[mr->cur], st));
-            HIPCHK(hipMemcpyAsync(mx + P, mr->mxo, (size_t)np * sizeof(float), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(am + P, mr->amo, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+            HIPCHK(launch_mr_copy_out(mx + P, mr->mxo, am + P, mr->amo, np, st));
             mr->cur ^= 1;
             for (auto *bk : mr->bank)
                 if (bk) bank_set_hist_cur(bk, bank_hist_cur(bk) ^ 1);   // as the captured stream calls did

@@ -202,6 +202,8 @@ size_t mr_chain_lds(int top, int lg);
 hipError_t launch_mr_chain(const MrChain &c, int top, int hh, const float *g, int lg, int64_t n_out, int T,
                            uint64_t *keys, int64_t ld_keys, float2 *out, int64_t ld_out, hipStream_t stream);
 int mr_key_chunks(int T);
+hipError_t launch_mr_copy_out(float *mx, const float *mxo, int32_t *am, const int32_t *amo, int64_t n,
+                              hipStream_t stream);
 
 // Whitening front end: frame FFTs (PSD or whitening mode), PSD average,
 // 1/sqrt(S) from a given PSD, overlap-add with history and pending half-frame.
