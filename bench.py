@@ -955,8 +955,10 @@ def run_precision(args, torch):
     modes = {}
     for prec, name in ((0, "fp32 + fp64 carries for |a| > 1-1e-5"), (2, "fp32 + fp64 carries for all"),
                        (1, "all fp32")):
-        with SpiirBank.from_bank(bank, precision=prec, filters_per_lane=args.fl,
+        with SpiirBank.from_bank(bank, precision=prec, filters_per_lane=args.fl, waves_per_group=args.wpg,
                                  time_split=args.time_split) as bk:
+            if prec == 0:
+                log("bank:", bk.info)
             mx = torch.empty(C, dtype=torch.float32, device="cuda")
             am = torch.empty(C, dtype=torch.int32, device="cuda")
 
