@@ -223,6 +223,33 @@ def mid():
     return bank, x, oracle.snr(bank, x)
 
 
+def test_segment_layout_for_banks_that_cannot_fill_the_device():
+    """A bank of more than 128 filters per compute unit that cannot fill the
+    device even at 4 filters per lane gets, when the layout is left to the
+    library, 4 filters per lane, 8-wave workgroups and 16 time segments;
+    SNR rows and the fused max/argmax against the oracle over two calls."""
+    bank = random_bank(61, 0, 40, 900, 1000, 0.99, 1 - 1e-5, 2047)
+    n, h = 20000, 12288
+    x = strain(n, 61)
+    banner("segment layout: %d templates, %d filters" % (bank.n_templates, bank.n_filters))
+    ref = oracle.snr(bank, x, nthreads=oracle.max_threads())
+    xd = dev(x)
+    with mk(bank) as bk:
+        info = bk.info
+        assert info["filters_per_lane"] == 4 and info["waves_per_group"] == 8
+        assert info["time_split"] == 16
+        s = torch.cat([bk.filter_block(xd[:h]), bk.filter_block(xd[h:])], dim=1).cpu().numpy()
+        bk.reset()
+        mx = torch.empty(n, dtype=torch.float32, device="cuda")
+        am = torch.empty(n, dtype=torch.int32, device="cuda")
+        bk.trigger_max(xd[:h], out=(mx[:h], am[:h]))
+        bk.trigger_max(xd[h:], out=(mx[h:], am[h:]))
+        torch.cuda.synchronize()
+    err, _ = snr_err(s, ref)
+    assert err <= SNR_TOL
+    check_argmax(mx.cpu().numpy(), am.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("fl,L,wpg,prec", [
     (2, 64, 0, 0), (2, 256, 0, 0), (3, 128, 8, 0), (4, 512, 0, 0),
     (2, 8, 0, 0), (2, 256, 8, 2), (3, 256, 6, 2), (4, 64, 3, 0)])
