@@ -342,18 +342,19 @@ int create_bank(spiir_bank **out, int32_t T, const int64_t *off, const double *a
     // a banded window is refilled every band samples (at most), so that several workgroups
     // share a compute unit
     const int nb_cap = band ? std::max(L, std::min(max_block, (band + L - 1) / L * L)) : max_block;
-    // A bank of more than 128 filters per compute unit that still cannot fill the device
-    // (fewer than 7 waves per CU at 4 filters per lane) is cut into time segments anyway.
-    // With long pieces the cost per update then matters more than the wave count: 4
-    // filters per lane, 8-wave workgroups (two waves per SIMD, several templates per
-    // workgroup) and up to 16 segments. On the 64 x 1,000-filter precision bank this ran
-    // at 2.29e12 updates/s against 1.39e12 for 2 filters per lane, one template per
-    // workgroup and 8 segments (the layout the wave-count rule below picks).
+    // A bank of more than 128 filters per compute unit that cannot fill the device with
+    // the lane count the wave-count rule below picks (fewer than 7 waves per CU) is cut
+    // into time segments anyway. With long pieces the cost per update then matters more
+    // than the wave count: 4 filters per lane, 8-wave workgroups (two waves per SIMD,
+    // several templates per workgroup) and up to 16 segments. On the 64 x 1,000-filter
+    // precision bank this ran at 2.29e12 updates/s against 1.39e12 for the wave-count
+    // rule's 2 filters per lane, one template per workgroup and 8 segments.
     bool seg_layout = false;
     if (!global_window && !band && o.filters_per_lane == 0 && o.waves_per_group == 0 && o.time_split == 0 &&
         max_block >= 8192 && off[T] > 128 * (int64_t)df.n_cu) {
         const Plan p4 = plan_rows(T, off, 4);
-        seg_layout = p4.max_nr <= 4 * kMaxWaves && (p4.total_rows + 3) / 4 < (int64_t)7 * df.n_cu;
+        const Plan pw = plan_rows(T, off, choose_fl(T, off, df.n_cu));
+        seg_layout = p4.max_nr <= 4 * kMaxWaves && (pw.total_rows + 3) / 4 < (int64_t)7 * df.n_cu;
     }
     if (seg_layout) seg_cap = std::max(seg_cap, 16);
     int fl = o.filters_per_lane;
