@@ -93,7 +93,13 @@ typedef struct {
                                  response is added. spiir_backward likewise cuts the
                                  reverse scan into segments (automatic count up to 16
                                  for 0, the given count for 2..32). 0 = automatic, 1 = off,
-                                 2..32 = forced. Not used by the per-template comparator. */
+                                 2..32 = forced. Not used by the per-template comparator.
+                                 With filters_per_lane, waves_per_group and time_split all
+                                 0, a bank of more than 128 filters per compute unit that
+                                 the automatic lane count cannot spread over 7 waves per
+                                 CU, with max_block >= 8192 and the strain window in LDS,
+                                 takes 4 filters per lane, 8-wave workgroups and up to 16
+                                 segments. */
     int32_t delay_band;       /* 0 = no delay bands (default: the strain window is staged in
                                  LDS when it fits, else read from global memory); w >= 1 =
                                  delay bands of width w: every workgroup holds filters with
