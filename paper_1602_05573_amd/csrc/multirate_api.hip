@@ -403,13 +403,16 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
     // the small levels share one launch per time-split pass (one stream, three
     // launches in place of three per level) when their banks agree in
     // workgroup size: with the automatic choice, rebuild the ones below the
-    // largest with that size
+    // largest with that size, and with at least 4 waves (one per SIMD). On the
+    // 1,024-template chirp bank a replayed block took 152 us with 4-wave
+    // workgroups for the group, 156.5 with 2 (the largest automatic size
+    // there), 180 with 1 and 172 with 8.
     for (int r = 0; r <= R; ++r)
         if (mr->bank[r] && small[r]) mr->multi.push_back(r);
     if (mr->multi.size() < 2 || mr->multi.size() > (size_t)kMultiMax) {
         mr->multi.clear();
     } else if (o.waves_per_group == 0) {
-        int wmax = 0;
+        int wmax = 4;
         for (int r : mr->multi) wmax = std::max(wmax, bank_wpg(mr->bank[r]));
         for (int r : mr->multi)
             if (bank_wpg(mr->bank[r]) != wmax) {
