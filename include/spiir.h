@@ -452,12 +452,13 @@ int spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches
  *                    samples (rounded down to a multiple of 2^R; level r gets
  *                    max_block / 2^r). With time_split = 0, a level of at most
  *                    128 filters per compute unit (a short serial recursion
- *                    per call) uses 64-sample chunks and up to 32 time
- *                    segments instead of chunk_len and 8; such levels run
- *                    as one group of launches when their banks agree in
- *                    layout (with waves_per_group = 0 the smaller ones are
- *                    built with the group's largest workgroup size), and
- *                    one bank call each while kernel timing is on.
+ *                    per call) takes up to 32 time segments instead of 8.
+ *                    Two or more such levels run as one group of launches
+ *                    when their banks agree in layout (with waves_per_group
+ *                    = 0 they are built with the group's largest workgroup
+ *                    size, at least 4 waves), and one bank call each while
+ *                    kernel timing is on; a single such level uses 64-sample
+ *                    chunks instead of chunk_len.
  * Calls take n a multiple of 2^R and continue one stream. Device memory held:
  * the level banks, the decimated streams, the level sums and ceil(T / 16) x
  * max_block uint64 keys. The interpolation runs in one launch per piece, each

@@ -359,16 +359,27 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         return bail(code);
     };
     std::vector<std::vector<int64_t>> offc(R + 1);
+    // a level whose filters leave most of the device idle ("small") is a short
+    // serial recursion per call: the automatic time split may cut it into up
+    // to 32 segments. Two or more small levels run as one group of launches
+    // (below) and keep chunk_len; a small level on its own takes 64-sample
+    // chunks so that its segments can be that short. On the 1,024-template
+    // chirp bank the group with 256-sample chunks replayed a block in 139 us,
+    // with 128 in 143-145 and with 64 in 151 (16-32 segments at most).
     std::vector<bool> small(R + 1, false);
-    // a level whose filters leave most of the device idle is a short serial
-    // recursion per call: let the automatic time split cut it into up to 32
-    // segments, with 64-sample chunks so that segments can be that short
+    int n_small = 0;
+    for (int r = 0; r <= R; ++r) {
+        const int64_t nf = filter_offsets[r][T];
+        small[r] = nf > 0 && o.time_split == 0 && nf <= 128 * (int64_t)df.n_cu;
+        n_small += small[r] ? 1 : 0;
+    }
+    const bool group_small = n_small >= 2 && n_small <= kMultiMax;
     auto make_bank = [&](int r, int wpg) -> int {
         spiir_bank_opts orr = o;
         orr.device = dev;
         orr.max_block = (int32_t)std::max<int64_t>(8, B >> r);
         if (wpg > 0) orr.waves_per_group = wpg;
-        if (small[r]) orr.chunk_len = 64;
+        if (small[r] && !group_small) orr.chunk_len = 64;
         spiir_bank *bk = nullptr;
         const int n_rows = (int32_t)(offc[r].size() - 1);
         const int code = orr.autotune
@@ -395,7 +406,6 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
         e = hipMemcpy(mr->zrow[r], row.data(), T * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "row map upload");
         if (off[T] == 0) continue;
-        small[r] = o.time_split == 0 && off[T] <= 128 * (int64_t)df.n_cu;
         if ((rc = make_bank(r, 0))) return bail(rc);
         e = dalloc(&mr->z[r], (size_t)(offc[r].size() - 1) * (size_t)(B >> r));
         if (e != hipSuccess) return alloc_fail(e);
