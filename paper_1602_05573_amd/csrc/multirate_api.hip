@@ -414,9 +414,10 @@ int spiir_multirate_create(spiir_multirate **out, int32_t n_levels, int32_t n_te
     // launches in place of three per level) when their banks agree in
     // workgroup size: with the automatic choice, rebuild the ones below the
     // largest with that size, and with at least 4 waves (one per SIMD). On the
-    // 1,024-template chirp bank a replayed block took 152 us with 4-wave
-    // workgroups for the group, 156.5 with 2 (the largest automatic size
-    // there), 180 with 1 and 172 with 8.
+    // 1,024-template chirp bank with 64-sample chunks a replayed block took
+    // 152 us with 4-wave workgroups for the group, 156.5 with 2 (the largest
+    // automatic size there), 180 with 1 and 172 with 8; with 256-sample chunks
+    // 139.0 with 4, 138.6 with 2 and 145 with 8.
     for (int r = 0; r <= R; ++r)
         if (mr->bank[r] && small[r]) mr->multi.push_back(r);
     if (mr->multi.size() < 2 || mr->multi.size() > (size_t)kMultiMax) {
