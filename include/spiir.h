@@ -259,7 +259,10 @@ int spiir_trigger_max(spiir_bank *bank, const float *x_dev, int64_t n,
  *   + (time split) 2 * segments * slots * 16 + (segments - 1) * T * segment_len * 8
  *   + (window not in LDS) (n + max_delay + 16) * 4,
  * each rounded up to 256; the 1,024-template bank at 4,096 samples per call
- * needs 7.9 MB. EINVAL (nothing launched) when a call needs more than 32 MiB;
+ * needs 7.9 MB. When the bank's time segments do not fit, the call cuts its
+ * launches into as many segments as do (results then agree with
+ * spiir_trigger_max to FP32 rounding instead of bitwise). EINVAL (nothing
+ * launched) when a call needs more than 32 MiB even without segments;
  * otherwise as spiir_trigger_max. Every call on one device shares that
  * device's array, which keeps the last call's contents: calls that overlap in
  * time on one device (several streams or host threads) race and must not be

@@ -523,6 +523,7 @@ int ensure_xwin(spiir_bank *bk, int64_t need) {
 struct CallScratch {
     uint64_t *keys = nullptr;
     int64_t keys_ld = 0;
+    int nseg = 0;   // time segments per launch for this call (0: the bank's)
     float4 *seg_end = nullptr, *seg_start = nullptr;
     float2 *zl = nullptr;
     float *xwin = nullptr;
@@ -574,8 +575,9 @@ int stream_call(spiir_bank *bk, const float *x, int64_t n, int mode, float *snr,
             a.ld = keys_ld;
         }
         int nseg = 1;
-        if (bk->nseg > 1) {
-            a.seg_len = ((np + bk->nseg - 1) / bk->nseg + bk->L - 1) / bk->L * bk->L;
+        const int bn = (cs && cs->nseg > 0) ? cs->nseg : bk->nseg;
+        if (bn > 1) {
+            a.seg_len = ((np + bn - 1) / bn + bk->L - 1) / bk->L * bk->L;
             nseg = (int)((np + a.seg_len - 1) / a.seg_len);
         }
         // the next call's history is written by a launch that follows every
@@ -950,7 +952,9 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // The allocation-free call's buffers carved from the device's scratch array
 // (scr = null: only the size). Bytes needed, or 0 with an error set.
-size_t plan_scratch(const spiir_bank *bk, int64_t n, unsigned char *scr, CallScratch &cs) {
+// Carves the call's buffers out of scr (null: sizes only) for time segments
+// of nseg per launch (at most the bank's count).
+size_t plan_scratch(const spiir_bank *bk, int64_t n, int nseg, unsigned char *scr, CallScratch &cs) {
     size_t at = 0;
     auto take = [&](size_t bytes) {
         unsigned char *p = scr ? scr + at : nullptr;
@@ -959,14 +963,15 @@ size_t plan_scratch(const spiir_bank *bk, int64_t n, unsigned char *scr, CallScr
     };
     const int64_t keys_ld = std::min<int64_t>(n, bk->max_block);
     cs.keys_ld = keys_ld;
+    cs.nseg = nseg;
     cs.keys = reinterpret_cast<uint64_t *>(
         take((size_t)(bk->lay.groups + (bk->n_split ? 1 : 0)) * keys_ld * sizeof(uint64_t)));
-    const size_t seg_bytes = (size_t)bk->nseg * bk->lay.nslots * sizeof(float4);
-    if (bk->nseg > 1) {
+    const size_t seg_bytes = (size_t)nseg * bk->lay.nslots * sizeof(float4);
+    if (nseg > 1) {
+        const int64_t seg_len = ((keys_ld + nseg - 1) / nseg + bk->L - 1) / bk->L * bk->L;
         cs.seg_end = reinterpret_cast<float4 *>(take(seg_bytes));
         cs.seg_start = reinterpret_cast<float4 *>(take(seg_bytes));
-        cs.zl = reinterpret_cast<float2 *>(
-            take((size_t)(bk->nseg - 1) * bk->T * bk->seg_len_max * sizeof(float2)));
+        cs.zl = reinterpret_cast<float2 *>(take((size_t)(nseg - 1) * bk->T * seg_len * sizeof(float2)));
     }
     if (!bk->xlds) cs.xwin = reinterpret_cast<float *>(take((size_t)(n + bk->dmax + 16) * sizeof(float)));
     return at;
@@ -980,7 +985,11 @@ int spiir_trigger_max_noalloc(spiir_bank *bk, const float *x, int64_t n, float *
     if (n == 0) return SPIIR_OK;
     if (!x || !mx || !am) return fail(SPIIR_EINVAL, "null device pointer");
     CallScratch cs;
-    const size_t need = plan_scratch(bk, n, nullptr, cs);
+    // the bank's time segments, or as many as the array holds (the per-segment
+    // states grow with the segment count)
+    int nseg = std::max(1, bk->nseg);
+    size_t need = plan_scratch(bk, n, nseg, nullptr, cs);
+    while (need > kScratchBytes && nseg > 1) need = plan_scratch(bk, n, --nseg, nullptr, cs);
     if (need > kScratchBytes)
         return fail(SPIIR_EINVAL,
                     "this call needs %zu bytes of working memory, more than the %zu bytes the allocation-free "
@@ -990,11 +999,11 @@ int spiir_trigger_max_noalloc(spiir_bank *bk, const float *x, int64_t n, float *
     unsigned char *scr = nullptr;
     const int rc = scratch_setup(bk->device, &scr);   // the address looked up when the bank was created
     if (rc) return rc;
-    plan_scratch(bk, n, scr, cs);
+    plan_scratch(bk, n, nseg, scr, cs);
     hipStream_t st = as_stream(stream);
-    if (bk->nseg > 1) {
+    if (nseg > 1) {
         // slots outside every template are chained from these buffers; start them at zero as the bank's own
-        const size_t seg_bytes = (size_t)bk->nseg * bk->lay.nslots * sizeof(float4);
+        const size_t seg_bytes = (size_t)nseg * bk->lay.nslots * sizeof(float4);
         HIPCHK(launch_fill_zero(cs.seg_end, seg_bytes, st));
         HIPCHK(launch_fill_zero(cs.seg_start, seg_bytes, st));
     }

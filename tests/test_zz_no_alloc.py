@@ -6,7 +6,8 @@ argmax rule against the FP64 oracle. Covered: a bank whose strain window sits
 in LDS, a time-split bank (segment states and local sums in the scratch
 array), a bank whose window stays in global memory (window in the scratch
 array), a bank with a template split over workgroups, two banks sharing the
-array call by call, and the size limit."""
+array call by call, a bank whose time segments must be cut to fit the array,
+and the size limit."""
 import numpy as np
 import pytest
 
@@ -140,6 +141,27 @@ def test_two_banks_share_the_array():
         r = {k: (v[0].cpu().numpy(), v[1].cpu().numpy()) for k, v in res.items()}
     for bank, pn, qn in ((b1, "p1", "q1"), (b2, "p2", "q2")):
         check_same(bank, x, [r[qn], r[pn]])
+
+
+def test_segments_cut_to_fit_the_array():
+    """A bank whose own time split (16 segments of 65,536 slots) does not fit
+    the array: the allocation-free call cuts its launches into fewer
+    segments, so it agrees with the allocating call to FP32 rounding (not
+    bitwise), and both pass the gate and the argmax rule against the oracle."""
+    from helpers import SNR_TOL
+    banner("noalloc: segments cut to fit")
+    bank = random_bank(77, 0, 64, 1000, 1000, 0.99, 0.99999, 2047)
+    x = strain(20000, 77)
+    outs, info = run_pair(bank, x, [0, 12288, 20000])
+    # the bank's segment states alone fill the array, beside the partial keys
+    assert info["time_split"] == 16 and info["n_slots"] * 16 * 2 * 16 >= SCRATCH_BYTES
+    (m0, a0), (m1, a1) = outs
+    ref = oracle.snr(bank, x, nthreads=oracle.max_threads())
+    peak = float(ref.max())
+    assert np.max(np.abs(m0.astype(np.float64) - m1)) <= SNR_TOL * peak
+    assert np.max(np.abs(m1.astype(np.float64) - ref.max(axis=0))) <= SNR_TOL * peak
+    check_argmax(m0, a0, ref)
+    check_argmax(m1, a1, ref)
 
 
 def test_size_limit_is_an_error():
